@@ -1,0 +1,447 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics: published known-answer vectors, closed forms, invariants,
+special cases that reduce to textbook or library routines, and brute force.
+None of these re-type the oracle's own formulas."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.spatial.distance import cdist
+from scipy.spatial.transform import Rotation
+
+from paper_2602_10114_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _arm(layout=scenes.LAYOUT_52, seed=3, **kw):
+    return scenes.franka_like_arm(np.random.default_rng(seed), layout, **kw)
+
+
+# ----------------------------------------------------------------- noise
+def test_philox_known_answers(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = orc.philox(v[0:4], v[4:6])
+        assert list(out) == v[6:10]
+
+
+def test_normals_distribution(orc):
+    """Kolmogorov-Smirnov against scipy's normal CDF, moments within 5 sigma
+    of their sampling error, and no correlation between joints or steps."""
+    d, n = 7, 3000
+    z = np.array([orc.normals(1234, 1, 5, 0, i, h, d) for i in range(n) for h in (0, 3)])
+    flat = z.ravel()
+    m = flat.size
+    assert abs(flat.mean()) < 5 / math.sqrt(m)
+    assert abs(flat.var() - 1) < 5 * math.sqrt(2 / m)
+    assert stats.kstest(flat, "norm").pvalue > 1e-3
+    c = np.corrcoef(z.T)
+    assert np.abs(c - np.eye(d)).max() < 5 / math.sqrt(z.shape[0])
+
+
+def test_normals_distinct_streams(orc):
+    """Different arm, step, iteration, rollout or horizon index give
+    different draws; the same index gives the same draw."""
+    base = orc.normals(7, 0, 0, 0, 0, 0, 7)
+    assert np.array_equal(base, orc.normals(7, 0, 0, 0, 0, 0, 7))
+    for args in [(7, 1, 0, 0, 0, 0), (7, 0, 1, 0, 0, 0), (7, 0, 0, 1, 0, 0),
+                 (7, 0, 0, 0, 1, 0), (7, 0, 0, 0, 0, 1), (8, 0, 0, 0, 0, 0)]:
+        assert not np.allclose(base, orc.normals(*args, 7))
+
+
+# ------------------------------------------------------------- dynamics
+def test_integrate_constant_acceleration_closed_form(orc):
+    rng = np.random.default_rng(0)
+    d, H, dt = 7, 25, 0.02
+    q0, qd0, a = rng.normal(size=d), rng.normal(size=d), rng.normal(size=d)
+    q, qd = orc.integrate(q0, qd0, np.tile(a, (H, 1)), dt)
+    h = np.arange(1, H + 1)[:, None]
+    np.testing.assert_allclose(qd, qd0 + a * dt * h, atol=1e-12)
+    np.testing.assert_allclose(q, q0 + h * dt * qd0 + a * dt * dt * h * (h + 1) / 2, atol=1e-12)
+
+
+# ------------------------------------------------------------ kinematics
+def _two_link():
+    arm = _arm()
+    dh = np.zeros((2, 4), np.float32)
+    dh[0] = (0, 0, 0.5, 0)
+    dh[1] = (0.3, np.float32(math.pi / 2), 0.1, 0)
+    return scenes.Arm(dh=dh, q_lim=arm.q_lim[:2], qd_max=arm.qd_max[:2],
+                      spheres=np.array([[0, 0, 0, 0.05], [0.1, 0, 0, 0.05]], np.float32),
+                      sphere_link=np.array([0, 1], np.int32), base=np.zeros(4, np.float32),
+                      tool=np.zeros(3, np.float32), n_rollouts=1, horizon=1)
+
+
+def _golden_fk():
+    out = {}
+    for l in open(os.path.join(GOLDEN, "fk_hand_derived.txt")):
+        if l.strip() and not l.startswith("#"):
+            f = l.split()
+            out[f[0]] = np.array([float(x) for x in f[1:]])
+    return out
+
+
+def test_fk_hand_derived_two_link(orc):
+    g = _golden_fk()
+    oa = orc.make_arm(_two_link())
+    for name in ("two_link_q00", "two_link_q90"):
+        v = g[name]
+        fr = orc.fk(oa, v[0:2])
+        # alpha = pi/2 is rounded to FP32 in the table, hence 1e-7.
+        np.testing.assert_allclose(fr[1][:3, 3], v[2:5], atol=1e-7)
+        np.testing.assert_allclose(fr[1][:3, :3].ravel(), v[5:14], atol=1e-7)
+
+
+def test_fk_franka_like_zero_pose(orc):
+    g = _golden_fk()
+    arm = _arm()
+    oa = orc.make_arm(arm)
+    fr = orc.fk(oa, np.zeros(7))
+    np.testing.assert_allclose(fr[6][:3, 3], g["franka_like_q0_frame7"], atol=1e-6)
+    flange = fr[6][:3, 3] + 0.107 * fr[6][:3, 2]
+    np.testing.assert_allclose(flange, g["franka_like_q0_flange"], atol=1e-6)
+
+
+def test_fk_orthonormal_and_spacing(orc):
+    arm = _arm()
+    oa = orc.make_arm(arm)
+    rng = np.random.default_rng(1)
+    dh = arm.dh.astype(np.float64)
+    for _ in range(20):
+        q = scenes.random_plan_inputs(rng, arm, 1)[0].astype(np.float64)
+        fr = orc.fk(oa, q)
+        for k in range(8):
+            R = fr[k][:3, :3]
+            np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
+            assert abs(np.linalg.det(R) - 1) < 1e-12
+            np.testing.assert_allclose(fr[k][3], [0, 0, 0, 1])
+        # origin of frame k+1 sits sqrt(a^2 + d^2) from frame k's origin
+        for k in range(6):
+            gap = np.linalg.norm(fr[k + 1][:3, 3] - fr[k][:3, 3])
+            assert abs(gap - math.hypot(dh[k + 1, 0], dh[k + 1, 2])) < 1e-12
+
+
+def test_fk_planar_chain_textbook(orc):
+    """All twists, offsets and d zero: joint origins follow
+    x_k = sum_i a_i cos(q_1 + ... + q_{i-1}), y likewise with sin."""
+    a = np.array([0.0, 0.4, 0.3, 0.25, 0.2], np.float32)
+    dh = np.zeros((5, 4), np.float32)
+    dh[:, 0] = a
+    arm = scenes.Arm(dh=dh, q_lim=np.zeros((5, 2), np.float32), qd_max=np.ones(5, np.float32),
+                     spheres=np.zeros((1, 4), np.float32), sphere_link=np.zeros(1, np.int32),
+                     base=np.zeros(4, np.float32), tool=np.zeros(3, np.float32),
+                     n_rollouts=1, horizon=1)
+    oa = orc.make_arm(arm)
+    q = np.array([0.3, -0.7, 1.1, 0.2, -0.4])
+    fr = orc.fk(oa, q)
+    ang = np.concatenate([[0.0], np.cumsum(q)])
+    for k in range(5):
+        x = sum(float(a[i]) * math.cos(ang[i]) for i in range(k + 1))
+        y = sum(float(a[i]) * math.sin(ang[i]) for i in range(k + 1))
+        np.testing.assert_allclose(fr[k][:2, 3], [x, y], atol=1e-12)
+        assert abs(math.atan2(fr[k][1, 0], fr[k][0, 0]) -
+                   math.atan2(math.sin(ang[k + 1]), math.cos(ang[k + 1]))) < 1e-12
+
+
+def test_fk_base_yaw_equals_first_joint(orc):
+    arm = _arm()
+    rng = np.random.default_rng(2)
+    q = scenes.random_plan_inputs(rng, arm, 1)[0].astype(np.float64)
+    psi = 0.7
+    yawed = scenes.Arm(**{**arm.__dict__, "base": np.array([0.1, -0.2, 0.05, psi], np.float32)})
+    plain = scenes.Arm(**{**arm.__dict__, "base": np.array([0.1, -0.2, 0.05, 0.0], np.float32)})
+    q2 = q.copy()
+    q2[0] += float(np.float32(psi))
+    np.testing.assert_allclose(orc.fk(orc.make_arm(yawed), q), orc.fk(orc.make_arm(plain), q2), atol=1e-12)
+
+
+def test_spheres_keep_body_offsets(orc):
+    arm = _arm()
+    oa = orc.make_arm(arm)
+    q = scenes.random_plan_inputs(np.random.default_rng(4), arm, 1)[0]
+    fr = orc.fk(oa, q)
+    sph = orc.spheres(oa, q)
+    for s in range(arm.n_spheres):
+        t = fr[arm.sphere_link[s]][:3, 3]
+        assert abs(np.linalg.norm(sph[s, :3] - t) - np.linalg.norm(arm.spheres[s, :3].astype(np.float64))) < 1e-12
+        assert sph[s, 3] == float(arm.spheres[s, 3])
+
+
+# ------------------------------------------------------------- distances
+def test_two_sphere_closed_form(orc):
+    assert abs(orc.sphere_rho([0, 0, 0, 0.1], [0.5, 0, 0, 0.2]) - 0.2) < 1e-15
+    assert abs(orc.sphere_rho([1, 2, 3, 0.3], [1, 2, 3.1, 0.2]) + 0.4) < 1e-12
+
+
+def test_set_distance_brute_force_and_invariance(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        na, nb = rng.integers(1, 5, size=2)
+        A = np.concatenate([rng.normal(size=(na, 3)), rng.uniform(0.01, 0.2, (na, 1))], 1)
+        B = np.concatenate([rng.normal(size=(nb, 3)), rng.uniform(0.01, 0.2, (nb, 1))], 1)
+        brute = (cdist(A[:, :3], B[:, :3]) - A[:, 3:4] - B[:, 3][None, :]).min()
+        assert abs(orc.rho_sets(A, B) - brute) < 1e-12
+        assert abs(orc.rho_sets(B, A) - brute) < 1e-12
+        R = Rotation.random(random_state=int(rng.integers(1 << 30))).as_matrix()
+        t = rng.normal(size=3)
+        A2, B2 = A.copy(), B.copy()
+        A2[:, :3] = A[:, :3] @ R.T + t
+        B2[:, :3] = B[:, :3] @ R.T + t
+        assert abs(orc.rho_sets(A2, B2) - brute) < 1e-12
+
+
+def test_self_pairs_skip_adjacent_bodies(orc):
+    c = np.array([[0, 0, 0, 0.1], [0.05, 0, 0, 0.1], [0.5, 0, 0, 0.1]], float)
+    # bodies 0,1 overlap but are adjacent; the surfaces of 0 and 2 are 0.3 apart.
+    assert abs(orc.rho_self(c, [0, 1, 2]) - 0.3) < 1e-12
+    assert orc.rho_self(c, [0, 1, 1]) == math.inf
+
+
+def test_hinge_special_values(orc):
+    B = 0.03
+    assert orc.hinge(B, B) == 0.0 and orc.hinge(0.5, B) == 0.0
+    assert orc.hinge(0.0, B) == 1.0 and orc.hinge(-0.2, B) == 1.0
+    assert abs(orc.hinge(B / 2, B) - 0.5) < 1e-15
+    assert orc.hinge(math.inf, B) == 0.0
+
+
+# --------------------------------------------------------------- costs
+def test_pose_rotation_term_matches_quaternion_inner_product(orc):
+    """(3 - tr(Rg^T R)) / 4 = 1 - <q, g>^2, with the quaternions taken from
+    scipy's independent rotation code."""
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        Rm = Rotation.random(random_state=int(rng.integers(1 << 30)))
+        T = np.eye(4)
+        T[:3, :3] = Rm.as_matrix()
+        T[:3, 3] = rng.normal(size=3)
+        g = np.concatenate([T[:3, 3] + [0.3, 0, 0], scenes.random_quaternion(rng)])
+        qx, qy, qz, qw = Rm.as_quat()
+        ip = qw * g[3] + qx * g[4] + qy * g[5] + qz * g[6]
+        expected = 0.3 + 0.1 * (1 - ip * ip)
+        assert abs(orc.pose_cost(T, g, 0.1) - expected) < 1e-12
+    # reached goal -> zero
+    T = np.eye(4)
+    T[:3, :3] = Rotation.from_euler("xyz", [0.2, -0.4, 1.0]).as_matrix()
+    x, y, z, w = Rotation.from_matrix(T[:3, :3]).as_quat()
+    assert abs(orc.pose_cost(T, [0, 0, 0, w, x, y, z], 0.1)) < 1e-14
+
+
+def test_quat_rotation_matches_scipy(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(10):
+        q = scenes.random_quaternion(rng)
+        R = orc.quat_to_rot(q * 1.7)  # normalised internally
+        np.testing.assert_allclose(R, Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix(), atol=1e-12)
+
+
+def test_stop_and_joint_special_cases(orc):
+    arm = _arm()
+    oa = orc.make_arm(arm)
+    H = 10
+    qd = np.array([0.5, -0.5, 0, 0, 0, 0, 0.1])
+    # last step: nothing may move
+    assert abs(orc.stop_cost(oa, H, H - 1, qd) - np.abs(qd).sum()) < 1e-14
+    # first step: limits are 0.9 qd_max > |qd|
+    assert orc.stop_cost(oa, H, 0, qd) == 0.0
+    mid = arm.q_lim.astype(np.float64).mean(1)
+    mid[3] = -1.5
+    assert orc.joint_cost(oa, mid, 0.05) == 0.0
+    q = mid.copy()
+    q[0] = float(arm.q_lim[0, 0]) - 0.1
+    assert abs(orc.joint_cost(oa, q, 0.05) - 0.15) < 1e-12
+
+
+def test_priority_properties(orc):
+    assert orc.priority(0.4, 0.1, 0.0, 1e-3, 0.5, 2.0) == 1.0
+    for da, db in [(0.3, 0.2), (0.05, 0.4), (0.7, 0.69)]:
+        p1 = orc.priority(da, db, 3.0, 1e-3, 0.0, 1e300)
+        p2 = orc.priority(db, da, 3.0, 1e-3, 0.0, 1e300)
+        assert abs(p1 * p2 - 1) < 1e-12
+        # the arm nearer its goal carries the smaller weight
+        assert (p1 < 1) == (da < db)
+    assert orc.priority(0.9, 0.1, 3.0, 1e-3, 0.5, 2.0) == 2.0
+    assert orc.priority(0.0, 0.0, 3.0, 1e-3, 0.5, 2.0) == 1.0
+
+
+# -------------------------------------------------------------- update
+def test_weights_properties(orc):
+    rng = np.random.default_rng(8)
+    C = rng.normal(size=200) * 3 + 1e4
+    w = orc.weights(C, 0.05)
+    assert abs(w.sum() - 1) < 1e-12
+    np.testing.assert_allclose(orc.weights(C + 123.0, 0.05), w, rtol=1e-9, atol=1e-300)
+    np.testing.assert_allclose(orc.weights(C, 1e30), np.full(200, 1 / 200), rtol=1e-12)
+    w0 = orc.weights(C, 1e-30)
+    assert w0[np.argmin(C)] == 1.0 and w0.sum() == 1.0
+
+
+def test_update_limits(orc):
+    rng = np.random.default_rng(9)
+    N, H, d = 64, 6, 7
+    U = rng.normal(size=(N, H, d))
+    C = rng.uniform(size=N)
+    np.testing.assert_allclose(orc.weighted_mean(orc.weights(C, 1e30), U), U.mean(0), atol=1e-12)
+    np.testing.assert_allclose(orc.weighted_mean(orc.weights(C, 1e-30), U), U[np.argmin(C)], atol=0)
+    np.testing.assert_allclose(orc.weighted_mean(orc.weights(C[:1], 0.05), U[:1]), U[0], atol=0)
+    mu = rng.normal(size=(H, d))
+    np.testing.assert_array_equal(orc.ema(mu, U[0], 0.0), mu)
+    np.testing.assert_array_equal(orc.ema(mu, U[0], 1.0), U[0])
+    s = mu
+    for _ in range(H):
+        s = orc.shift(s)
+    np.testing.assert_array_equal(s, np.tile(mu[-1], (H, 1)))
+    assert orc.argmin(np.array([3.0, 1.0, 1.0, 2.0])) == 1
+
+
+def test_total_cost_geometric(orc):
+    # constant stage cost c: sum_{h<H} gamma^h c = c (1 - gamma^H) / (1 - gamma)
+    g, H = 0.99, 30
+    assert abs(orc.total_cost(np.full(H, 2.5), g) - 2.5 * (1 - g ** H) / (1 - g)) < 1e-12
+    assert orc.total_cost(np.arange(5.0), 1.0) == 10.0
+
+
+# --------------------------------------------------------- full controller
+def _scene_controller(orc, cfg, **over):
+    sc = scenes.make_scene(cfg, **over)
+    return sc, orc.Controller(sc.arms, sc.params)
+
+
+def test_step_act_consistency_at_zero_temperature(orc):
+    """lambda -> 0 with alpha_mu = 1: the new mean's first step is the
+    executed command (both pick the minimum-cost rollout)."""
+    sc, ctl = _scene_controller(orc, 1, lam=1e-30)
+    u = ctl.step(sc.state, sc.goal, sc.obstacles)
+    mu = ctl.mean(0)
+    np.testing.assert_allclose(mu[0], u[0], atol=1e-15)
+
+
+def test_step_costs_match_stage_function(orc):
+    """The controller's stage costs equal the stage function applied to the
+    rollouts rebuilt from its own noise (integration + FK done here through
+    the primitive functions)."""
+    sc, ctl = _scene_controller(orc, 1)
+    arm = sc.arms[0]
+    arm.n_rollouts = 8
+    sc.arms[0] = arm
+    ctl = orc.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    eps = ctl.noise(0)[:8, :arm.horizon]
+    tot, st, w = ctl.costs(0)
+    oa = orc.make_arm(arm)
+    H, d = arm.horizon, arm.dof
+    q0 = sc.state[0, :, 0].astype(np.float64)
+    qd0 = sc.state[0, :, 1].astype(np.float64)
+    qs, qds, sphs = [], [], []
+    for n in range(8):
+        q, qd = orc.integrate(q0, qd0, eps[n], float(np.float32(0.02)))
+        qs.append(q)
+        qds.append(qd)
+        sphs.append(np.stack([orc.spheres(oa, q[h]) for h in range(H)]))
+    prm = orc.make_params(sc.params)
+    stage = orc.stage_costs_batch(oa, prm, np.stack(qs), np.stack(qds), np.stack(sphs), sc.goal[0],
+                                  sc.obstacles, np.zeros((0,)), [], [], [], [])
+    np.testing.assert_allclose(stage, st[:H, :8], rtol=1e-12)
+    for n in range(8):
+        assert abs(orc.total_cost(stage[:, n], float(np.float32(0.99))) - tot[n]) < 1e-9
+
+
+def test_unpublished_neighbours_are_ignored(orc):
+    """Without a publish, the second arm's plan never enters the first arm's
+    cost: the costs equal those of a run where w_dyn = 0."""
+    sc, ctl = _scene_controller(orc, 2)
+    for a in sc.arms:
+        a.n_rollouts = 16
+        a.horizon = 8
+    ctl = orc.Controller(sc.arms, sc.params)
+    ctl0 = orc.Controller(sc.arms, {**sc.params, "w_dyn": 0.0})
+    for _ in range(2):
+        ctl.step(sc.state, sc.goal, sc.obstacles)
+        ctl0.step(sc.state, sc.goal, sc.obstacles)
+    np.testing.assert_array_equal(ctl.costs(0)[0], ctl0.costs(0)[0])
+    # after a publish the plans do enter (the arms start 1 cm apart)
+    ctl.share_plans()
+    ctl0.share_plans()
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    ctl0.step(sc.state, sc.goal, sc.obstacles)
+    assert np.any(ctl.costs(0)[0] != ctl0.costs(0)[0])
+    assert ctl.alpha()[0][0, 1] > 0
+
+
+def test_cost_weights_scale_linearly(orc):
+    sc = scenes.make_scene(2)
+    arm = sc.arms[0]
+    oa = orc.make_arm(arm)
+    rng = np.random.default_rng(10)
+    q = scenes.random_plan_inputs(rng, arm, 6).reshape(2, 3, 7).astype(np.float64)
+    qd = rng.normal(size=q.shape)
+    sph = np.stack([[orc.spheres(oa, q[n, h]) for h in range(3)] for n in range(2)])
+    other = orc.make_arm(sc.arms[1])
+    plan = np.stack([orc.spheres(other, q[1, h]) for h in range(3)])[None]
+    args = (q, qd, sph, sc.goal[0], np.array([[0.2, 0, 0.4, 0.1]]), plan, [52], [3], [1], [1.3])
+    p1 = orc.make_params(sc.params)
+    over = {k: sc.params[k] * 3 for k in ("w_pose", "w_stop", "w_joint", "w_coll", "w_dyn")}
+    p3 = orc.make_params({**sc.params, **over})
+    c1 = orc.stage_costs_batch(oa, p1, *args)
+    c3 = orc.stage_costs_batch(oa, p3, *args)
+    np.testing.assert_allclose(c3, 3 * c1, rtol=1e-12)
+
+
+def test_pair_count_formula(orc):
+    assert orc.pair_count(40, 4096, 64, [64] * 7) == 40 * 4096 * 64 * 448
+
+
+# --------------------------------------------------- learned arm-pair part
+def test_arm_pair_rho_is_set_distance(orc):
+    sc = scenes.make_scene(2)
+    a, b = (orc.make_arm(x) for x in sc.arms)
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        qa, qb = (scenes.random_plan_inputs(rng, sc.arms[0], 1)[0] for _ in range(2))
+        r = orc.arm_pair_rho(a, qa, b, qb)
+        sa, sb = orc.spheres(a, qa), orc.spheres(b, qb)
+        brute = (cdist(sa[:, :3], sb[:, :3]) - sa[:, 3:4] - sb[:, 3][None, :]).min()
+        assert abs(r - brute) < 1e-12
+        assert abs(orc.arm_pair_rho(b, qb, a, qa) - r) < 1e-12
+
+
+def test_mlp_forward_hand_computed(orc):
+    # 2 -> 2 -> 1: W0 = [[1, -1], [2, 0.5]], b0 = [0, -1]; W1 = [[1, 3]], b1 = [0.5]
+    params = np.array([1, -1, 2, 0.5, 0, -1, 1, 3, 0.5], float)
+    x = np.array([[1.0, 2.0], [-1.0, 0.0]])
+    # x0: z = [-1, 2] -> relu [0, 2] -> 6.5; x1: z = [-1, -3] -> 0 -> 0.5
+    np.testing.assert_allclose(orc.mlp_forward([2, 2, 1], params, x)[:, 0], [6.5, 0.5])
+
+
+def test_mlp_gradient_finite_difference(orc):
+    widths = [5, 7, 6, 1]
+    rng = np.random.default_rng(12)
+    n = orc.mlp_param_count(widths)
+    p = rng.normal(size=n) * 0.5
+    x = rng.normal(size=(9, 5))
+    t = rng.normal(size=9)
+    loss, g = orc.mlp_loss_grad(widths, p, x, t, 4.0)
+    h = 1e-6
+    for i in range(n):
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (orc.mlp_loss_grad(widths, pp, x, t, 4.0)[0] - orc.mlp_loss_grad(widths, pm, x, t, 4.0)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
+    y = orc.mlp_forward(widths, p, x)[:, 0]
+    e = y - t
+    assert abs(loss - np.mean(e * e + 4.0 * np.maximum(e, 0) ** 2)) < 1e-12
+
+
+def test_adam_first_step_is_signed_lr(orc):
+    p = np.array([1.0, -2.0, 0.5])
+    m, v = np.zeros(3), np.zeros(3)
+    g = np.array([0.3, -4.0, 1e-3])
+    orc.adam(p, m, v, g, 0.01, 0.9, 0.999, 1e-12, 1)
+    np.testing.assert_allclose(p, [0.99, -1.99, 0.49], atol=1e-8)
