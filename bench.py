@@ -1,0 +1,172 @@
+"""Throughput of the batched MR-STORM control step on one MI355X.
+
+Workload: 8 arms in two facing rows of 4 (0.5 m pitch), 4096 rollouts x 40
+horizon steps per arm, 64 collision spheres per arm, 20 moving obstacle
+spheres, every arm scored against the 7 published neighbour plans (exact
+coordination distances).  One step = Publish + mpc_step (Sense, Shift,
+sampling, dynamics, kinematics, scoring, update, ToPlan, PickBest) + the
+plant stand-in, on inputs already resident in HBM; obstacle positions for
+every step are precomputed and uploaded before the timed region.
+
+Prints one JSON line: rollout-steps/s, p50/p99 step latency, the roofline of
+the fused rollout kernel (FP32 ALU bound, achieved algorithmic TFLOP/s over
+its HIP-event-timed launches) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/s (arms×rollouts×horizon) + p50/p99 step latency, exact vs surrogate"
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, 256 CUs at 2.4 GHz
+
+
+def algorithmic_flops_per_step(scene, active_neighbours=True):
+    """Algorithmic work of one rollout launch: 11 FLOP per sphere pair (3 sub,
+    5 for the dot product, sqrt, minus radii, min) plus the per rollout-step
+    base 4d (sampling and integration) + 8*63 (frame composition) + 18 S
+    (sphere placement) + 30 (pose) + 7 d (stop and joint limits)."""
+    total = 0
+    d = 7
+    O = scene.obstacles.shape[0]
+    for a, arm in enumerate(scene.arms):
+        L = arm.sphere_link
+        S = arm.n_spheres
+        self_pairs = int(sum(1 for s in range(S) for t in range(s + 1, S) if abs(int(L[s]) - int(L[t])) >= 2))
+        base = 4 * d + 8 * 63 + 18 * S + 30 + 7 * d
+        for h in range(arm.horizon):
+            dyn = 0
+            if active_neighbours:
+                dyn = sum(S * b.n_spheres for i, b in enumerate(scene.arms) if i != a and h < b.horizon)
+            total += arm.n_rollouts * (11 * (self_pairs + S * O + dyn) + base)
+    return total * int(scene.params["iters"])
+
+
+def cpu_baseline(scene, seconds_hint=True):
+    """The FP64 oracle on a bounded sample of the same workload: one control
+    step of all 8 arms restricted to their first `window` rollouts, after one
+    warm step that publishes plans (so every neighbour term is active)."""
+    import oracle
+    window = 320
+    orc = oracle.Controller(scene.arms, scene.params)
+    orc.set_window(0, 1)
+    orc.step(scene.state, scene.goal, scene.obstacles)
+    orc.share_plans()
+    orc.set_window(0, window)
+    t0 = time.perf_counter()
+    orc.step(scene.state, scene.goal, scene.obstacles)
+    dt = time.perf_counter() - t0
+    rs = window * sum(a.horizon for a in scene.arms)
+    return {"value": rs / dt, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one control step of all 8 arms restricted to {window} of 4096 rollouts each "
+                      f"({rs} rollout-steps, {dt:.1f} s on one host thread, FP64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU plan all-gather "
+                                   "is a design, not a runnable path (--gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2602_10114_amd import native, scenes
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    scene = scenes.make_scene(5, collision_mode=0)
+    A = scene.n_arms
+    total_steps = args.warmup + 2 * args.steps
+    # Obstacle trajectories for every step, uploaded once.
+    obs_traj = []
+    for _ in range(total_steps):
+        obs_traj.append(scene.obstacles.copy())
+        scenes.move_obstacles(scene, float(scene.params["dt"]))
+    obs_dev = torch.as_tensor(np.stack(obs_traj), device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        state = torch.as_tensor(scene.state, device=dev).contiguous()
+        goal = torch.as_tensor(scene.goal, device=dev).contiguous()
+        u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
+        ctl = native.Controller(scene.arms, scene.params, stream=stream)
+        k = 0
+
+        def one_step():
+            nonlocal k
+            ctl.share_plans()
+            ctl.step(state, goal, obs_dev[k], u_out=u)
+            ctl.sim_execute(state, u)
+            k += 1
+
+        for _ in range(args.warmup):
+            one_step()
+        stream.synchronize()
+        print(f"bench: warmup done, tuning {ctl.tuning()}", file=sys.stderr, flush=True)
+        # Timed region: graph-launched steps, one event pair per step.
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            one_step()
+            ev[i][1].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        print(f"bench: timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+        # Same steps again with the rollout launches bracketed by HIP events.
+        ctl.profile_enable(True)
+        for i in range(args.steps):
+            one_step()
+        ms_roll, n_roll = ctl.profile_read()
+        ctl.profile_enable(False)
+        stream.synchronize()
+    rs_per_step = scene.rollout_steps()
+    ms_per_step = 1e3 * wall / args.steps
+    flops = algorithmic_flops_per_step(scene)
+    roll_ms = ms_roll / max(n_roll, 1)
+    achieved = flops / (roll_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": rs_per_step / (wall / args.steps),
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "8 arms (two facing rows of 4, 0.5 m pitch) x 4096 rollouts x 40 steps, "
+                               "64 spheres/arm, 20 moving obstacles, exact coordination distances, K=1",
+                   "arms": A, "rollouts": 4096, "horizon": 40, "spheres": 64, "obstacles": 20,
+                   "mode": "exact", "tuning": list(ctl.tuning())},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "roofline": {"kernel": "k_rollout", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms": roll_ms, "algorithmic_flop_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene)
+    ctl.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

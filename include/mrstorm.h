@@ -1,0 +1,199 @@
+/* mrstorm.h -- C-ABI of the MI355X (gfx950) MR-STORM control-step library.
+ *
+ * One call of mpc_step runs one MPC control step for every arm of a scene,
+ * as each arm's controller does in the paper's per-arm loop (arXiv
+ * 2602.10114, Alg. 1): Sense (current distance to goal and the priority
+ * factors of Eq. 10 against every published neighbour plan), Shift, K
+ * optimisation iterations of SampleControls -> Rollout (dynamics, forward
+ * kinematics over the collision spheres, the stage cost of Eq. 5 extended by
+ * the coordination cost of Eqs. 6-9) -> UpdateDistribution (Eqs. 1-4), then
+ * ToPlan and PickBest.  mpc_share_plans is the Publish step that makes the
+ * plans written by the last mpc_step visible to the other arms.
+ *
+ * Conventions for every entry point below:
+ *  - Arrays passed to mpc_step / mpc_get_plan / mpc_debug_get / mpc_set_plan /
+ *    mpc_set_mean / mpc_sim_execute are DEVICE pointers owned by the caller.
+ *    They are read or written in stream order on the stream given to
+ *    mpc_init; the calls return without waiting for the GPU.
+ *  - mpc_init takes HOST descriptors and copies them; the caller may free
+ *    them on return.
+ *  - The context owns every internal buffer.  One context must not be used
+ *    from two threads at the same time.
+ *  - All floating-point data is FP32.  Lengths are metres, angles radians.
+ *  - Return codes: MPC_OK (0), or a negative MPC_E* code; mpc_last_error
+ *    gives the message.  Nothing throws across the ABI, and there is no host
+ *    fallback: without a usable gfx950 device mpc_init fails with MPC_EHIP.
+ */
+#ifndef MRSTORM_H
+#define MRSTORM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPC_OK 0
+#define MPC_EINVAL (-1)      /* a size, index or value out of range */
+#define MPC_ENOMEM (-2)      /* device allocation failed */
+#define MPC_EHIP (-3)        /* HIP runtime error (text in mpc_last_error) */
+#define MPC_ESTATE (-4)      /* call not valid in the current state */
+#define MPC_EUNSUPPORTED (-5)
+
+#define MPC_MAX_ARMS 8
+#define MPC_MAX_DOF 8
+#define MPC_MAX_SPHERES 64
+#define MPC_MAX_SPHERES_PER_BODY 8
+#define MPC_MAX_HORIZON 64
+#define MPC_MAX_ROLLOUTS 16384
+#define MPC_MAX_OBSTACLES 64
+
+typedef struct mpc_ctx mpc_ctx;
+
+/* One arm (Sec. III: joint state Theta in R^{d x 3}; Sec. IV-A: the sphere
+ * matrix S in R^{N_S x 4} at constant transforms from the links). */
+typedef struct {
+  int dof;                 /* d: revolute joints, 1..MPC_MAX_DOF */
+  int n_spheres;           /* N_S: 1..MPC_MAX_SPHERES, at most 8 per body */
+  int n_rollouts;          /* N: 1..MPC_MAX_ROLLOUTS (any value; internally padded to 64) */
+  int horizon;             /* H: 1..MPC_MAX_HORIZON */
+  const float *dh;         /* [dof][4]: a_{k-1}, alpha_{k-1}, d_k, theta offset (modified DH) */
+  const float *q_lim;      /* [dof][2]: lower, upper joint limit */
+  const float *qd_max;     /* [dof]: joint speed limit used by the stopping cost */
+  const float *spheres;    /* [n_spheres][4]: centre in its body frame, radius */
+  const int *sphere_link;  /* [n_spheres]: body 0..dof-1 = link frame 1..dof, dof = hand */
+  float base[4];           /* base pose in the world: x, y, z, yaw about z */
+  float tool[3];           /* end-effector point in the last link frame */
+} mpc_arm_desc;
+
+/* Controller parameters shared by all arms (Sec. III-A and Sec. IV; the
+ * paper's standard variant uses w_dyn = 5000, buf_dyn = 0.03, tau = 3). */
+typedef struct {
+  float dt;                /* integration step of the rollout dynamics, s */
+  float sigma;             /* sampling standard deviation, Sigma = sigma^2 I */
+  float lambda;            /* softmax temperature (Eq. 2) */
+  float gamma;             /* discount (Eq. 1) */
+  float alpha_mu;          /* mean step size (Eq. 4), in (0, 1] */
+  int iters;               /* K optimisation iterations per control step, 1..8 */
+  float w_pose, w_rot, w_stop, w_joint, w_coll, w_dyn;  /* cost weights (Eqs. 5, 7, 9) */
+  float buf_env, buf_self, buf_dyn;  /* hinge buffers; buf_dyn is B of Sec. IV-A */
+  float tau;               /* trust exponent of the priority factor (Eq. 10) */
+  float prio_min, prio_max;  /* clamp of the priority factor */
+  float dist_floor;        /* floor of the distances in Eq. 10 */
+  float joint_margin;      /* soft joint-limit margin */
+  unsigned long long seed; /* key of the counter-based noise */
+  int max_obstacles;       /* capacity for obstacle spheres per step, <= MPC_MAX_OBSTACLES */
+  int collision_mode;      /* 0: exact coordination distances; 1: learned distance with exact fallback */
+  float surrogate_margin;  /* mode 1: predictions below this (metres) are checked exactly */
+} mpc_params;
+
+/* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).
+ * hip_stream: a hipStream_t (NULL = the default stream).  Host pointers.
+ * The controls' means start at zero (reading of the random initialisation:
+ * a deterministic start) and no plan is published. */
+int mpc_init(const mpc_arm_desc *arms, int n_arms, const mpc_params *params,
+             void *hip_stream, mpc_ctx **out);
+
+/* Publish (Alg. 1): the plans and distances-to-goal that the last mpc_step
+ * wrote for the arms in publish_mask (host [n_arms] bytes; NULL = all)
+ * become the ones the other arms read at their next Sense.  An arm that never
+ * stepped has nothing to publish and stays invisible (Sec. IV-C: neighbours
+ * whose plans were never published are ignored). */
+int mpc_share_plans(mpc_ctx *c, const unsigned char *publish_mask);
+
+/* One control step for every arm.
+ *  state      [n_arms][dof][3] device: theta, theta_dot, theta_ddot per joint
+ *  goal       [n_arms][7] device: goal position xyz, goal orientation quaternion w,x,y,z
+ *  obstacles  [n_obstacles][4] device: world-frame sphere centre, radius;
+ *             held fixed over the horizon (Sec. IV-A); may be NULL if 0
+ *  u_out      [n_arms][dof] device: the executed command U* (first step of
+ *             the minimum-cost rollout of the last iteration, Sec. III-A Act)
+ * Errors: MPC_EINVAL if n_obstacles is outside [0, max_obstacles]. */
+int mpc_step(mpc_ctx *c, const float *state, const float *goal, const float *obstacles,
+             int n_obstacles, float *u_out);
+
+/* The anticipated plan of one arm as written by the last mpc_step (Sec. IV-A:
+ * P in R^{N_S x 4 x H}).
+ *  plan    [n_spheres][4][horizon] device (paper layout), or NULL
+ *  plan_q  [horizon][dof] device: the planned joint positions, or NULL
+ *  mean    [horizon][dof] device: the control means mu after the update, or NULL
+ * Errors: MPC_ESTATE before the first mpc_step, MPC_EINVAL for a bad arm. */
+int mpc_get_plan(mpc_ctx *c, int arm, float *plan, float *plan_q, float *mean);
+
+/* Release the context (waits for its stream). */
+void mpc_destroy(mpc_ctx *c);
+
+/* Message of the last error on c, or of the last failed mpc_init if c is NULL. */
+const char *mpc_last_error(const mpc_ctx *c);
+
+/* ---- inspection and test hooks (same conventions) ---- */
+
+/* Block until every call issued on the context's stream has finished. */
+int mpc_sync(mpc_ctx *c);
+
+/* Debug capture: when on, every mpc_step also stores the rollout joint
+ * states, world-frame spheres, stage costs and the distance-query counter.
+ * Allocates the capture buffers on first use. */
+int mpc_debug_enable(mpc_ctx *c, int on);
+
+enum {
+  MPC_DBG_NOISE = 0,       /* float [horizon][dof][n_rollouts]: eps of the last iteration */
+  MPC_DBG_Q = 1,           /* float [n_rollouts][horizon][dof]: rollout joint positions */
+  MPC_DBG_QD = 2,          /* float [n_rollouts][horizon][dof]: rollout joint velocities */
+  MPC_DBG_SPHERES = 3,     /* float [n_rollouts][horizon][n_spheres][4]: world-frame spheres */
+  MPC_DBG_STAGE_COST = 4,  /* float [horizon][n_rollouts]: Eq. 5 + Eq. 9 stage costs */
+  MPC_DBG_COST = 5,        /* float [n_rollouts]: discounted totals (Eq. 1) */
+  MPC_DBG_WEIGHTS = 6,     /* float [n_rollouts]: softmax weights (Eq. 2) */
+  MPC_DBG_MEAN = 7,        /* float [horizon][dof]: mu after the update */
+  MPC_DBG_ALPHA = 8,       /* float [n_arms]: priority factors alpha^(arm,i) used at this step (0 = ignored) */
+  MPC_DBG_DIST = 9,        /* float [1]: this arm's distance to goal at Sense */
+  MPC_DBG_PAIRS = 10,      /* unsigned long long [1]: coordination distance queries evaluated */
+  MPC_DBG_ARGMIN = 11      /* int [1]: index of the executed rollout */
+};
+/* Copy one captured quantity of one arm into dev_out (device). */
+int mpc_debug_get(mpc_ctx *c, int what, int arm, void *dev_out);
+
+/* Read-side plan board of one arm (what the other arms see at Sense):
+ * plan [horizon][n_spheres][4], plan_q [horizon][dof] device (either may be
+ * NULL); *dist and *valid are host outputs. */
+int mpc_get_board(mpc_ctx *c, int arm, float *plan, float *plan_q, float *dist, int *valid);
+
+/* Overwrite the read side of one arm's board (fault injection, external or
+ * stale plans).  plan [horizon][n_spheres][4] and plan_q [horizon][dof]
+ * device (NULL leaves that part); valid = 0 hides the arm. */
+int mpc_set_board(mpc_ctx *c, int arm, const float *plan, const float *plan_q, float dist, int valid);
+
+/* Replace the control means of one arm: mean [horizon][dof] device. */
+int mpc_set_mean(mpc_ctx *c, int arm, const float *mean);
+
+/* Step counter t used by the noise stream (advanced by every mpc_step). */
+int mpc_get_step(const mpc_ctx *c, unsigned int *t);
+int mpc_set_step(mpc_ctx *c, unsigned int t);
+
+/* Plant stand-in for Execute (Alg. 1): advance state [n_arms][dof][3]
+ * (device, in place) by one step of the rollout dynamics under u [n_arms][dof]. */
+int mpc_sim_execute(mpc_ctx *c, float *state, const float *u);
+
+/* Rollout-kernel launch shape picked by the tuner (rollouts per block,
+ * horizon steps per work item, workgroups); valid after the first step. */
+int mpc_get_tuning(const mpc_ctx *c, int *rollouts_per_block, int *h_tile, int *grid);
+/* Force a launch shape (0 = let the tuner choose); takes effect at the next
+ * mpc_step. */
+int mpc_set_tuning(mpc_ctx *c, int rollouts_per_block, int h_tile, int grid);
+
+/* Kernel timing for measurement: while on, mpc_step launches its kernels
+ * directly (no graph) and brackets every rollout launch (the fused sampling,
+ * dynamics, kinematics and scoring kernel) with HIP events on the context's
+ * stream. */
+int mpc_profile_enable(mpc_ctx *c, int on);
+/* Total and count of the bracketed rollout-launch durations since the last
+ * read; waits for them and clears the record. */
+int mpc_profile_read(mpc_ctx *c, double *total_ms, int *launches);
+
+/* Device Philox4x32-10 (the noise generator) on n counters: ctr [n][4],
+ * key [n][2], out [n][4], all device uint32.  Runs on hip_stream. */
+int mpc_philox(const unsigned int *ctr, const unsigned int *key, unsigned int *out, int n,
+               void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,722 @@
+// Host runtime of the MR-STORM step library: validation, HBM layout, the
+// plan board, launch-shape tuning and hipGraph capture, and the C-ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mrstorm.h"
+
+using namespace mrs;
+
+static thread_local std::string g_last_error;
+
+struct mpc_ctx {
+  int A = 0, Hmax = 0, Smax = 0, Nmax = 0, layout = 0;
+  hipStream_t stream = nullptr;
+  Params P{};
+  std::vector<DevArm> harms;
+  DevArm* d_arms = nullptr;
+  Params* d_P = nullptr;
+  StepState* d_ss = nullptr;
+  BoardMeta* d_meta = nullptr;
+  float* mu = nullptr;
+  float* eps = nullptr;
+  float* partial = nullptr;
+  float* cost = nullptr;
+  float* w = nullptr;
+  float* st_state = nullptr;
+  float* st_goal = nullptr;
+  float* st_goalR = nullptr;
+  float* st_obs = nullptr;
+  float* plan[2] = {nullptr, nullptr};
+  float* planq[2] = {nullptr, nullptr};
+  float* u_stage = nullptr;
+  int* argmin = nullptr;
+  Item* d_items = nullptr;
+  size_t items_cap = 0;
+  int n_items = 0;
+  int h_tile = 0, grid = 0;
+  int force_tile = 0, force_grid = 0;
+  bool tuned = false;
+  hipGraphExec_t gexec = nullptr;
+  bool debug = false;
+  float* dbg_q = nullptr;
+  float* dbg_qd = nullptr;
+  float* dbg_sph = nullptr;
+  float* dbg_stage = nullptr;
+  unsigned long long* dbg_pairs = nullptr;
+  uint32_t t = 0;
+  bool stepped = false;
+  bool profile = false;
+  std::vector<hipEvent_t> prof_events;  // pairs (start, end) of recorded rollout launches
+  size_t prof_used = 0;
+  std::string err;
+  std::vector<void*> allocations;
+};
+
+static int fail(mpc_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(c, x)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail((c), MPC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+static int dalloc(mpc_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, MPC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemset(q, 0, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, MPC_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+  c->allocations.push_back(q);
+  *p = static_cast<T*>(q);
+  return MPC_OK;
+}
+
+static bool finite_all(const float* p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+static int build_arm(mpc_ctx* c, const mpc_arm_desc& d, int layout, DevArm& o) {
+  memset(&o, 0, sizeof(o));
+  o.dof = d.dof;
+  o.S = d.n_spheres;
+  o.N = d.n_rollouts;
+  o.H = d.horizon;
+  o.Npad = (d.n_rollouts + kWave - 1) / kWave * kWave;
+  o.layout = layout;
+  for (int k = 0; k < 7; ++k) {
+    o.a[k] = d.dh[4 * k + 0];
+    o.cal[k] = (float)std::cos((double)d.dh[4 * k + 1]);
+    o.sal[k] = (float)std::sin((double)d.dh[4 * k + 1]);
+    o.d[k] = d.dh[4 * k + 2];
+    o.off[k] = d.dh[4 * k + 3];
+    o.qlo[k] = d.q_lim[2 * k];
+    o.qhi[k] = d.q_lim[2 * k + 1];
+    o.qdmax[k] = d.qd_max[k];
+  }
+  o.base[0] = d.base[0];
+  o.base[1] = d.base[1];
+  o.base[2] = d.base[2];
+  o.cyaw = (float)std::cos((double)d.base[3]);
+  o.syaw = (float)std::sin((double)d.base[3]);
+  o.tool[0] = d.tool[0];
+  o.tool[1] = d.tool[1];
+  o.tool[2] = d.tool[2];
+  for (int s = 0; s < kMaxSpheres; ++s) {
+    o.slot_src[s] = -1;
+    o.slot[s][0] = o.slot[s][1] = o.slot[s][2] = 0.f;
+    o.slot[s][3] = -1.f;  // parked
+  }
+  int fill[kBodies] = {0};
+  for (int s = 0; s < d.n_spheres; ++s) {
+    const int b = d.sphere_link[s];
+    const int slot = kLayoutStart[layout][b] + fill[b]++;
+    for (int i = 0; i < 4; ++i) {
+      o.slot[slot][i] = d.spheres[4 * s + i];
+      o.usph[s][i] = d.spheres[4 * s + i];
+    }
+    o.slot_src[slot] = s;
+    o.link[s] = b;
+  }
+  (void)c;
+  return MPC_OK;
+}
+
+static int validate_arm(mpc_ctx* c, const mpc_arm_desc& d, int i, int counts[kBodies]) {
+  char buf[160];
+  auto bad = [&](const char* what) {
+    snprintf(buf, sizeof(buf), "arm %d: %s", i, what);
+    return fail(c, MPC_EINVAL, buf);
+  };
+  if (d.dof != 7) {
+    snprintf(buf, sizeof(buf), "arm %d: dof %d not supported (this build runs 7-DoF chains)", i, d.dof);
+    return fail(c, MPC_EUNSUPPORTED, buf);
+  }
+  if (d.n_spheres < 1 || d.n_spheres > MPC_MAX_SPHERES) return bad("n_spheres out of range");
+  if (d.n_rollouts < 1 || d.n_rollouts > MPC_MAX_ROLLOUTS) return bad("n_rollouts out of range");
+  if (d.horizon < 1 || d.horizon > MPC_MAX_HORIZON) return bad("horizon out of range");
+  if (!d.dh || !d.q_lim || !d.qd_max || !d.spheres || !d.sphere_link) return bad("null table");
+  if (!finite_all(d.dh, 28) || !finite_all(d.q_lim, 14) || !finite_all(d.qd_max, 7) ||
+      !finite_all(d.spheres, 4 * d.n_spheres) || !finite_all(d.base, 4) || !finite_all(d.tool, 3))
+    return bad("non-finite value");
+  for (int k = 0; k < kBodies; ++k) counts[k] = 0;
+  for (int s = 0; s < d.n_spheres; ++s) {
+    const int b = d.sphere_link[s];
+    if (b < 0 || b > 7) return bad("sphere_link outside 0..7");
+    if (++counts[b] > MPC_MAX_SPHERES_PER_BODY) return bad("more than 8 spheres on one body");
+    if (!(d.spheres[4 * s + 3] >= 0.f) || d.spheres[4 * s + 3] > 1.f) return bad("sphere radius outside [0, 1]");
+    for (int k = 0; k < 3; ++k)
+      if (std::fabs(d.spheres[4 * s + k]) > 1.5f) return bad("sphere centre more than 1.5 m from its link");
+  }
+  for (int k = 0; k < 7; ++k) {
+    if (std::fabs(d.dh[4 * k]) > 1.5f || std::fabs(d.dh[4 * k + 2]) > 1.5f) return bad("link length above 1.5 m");
+    if (!(d.q_lim[2 * k] <= d.q_lim[2 * k + 1])) return bad("joint limits reversed");
+  }
+  // The squared-gap filter is sized for world coordinates within 6 m of the
+  // origin: the base within 3 m, the chain within 2.6 m of its base.
+  if (std::sqrt(d.base[0] * d.base[0] + d.base[1] * d.base[1] + d.base[2] * d.base[2]) > 3.f)
+    return bad("base more than 3 m from the world origin");
+  return MPC_OK;
+}
+
+extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* p, void* hip_stream,
+                        mpc_ctx** out) {
+  if (!out) return fail(nullptr, MPC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!arms || !p) return fail(nullptr, MPC_EINVAL, "arms or params is NULL");
+  if (n_arms < 1 || n_arms > MPC_MAX_ARMS) return fail(nullptr, MPC_EINVAL, "n_arms outside 1..8");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, MPC_EHIP, "no HIP device available");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, MPC_EHIP, "hipGetDeviceProperties failed");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MPC_EHIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  const float pf[] = {p->dt, p->sigma, p->lambda, p->gamma, p->alpha_mu, p->w_pose, p->w_rot,
+                      p->w_stop, p->w_joint, p->w_coll, p->w_dyn, p->buf_env, p->buf_self,
+                      p->buf_dyn, p->tau, p->prio_min, p->prio_max, p->dist_floor, p->joint_margin};
+  if (!finite_all(pf, (int)(sizeof(pf) / sizeof(float)))) return fail(nullptr, MPC_EINVAL, "non-finite parameter");
+  if (!(p->lambda > 0.f) || !(p->dt > 0.f) || !(p->sigma >= 0.f) || !(p->alpha_mu >= 0.f && p->alpha_mu <= 1.f) ||
+      !(p->buf_env > 0.f && p->buf_self > 0.f && p->buf_dyn > 0.f) || !(p->prio_min <= p->prio_max) ||
+      !(p->dist_floor > 0.f))
+    return fail(nullptr, MPC_EINVAL, "parameter out of range");
+  if (p->iters < 1 || p->iters > 8) return fail(nullptr, MPC_EINVAL, "iters outside 1..8");
+  if (p->max_obstacles < 0 || p->max_obstacles > MPC_MAX_OBSTACLES)
+    return fail(nullptr, MPC_EINVAL, "max_obstacles outside 0..64");
+  if (p->collision_mode != 0) return fail(nullptr, MPC_EUNSUPPORTED, "collision_mode 1 needs a trained distance model");
+
+  mpc_ctx* c = new mpc_ctx();
+  c->A = n_arms;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  bool all52 = true;
+  for (int i = 0; i < n_arms; ++i) {
+    int counts[kBodies];
+    const int rc = validate_arm(c, arms[i], i, counts);
+    if (rc != MPC_OK) {
+      g_last_error = c->err;
+      delete c;
+      return rc;
+    }
+    for (int b = 0; b < kBodies; ++b) all52 = all52 && counts[b] == kLayoutCount[0][b];
+    c->Hmax = std::max(c->Hmax, arms[i].horizon);
+    c->Smax = std::max(c->Smax, arms[i].n_spheres);
+    c->Nmax = std::max(c->Nmax, (arms[i].n_rollouts + kWave - 1) / kWave * kWave);
+  }
+  c->layout = all52 ? 0 : 1;
+  c->harms.resize(n_arms);
+  long long eps_off = 0;
+  for (int i = 0; i < n_arms; ++i) {
+    build_arm(c, arms[i], c->layout, c->harms[i]);
+    c->harms[i].eps_off = eps_off;
+    eps_off += (long long)arms[i].horizon * 7 * c->harms[i].Npad;
+  }
+  Params& P = c->P;
+  P.dt = p->dt; P.sigma = p->sigma; P.lambda = p->lambda; P.gamma = p->gamma; P.alpha_mu = p->alpha_mu;
+  P.w_pose = p->w_pose; P.w_rot = p->w_rot; P.w_stop = p->w_stop; P.w_joint = p->w_joint;
+  P.w_coll = p->w_coll; P.w_dyn = p->w_dyn; P.buf_env = p->buf_env; P.buf_self = p->buf_self;
+  P.buf_dyn = p->buf_dyn; P.tau = p->tau; P.prio_min = p->prio_min; P.prio_max = p->prio_max;
+  P.dist_floor = p->dist_floor; P.joint_margin = p->joint_margin;
+  P.seed_lo = (uint32_t)(p->seed & 0xffffffffull);
+  P.seed_hi = (uint32_t)(p->seed >> 32);
+  P.iters = p->iters; P.A = n_arms; P.dof = 7; P.Hmax = c->Hmax; P.Smax = c->Smax; P.Nmax = c->Nmax;
+  P.max_obs = p->max_obstacles;
+  for (int h = 0; h < kMaxH; ++h) P.gpow[h] = (float)std::pow((double)p->gamma, (double)h);
+
+  int rc = MPC_OK;
+  const size_t A = n_arms, H = c->Hmax, S = c->Smax, N = c->Nmax;
+  if ((rc = dalloc(c, &c->d_arms, A)) || (rc = dalloc(c, &c->d_P, 1)) || (rc = dalloc(c, &c->d_ss, 1)) ||
+      (rc = dalloc(c, &c->d_meta, 1)) || (rc = dalloc(c, &c->mu, A * H * 7)) ||
+      (rc = dalloc(c, &c->eps, (size_t)eps_off)) || (rc = dalloc(c, &c->partial, A * kMaxH * N)) ||
+      (rc = dalloc(c, &c->cost, A * N)) || (rc = dalloc(c, &c->w, A * N)) ||
+      (rc = dalloc(c, &c->st_state, A * 21)) || (rc = dalloc(c, &c->st_goal, A * 7)) ||
+      (rc = dalloc(c, &c->st_goalR, A * 9)) || (rc = dalloc(c, &c->st_obs, (size_t)kMaxObs * 4)) ||
+      (rc = dalloc(c, &c->plan[0], A * H * S * 4)) || (rc = dalloc(c, &c->plan[1], A * H * S * 4)) ||
+      (rc = dalloc(c, &c->planq[0], A * H * 7)) || (rc = dalloc(c, &c->planq[1], A * H * 7)) ||
+      (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A))) {
+    g_last_error = c->err;
+    mpc_destroy(c);
+    return rc;
+  }
+  if (hipMemcpy(c->d_arms, c->harms.data(), A * sizeof(DevArm), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_P, &c->P, sizeof(Params), hipMemcpyHostToDevice) != hipSuccess) {
+    fail(c, MPC_EHIP, "upload of arm tables failed");
+    mpc_destroy(c);
+    return MPC_EHIP;
+  }
+  *out = c;
+  return MPC_OK;
+}
+
+extern "C" void mpc_destroy(mpc_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+  for (void* p : c->allocations) (void)hipFree(p);
+  delete c;
+}
+
+extern "C" const char* mpc_last_error(const mpc_ctx* c) {
+  return c ? c->err.c_str() : g_last_error.c_str();
+}
+
+extern "C" int mpc_sync(mpc_ctx* c) {
+  if (!c) return MPC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Work items of the rollout launch for a horizon tile T: every arm's 64-rollout
+// blocks times its ceil(H/T) tiles, heaviest (longest tile) first.
+static void build_items(const mpc_ctx* c, int T, std::vector<Item>& items) {
+  items.clear();
+  for (int a = 0; a < c->A; ++a) {
+    const DevArm& arm = c->harms[a];
+    const int blocks = arm.Npad / kWave;
+    for (int h0 = 0; h0 < arm.H; h0 += T)
+      for (int b = 0; b < blocks; ++b) items.push_back(Item{a, b, h0, std::min(arm.H, h0 + T)});
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item& x, const Item& y) { return (x.h1 - x.h0) > (y.h1 - y.h0); });
+}
+
+static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
+  RolloutArgs R{};
+  R.arms = c->d_arms;
+  R.P = c->d_P;
+  R.ss = c->d_ss;
+  R.items = c->d_items;
+  R.n_items = c->n_items;
+  R.h_tile = c->h_tile;
+  R.k = k;
+  R.mu = c->mu;
+  R.eps = c->eps;
+  R.partial = c->partial;
+  R.state = c->st_state;
+  R.goal = c->st_goal;
+  R.goalR = c->st_goalR;
+  R.obs = c->st_obs;
+  R.plan_read = c->plan[0];
+  R.dbg_q = c->dbg_q;
+  R.dbg_qd = c->dbg_qd;
+  R.dbg_sph = c->dbg_sph;
+  R.dbg_stage = c->dbg_stage;
+  R.dbg_pairs = c->dbg_pairs;
+  return R;
+}
+
+static ReduceArgs reduce_args(const mpc_ctx* c) {
+  ReduceArgs R{};
+  R.arms = c->d_arms;
+  R.P = c->d_P;
+  R.ss = c->d_ss;
+  R.h_tile = c->h_tile;
+  R.partial = c->partial;
+  R.cost = c->cost;
+  R.w = c->w;
+  R.eps = c->eps;
+  R.mu = c->mu;
+  R.u_out = c->u_stage;
+  R.argmin = c->argmin;
+  R.st_state = c->st_state;
+  R.plan_write = c->plan[1];
+  R.planq_write = c->planq[1];
+  R.meta = c->d_meta;
+  return R;
+}
+
+static int set_items(mpc_ctx* c, int T) {
+  std::vector<Item> items;
+  build_items(c, T, items);
+  if (items.size() > c->items_cap) {
+    Item* p = nullptr;
+    HIPCHK(c, hipMalloc(&p, items.size() * sizeof(Item)));
+    c->allocations.push_back(p);
+    c->d_items = p;
+    c->items_cap = items.size();
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  c->n_items = (int)items.size();
+  c->h_tile = T;
+  return MPC_OK;
+}
+
+// Launch-shape tuner: times the rollout launch for every candidate horizon
+// tile and grid size on the live inputs of the first step, keeps the fastest.
+static int tune(mpc_ctx* c) {
+  std::vector<int> tiles;
+  if (c->force_tile > 0) {
+    tiles.push_back(std::min(c->force_tile, c->Hmax));
+  } else {
+    for (int T : {1, 2, 4, 5, 8, 10, 16, 20, 32, 64})
+      if (T <= c->Hmax) tiles.push_back(T);
+    if (std::find(tiles.begin(), tiles.end(), c->Hmax) == tiles.end()) tiles.push_back(c->Hmax);
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best_T = tiles[0], best_grid = 0;
+  for (int T : tiles) {
+    int rc = set_items(c, T);
+    if (rc) return rc;
+    std::vector<int> grids;
+    if (c->force_grid > 0) {
+      grids.push_back(std::min(c->force_grid, c->n_items));
+    } else {
+      grids.push_back(c->n_items);
+      for (int g : {1024, 2048, 4096})
+        if (g < c->n_items) grids.push_back(g);
+    }
+    for (int g : grids) {
+      RolloutArgs R = rollout_args(c, 0);
+      HIPCHK(c, launch_rollout(R, c->layout, false, g, c->stream));
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < 3; ++r) HIPCHK(c, launch_rollout(R, c->layout, false, g, c->stream));
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_T = T;
+        best_grid = g;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc = set_items(c, best_T);
+  if (rc) return rc;
+  c->grid = best_grid;
+  c->tuned = true;
+  return MPC_OK;
+}
+
+// The per-step device work after Sense: K x {rollout, softmax/act, weighted
+// mean + update}, then ToPlan.
+static int enqueue_body(mpc_ctx* c, bool debug) {
+  ReduceArgs Rr = reduce_args(c);
+  for (int k = 0; k < c->P.iters; ++k) {
+    RolloutArgs R = rollout_args(c, k);
+    hipEvent_t e1 = nullptr;
+    if (c->profile) {
+      while (c->prof_events.size() < c->prof_used + 2) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->prof_events.push_back(e);
+      }
+      HIPCHK(c, hipEventRecord(c->prof_events[c->prof_used], c->stream));
+      e1 = c->prof_events[c->prof_used + 1];
+      c->prof_used += 2;
+    }
+    HIPCHK(c, launch_rollout(R, c->layout, debug, c->grid, c->stream));
+    if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, launch_softmax(Rr, c->A, c->stream));
+    HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->stream));
+  }
+  HIPCHK(c, launch_toplan(Rr, c->A, c->stream));
+  return MPC_OK;
+}
+
+static int capture_graph(mpc_ctx* c) {
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->stream == nullptr) return MPC_OK;  // the null stream cannot be captured
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_body(c, false);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(c, MPC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(c, MPC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return MPC_OK;
+}
+
+extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const float* obstacles,
+                        int n_obstacles, float* u_out) {
+  if (!c) return MPC_EINVAL;
+  if (!state || !goal || !u_out) return fail(c, MPC_EINVAL, "state, goal and u_out must be device pointers");
+  if (n_obstacles < 0 || n_obstacles > c->P.max_obs)
+    return fail(c, MPC_EINVAL, "n_obstacles outside [0, max_obstacles]");
+  if (n_obstacles > 0 && !obstacles) return fail(c, MPC_EINVAL, "obstacles is NULL");
+  SenseArgs S{};
+  S.arms = c->d_arms;
+  S.P = c->d_P;
+  S.ss = c->d_ss;
+  S.meta = c->d_meta;
+  S.state = state;
+  S.goal = goal;
+  S.obstacles = obstacles;
+  S.n_obs = n_obstacles;
+  S.t = c->t;
+  S.st_state = c->st_state;
+  S.st_goal = c->st_goal;
+  S.st_obs = c->st_obs;
+  S.goalR = c->st_goalR;
+  S.mu = c->mu;
+  HIPCHK(c, launch_sense(S, c->stream));
+  int rc;
+  if (!c->tuned) {
+    if ((rc = tune(c))) return rc;
+    if ((rc = capture_graph(c))) return rc;
+  }
+  if (c->debug) {
+    HIPCHK(c, hipMemsetAsync(c->dbg_pairs, 0, sizeof(unsigned long long) * c->A, c->stream));
+    if ((rc = enqueue_body(c, true))) return rc;
+  } else if (c->gexec && !c->profile) {
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    if ((rc = enqueue_body(c, false))) return rc;
+  }
+  HIPCHK(c, hipMemcpyAsync(u_out, c->u_stage, sizeof(float) * 7 * c->A, hipMemcpyDeviceToDevice, c->stream));
+  c->t += 1;
+  c->stepped = true;
+  return MPC_OK;
+}
+
+extern "C" int mpc_share_plans(mpc_ctx* c, const unsigned char* mask) {
+  if (!c) return MPC_EINVAL;
+  PublishArgs P{};
+  P.plan_write = c->plan[1];
+  P.planq_write = c->planq[1];
+  P.plan_read = c->plan[0];
+  P.planq_read = c->planq[0];
+  P.meta = c->d_meta;
+  P.Hmax = c->Hmax;
+  P.Smax = c->Smax;
+  uint32_t m = 0;
+  for (int a = 0; a < c->A; ++a)
+    if (!mask || mask[a]) m |= 1u << a;
+  P.mask = m;
+  HIPCHK(c, launch_publish(P, c->A, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_get_plan(mpc_ctx* c, int arm, float* plan, float* plan_q, float* mean) {
+  if (!c) return MPC_EINVAL;
+  if (arm < 0 || arm >= c->A) return fail(c, MPC_EINVAL, "arm out of range");
+  if (!c->stepped) return fail(c, MPC_ESTATE, "no plan before the first mpc_step");
+  const DevArm& d = c->harms[arm];
+  const long long H = c->Hmax, S = c->Smax;
+  if (plan) {
+    const float* src = c->plan[1] + (size_t)arm * H * S * 4;
+    // src [h][s][c] -> dst [s][c][h]
+    HIPCHK(c, launch_copy3d(src, 4, 1, S * 4, plan, 4LL * d.H, d.H, 1, d.S, 4, d.H, c->stream));
+  }
+  if (plan_q)
+    HIPCHK(c, hipMemcpyAsync(plan_q, c->planq[1] + (size_t)arm * H * 7, sizeof(float) * d.H * 7,
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (mean)
+    HIPCHK(c, hipMemcpyAsync(mean, c->mu + (size_t)arm * H * 7, sizeof(float) * d.H * 7,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return MPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" int mpc_debug_enable(mpc_ctx* c, int on) {
+  if (!c) return MPC_EINVAL;
+  if (on && !c->dbg_q) {
+    const size_t A = c->A, N = c->Nmax, H = c->Hmax, S = c->Smax;
+    int rc;
+    if ((rc = dalloc(c, &c->dbg_q, A * N * H * 7)) || (rc = dalloc(c, &c->dbg_qd, A * N * H * 7)) ||
+        (rc = dalloc(c, &c->dbg_sph, A * N * H * S * 4)) || (rc = dalloc(c, &c->dbg_stage, A * H * N)) ||
+        (rc = dalloc(c, &c->dbg_pairs, A)))
+      return rc;
+  }
+  c->debug = on != 0;
+  return MPC_OK;
+}
+
+extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
+  if (!c) return MPC_EINVAL;
+  if (arm < 0 || arm >= c->A || !dev_out) return fail(c, MPC_EINVAL, "bad arm or output");
+  const DevArm& d = c->harms[arm];
+  const long long N = c->Nmax, H = c->Hmax, S = c->Smax;
+  float* out = static_cast<float*>(dev_out);
+  const bool needs_dbg = what == MPC_DBG_Q || what == MPC_DBG_QD || what == MPC_DBG_SPHERES ||
+                         what == MPC_DBG_STAGE_COST || what == MPC_DBG_PAIRS;
+  if (needs_dbg && !c->dbg_q) return fail(c, MPC_ESTATE, "debug capture is off");
+  switch (what) {
+    case MPC_DBG_NOISE:
+      HIPCHK(c, launch_copy3d(c->eps + d.eps_off, d.Npad, 1, 0, out, d.N, 1, 0, d.H * 7, d.N, 1, c->stream));
+      break;
+    case MPC_DBG_Q:
+    case MPC_DBG_QD: {
+      const float* src = (what == MPC_DBG_Q ? c->dbg_q : c->dbg_qd) + (size_t)arm * N * H * 7;
+      HIPCHK(c, launch_copy3d(src, H * 7, 1, 0, out, d.H * 7LL, 1, 0, d.N, d.H * 7, 1, c->stream));
+      break;
+    }
+    case MPC_DBG_SPHERES: {
+      const float* src = c->dbg_sph + (size_t)arm * N * H * S * 4;
+      HIPCHK(c, launch_copy3d(src, H * S * 4, S * 4, 1, out, (long long)d.H * d.S * 4, d.S * 4LL, 1, d.N, d.H,
+                              d.S * 4, c->stream));
+      break;
+    }
+    case MPC_DBG_STAGE_COST:
+      HIPCHK(c, launch_copy3d(c->dbg_stage + (size_t)arm * H * N, N, 1, 0, out, d.N, 1, 0, d.H, d.N, 1, c->stream));
+      break;
+    case MPC_DBG_COST:
+      HIPCHK(c, hipMemcpyAsync(out, c->cost + (size_t)arm * N, sizeof(float) * d.N, hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_WEIGHTS:
+      HIPCHK(c, hipMemcpyAsync(out, c->w + (size_t)arm * N, sizeof(float) * d.N, hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_MEAN:
+      HIPCHK(c, hipMemcpyAsync(out, c->mu + (size_t)arm * H * 7, sizeof(float) * d.H * 7, hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_ALPHA:
+      HIPCHK(c, hipMemcpyAsync(out, &c->d_ss->alpha[arm][0], sizeof(float) * c->A, hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_DIST:
+      HIPCHK(c, hipMemcpyAsync(out, &c->d_ss->dist_now[arm], sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_PAIRS:
+      HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + arm, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_ARGMIN:
+      HIPCHK(c, hipMemcpyAsync(out, c->argmin + arm, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    default:
+      return fail(c, MPC_EINVAL, "unknown debug quantity");
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_get_board(mpc_ctx* c, int arm, float* plan, float* plan_q, float* dist, int* valid) {
+  if (!c) return MPC_EINVAL;
+  if (arm < 0 || arm >= c->A) return fail(c, MPC_EINVAL, "arm out of range");
+  const DevArm& d = c->harms[arm];
+  const long long H = c->Hmax, S = c->Smax;
+  if (plan)
+    HIPCHK(c, launch_copy3d(c->plan[0] + (size_t)arm * H * S * 4, S * 4, 1, 0, plan, d.S * 4LL, 1, 0, d.H, d.S * 4, 1,
+                            c->stream));
+  if (plan_q)
+    HIPCHK(c, hipMemcpyAsync(plan_q, c->planq[0] + (size_t)arm * H * 7, sizeof(float) * d.H * 7,
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (dist || valid) {
+    BoardMeta m;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&m, c->d_meta, sizeof(m), hipMemcpyDeviceToHost));
+    if (dist) *dist = m.dist[0][arm];
+    if (valid) *valid = m.valid[0][arm];
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_set_board(mpc_ctx* c, int arm, const float* plan, const float* plan_q, float dist, int valid) {
+  if (!c) return MPC_EINVAL;
+  if (arm < 0 || arm >= c->A) return fail(c, MPC_EINVAL, "arm out of range");
+  if (!std::isfinite(dist)) return fail(c, MPC_EINVAL, "non-finite distance");
+  const DevArm& d = c->harms[arm];
+  const long long H = c->Hmax, S = c->Smax;
+  if (plan)
+    HIPCHK(c, launch_copy3d(plan, d.S * 4LL, 1, 0, c->plan[0] + (size_t)arm * H * S * 4, S * 4, 1, 0, d.H, d.S * 4, 1,
+                            c->stream));
+  if (plan_q)
+    HIPCHK(c, hipMemcpyAsync(c->planq[0] + (size_t)arm * H * 7, plan_q, sizeof(float) * d.H * 7,
+                             hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, launch_set_meta(c->d_meta, arm, dist, valid ? 1 : 0, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_set_mean(mpc_ctx* c, int arm, const float* mean) {
+  if (!c) return MPC_EINVAL;
+  if (arm < 0 || arm >= c->A || !mean) return fail(c, MPC_EINVAL, "bad arm or mean");
+  HIPCHK(c, hipMemcpyAsync(c->mu + (size_t)arm * c->Hmax * 7, mean, sizeof(float) * c->harms[arm].H * 7,
+                           hipMemcpyDeviceToDevice, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_get_step(const mpc_ctx* c, unsigned int* t) {
+  if (!c || !t) return MPC_EINVAL;
+  *t = c->t;
+  return MPC_OK;
+}
+
+extern "C" int mpc_set_step(mpc_ctx* c, unsigned int t) {
+  if (!c) return MPC_EINVAL;
+  c->t = t;
+  return MPC_OK;
+}
+
+extern "C" int mpc_sim_execute(mpc_ctx* c, float* state, const float* u) {
+  if (!c) return MPC_EINVAL;
+  if (!state || !u) return fail(c, MPC_EINVAL, "null state or command");
+  HIPCHK(c, launch_sim_execute(state, u, c->A * 7, c->P.dt, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_get_tuning(const mpc_ctx* c, int* rollouts_per_block, int* h_tile, int* grid) {
+  if (!c) return MPC_EINVAL;
+  if (rollouts_per_block) *rollouts_per_block = kWave;
+  if (h_tile) *h_tile = c->h_tile;
+  if (grid) *grid = c->grid;
+  return c->tuned ? MPC_OK : MPC_ESTATE;
+}
+
+extern "C" int mpc_set_tuning(mpc_ctx* c, int rollouts_per_block, int h_tile, int grid) {
+  if (!c) return MPC_EINVAL;
+  if (rollouts_per_block != 0 && rollouts_per_block != kWave)
+    return fail(c, MPC_EUNSUPPORTED, "this build runs 64 rollouts per block");
+  if (h_tile < 0 || grid < 0) return fail(c, MPC_EINVAL, "negative tuning value");
+  c->force_tile = h_tile;
+  c->force_grid = grid;
+  c->tuned = false;
+  return MPC_OK;
+}
+
+extern "C" int mpc_profile_enable(mpc_ctx* c, int on) {
+  if (!c) return MPC_EINVAL;
+  c->profile = on != 0;
+  return MPC_OK;
+}
+
+extern "C" int mpc_profile_read(mpc_ctx* c, double* total_ms, int* launches) {
+  if (!c || !total_ms || !launches) return MPC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_events[i], c->prof_events[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int)(c->prof_used / 2);
+  c->prof_used = 0;
+  return MPC_OK;
+}
+
+extern "C" int mpc_philox(const unsigned int* ctr, const unsigned int* key, unsigned int* out, int n,
+                          void* hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(nullptr, MPC_EINVAL, "bad philox arguments");
+  hipError_t e = launch_philox(ctr, key, out, n, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(nullptr, MPC_EHIP, hipGetErrorString(e));
+  return MPC_OK;
+}

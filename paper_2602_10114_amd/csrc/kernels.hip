@@ -1,0 +1,755 @@
+// gfx950 kernels of one MR-STORM control step (arXiv 2602.10114, Alg. 1):
+//   k_sense      Sense + Shift: stage inputs, own distance to goal, priority
+//                factors (Eq. 10), neighbour table, left shift of the means.
+//   k_rollout    SampleControls + Rollout for every arm in one launch: noise,
+//                dynamics, forward kinematics over the collision spheres, the
+//                stage cost of Eq. 5 with the coordination term of Eqs. 6-9,
+//                discounted partial sums (Eq. 1).
+//   k_softmax    Eq. 1 totals, Eq. 2 weights, PickBest (Act).
+//   k_wmean      Eq. 3 weighted mean and Eq. 4 update of the means.
+//   k_toplan     ToPlan: integrate the means, forward kinematics, plan spheres.
+//   k_publish    Publish: board write side -> read side.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace mrs {
+
+// Sphere sets scored against the own spheres at one rollout step are staged in
+// LDS: obstacles (one set) and each published neighbour plan that reaches the
+// step (one set each).  The set's hinge buffer B is folded into the staged
+// radius, so the squared-gap expansion
+//   |c_s - p_k|^2 - (r_s + r_k + B)^2 = E_s + F_k + c_s.w_xyz + r_s w_r,
+//   E_s = |c_s|^2 - r_s^2,  w = -2 (p_k, r_k + B),  F_k = |p_k|^2 - (r_k + B)^2,
+// is negative exactly when the pair's gap rho is below B, and the own-sphere
+// terms do not depend on the set.  raw keeps (p_k, r_k) for the FP64 gap.
+constexpr int kLdsSpheres = kMaxObs + (kMaxArms - 1) * kMaxSpheres;
+constexpr int kMaxSets = kMaxArms;  // obstacles + up to 7 neighbours
+
+struct LdsSets {
+  float4 w[kLdsSpheres];
+  float4 raw[kLdsSpheres];
+  float F[kLdsSpheres];
+  float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
+  int set_k0[kMaxSets], set_n[kMaxSets];
+  float set_buf[kMaxSets], set_wt[kMaxSets];
+};
+
+__device__ __forceinline__ void stage_sphere(LdsSets& L, int dst, float4 s, float buf) {
+  L.raw[dst] = s;
+  const float rb = s.w + buf;
+  L.w[dst] = make_float4(-2.f * s.x, -2.f * s.y, -2.f * s.z, -2.f * rb);
+  L.F[dst] = fmaf_(s.x, s.x, fmaf_(s.y, s.y, fmaf_(s.z, s.z, -rb * rb)));
+}
+
+// Filter value given to unused slots of a padded layout: never below the slack.
+constexpr float kParked = 1.0e30f;
+
+// Slack of the squared-gap filter, m^2.  FP32 rounding of the expansion is
+// below 1e-5 m^2 for coordinates within 6 m of the origin (checked at init);
+// a pair with true gap < B therefore always has a filter value < slack.
+constexpr float kSlack = 1.0e-4f;
+
+// Cached joint sines and cosines of one rollout step, and the arm constants
+// the chain walk needs.
+struct Chain {
+  float c[7], s[7];
+};
+
+__device__ __forceinline__ void chain_angles(Chain& C, const DevArm* __restrict__ arm, const float q[8]) {
+#pragma unroll
+  for (int k = 0; k < 7; ++k) sincosf(q[k] + arm->off[k], &C.s[k], &C.c[k]);
+}
+
+// Advance a walking frame across joint k (frame of link k+1 = body k).
+__device__ __forceinline__ void walk(Frame& W, const DevArm* __restrict__ arm, const Chain& C, int k) {
+  frame_joint(W, arm->a[k], arm->cal[k], arm->sal[k], arm->d[k], C.c[k], C.s[k]);
+}
+
+// Own spheres of one body: u = (c, r + buf), E = |c|^2 - (r + buf)^2.  The
+// compiler barrier keeps sphere centres from being hoisted or shared across
+// passes (that would hold every centre of the arm live at once).
+template <int LAY, int B_>
+__device__ __forceinline__ void body_spheres(const Frame& Fb, const LdsSets& L, float buf, float ux[8],
+                                             float uy[8], float uz[8], float ur[8], float E[8]) {
+  constexpr int C = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const float4 p = L.slot[S0 + j];
+    float x, y, z;
+    frame_point(Fb, p.x, p.y, p.z, x, y, z);
+    const float rb = p.w + buf;
+    const bool parked = p.w < 0.f;  // unused slot of a padded layout
+    ux[j] = parked ? 0.f : x;
+    uy[j] = parked ? 0.f : y;
+    uz[j] = parked ? 0.f : z;
+    ur[j] = parked ? 0.f : rb;
+    E[j] = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
+  }
+}
+
+// min over the body's spheres and the staged spheres [k0, k0+K) of the
+// squared-gap expansion.
+template <int C>
+__device__ __forceinline__ float filter_range(const float ux[8], const float uy[8], const float uz[8],
+                                              const float ur[8], const float E[8], const LdsSets& L,
+                                              int k0, int K, float g) {
+  for (int k = k0; k < k0 + K; ++k) {
+    const float4 w = L.w[k];
+    const float Fk = L.F[k];
+    float m = 3.0e38f;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      float t = fmaf_(ux[j], w.x, E[j]);
+      t = fmaf_(uy[j], w.y, t);
+      t = fmaf_(uz[j], w.z, t);
+      t = fmaf_(ur[j], w.w, t);
+      m = fminf(m, t);
+    }
+    g = fminf(g, m + Fk);
+  }
+  return g;
+}
+
+// Filter pass over one staged set: body by body down the chain (one walking
+// frame), running minimum of the squared-gap expansion.
+template <int LAY, int B_>
+__device__ __forceinline__ void set_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
+                                           const LdsSets& L, int k0, int K, float& gmin) {
+  constexpr int Cb = kLayoutCount[LAY][B_];
+  if constexpr (B_ < 7) walk(W, arm, C, B_);
+  float ux[8], uy[8], uz[8], ur[8], E[8];
+  body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
+  gmin = filter_range<Cb>(ux, uy, uz, ur, E, L, k0, K, gmin);
+  if constexpr (B_ + 1 < kBodies) set_filter<LAY, B_ + 1>(W, arm, C, L, k0, K, gmin);
+}
+
+// Exact pass for one set: the FP64 gap of every pair the filter can flag; the
+// minimum over them is the set distance whenever that distance is below B.
+template <int LAY, int B_>
+__device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
+                                           const LdsSets& L, int k0, int K, double& best) {
+  constexpr int Cb = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
+  if constexpr (B_ < 7) walk(W, arm, C, B_);
+  float ux[8], uy[8], uz[8], ur[8], E[8];
+  body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
+  for (int k = k0; k < k0 + K; ++k) {
+    const float4 w = L.w[k];
+    const float Fk = L.F[k];
+#pragma unroll
+    for (int j = 0; j < Cb; ++j) {
+      float t = fmaf_(ux[j], w.x, E[j]);
+      t = fmaf_(uy[j], w.y, t);
+      t = fmaf_(uz[j], w.z, t);
+      t = fmaf_(ur[j], w.w, t);
+      if (t + Fk < kSlack) {
+        const float4 r = L.raw[k];
+        const double g = sphere_gap64(ux[j], uy[j], uz[j], L.slot[S0 + j].w, r.x, r.y, r.z, r.w);
+        best = g < best ? g : best;
+      }
+    }
+  }
+  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, best);
+}
+
+// Self collision: sphere pairs on bodies at least two apart in the chain.  A
+// second walking frame runs from body B1 down the chain to every B2 > B1.
+template <int LAY, int B1, int B2>
+__device__ __forceinline__ void self_inner(Frame& W2, const DevArm* __restrict__ arm, const Chain& C,
+                                           const LdsSets& L, float buf, const float ux[8],
+                                           const float uy[8], const float uz[8], const float ur[8],
+                                           const float E[8], bool refine, float& gmin, double& best) {
+  constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
+  constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
+  if constexpr (B2 < 7) walk(W2, arm, C, B2);
+  if constexpr (B2 >= B1 + 2) {
+    for (int i = 0; i < C2; ++i) {
+      asm volatile("" ::: "memory");
+      const float4 p = L.slot[S2 + i];
+      float x, y, z;
+      frame_point(W2, p.x, p.y, p.z, x, y, z);
+      const float r = p.w;
+      const float rb = r + buf;
+      const bool parked = r < 0.f;
+      const float wx = parked ? 0.f : -2.f * x, wy = parked ? 0.f : -2.f * y;
+      const float wz = parked ? 0.f : -2.f * z, wr = parked ? 0.f : -2.f * rb;
+      const float Fk = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
+      if (!refine) {
+        float m = 3.0e38f;
+#pragma unroll
+        for (int j = 0; j < C1; ++j) {
+          float t = fmaf_(ux[j], wx, E[j]);
+          t = fmaf_(uy[j], wy, t);
+          t = fmaf_(uz[j], wz, t);
+          t = fmaf_(ur[j], wr, t);
+          m = fminf(m, t);
+        }
+        gmin = fminf(gmin, m + Fk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < C1; ++j) {
+          float t = fmaf_(ux[j], wx, E[j]);
+          t = fmaf_(uy[j], wy, t);
+          t = fmaf_(uz[j], wz, t);
+          t = fmaf_(ur[j], wr, t);
+          if (t + Fk < kSlack) {
+            const double g = sphere_gap64(ux[j], uy[j], uz[j], L.slot[S1 + j].w, x, y, z, r);
+            best = g < best ? g : best;
+          }
+        }
+      }
+    }
+  }
+  if constexpr (B2 + 1 < kBodies)
+    self_inner<LAY, B1, B2 + 1>(W2, arm, C, L, buf, ux, uy, uz, ur, E, refine, gmin, best);
+}
+
+template <int LAY, int B1>
+__device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__ arm, const Chain& C,
+                                           const LdsSets& L, float buf, bool refine, float& gmin,
+                                           double& best) {
+  if constexpr (B1 + 2 < kBodies) {
+    walk(W1, arm, C, B1);
+    float ux[8], uy[8], uz[8], ur[8], E[8];
+    body_spheres<LAY, B1>(W1, L, 0.f, ux, uy, uz, ur, E);
+    Frame W2 = W1;
+    self_inner<LAY, B1, B1 + 1>(W2, arm, C, L, buf, ux, uy, uz, ur, E, refine, gmin, best);
+    self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, gmin, best);
+  }
+}
+
+template <int LAY>
+__device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, const Chain& C,
+                                            const LdsSets& L, float buf) {
+  float gmin = 3.0e38f;
+  double best = 1.0e300;
+  Frame W;
+  frame_base(W, arm);
+  self_outer<LAY, 0>(W, arm, C, L, buf, false, gmin, best);
+  const bool near = gmin < kSlack;
+  if (!wave_any(near)) return 0.f;
+  frame_base(W, arm);
+  self_outer<LAY, 0>(W, arm, C, L, buf, true, gmin, best);
+  return near ? (float)hinge64(best, (double)buf) : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+template <int LAY, bool DBG>
+__global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ arms,
+                                                   const Params* __restrict__ Pp,
+                                                   const StepState* __restrict__ ssp,
+                                                   const Item* __restrict__ items,
+                                                   const float* __restrict__ mu_all,
+                                                   const float* __restrict__ state,
+                                                   const float* __restrict__ goal,
+                                                   const float* __restrict__ goalR,
+                                                   const float* __restrict__ obs,
+                                                   const float* __restrict__ plan_read,
+                                                   RolloutArgs A) {
+  __shared__ LdsSets L;
+  const int lane = threadIdx.x;
+  const Params& P = *Pp;
+  const StepState& SS = *ssp;
+  const uint32_t t = SS.t;
+  const int n_obs = SS.n_obs;
+  // Obstacles are the same for every item of this launch.
+  for (int o = lane; o < n_obs; o += kWave)
+    stage_sphere(L, o, reinterpret_cast<const float4*>(obs)[o], P.buf_env);
+
+  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) {
+    const Item item = items[it];
+    const int a = item.arm;
+    const DevArm* __restrict__ arm = arms + a;
+    const int N = arm->N, H = arm->H;
+    const int n = item.block * kWave + lane;
+    const bool live = n < N;
+    const float* __restrict__ mu = mu_all + (size_t)a * P.Hmax * 7;
+    float* __restrict__ eps = A.eps + arm->eps_off;
+    const int Npad = arm->Npad;
+    __syncthreads();
+    L.slot[lane] = reinterpret_cast<const float4*>(arm->slot)[lane];
+    float q[8], qd[8];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      q[j] = state[(a * 7 + j) * 3 + 0];
+      qd[j] = state[(a * 7 + j) * 3 + 1];
+    }
+    q[7] = qd[7] = 0.f;
+    // Integration prefix of this horizon tile (noise regenerated, not stored).
+    for (int h = 0; h < item.h0; ++h) {
+      float z[8];
+      normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float u = P.sigma * z[j] + mu[h * 7 + j];
+        qd[j] = fmaf_(P.dt, u, qd[j]);
+        q[j] = fmaf_(P.dt, qd[j], q[j]);
+      }
+    }
+    const float* __restrict__ gR = goalR + a * 9;
+    const float* __restrict__ g = goal + a * 7;
+    const int nnb = SS.nb_count[a];
+    float acc = 0.f;
+    unsigned long long pairs = 0;
+    for (int h = item.h0; h < item.h1; ++h) {
+      float z[8];
+      normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float e = P.sigma * z[j];
+        const float u = e + mu[h * 7 + j];
+        if (live) eps[((size_t)h * 7 + j) * Npad + n] = e;
+        qd[j] = fmaf_(P.dt, u, qd[j]);
+        q[j] = fmaf_(P.dt, qd[j], q[j]);
+      }
+      Chain C;
+      chain_angles(C, arm, q);
+
+      // Stage the sets scored at step h: obstacles (set 0) and every
+      // published neighbour plan that reaches this step (Sec. IV-C: the
+      // shorter of the two horizons applies).
+      __syncthreads();
+      int nsets = 0;
+      if (n_obs > 0) {
+        if (lane == 0) {
+          L.set_k0[0] = 0;
+          L.set_n[0] = n_obs;
+          L.set_buf[0] = P.buf_env;
+          L.set_wt[0] = P.w_coll;
+        }
+        nsets = 1;
+      }
+      {
+        int off = kMaxObs;
+        for (int i = 0; i < nnb; ++i) {
+          const Nb nb = SS.nb[a][i];
+          if (h >= nb.H) continue;
+          const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
+          for (int s = lane; s < nb.S; s += kWave) stage_sphere(L, off + s, src[s], P.buf_dyn);
+          if (lane == 0) {
+            L.set_k0[nsets] = off;
+            L.set_n[nsets] = nb.S;
+            L.set_buf[nsets] = P.buf_dyn;
+            L.set_wt[nsets] = P.w_dyn * nb.alpha;
+          }
+          if (DBG) pairs += (unsigned long long)arm->S * (unsigned long long)nb.S;
+          ++nsets;
+          off += nb.S;
+        }
+      }
+      __syncthreads();
+
+      // Goal pose (Eq. 5, C_pose) at the end-effector point of the last link.
+      float c;
+      {
+        Frame W;
+        frame_base(W, arm);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) walk(W, arm, C, k);
+        float ex, ey, ez;
+        frame_point(W, arm->tool[0], arm->tool[1], arm->tool[2], ex, ey, ez);
+        const float dx = ex - g[0], dy = ey - g[1], dz = ez - g[2];
+        const float pos = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
+        float tr = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          tr = fmaf_(gR[i * 3 + 0], W.x[i], tr);
+          tr = fmaf_(gR[i * 3 + 1], W.y[i], tr);
+          tr = fmaf_(gR[i * 3 + 2], W.z[i], tr);
+        }
+        const float pose = fmaf_(P.w_rot, (3.f - tr) * 0.25f, pos);
+        // Safe stopping and joint limits.
+        float stop = 0.f, joint = 0.f;
+        const float frac = (float)(H - 1 - h) / (float)H;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          stop += fmaxf(0.f, fabsf(qd[j]) - arm->qdmax[j] * frac);
+          joint += fmaxf(0.f, arm->qlo[j] + P.joint_margin - q[j]);
+          joint += fmaxf(0.f, q[j] - arm->qhi[j] + P.joint_margin);
+        }
+        c = P.w_pose * pose;
+        c = fmaf_(P.w_stop, stop, c);
+        c = fmaf_(P.w_joint, joint, c);
+      }
+      // Self collision.
+      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self), c);
+      // Obstacles and neighbours' plans (Eqs. 6, 8, 9): a filter pass per set,
+      // then the exact pass if some lane of the wave may be within B.
+#pragma nounroll
+      for (int si = 0; si < nsets; ++si) {
+        const int k0 = L.set_k0[si], K = L.set_n[si];
+        float gmin = 3.0e38f;
+        {
+          Frame W;
+          frame_base(W, arm);
+          set_filter<LAY, 0>(W, arm, C, L, k0, K, gmin);
+        }
+        const bool near = gmin < kSlack;
+        if (wave_any(near)) {
+          double best = 1.0e300;
+          Frame W;
+          frame_base(W, arm);
+          set_refine<LAY, 0>(W, arm, C, L, k0, K, best);
+          const float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
+          c = fmaf_(L.set_wt[si], hv, c);
+        }
+      }
+      acc = fmaf_(P.gpow[h], c, acc);
+
+      if (DBG && live) {
+        const size_t row = ((size_t)a * P.Nmax + n) * P.Hmax + h;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          A.dbg_q[row * 7 + j] = q[j];
+          A.dbg_qd[row * 7 + j] = qd[j];
+        }
+        float4* sp = reinterpret_cast<float4*>(A.dbg_sph) + row * P.Smax;
+        Frame W;
+        frame_base(W, arm);
+#pragma unroll
+        for (int b = 0; b < kBodies; ++b) {
+          if (b < 7) walk(W, arm, C, b);
+          for (int j = kLayoutStart[LAY][b]; j < kLayoutStart[LAY][b + 1]; ++j) {
+            const int u = arm->slot_src[j];
+            if (u < 0) continue;
+            const float4 p = L.slot[j];
+            float x, y, zz;
+            frame_point(W, p.x, p.y, p.z, x, y, zz);
+            sp[u] = make_float4(x, y, zz, p.w);
+          }
+        }
+        A.dbg_stage[((size_t)a * P.Hmax + h) * P.Nmax + n] = c;
+      }
+    }
+    if (live) A.partial[((size_t)a * kMaxH + item.h0 / A.h_tile) * P.Nmax + n] = acc;
+    if (DBG && live) atomicAdd(A.dbg_pairs + a, pairs);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sense + Shift for every arm (runs on the caller's input pointers, so it is
+// launched outside the captured graph).
+__global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
+  __shared__ float s_mu[kMaxArms * kMaxH * kMaxDof];
+  const int tid = threadIdx.x;
+  const Params& P = *A.P;
+  StepState& SS = *A.ss;
+  const int nA = P.A;
+  for (int i = tid; i < nA * 21; i += blockDim.x) A.st_state[i] = A.state[i];
+  for (int i = tid; i < nA * 7; i += blockDim.x) A.st_goal[i] = A.goal[i];
+  for (int i = tid; i < A.n_obs * 4; i += blockDim.x) A.st_obs[i] = A.obstacles[i];
+  for (int i = tid; i < nA * P.Hmax * 7; i += blockDim.x) s_mu[i] = A.mu[i];
+  __syncthreads();
+  // Shift: mu_h <- mu_{h+1}, the last step keeps its value.
+  for (int i = tid; i < nA * P.Hmax * 7; i += blockDim.x) {
+    const int a = i / (P.Hmax * 7), r = i % (P.Hmax * 7), h = r / 7;
+    const int H = A.arms[a].H;
+    if (h + 1 < H) A.mu[i] = s_mu[i + 7];
+  }
+  if (tid < nA) {
+    const int a = tid;
+    const DevArm* arm = A.arms + a;
+    float q[8];
+    for (int j = 0; j < 7; ++j) q[j] = A.state[(a * 7 + j) * 3];
+    q[7] = 0.f;
+    Frame F[7];
+    forward_kinematics(F, arm, q);
+    float ex, ey, ez;
+    frame_point(F[6], arm->tool[0], arm->tool[1], arm->tool[2], ex, ey, ez);
+    const float* g = A.goal + a * 7;
+    const float dx = ex - g[0], dy = ey - g[1], dz = ez - g[2];
+    SS.dist_now[a] = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
+    // Goal rotation from the (normalised) quaternion w, x, y, z.
+    float w = g[3], x = g[4], y = g[5], z = g[6];
+    const float inv = 1.0f / sqrtf(fmaf_(w, w, fmaf_(x, x, fmaf_(y, y, z * z))));
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    float* R = A.goalR + a * 9;
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+  }
+  if (tid == 0) {
+    SS.t = A.t;
+    SS.n_obs = A.n_obs;
+  }
+  __syncthreads();
+  // Priority factors against every published neighbour (Eq. 10) and the
+  // per-arm neighbour table.
+  if (tid < nA) {
+    const int a = tid;
+    const float da = fmaxf(SS.dist_now[a], P.dist_floor);
+    int cnt = 0;
+    for (int i = 0; i < nA; ++i) {
+      float al = 0.f;
+      if (i != a && A.meta->valid[0][i]) {
+        const float di = fmaxf(A.meta->dist[0][i], P.dist_floor);
+        al = fminf(fmaxf(powf(da / di, P.tau), P.prio_min), P.prio_max);
+        Nb nb;
+        nb.arm = i;
+        nb.S = A.arms[i].S;
+        nb.H = A.arms[i].H;
+        nb.pad = 0;
+        nb.alpha = al;
+        nb.pad1 = nb.pad2 = nb.pad3 = 0.f;
+        SS.nb[a][cnt++] = nb;
+      }
+      SS.alpha[a][i] = al;
+    }
+    SS.nb_count[a] = cnt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 1 totals, Eq. 2 weights and PickBest for one arm per block.
+__global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
+  __shared__ float s_v[1024];
+  __shared__ int s_i[1024];
+  const int a = blockIdx.x, tid = threadIdx.x;
+  const Params& P = *A.P;
+  const DevArm* arm = A.arms + a;
+  const int N = arm->N, H = arm->H;
+  const int tiles = (H + A.h_tile - 1) / A.h_tile;
+  const float* part = A.partial + (size_t)a * kMaxH * P.Nmax;
+  float* cost = A.cost + (size_t)a * P.Nmax;
+  float best = 3.4e38f;
+  int bi = 0x7fffffff;
+  for (int n = tid; n < N; n += blockDim.x) {
+    float c = 0.f;
+    for (int k = 0; k < tiles; ++k) c += part[(size_t)k * P.Nmax + n];
+    cost[n] = c;
+    if (c < best) { best = c; bi = n; }
+  }
+  s_v[tid] = best;
+  s_i[tid] = bi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const float v2 = s_v[tid + s];
+      const int i2 = s_i[tid + s];
+      if (v2 < s_v[tid] || (v2 == s_v[tid] && i2 < s_i[tid])) { s_v[tid] = v2; s_i[tid] = i2; }
+    }
+    __syncthreads();
+  }
+  const float m = s_v[0];
+  // All-NaN costs leave no minimum; fall back to rollout 0 so every index stays in range.
+  const int nstar = s_i[0] < N ? s_i[0] : 0;
+  __syncthreads();
+  const float inv_lambda = 1.0f / P.lambda;
+  float z = 0.f;
+  for (int n = tid; n < N; n += blockDim.x) z += expf(-(cost[n] - m) * inv_lambda);
+  s_v[tid] = z;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) s_v[tid] += s_v[tid + s];
+    __syncthreads();
+  }
+  const float zinv = 1.0f / s_v[0];
+  float* w = A.w + (size_t)a * P.Nmax;
+  for (int n = tid; n < N; n += blockDim.x) w[n] = expf(-(cost[n] - m) * inv_lambda) * zinv;
+  if (tid < 7) {
+    const float* eps = A.eps + arm->eps_off;
+    A.u_out[a * 7 + tid] = A.mu[(size_t)a * P.Hmax * 7 + tid] + eps[(size_t)tid * arm->Npad + nstar];
+  }
+  if (tid == 0) A.argmin[a] = nstar;
+}
+
+// Eq. 3 (weighted mean) and Eq. 4 (mean update), one block per (arm, step).
+__global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
+  __shared__ float s_r[7][256];
+  const int a = blockIdx.y, h = blockIdx.x, tid = threadIdx.x;
+  const Params& P = *A.P;
+  const DevArm* arm = A.arms + a;
+  if (h >= arm->H) return;
+  const int N = arm->N, Npad = arm->Npad;
+  const float* w = A.w + (size_t)a * P.Nmax;
+  const float* eps = A.eps + arm->eps_off + (size_t)h * 7 * Npad;
+  float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int n = tid; n < N; n += blockDim.x) {
+    const float wn = w[n];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) s[j] = fmaf_(wn, eps[(size_t)j * Npad + n], s[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 7; ++j) s_r[j][tid] = s[j];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) s_r[j][tid] += s_r[j][tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid < 7) {
+    float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + tid;
+    const float m0 = *mu;
+    const float mt = m0 + s_r[tid][0];
+    *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
+  }
+}
+
+// ToPlan: integrate the updated means from the current state, forward
+// kinematics per step, plan spheres into the board's write side.
+__global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
+  __shared__ float s_q[kMaxH][8];
+  const int a = blockIdx.x, tid = threadIdx.x;
+  const Params& P = *A.P;
+  const DevArm* arm = A.arms + a;
+  const int H = arm->H;
+  if (tid == 0) {
+    float q[7], qd[7];
+    for (int j = 0; j < 7; ++j) {
+      q[j] = A.st_state[(a * 7 + j) * 3 + 0];
+      qd[j] = A.st_state[(a * 7 + j) * 3 + 1];
+    }
+    const float* mu = A.mu + (size_t)a * P.Hmax * 7;
+    for (int h = 0; h < H; ++h)
+      for (int j = 0; j < 7; ++j) {
+        qd[j] = fmaf_(P.dt, mu[h * 7 + j], qd[j]);
+        q[j] = fmaf_(P.dt, qd[j], q[j]);
+        s_q[h][j] = q[j];
+      }
+  }
+  __syncthreads();
+  for (int h = tid; h < H; h += blockDim.x) {
+    float q[8];
+    for (int j = 0; j < 7; ++j) q[j] = s_q[h][j];
+    q[7] = 0.f;
+    Frame F[7];
+    forward_kinematics(F, arm, q);
+    float4* out = reinterpret_cast<float4*>(A.plan_write) + ((size_t)a * P.Hmax + h) * P.Smax;
+    for (int s = 0; s < arm->S; ++s) {
+      const int b = arm->link[s];
+      const Frame& Fb = F[b < 7 ? b : 6];
+      const float* p = arm->usph[s];
+      float x, y, z;
+      frame_point(Fb, p[0], p[1], p[2], x, y, z);
+      out[s] = make_float4(x, y, z, p[3]);
+    }
+    for (int j = 0; j < 7; ++j) A.planq_write[((size_t)a * P.Hmax + h) * 7 + j] = q[j];
+  }
+  if (tid == 0) {
+    A.meta->dist[1][a] = A.ss->dist_now[a];
+    A.meta->valid[1][a] = 1;
+  }
+}
+
+// Publish: copy the masked arms' written plans to the read side.
+__global__ __launch_bounds__(256) void k_publish(PublishArgs A) {
+  const int a = blockIdx.x;
+  if (!((A.mask >> a) & 1u)) return;
+  if (!A.meta->valid[1][a]) return;
+  const size_t n = (size_t)A.Hmax * A.Smax * 4, nq = (size_t)A.Hmax * 7;
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) A.plan_read[a * n + i] = A.plan_write[a * n + i];
+  for (size_t i = threadIdx.x; i < nq; i += blockDim.x) A.planq_read[a * nq + i] = A.planq_write[a * nq + i];
+  if (threadIdx.x == 0) {
+    A.meta->dist[0][a] = A.meta->dist[1][a];
+    A.meta->valid[0][a] = 1;
+  }
+}
+
+__global__ void k_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
+  philox4x32_10(c0, c1, c2, c3, key[2 * i], key[2 * i + 1]);
+  out[4 * i] = c0;
+  out[4 * i + 1] = c1;
+  out[4 * i + 2] = c2;
+  out[4 * i + 3] = c3;
+}
+
+// Plant stand-in: one step of the rollout dynamics under u.
+__global__ void k_sim_execute(float* state, const float* u, int n, float dt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float acc = u[i];
+  const float v = fmaf_(dt, acc, state[3 * i + 1]);
+  state[3 * i + 0] = fmaf_(dt, v, state[3 * i + 0]);
+  state[3 * i + 1] = v;
+  state[3 * i + 2] = acc;
+}
+
+// Strided 3-D copy of floats (debug capture, board access, plan transpose):
+// dst[i0*d0 + i1*d1 + i2*d2] = src[i0*s0 + i1*s1 + i2*s2].
+__global__ void k_copy3d(const float* src, long long s0, long long s1, long long s2, float* dst,
+                         long long d0, long long d1, long long d2, int n0, int n1, int n2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)n0 * n1 * n2;
+  if (i >= total) return;
+  const long long i2 = i % n2, r = i / n2, i1 = r % n1, i0 = r / n1;
+  dst[i0 * d0 + i1 * d1 + i2 * d2] = src[i0 * s0 + i1 * s1 + i2 * s2];
+}
+
+__global__ void k_set_meta(BoardMeta* meta, int arm, float dist, int valid) {
+  meta->dist[0][arm] = dist;
+  meta->valid[0][arm] = valid;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+template <int LAY, bool DBG>
+static hipError_t launch_rollout_t(const RolloutArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_rollout<LAY, DBG>), dim3(grid), dim3(kWave), 0, s, A.arms, A.P, A.ss, A.items,
+                     A.mu, A.state, A.goal, A.goalR, A.obs, A.plan_read, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s) {
+  if (layout == 0) return debug ? launch_rollout_t<0, true>(A, grid, s) : launch_rollout_t<0, false>(A, grid, s);
+  return debug ? launch_rollout_t<1, true>(A, grid, s) : launch_rollout_t<1, false>(A, grid, s);
+}
+
+hipError_t launch_sense(const SenseArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_sense, dim3(1), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s) {
+  hipLaunchKernelGGL(k_softmax, dim3(n_arms), dim3(1024), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_wmean, dim3(hmax, n_arms), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s) {
+  hipLaunchKernelGGL(k_toplan, dim3(n_arms), dim3(64), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(n_arms), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3((n + 255) / 256), dim3(256), 0, s, ctr, key, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sim_execute(float* state, const float* u, int n, float dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_sim_execute, dim3((n + 63) / 64), dim3(64), 0, s, state, u, n, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy3d(const float* src, long long s0, long long s1, long long s2, float* dst,
+                         long long d0, long long d1, long long d2, int n0, int n1, int n2, hipStream_t s) {
+  const long long total = (long long)n0 * n1 * n2;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy3d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, s0, s1, s2, dst,
+                     d0, d1, d2, n0, n1, n2);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_meta(BoardMeta* meta, int arm, float dist, int valid, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_meta, dim3(1), dim3(1), 0, s, meta, arm, dist, valid);
+  return hipGetLastError();
+}
+
+}  // namespace mrs

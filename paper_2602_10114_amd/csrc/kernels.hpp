@@ -1,0 +1,93 @@
+// Kernel argument blocks and launchers of the MR-STORM step (host side view).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mrs {
+
+struct RolloutArgs {
+  const DevArm* arms;
+  const Params* P;
+  const StepState* ss;
+  const Item* items;
+  int n_items;
+  int h_tile;
+  int k;                       // optimisation iteration
+  int pad;
+  const float* mu;             // [A][Hmax][7]
+  float* eps;                  // per-arm [H][7][Npad] blocks
+  float* partial;              // [A][kMaxH][Nmax]
+  const float* state;          // staged [A][7][3]
+  const float* goal;           // staged [A][7]
+  const float* goalR;          // [A][9]
+  const float* obs;            // staged [O][4]
+  const float* plan_read;      // [A][Hmax][Smax][4]
+  // debug capture (only read by the capturing instantiation)
+  float* dbg_q;                // [A][Nmax][Hmax][7]
+  float* dbg_qd;
+  float* dbg_sph;              // [A][Nmax][Hmax][Smax][4]
+  float* dbg_stage;            // [A][Hmax][Nmax]
+  unsigned long long* dbg_pairs;  // [A]
+};
+
+struct SenseArgs {
+  const DevArm* arms;
+  const Params* P;
+  StepState* ss;
+  const BoardMeta* meta;
+  const float* state;          // caller [A][7][3]
+  const float* goal;           // caller [A][7]
+  const float* obstacles;      // caller [O][4]
+  int n_obs;
+  uint32_t t;
+  float* st_state;
+  float* st_goal;
+  float* st_obs;
+  float* goalR;
+  float* mu;
+};
+
+struct ReduceArgs {
+  const DevArm* arms;
+  const Params* P;
+  const StepState* ss;
+  int h_tile;
+  int pad;
+  const float* partial;
+  float* cost;                 // [A][Nmax]
+  float* w;                    // [A][Nmax]
+  const float* eps;
+  float* mu;
+  float* u_out;                // [A][7]
+  int* argmin;                 // [A]
+  const float* st_state;
+  float* plan_write;
+  float* planq_write;
+  BoardMeta* meta;
+};
+
+struct PublishArgs {
+  const float* plan_write;
+  const float* planq_write;
+  float* plan_read;
+  float* planq_read;
+  BoardMeta* meta;
+  uint32_t mask;
+  int Hmax, Smax;
+};
+
+hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
+hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s);
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s);
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s);
+hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
+hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n, hipStream_t s);
+hipError_t launch_sim_execute(float* state, const float* u, int n, float dt, hipStream_t s);
+hipError_t launch_copy3d(const float* src, long long s0, long long s1, long long s2, float* dst,
+                         long long d0, long long d1, long long d2, int n0, int n1, int n2, hipStream_t s);
+hipError_t launch_set_meta(BoardMeta* meta, int arm, float dist, int valid, hipStream_t s);
+
+}  // namespace mrs

@@ -1,0 +1,75 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point the header declares, the ctypes structures match the C
+layout, and init fails loudly without a gfx950 device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2602_10114_amd import native, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mrstorm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mpc_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = native.lib()
+    names = _declared()
+    assert "mpc_init" in names and "mpc_step" in names and "mpc_share_plans" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(native.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "mrstorm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(mpc_arm_desc), offsetof(mpc_arm_desc, sphere_link),
+         offsetof(mpc_arm_desc, base), offsetof(mpc_arm_desc, tool), sizeof(mpc_params));
+  printf("%zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
+         offsetof(mpc_params, collision_mode), offsetof(mpc_params, surrogate_margin));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    A, P = native.MpcArmDesc, native.MpcParams
+    expect = [C.sizeof(A), A.sphere_link.offset, A.base.offset, A.tool.offset, C.sizeof(P),
+              P.iters.offset, P.seed.offset, P.collision_mode.offset, P.surrogate_margin.offset]
+    assert [int(x) for x in out] == expect
+
+
+def test_init_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = native.lib()
+    sc = scenes.make_scene(1)
+    descs = (native.MpcArmDesc * 1)()
+    prm = native.params_struct(sc.params)
+    h = C.c_void_p()
+    rc = L.mpc_init(descs, 1, C.byref(prm), None, C.byref(h))
+    assert rc == native.MPC_EHIP
+    assert b"device" in L.mpc_last_error(None)
+    assert not h.value
+
+
+def test_bad_arguments_rejected_before_device_use():
+    L = native.lib()
+    h = C.c_void_p()
+    assert L.mpc_init(None, 1, None, None, C.byref(h)) == native.MPC_EINVAL
+    assert L.mpc_step(None, None, None, None, 0, None) == native.MPC_EINVAL
+    assert L.mpc_share_plans(None, None) == native.MPC_EINVAL
+    assert L.mpc_philox(None, None, None, -1, None) == native.MPC_EINVAL

@@ -1,0 +1,387 @@
+"""GPU parity of the HIP control step against the FP64 CPU oracle, through
+the C-ABI.  Tolerances (FP32 GPU vs FP64 oracle):
+  noise eps             1e-6 absolute (sigma * 2e-6 on the normals, rounded up)
+  sphere centres        1e-5 m, end to end
+  stage / rollout costs 1e-4 relative with floor max(|C|, 1), stage-isolated
+                        (the oracle's cost stage is fed the GPU's FP32 joint
+                        states, spheres, plans and priority factors)
+  updated means         1e-5 absolute, stage-isolated (oracle update fed the
+                        GPU's FP32 costs and noise)
+  plans                 1e-5 m (oracle ToPlan fed the GPU's updated means)
+Integer and index results (Philox words, argmin, query counts) are exact.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2602_10114_amd import native, scenes
+from helpers import Capture, f32, oracle_stage, read_boards, rel_err, small_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+    yield
+
+
+def _obs(sc):
+    return sc.obstacles if sc.obstacles.shape[0] else None
+
+
+# --------------------------------------------------------------------- noise
+def test_philox_bitwise():
+    _say("case: philox 4096 random counters")
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0], key[0] = 0, 0
+    out = native.philox(torch.from_numpy(ctr.view(np.int32)).cuda(), torch.from_numpy(key.view(np.int32)).cuda())
+    got = out.cpu().numpy().view(np.uint32)
+    for i in range(0, 4096, 97):
+        assert list(got[i]) == list(oracle.philox(ctr[i], key[i]))
+    assert list(got[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+
+
+# ------------------------------------------------------------ single arm
+@pytest.fixture(scope="module")
+def cfg1_ragged():
+    _say("case: config 1, N=100 (ragged tail), H=20, one step with capture")
+    sc = small_scene(1, n=100)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.debug_enable(True)
+    u = ctl.step(sc.state, sc.goal, sc.obstacles).cpu().numpy()
+    ctl.sync()
+    cap = Capture(ctl, 0)
+    plan, pq, mean = (x.cpu().numpy().astype(np.float64) for x in ctl.get_plan(0))
+    yield sc, ctl, cap, u, plan, pq
+    ctl.close()
+
+
+def test_noise_matches_oracle(cfg1_ragged):
+    sc, _, cap, _, _, _ = cfg1_ragged
+    p = sc.params
+    N, H = sc.arms[0].n_rollouts, sc.arms[0].horizon
+    err = 0.0
+    for n in range(N):
+        for h in range(H):
+            z = oracle.normals(p["seed"], 0, 0, 0, n, h, 7)
+            err = max(err, np.abs(cap.eps[h, :, n] - f32(p["sigma"]) * z).max())
+    assert err < 1e-6, err
+
+
+def test_spheres_end_to_end(cfg1_ragged):
+    sc, _, cap, _, _, _ = cfg1_ragged
+    p, arm = sc.params, sc.arms[0]
+    oa = oracle.make_arm(arm)
+    st = sc.state[0].astype(np.float64)
+    err = 0.0
+    for n in list(range(0, arm.n_rollouts, 9)) + [arm.n_rollouts - 1]:
+        U = np.stack([f32(p["sigma"]) * oracle.normals(p["seed"], 0, 0, 0, n, h, 7) for h in range(arm.horizon)])
+        q, qd = oracle.integrate(st[:, 0], st[:, 1], U, f32(p["dt"]))
+        np.testing.assert_allclose(cap.q[n], q, atol=2e-6)
+        np.testing.assert_allclose(cap.qd[n], qd, atol=2e-6)
+        for h in range(arm.horizon):
+            err = max(err, np.abs(oracle.spheres(oa, q[h]) - cap.sph[n, h]).max())
+    assert err < 1e-5, err
+
+
+def test_stage_costs_stage_isolated(cfg1_ragged):
+    sc, ctl, cap, _, _, _ = cfg1_ragged
+    boards = read_boards(ctl, sc)
+    ref = oracle_stage(sc, 0, cap, sc.obstacles, boards)
+    assert rel_err(cap.stage, ref) < 1e-4
+    tot = np.array([oracle.total_cost(cap.stage[:, n], f32(sc.params["gamma"])) for n in range(cap.stage.shape[1])])
+    assert rel_err(cap.cost, tot) < 1e-5
+
+
+def test_update_and_act_stage_isolated(cfg1_ragged):
+    sc, _, cap, u, _, _ = cfg1_ragged
+    lam = f32(sc.params["lam"])
+    w = oracle.weights(cap.cost, lam)
+    np.testing.assert_allclose(cap.w, w, atol=1e-6, rtol=1e-4)
+    U = np.transpose(cap.eps, (2, 0, 1))  # the means were zero before this step
+    mt = oracle.weighted_mean(w, U)
+    assert np.abs(cap.mu - mt).max() < 1e-5
+    n_star = oracle.argmin(cap.cost)
+    assert cap.argmin == n_star
+    assert np.abs(u[0] - U[n_star, 0]).max() < 1e-6
+
+
+def test_plan_stage_isolated(cfg1_ragged):
+    sc, _, cap, _, plan, pq = cfg1_ragged
+    arm = sc.arms[0]
+    oa = oracle.make_arm(arm)
+    st = sc.state[0].astype(np.float64)
+    q, _ = oracle.integrate(st[:, 0], st[:, 1], cap.mu, f32(sc.params["dt"]))
+    assert np.abs(pq - q).max() < 2e-6
+    for h in range(arm.horizon):
+        s = oracle.spheres(oa, q[h])
+        assert np.abs(plan[:, :, h] - s).max() < 1e-5
+
+
+# -------------------------------------------------------------- many arms
+def _run_multi(sc, steps, publish=True, debug_last=True, stream=None):
+    ctl = native.Controller(sc.arms, sc.params, stream=stream)
+    caps, boards, us = None, None, None
+    for t in range(steps):
+        last = t == steps - 1
+        if last and debug_last:
+            ctl.debug_enable(True)
+            ctl.sync()
+            boards = read_boards(ctl, sc)
+        u = ctl.step(sc.state, sc.goal, _obs(sc))
+        if publish:
+            ctl.share_plans()
+        us = u
+    ctl.sync()
+    if debug_last:
+        caps = [Capture(ctl, a) for a in range(sc.n_arms)]
+    return ctl, caps, boards, us.cpu().numpy()
+
+
+def test_two_arms_plan_sharing():
+    _say("case: config 2 shape, N=128, H=12, 3 steps with plan sharing")
+    sc = small_scene(2, n=128, h=12)
+    ctl, caps, boards, u = _run_multi(sc, 3)
+    for a in range(2):
+        assert boards[1 - a][1] == 1
+        ref = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+        assert rel_err(caps[a].stage, ref) < 1e-4
+        # priority factor from the GPU's distance and the published one
+        d_other = boards[1 - a][2]
+        al = oracle.priority(caps[a].dist, d_other, f32(3.0), f32(1e-3), f32(0.5), f32(2.0))
+        assert abs(caps[a].alpha[1 - a] - al) < 1e-5 * max(1.0, al)
+    # the coordination term is live in this scene (arms start ~1 cm apart)
+    assert any((c.stage > 100).any() for c in caps)
+    ctl.close()
+
+
+def test_uneven_batch_and_counter():
+    _say("case: config 3 shape, ragged N (64,100,128,192), H (8,12,12,16), 3 steps")
+    sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
+    ctl, caps, boards, u = _run_multi(sc, 3)
+    for a in range(4):
+        ref = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+        assert rel_err(caps[a].stage, ref) < 1e-4, a
+        # Sec. IV-A complexity: H N N_S sum_i N_S^(i) queries, counted over the
+        # steps each neighbour's (shorter) horizon reaches.
+        arm = sc.arms[a]
+        expect = sum(arm.n_rollouts * arm.n_spheres * sum(sc.arms[i].n_spheres for i in range(4)
+                                                          if i != a and h < sc.arms[i].horizon and boards[i][1])
+                     for h in range(arm.horizon))
+        assert caps[a].pairs == expect
+    ctl.close()
+
+
+def test_unpublished_neighbours_ignored():
+    _say("case: config 2 shape without publish")
+    sc = small_scene(2, n=64, h=10)
+    ctl, caps, boards, _ = _run_multi(sc, 2, publish=False)
+    for a in range(2):
+        assert caps[a].alpha[1 - a] == 0.0
+        assert caps[a].pairs == 0
+    ctl.close()
+    sc0 = small_scene(2, n=64, h=10, w_dyn=0.0)
+    ctl0, caps0, _, _ = _run_multi(sc0, 2, publish=True)
+    for a in range(2):
+        np.testing.assert_array_equal(caps[a].stage, caps0[a].stage)
+    ctl0.close()
+
+
+def test_fault_injected_plan():
+    _say("case: injected neighbour plan through the board")
+    sc = small_scene(2, n=64, h=10)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    # put arm 1's plan right on top of arm 0's current spheres
+    oa = oracle.make_arm(sc.arms[0])
+    s0 = oracle.spheres(oa, sc.state[0, :, 0].astype(np.float64))
+    fake = np.repeat(s0[None], 10, axis=0).astype(np.float32)
+    ctl.set_board(1, fake, np.zeros((10, 7), np.float32), 0.5, 1)
+    ctl.debug_enable(True)
+    boards = read_boards(ctl, sc)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    cap = Capture(ctl, 0)
+    ref = oracle_stage(sc, 0, cap, sc.obstacles, boards)
+    assert rel_err(cap.stage, ref) < 1e-4
+    assert cap.stage.min() > 5000 * 0.5 * 0.9  # every rollout overlaps the injected plan
+    ctl.close()
+
+
+def test_update_second_step_and_shift():
+    _say("case: config 1, two steps, update stage-isolated on the shifted means")
+    sc = small_scene(1, n=128, alpha_mu=0.5)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    ctl.sync()
+    mu1 = ctl.get_plan(0)[2].cpu().numpy().astype(np.float64)
+    ctl.debug_enable(True)
+    u = ctl.step(sc.state, sc.goal, sc.obstacles).cpu().numpy()
+    ctl.sync()
+    cap = Capture(ctl, 0)
+    mu_prev = oracle.shift(mu1)
+    U = mu_prev[None] + np.transpose(cap.eps, (2, 0, 1))
+    w = oracle.weights(cap.cost, f32(sc.params["lam"]))
+    mt = oracle.weighted_mean(w, U)
+    new = oracle.ema(mu_prev, mt, f32(0.5))
+    assert np.abs(cap.mu - new).max() < 1e-5
+    n_star = oracle.argmin(cap.cost)
+    assert np.abs(u[0] - U[n_star, 0]).max() < 1e-6
+    ctl.close()
+
+
+def test_graph_path_bitwise_equals_capture_path():
+    _say("case: graph-captured production kernel vs capturing kernel, config 3 shape")
+    sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c1, _, _, u1 = _run_multi(sc, 3, debug_last=False, stream=s)
+        c2, _, _, u2 = _run_multi(sc, 3, debug_last=True, stream=s)
+        m1 = [c1.get_plan(a)[2].cpu().numpy() for a in range(4)]
+        m2 = [c2.get_plan(a)[2].cpu().numpy() for a in range(4)]
+    s.synchronize()
+    np.testing.assert_array_equal(u1, u2)
+    for a in range(4):
+        np.testing.assert_array_equal(m1[a], m2[a])
+    c1.close()
+    c2.close()
+
+
+def test_deterministic_repeat():
+    _say("case: repeat run bitwise, config 2 shape")
+    sc = small_scene(2, n=256, h=16)
+    outs = []
+    for _ in range(2):
+        ctl, _, _, u = _run_multi(sc, 4, debug_last=False)
+        outs.append((u, [ctl.get_plan(a)[2].cpu().numpy() for a in range(2)]))
+        ctl.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    for a in range(2):
+        np.testing.assert_array_equal(outs[0][1][a], outs[1][1][a])
+
+
+def test_tiles_do_not_change_results():
+    _say("case: forced horizon tiles 1, 3, H give identical costs")
+    sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
+    res = []
+    for T in (1, 3, 16):
+        ctl = native.Controller(sc.arms, sc.params)
+        ctl.set_tuning(0, T, 0)
+        ctl.debug_enable(True)
+        ctl.step(sc.state, sc.goal, sc.obstacles)
+        ctl.sync()
+        res.append([ctl.debug_get("STAGE_COST", a).cpu().numpy() for a in range(4)])
+        assert ctl.tuning()[1] == T
+        ctl.close()
+    for r in res[1:]:
+        for a in range(4):
+            np.testing.assert_array_equal(r[a], res[0][a])
+
+
+# ------------------------------------------------------------- edge cases
+def test_single_rollout_and_single_step_horizon():
+    _say("case: N=1, H=1")
+    sc = small_scene(1, n=1, h=1)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.debug_enable(True)
+    u = ctl.step(sc.state, sc.goal, sc.obstacles).cpu().numpy()
+    ctl.sync()
+    cap = Capture(ctl, 0)
+    assert cap.w[0] == 1.0
+    np.testing.assert_allclose(cap.mu[0], cap.eps[0, :, 0], atol=1e-7)
+    np.testing.assert_allclose(u[0], cap.eps[0, :, 0], atol=1e-7)
+    boards = read_boards(ctl, sc)
+    assert rel_err(cap.stage, oracle_stage(sc, 0, cap, sc.obstacles, boards)) < 1e-4
+    ctl.close()
+
+
+def test_no_obstacles_and_errors():
+    _say("case: zero obstacles, argument errors")
+    sc = small_scene(1, n=64, h=6)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.debug_enable(True)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    cap = Capture(ctl, 0)
+    assert rel_err(cap.stage, oracle_stage(sc, 0, cap, np.zeros((0, 4)), read_boards(ctl, sc))) < 1e-4
+    too_many = np.zeros((sc.params["max_obstacles"] + 1, 4), np.float32)
+    with pytest.raises(native.MpcError) as e:
+        ctl.step(sc.state, sc.goal, too_many)
+    assert e.value.code == native.MPC_EINVAL
+    with pytest.raises(native.MpcError):
+        ctl.get_plan(5)
+    ctl.close()
+    fresh = native.Controller(sc.arms, sc.params)
+    with pytest.raises(native.MpcError) as e:
+        fresh.get_plan(0)
+    assert e.value.code == native.MPC_ESTATE
+    fresh.close()
+    bad = small_scene(1, n=64, h=6)
+    bad.arms[0].horizon = 65
+    with pytest.raises(native.MpcError) as e:
+        native.Controller(bad.arms, bad.params)
+    assert e.value.code == native.MPC_EINVAL
+
+
+def test_padded_sphere_layout():
+    _say("case: 64-sphere layout (8 per body), config 5 arm shape, 2 arms")
+    sc = scenes.make_scene(5, collision_mode=0)
+    sc.arms = sc.arms[:2]
+    sc.arms[1] = scenes.dataclasses.replace(sc.arms[1], base=np.array([-0.75, 0.4, 0.0, -np.pi / 2], np.float32))
+    for a in sc.arms:
+        a.n_rollouts, a.horizon = 64, 8
+    sc.state, sc.goal = sc.state[:2], sc.goal[:2]
+    ctl, caps, boards, _ = _run_multi(sc, 2)
+    for a in range(2):
+        assert rel_err(caps[a].stage, oracle_stage(sc, a, caps[a], sc.obstacles, boards)) < 1e-4
+    ctl.close()
+
+
+def test_mixed_layout_arms():
+    _say("case: arms with 52 and 40 spheres (padded layout for both)")
+    sc = small_scene(2, n=64, h=8)
+    a1 = sc.arms[1]
+    keep = np.arange(a1.n_spheres) % 4 != 3
+    sc.arms[1] = scenes.dataclasses.replace(a1, spheres=a1.spheres[keep], sphere_link=a1.sphere_link[keep])
+    ctl, caps, boards, _ = _run_multi(sc, 2)
+    for a in range(2):
+        assert rel_err(caps[a].stage, oracle_stage(sc, a, caps[a], sc.obstacles, boards)) < 1e-4
+    ctl.close()
+
+
+def test_end_to_end_within_conditioning_bound():
+    """End to end (oracle from its own FP64 noise) the means agree within the
+    softmax conditioning bound max|U| * max_n |dC_n| / lambda."""
+    _say("case: end-to-end vs full oracle controller, config 2 shape, 3 steps")
+    sc = small_scene(2, n=64, h=10)
+    ctl = native.Controller(sc.arms, sc.params)
+    orc = oracle.Controller(sc.arms, sc.params)
+    for t in range(3):
+        ctl.debug_enable(t == 2)
+        ctl.step(sc.state, sc.goal, None)
+        orc.step(sc.state, sc.goal, sc.obstacles)
+        ctl.share_plans()
+        orc.share_plans()
+    ctl.sync()
+    lam = f32(sc.params["lam"])
+    for a in range(2):
+        cap = Capture(ctl, a, want_spheres=False)
+        tot, _, _ = orc.costs(a)
+        dC = np.abs(cap.cost - tot[:64]).max()
+        mu_o = orc.mean(a)[:10]
+        U = np.abs(np.transpose(cap.eps, (2, 0, 1))).max() + np.abs(mu_o).max()
+        bound = U * dC / lam + 1e-4
+        assert np.abs(cap.mu - mu_o).max() <= bound
+    ctl.close()
