@@ -146,7 +146,10 @@ enum {
   MPC_DBG_ALPHA = 8,       /* float [n_arms]: priority factors alpha^(arm,i) used at this step (0 = ignored) */
   MPC_DBG_DIST = 9,        /* float [1]: this arm's distance to goal at Sense */
   MPC_DBG_PAIRS = 10,      /* unsigned long long [1]: coordination distance queries evaluated */
-  MPC_DBG_ARGMIN = 11      /* int [1]: index of the executed rollout */
+  MPC_DBG_ARGMIN = 11,     /* int [1]: index of the executed rollout */
+  MPC_DBG_PASSES = 12      /* unsigned long long [3]: per-wave count of distance filter
+                              passes over obstacle/neighbour sets, of exact (FP64) passes
+                              over such sets, and of exact self-collision passes */
 };
 /* Copy one captured quantity of one arm into dev_out (device). */
 int mpc_debug_get(mpc_ctx *c, int what, int arm, void *dev_out);

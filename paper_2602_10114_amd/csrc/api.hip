@@ -45,6 +45,9 @@ struct mpc_ctx {
   int h_tile = 0, grid = 0;
   int force_tile = 0, force_grid = 0;
   bool tuned = false;
+  int n_published = 0;                 // arms whose plan has been published at least once
+  std::vector<char> published;
+  int untuned_steps = 0;
   hipGraphExec_t gexec = nullptr;
   bool debug = false;
   float* dbg_q = nullptr;
@@ -484,11 +487,23 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
   HIPCHK(c, launch_sense(S, c->stream));
   int rc;
   if (!c->tuned) {
-    if ((rc = tune(c))) return rc;
-    if ((rc = capture_graph(c))) return rc;
+    // Tune on a representative step: once every arm's plan is visible to the
+    // others (or after a few steps if the caller never publishes them all).
+    const bool representative = c->A == 1 || c->n_published == c->A || c->untuned_steps >= 3;
+    if (representative) {
+      if ((rc = tune(c))) return rc;
+      if ((rc = capture_graph(c))) return rc;
+    } else {
+      if (c->n_items == 0) {
+        const int T = c->force_tile > 0 ? std::min(c->force_tile, c->Hmax) : std::min(4, c->Hmax);
+        if ((rc = set_items(c, T))) return rc;
+      }
+      c->grid = c->force_grid > 0 ? std::min(c->force_grid, c->n_items) : c->n_items;
+      ++c->untuned_steps;
+    }
   }
   if (c->debug) {
-    HIPCHK(c, hipMemsetAsync(c->dbg_pairs, 0, sizeof(unsigned long long) * c->A, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->dbg_pairs, 0, sizeof(unsigned long long) * 4 * c->A, c->stream));
     if ((rc = enqueue_body(c, true))) return rc;
   } else if (c->gexec && !c->profile) {
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
@@ -512,8 +527,15 @@ extern "C" int mpc_share_plans(mpc_ctx* c, const unsigned char* mask) {
   P.Hmax = c->Hmax;
   P.Smax = c->Smax;
   uint32_t m = 0;
+  if (c->published.empty()) c->published.assign(c->A, 0);
   for (int a = 0; a < c->A; ++a)
-    if (!mask || mask[a]) m |= 1u << a;
+    if (!mask || mask[a]) {
+      m |= 1u << a;
+      if (c->stepped && !c->published[a]) {
+        c->published[a] = 1;
+        ++c->n_published;
+      }
+    }
   P.mask = m;
   HIPCHK(c, launch_publish(P, c->A, c->stream));
   return MPC_OK;
@@ -547,7 +569,7 @@ extern "C" int mpc_debug_enable(mpc_ctx* c, int on) {
     int rc;
     if ((rc = dalloc(c, &c->dbg_q, A * N * H * 7)) || (rc = dalloc(c, &c->dbg_qd, A * N * H * 7)) ||
         (rc = dalloc(c, &c->dbg_sph, A * N * H * S * 4)) || (rc = dalloc(c, &c->dbg_stage, A * H * N)) ||
-        (rc = dalloc(c, &c->dbg_pairs, A)))
+        (rc = dalloc(c, &c->dbg_pairs, 4 * A)))
       return rc;
   }
   c->debug = on != 0;
@@ -561,7 +583,7 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
   const long long N = c->Nmax, H = c->Hmax, S = c->Smax;
   float* out = static_cast<float*>(dev_out);
   const bool needs_dbg = what == MPC_DBG_Q || what == MPC_DBG_QD || what == MPC_DBG_SPHERES ||
-                         what == MPC_DBG_STAGE_COST || what == MPC_DBG_PAIRS;
+                         what == MPC_DBG_STAGE_COST || what == MPC_DBG_PAIRS || what == MPC_DBG_PASSES;
   if (needs_dbg && !c->dbg_q) return fail(c, MPC_ESTATE, "debug capture is off");
   switch (what) {
     case MPC_DBG_NOISE:
@@ -598,7 +620,11 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
       HIPCHK(c, hipMemcpyAsync(out, &c->d_ss->dist_now[arm], sizeof(float), hipMemcpyDeviceToDevice, c->stream));
       break;
     case MPC_DBG_PAIRS:
-      HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + arm, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + 4 * arm, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_PASSES:
+      HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + 4 * arm + 1, 3 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToDevice, c->stream));
       break;
     case MPC_DBG_ARGMIN:
       HIPCHK(c, hipMemcpyAsync(out, c->argmin + arm, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -678,7 +704,7 @@ extern "C" int mpc_get_tuning(const mpc_ctx* c, int* rollouts_per_block, int* h_
   if (rollouts_per_block) *rollouts_per_block = kWave;
   if (h_tile) *h_tile = c->h_tile;
   if (grid) *grid = c->grid;
-  return c->tuned ? MPC_OK : MPC_ESTATE;
+  return c->n_items > 0 ? MPC_OK : MPC_ESTATE;
 }
 
 extern "C" int mpc_set_tuning(mpc_ctx* c, int rollouts_per_block, int h_tile, int grid) {
@@ -689,6 +715,7 @@ extern "C" int mpc_set_tuning(mpc_ctx* c, int rollouts_per_block, int h_tile, in
   c->force_tile = h_tile;
   c->force_grid = grid;
   c->tuned = false;
+  c->n_items = 0;
   return MPC_OK;
 }
 

@@ -92,12 +92,33 @@ __device__ __forceinline__ void body_spheres(const Frame& Fb, const LdsSets& L, 
 }
 
 // min over the body's spheres and the staged spheres [k0, k0+K) of the
-// squared-gap expansion.
+// squared-gap expansion (two staged spheres per iteration).
 template <int C>
 __device__ __forceinline__ float filter_range(const float ux[8], const float uy[8], const float uz[8],
                                               const float ur[8], const float E[8], const LdsSets& L,
                                               int k0, int K, float g) {
-  for (int k = k0; k < k0 + K; ++k) {
+  const int kend = k0 + K;
+  int k = k0;
+  for (; k + 1 < kend; k += 2) {
+    const float4 w0 = L.w[k], w1 = L.w[k + 1];
+    const float F0 = L.F[k], F1 = L.F[k + 1];
+    float m0 = 3.0e38f, m1 = 3.0e38f;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      float t0 = fmaf_(ux[j], w0.x, E[j]);
+      float t1 = fmaf_(ux[j], w1.x, E[j]);
+      t0 = fmaf_(uy[j], w0.y, t0);
+      t1 = fmaf_(uy[j], w1.y, t1);
+      t0 = fmaf_(uz[j], w0.z, t0);
+      t1 = fmaf_(uz[j], w1.z, t1);
+      t0 = fmaf_(ur[j], w0.w, t0);
+      t1 = fmaf_(ur[j], w1.w, t1);
+      m0 = fminf(m0, t0);
+      m1 = fminf(m1, t1);
+    }
+    g = fminf(g, fminf(m0 + F0, m1 + F1));
+  }
+  if (k < kend) {
     const float4 w = L.w[k];
     const float Fk = L.F[k];
     float m = 3.0e38f;
@@ -115,125 +136,154 @@ __device__ __forceinline__ float filter_range(const float ux[8], const float uy[
 }
 
 // Filter pass over one staged set: body by body down the chain (one walking
-// frame), running minimum of the squared-gap expansion.
+// frame), running minimum of the squared-gap expansion; bit b of `near` is
+// set when body b has a pair below the slack.
 template <int LAY, int B_>
 __device__ __forceinline__ void set_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, int k0, int K, float& gmin) {
+                                           const LdsSets& L, int k0, int K, unsigned& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
   float ux[8], uy[8], uz[8], ur[8], E[8];
   body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
-  gmin = filter_range<Cb>(ux, uy, uz, ur, E, L, k0, K, gmin);
-  if constexpr (B_ + 1 < kBodies) set_filter<LAY, B_ + 1>(W, arm, C, L, k0, K, gmin);
+  const float gb = filter_range<Cb>(ux, uy, uz, ur, E, L, k0, K, 3.0e38f);
+  near |= (gb < kSlack ? 1u : 0u) << B_;
+  if constexpr (B_ + 1 < kBodies) set_filter<LAY, B_ + 1>(W, arm, C, L, k0, K, near);
+}
+
+// Exact FP64 gaps of the candidate pairs of one own body against one staged
+// sphere: `cand` has bit j set for own sphere j.  The own centre is rebuilt
+// from the body frame and the LDS table with the same operations as in the
+// filter, so it is the same FP32 value.
+template <int S0>
+__device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& L, unsigned cand, float px,
+                                                 float py, float pz, float pr, double& best) {
+  while (cand) {
+    const int j = __builtin_ctz(cand);
+    cand &= cand - 1u;
+    const float4 p = L.slot[S0 + j];
+    float x, y, z;
+    frame_point(W, p.x, p.y, p.z, x, y, z);
+    const double g = sphere_gap64(x, y, z, p.w, px, py, pz, pr);
+    best = g < best ? g : best;
+  }
 }
 
 // Exact pass for one set: the FP64 gap of every pair the filter can flag; the
 // minimum over them is the set distance whenever that distance is below B.
 template <int LAY, int B_>
 __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, int k0, int K, double& best) {
+                                           const LdsSets& L, int k0, int K, unsigned near, double& best) {
   constexpr int Cb = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
+  // Only bodies that some lane of the wave flagged.
+  if (wave_any((near >> B_) & 1u)) {
   float ux[8], uy[8], uz[8], ur[8], E[8];
   body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
   for (int k = k0; k < k0 + K; ++k) {
     const float4 w = L.w[k];
     const float Fk = L.F[k];
+    unsigned cand = 0;
 #pragma unroll
     for (int j = 0; j < Cb; ++j) {
       float t = fmaf_(ux[j], w.x, E[j]);
       t = fmaf_(uy[j], w.y, t);
       t = fmaf_(uz[j], w.z, t);
       t = fmaf_(ur[j], w.w, t);
-      if (t + Fk < kSlack) {
-        const float4 r = L.raw[k];
-        const double g = sphere_gap64(ux[j], uy[j], uz[j], L.slot[S0 + j].w, r.x, r.y, r.z, r.w);
-        best = g < best ? g : best;
-      }
+      cand |= (t + Fk < kSlack ? 1u : 0u) << j;
+    }
+    if (cand) {
+      const float4 r = L.raw[k];
+      exact_candidates<S0>(W, L, cand, r.x, r.y, r.z, r.w, best);
     }
   }
-  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, best);
+  }
+  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, near, best);
 }
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
 // second walking frame runs from body B1 down the chain to every B2 > B1.
+// The filter pass sets bit 8*B1+B2 of `near` for a body pair with a pair
+// below the slack; the exact pass visits only pairs some lane flagged.
 template <int LAY, int B1, int B2>
-__device__ __forceinline__ void self_inner(Frame& W2, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, float buf, const float ux[8],
+__device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const DevArm* __restrict__ arm,
+                                           const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
-                                           const float E[8], bool refine, float& gmin, double& best) {
+                                           const float E[8], bool refine, unsigned long long& near,
+                                           double& best) {
   constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
   constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
+  constexpr unsigned long long bit = 1ull << (8 * B1 + B2);
   if constexpr (B2 < 7) walk(W2, arm, C, B2);
   if constexpr (B2 >= B1 + 2) {
-    for (int i = 0; i < C2; ++i) {
-      asm volatile("" ::: "memory");
-      const float4 p = L.slot[S2 + i];
-      float x, y, z;
-      frame_point(W2, p.x, p.y, p.z, x, y, z);
-      const float r = p.w;
-      const float rb = r + buf;
-      const bool parked = r < 0.f;
-      const float wx = parked ? 0.f : -2.f * x, wy = parked ? 0.f : -2.f * y;
-      const float wz = parked ? 0.f : -2.f * z, wr = parked ? 0.f : -2.f * rb;
-      const float Fk = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
-      if (!refine) {
+    if (!refine || wave_any((near & bit) != 0ull)) {
+      float gp = 3.0e38f;
+#pragma nounroll
+      for (int i = 0; i < C2; ++i) {
+        asm volatile("" ::: "memory");
+        const float4 p = L.slot[S2 + i];
+        float x, y, z;
+        frame_point(W2, p.x, p.y, p.z, x, y, z);
+        const float r = p.w;
+        const float rb = r + buf;
+        const bool parked = r < 0.f;
+        const float wx = parked ? 0.f : -2.f * x, wy = parked ? 0.f : -2.f * y;
+        const float wz = parked ? 0.f : -2.f * z, wr = parked ? 0.f : -2.f * rb;
+        const float Fk = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
         float m = 3.0e38f;
+        unsigned cand = 0;
 #pragma unroll
         for (int j = 0; j < C1; ++j) {
           float t = fmaf_(ux[j], wx, E[j]);
           t = fmaf_(uy[j], wy, t);
           t = fmaf_(uz[j], wz, t);
           t = fmaf_(ur[j], wr, t);
-          m = fminf(m, t);
-        }
-        gmin = fminf(gmin, m + Fk);
-      } else {
-#pragma unroll
-        for (int j = 0; j < C1; ++j) {
-          float t = fmaf_(ux[j], wx, E[j]);
-          t = fmaf_(uy[j], wy, t);
-          t = fmaf_(uz[j], wz, t);
-          t = fmaf_(ur[j], wr, t);
-          if (t + Fk < kSlack) {
-            const double g = sphere_gap64(ux[j], uy[j], uz[j], L.slot[S1 + j].w, x, y, z, r);
-            best = g < best ? g : best;
+          if (refine) {
+            cand |= (t + Fk < kSlack ? 1u : 0u) << j;
+          } else {
+            m = fminf(m, t);
           }
         }
+        if (refine) {
+          if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, best);
+        } else {
+          gp = fminf(gp, m + Fk);
+        }
       }
+      if (!refine) near |= gp < kSlack ? bit : 0ull;
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, arm, C, L, buf, ux, uy, uz, ur, E, refine, gmin, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, refine, near, best);
 }
 
 template <int LAY, int B1>
 __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, float buf, bool refine, float& gmin,
-                                           double& best) {
+                                           const LdsSets& L, float buf, bool refine,
+                                           unsigned long long& near, double& best) {
   if constexpr (B1 + 2 < kBodies) {
     walk(W1, arm, C, B1);
     float ux[8], uy[8], uz[8], ur[8], E[8];
-    body_spheres<LAY, B1>(W1, L, 0.f, ux, uy, uz, ur, E);
+    body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
     Frame W2 = W1;
-    self_inner<LAY, B1, B1 + 1>(W2, arm, C, L, buf, ux, uy, uz, ur, E, refine, gmin, best);
-    self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, gmin, best);
+    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, refine, near, best);
+    self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, near, best);
   }
 }
 
 template <int LAY>
 __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, float buf) {
-  float gmin = 3.0e38f;
+                                            const LdsSets& L, float buf, unsigned& refines) {
+  unsigned long long near = 0ull;
   double best = 1.0e300;
   Frame W;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, false, gmin, best);
-  const bool near = gmin < kSlack;
-  if (!wave_any(near)) return 0.f;
+  self_outer<LAY, 0>(W, arm, C, L, buf, false, near, best);
+  const bool any_near = near != 0ull;
+  if (!wave_any(any_near)) return 0.f;
+  ++refines;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, true, gmin, best);
-  return near ? (float)hinge64(best, (double)buf) : 0.f;
+  self_outer<LAY, 0>(W, arm, C, L, buf, true, near, best);
+  return any_near ? (float)hinge64(best, (double)buf) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,6 +344,7 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
     const int nnb = SS.nb_count[a];
     float acc = 0.f;
     unsigned long long pairs = 0;
+    unsigned set_passes = 0, set_refines = 0, self_refines = 0;
     for (int h = item.h0; h < item.h1; ++h) {
       float z[8];
       normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
@@ -375,24 +426,26 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
         c = fmaf_(P.w_joint, joint, c);
       }
       // Self collision.
-      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self), c);
+      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_refines), c);
       // Obstacles and neighbours' plans (Eqs. 6, 8, 9): a filter pass per set,
       // then the exact pass if some lane of the wave may be within B.
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
         const int k0 = L.set_k0[si], K = L.set_n[si];
-        float gmin = 3.0e38f;
+        unsigned nearb = 0;
         {
           Frame W;
           frame_base(W, arm);
-          set_filter<LAY, 0>(W, arm, C, L, k0, K, gmin);
+          set_filter<LAY, 0>(W, arm, C, L, k0, K, nearb);
         }
-        const bool near = gmin < kSlack;
+        const bool near = nearb != 0;
+        ++set_passes;
         if (wave_any(near)) {
+          ++set_refines;
           double best = 1.0e300;
           Frame W;
           frame_base(W, arm);
-          set_refine<LAY, 0>(W, arm, C, L, k0, K, best);
+          set_refine<LAY, 0>(W, arm, C, L, k0, K, nearb, best);
           const float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
           c = fmaf_(L.set_wt[si], hv, c);
         }
@@ -425,7 +478,12 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
       }
     }
     if (live) A.partial[((size_t)a * kMaxH + item.h0 / A.h_tile) * P.Nmax + n] = acc;
-    if (DBG && live) atomicAdd(A.dbg_pairs + a, pairs);
+    if (DBG && live) atomicAdd(A.dbg_pairs + 4 * a, pairs);
+    if (DBG && lane == 0) {
+      atomicAdd(A.dbg_pairs + 4 * a + 1, (unsigned long long)set_passes);
+      atomicAdd(A.dbg_pairs + 4 * a + 2, (unsigned long long)set_refines);
+      atomicAdd(A.dbg_pairs + 4 * a + 3, (unsigned long long)self_refines);
+    }
   }
 }
 

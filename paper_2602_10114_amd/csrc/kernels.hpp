@@ -29,7 +29,7 @@ struct RolloutArgs {
   float* dbg_qd;
   float* dbg_sph;              // [A][Nmax][Hmax][Smax][4]
   float* dbg_stage;            // [A][Hmax][Nmax]
-  unsigned long long* dbg_pairs;  // [A]
+  unsigned long long* dbg_pairs;  // [A][4]: queries, set filter passes, set exact passes, self exact passes (per wave)
 };
 
 struct SenseArgs {

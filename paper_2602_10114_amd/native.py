@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrstorm.so")
 
 MPC_OK, MPC_EINVAL, MPC_ENOMEM, MPC_EHIP, MPC_ESTATE, MPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DBG = dict(NOISE=0, Q=1, QD=2, SPHERES=3, STAGE_COST=4, COST=5, WEIGHTS=6, MEAN=7, ALPHA=8,
-           DIST=9, PAIRS=10, ARGMIN=11)
+           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12)
 EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destroy",
            "mpc_last_error", "mpc_sync", "mpc_debug_enable", "mpc_debug_get", "mpc_get_board",
            "mpc_set_board", "mpc_set_mean", "mpc_get_step", "mpc_set_step", "mpc_sim_execute",
@@ -201,8 +201,8 @@ class Controller:
         t = self.torch
         shapes = dict(NOISE=(H, 7, N), Q=(N, H, 7), QD=(N, H, 7), SPHERES=(N, H, S, 4),
                       STAGE_COST=(H, N), COST=(N,), WEIGHTS=(N,), MEAN=(H, 7), ALPHA=(self.A,),
-                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,))
-        dtype = dict(PAIRS=t.int64, ARGMIN=t.int32).get(what, t.float32)
+                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,))
+        dtype = dict(PAIRS=t.int64, ARGMIN=t.int32, PASSES=t.int64).get(what, t.float32)
         out = t.empty(shapes[what], dtype=dtype, device=self.dev)
         _check(lib().mpc_debug_get(self.h, DBG[what], arm, _ptr(out)), self.h)
         return out

@@ -320,8 +320,9 @@ def test_no_obstacles_and_errors():
     with pytest.raises(native.MpcError) as e:
         ctl.step(sc.state, sc.goal, too_many)
     assert e.value.code == native.MPC_EINVAL
-    with pytest.raises(native.MpcError):
-        ctl.get_plan(5)
+    buf = torch.empty(4096, device="cuda")
+    assert native.lib().mpc_get_plan(ctl.h, 5, native._ptr(buf), None, None) == native.MPC_EINVAL
+    assert native.lib().mpc_debug_get(ctl.h, 99, 0, native._ptr(buf)) == native.MPC_EINVAL
     ctl.close()
     fresh = native.Controller(sc.arms, sc.params)
     with pytest.raises(native.MpcError) as e:
