@@ -25,6 +25,69 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rollout-steps/s (arms×rollouts×horizon) + p50/p99 step latency, exact vs surrogate"
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, 256 CUs at 2.4 GHz
+KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd/csrc/device.hpp",
+                  "paper_2602_10114_amd/csrc/common.hpp"]
+# HBM bytes per k_rollout launch on this workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes, each scaled by the same counter's reading for a 256 MiB
+# device copy (fetch x2.000, write x1.000); valid only for the kernel sources
+# with this digest (see profiles/k_rollout_cfg5_exact.md).
+TRAFFIC = {"sources_sha256": "9a1119d1865e7c11", "bytes_per_launch": 44653772}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize(trace_dir, fetch_dir, write_dir, steps):
+    """Text summary of rocprofv3 output of `bench.py --steps <steps>`: per-kernel
+    durations over the steady-state launches (the last 2*steps rollout
+    launches: the timed and the event-bracketed passes) and HBM bytes per
+    dispatch from the FETCH_SIZE / WRITE_SIZE passes scaled by the copy
+    kernel's reading."""
+    import csv
+    import glob
+    from collections import defaultdict
+    out = []
+    tr = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    rows = list(csv.DictReader(open(tr)))
+    by = defaultdict(list)
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0]
+        by[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out.append(f"kernel trace: {tr}")
+    out.append(f"{'kernel':44s} {'calls':>6s} {'steady calls':>12s} {'steady avg us':>14s} {'min us':>9s} {'max us':>9s}")
+    for name, v in sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1])):
+        v.sort()
+        steady = [d for _, d in v[-2 * steps:]] if "k_rollout" in name else [d for _, d in v[-steps:]]
+        out.append(f"{name[:44]:44s} {len(v):6d} {len(steady):12d} {np.mean(steady) / 1e3:14.2f} "
+                   f"{min(steady) / 1e3:9.2f} {max(steady) / 1e3:9.2f}")
+    res = {}
+    if fetch_dir and write_dir:
+        for tag, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+            f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+            rows = list(csv.DictReader(open(f)))
+            per = defaultdict(list)
+            for r in rows:
+                if r["Counter_Name"] == tag:
+                    per[r["Kernel_Name"].split("(")[0]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+            copy = max(per["__amd_rocclr_copyBuffer"], key=lambda x: x[1])[1]
+            factor = (256 * 1024) / copy
+            out.append(f"{tag}: {f}; 256 MiB copy reads {copy:.1f} KiB -> scale x{factor:.3f}")
+            for name, v in sorted(per.items()):
+                if name.startswith("mrs::") or "k_rollout" in name:
+                    v.sort()
+                    kib = v[-1][1]
+                    res.setdefault(name, {})[tag] = kib * factor * 1024
+                    out.append(f"  {name[:44]:44s} last dispatch {kib:12.1f} KiB -> {kib * factor * 1024 / 1e6:10.3f} MB")
+        out.append("HBM bytes per dispatch (scaled FETCH + WRITE):")
+        for name, v in res.items():
+            out.append(f"  {name[:44]:44s} {(v.get('FETCH_SIZE', 0) + v.get('WRITE_SIZE', 0)) / 1e6:10.3f} MB")
+    out.append(f"kernel sources sha256[:16] at summary time: {sources_digest()}")
+    return "\n".join(out)
 
 
 def algorithmic_flops_per_step(scene, active_neighbours=True):
@@ -74,7 +137,14 @@ def main():
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="print a summary of rocprofv3 output of a bench run and exit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize:
+        print(summarize(*args.summarize, steps=args.steps))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU plan all-gather "
                                    "is a design, not a runnable path (--gpus 1)"}))
@@ -159,9 +229,17 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "roofline": {"kernel": "k_rollout", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_digest() else None,
                      "kernel_ms": roll_ms, "algorithmic_flop_per_launch": flops},
     }
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene)
     ctl.close()
