@@ -147,9 +147,11 @@ enum {
   MPC_DBG_DIST = 9,        /* float [1]: this arm's distance to goal at Sense */
   MPC_DBG_PAIRS = 10,      /* unsigned long long [1]: coordination distance queries evaluated */
   MPC_DBG_ARGMIN = 11,     /* int [1]: index of the executed rollout */
-  MPC_DBG_PASSES = 12      /* unsigned long long [3]: per-wave count of distance filter
+  MPC_DBG_PASSES = 12,     /* unsigned long long [3]: per-wave count of distance filter
                               passes over obstacle/neighbour sets, of exact (FP64) passes
                               over such sets, and of exact self-collision passes */
+  MPC_DBG_PRED = 13        /* float [n_arms][horizon][n_rollouts]: learned-distance
+                              prediction against each neighbour (collision mode 1) */
 };
 /* Copy one captured quantity of one arm into dev_out (device). */
 int mpc_debug_get(mpc_ctx *c, int what, int arm, void *dev_out);
@@ -190,6 +192,77 @@ int mpc_profile_enable(mpc_ctx *c, int on);
 /* Total and count of the bracketed rollout-launch durations since the last
  * read; waits for them and clears the record. */
 int mpc_profile_read(mpc_ctx *c, double *total_ms, int *launches);
+
+/* ---- learned arm-pair distance (collision_mode 1) ----
+ *
+ * An MLP 17 -> 256 -> 256 -> 256 -> 1 (ReLU) predicts the signed minimum
+ * sphere distance (Eq. 6) between two arms of the same model from their joint
+ * positions and base offset.  In collision mode 1, every (rollout, step,
+ * neighbour) query whose prediction is at least surrogate_margin (and whose
+ * inputs lie inside the training box) skips the exact sphere-pair check of
+ * the coordination cost (its hinge is taken as zero); every other query is
+ * checked exactly.  The margin must be at least buf_dyn.  Inputs, in the
+ * first arm's base frame: its 7 joints normalised to [-1, 1] by the limits,
+ * the other arm's first joint plus the yaw difference (wrapped, / pi), the
+ * other arm's 6 further normalised joints, and the base offset (metres).
+ * Training uses bfloat16 operands with FP32 accumulation, FP32 master
+ * weights and Adam, on distances the exact kernel generates. */
+typedef struct {
+  int samples;             /* training set size (>= 1024) */
+  int epochs;
+  int batch;               /* 64..65536 */
+  float lr, beta1, beta2, adam_eps;
+  float over_weight;       /* loss = mean (y-t)^2 + over_weight * max(0, y-t)^2 */
+  float target_clip;       /* targets min(rho, clip), metres */
+  float val_fraction;      /* held-out share, [0, 0.5) */
+  unsigned long long seed;
+  float lr_final;          /* step size at the end of the cosine schedule, (0, lr] */
+} mpc_train_params;
+
+typedef struct {
+  float final_loss;        /* mean training loss of the last epoch */
+  float val_mae, val_rmse, val_p99;  /* held-out absolute error statistics, metres */
+  float val_max_over;      /* largest over-prediction (prediction - target) */
+  float val_min_err;       /* most negative error */
+  long long steps;         /* optimiser steps */
+  float seconds;           /* device time of sampling + training + validation */
+} mpc_train_report;
+
+/* Exact signed distance (Eq. 6, min over all sphere pairs) between arm_i at
+ * q_i [m][7] and arm_j at q_j [m][7], at their bases; rho [m].  Device. */
+int mpc_pair_distance(mpc_ctx *c, int arm_i, int arm_j, const float *q_i, const float *q_j, int m, float *rho);
+/* Input features [m][17] of the learned distance for the same queries.  Device. */
+int mpc_pair_features(mpc_ctx *c, int arm_i, int arm_j, const float *q_i, const float *q_j, int m,
+                      float *features);
+/* Draw training samples (every directed arm pair of the context, joints
+ * uniform in the limits, counter-based draws keyed by seed, sample indices
+ * first..first+m-1): features [m][17] (the bfloat16 values the network sees),
+ * targets [m] = min(rho, clip), joints [m][14] (q_i, q_j; may be NULL).  Device. */
+int mpc_surrogate_samples(mpc_ctx *c, unsigned long long seed, long long first, int m, float clip,
+                          float *features, float *targets, float *joints);
+/* Train the network from scratch on freshly drawn samples (weights and biases
+ * uniform in +-1/sqrt(fan_in), Adam, step size on a cosine from lr to
+ * lr_final); waits for the GPU. */
+int mpc_surrogate_train(mpc_ctx *c, const mpc_train_params *tp, mpc_train_report *report);
+/* FP32 parameters [136449], packed per layer as W[out][in] then b[out].  Device. */
+int mpc_surrogate_get_params(mpc_ctx *c, float *params);
+int mpc_surrogate_set_params(mpc_ctx *c, const float *params);
+/* Network output for features [m][17]; y [m].  Device; waits for the GPU. */
+int mpc_surrogate_predict(mpc_ctx *c, const float *features, int m, float *y);
+/* One forward + backward pass of the training dataflow on a batch
+ * (features [B][17], targets [B]): gradient [136449] (device), loss (host). */
+int mpc_surrogate_grad(mpc_ctx *c, const float *features, const float *targets, int B, float over_weight,
+                       float *grad, float *loss);
+/* Switch between exact (0) and learned (1) coordination distances. */
+int mpc_set_collision_mode(mpc_ctx *c, int mode);
+/* Audit: in mode 1 also run the exact check of every query and count the
+ * queries predicted beyond the margin whose exact distance is below buf_dyn
+ * (misses) or below zero (missed collisions). */
+int mpc_surrogate_audit(mpc_ctx *c, int on);
+/* Counters summed over arms since the last reset: out[5] = queries,
+ * predicted beyond the margin, wave-level skips (64 rollouts), misses,
+ * missed collisions.  Waits for the GPU. */
+int mpc_surrogate_stats(mpc_ctx *c, unsigned long long *out, int reset);
 
 /* Device Philox4x32-10 (the noise generator) on n counters: ctr [n][4],
  * key [n][2], out [n][4], all device uint32.  Runs on hip_stream. */

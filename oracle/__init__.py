@@ -120,6 +120,11 @@ def lib():
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_adam.argtypes = [C.c_longlong, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int]
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_bf16.restype = C.c_double
+        L.orc_mlp_loss_grad_bf16.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp, C.c_double, _dp]
+        L.orc_mlp_loss_grad_bf16.restype = C.c_double
+        L.orc_pair_features.argtypes = [C.POINTER(OrcArm), _dp, C.POINTER(OrcArm), _dp, _dp]
         _lib = L
     return _lib
 
@@ -335,6 +340,25 @@ def mlp_loss_grad(widths, params, x, t, over_w):
     loss = lib().orc_mlp_loss_grad(len(widths) - 1, w, _f64(params), x.shape[0], x, _f64(t),
                                    over_w, g)
     return loss, g
+
+
+def bf16(x):
+    return lib().orc_bf16(float(x))
+
+
+def mlp_loss_grad_bf16(widths, params, x, t, over_w):
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    x = _f64(x)
+    g = np.zeros(mlp_param_count(widths))
+    loss = lib().orc_mlp_loss_grad_bf16(len(widths) - 1, w, _f64(params), x.shape[0], x, _f64(t),
+                                        over_w, g)
+    return loss, g
+
+
+def pair_features(oa, qa, oi, qi):
+    f = np.zeros(17)
+    lib().orc_pair_features(C.byref(oa), _f64(qa), C.byref(oi), _f64(qi), f)
+    return f
 
 
 def adam(p, m, v, g, lr, b1, b2, eps, step):

@@ -723,3 +723,98 @@ void orc_adam(long long n, double *p, double *m, double *v, const double *g, dou
     p[i] -= lr * mh / (sqrt(vh) + eps);
   }
 }
+
+/* Round-to-nearest-even to bfloat16 of the FP32 value of x. */
+double orc_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x; /* inf / nan */
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  r &= 0xffff0000u;
+  memcpy(&f, &r, 4);
+  return (double)f;
+}
+
+/* Reduced-precision dataflow of the training kernels (definition above):
+ * Z_l = bf(A_{l-1}) bf(W_l)^T + b_l, A_l = relu(Z_l), y = Z_L;
+ * dZ_L = dy; dW_l = bf(dZ_l)^T bf(A_{l-1}); db_l = sum dZ_l;
+ * dA_{l-1} = bf(dZ_l) bf(W_l); dZ_{l-1} = dA_{l-1} * [Z_{l-1} > 0]. */
+double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
+                              const double *t, double over_w, double *grad) {
+  long long np = orc_mlp_param_count(L, w);
+  memset(grad, 0, sizeof(double) * np);
+  double *pb = (double *)malloc(sizeof(double) * np);
+  for (long long k = 0; k < np; ++k) pb[k] = orc_bf16(params[k]);
+  size_t acts = 0;
+  for (int l = 0; l <= L; ++l) acts += w[l];
+  double *A = (double *)malloc(sizeof(double) * acts), *Z = (double *)malloc(sizeof(double) * acts);
+  double *D = (double *)malloc(sizeof(double) * acts);
+  size_t off[32], po[32];
+  off[0] = 0;
+  for (int l = 0; l < L; ++l) off[l + 1] = off[l] + w[l];
+  po[0] = 0;
+  for (int l = 0; l < L; ++l) po[l + 1] = po[l] + (size_t)w[l + 1] * w[l] + w[l + 1];
+  double loss = 0.0;
+  for (int s = 0; s < B; ++s) {
+    for (int i = 0; i < w[0]; ++i) { A[i] = orc_bf16(x[(size_t)s * w[0] + i]); Z[i] = A[i]; }
+    for (int l = 0; l < L; ++l) {
+      const double *W = pb + po[l], *bb = params + po[l] + (size_t)w[l + 1] * w[l];
+      for (int o = 0; o < w[l + 1]; ++o) {
+        double z = 0.0;
+        for (int i = 0; i < w[l]; ++i) z += W[(size_t)o * w[l] + i] * A[off[l] + i];
+        z += bb[o];
+        Z[off[l + 1] + o] = z;
+        /* hidden activations enter the next product as bfloat16 */
+        A[off[l + 1] + o] = (l + 1 < L) ? orc_bf16(z < 0.0 ? 0.0 : z) : z;
+      }
+    }
+    double e = A[off[L]] - t[s], pos = e > 0.0 ? e : 0.0;
+    loss += e * e + over_w * pos * pos;
+    D[off[L]] = (2.0 * e + 2.0 * over_w * pos) / B;
+    for (int l = L - 1; l >= 0; --l) {
+      const double *W = pb + po[l];
+      double *gW = grad + po[l], *gb = gW + (size_t)w[l + 1] * w[l];
+      for (int o = 0; o < w[l + 1]; ++o) {
+        double dz = D[off[l + 1] + o], dzb = orc_bf16(dz);
+        gb[o] += dz;
+        for (int i = 0; i < w[l]; ++i) gW[(size_t)o * w[l] + i] += dzb * A[off[l] + i];
+      }
+      if (l > 0) {
+        for (int i = 0; i < w[l]; ++i) {
+          double s2 = 0.0;
+          for (int o = 0; o < w[l + 1]; ++o) s2 += W[(size_t)o * w[l] + i] * orc_bf16(D[off[l + 1] + o]);
+          D[off[l] + i] = Z[off[l] + i] > 0.0 ? s2 : 0.0;
+        }
+      }
+    }
+  }
+  free(pb); free(A); free(Z); free(D);
+  return loss / B;
+}
+
+/* Canonical frame of arm a: apply the inverse of a's base transform to both
+ * arms.  Arm a then stands at the origin with no yaw; arm i stands at
+ * Rz(-yaw_a)(b_i - b_a) with yaw yaw_i - yaw_a, and because the first joint
+ * turns about the base z axis (a_0 = alpha_0 = 0), that yaw adds to q_i[0]
+ * (pinned by the base-yaw test of the kinematics). */
+void orc_pair_features(const orc_arm *a, const double *qa, const orc_arm *i, const double *qi, double *f) {
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < 7; ++j) {
+    double mid = 0.5 * (a->qlim[j][0] + a->qlim[j][1]), half = 0.5 * (a->qlim[j][1] - a->qlim[j][0]);
+    f[j] = (qa[j] - mid) / half;
+  }
+  double q0 = qi[0] + (i->base[3] - a->base[3]);
+  q0 = fmod(q0 + pi, 2.0 * pi);
+  if (q0 < 0.0) q0 += 2.0 * pi;
+  f[7] = (q0 - pi) / pi;
+  for (int j = 1; j < 7; ++j) {
+    double mid = 0.5 * (a->qlim[j][0] + a->qlim[j][1]), half = 0.5 * (a->qlim[j][1] - a->qlim[j][0]);
+    f[7 + j] = (qi[j] - mid) / half;
+  }
+  double dx = i->base[0] - a->base[0], dy = i->base[1] - a->base[1], dz = i->base[2] - a->base[2];
+  double c = cos(a->base[3]), s = sin(a->base[3]);
+  f[14] = c * dx + s * dy;
+  f[15] = -s * dx + c * dy;
+  f[16] = dz;
+}

@@ -122,4 +122,16 @@ double orc_mlp_loss_grad(int L, const int *w, const double *params, int B, const
                          const double *t, double over_w, double *grad);
 void orc_adam(long long n, double *p, double *m, double *v, const double *g, double lr,
               double b1, double b2, double eps, int step);
+/* bfloat16 rounding (round to nearest, ties to even) of a double taken as FP32. */
+double orc_bf16(double x);
+/* The same loss and gradient with the reduced-precision training dataflow
+ * written out: every product operand (inputs, weights, hidden activations,
+ * back-propagated deltas) rounded to bfloat16, sums and biases exact. */
+double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
+                              const double *t, double over_w, double *grad);
+/* Input features of the learned distance between arm a at q_a (own) and arm
+ * i at q_i (neighbour), in arm a's base frame: 7 normalised own joints, the
+ * neighbour's first joint plus the yaw difference (wrapped, / pi), its other
+ * 6 normalised joints, and the base offset rotated into arm a's frame. */
+void orc_pair_features(const orc_arm *a, const double *qa, const orc_arm *i, const double *qi, double *f);
 #endif

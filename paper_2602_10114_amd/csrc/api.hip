@@ -12,6 +12,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mrstorm.h"
+#include "surrogate.hpp"
 
 using namespace mrs;
 
@@ -60,6 +61,24 @@ struct mpc_ctx {
   bool profile = false;
   std::vector<hipEvent_t> prof_events;  // pairs (start, end) of recorded rollout launches
   size_t prof_used = 0;
+  // learned arm-pair distance
+  int collision_mode = 0;
+  bool sur_ready = false;              // trained or set parameters present
+  bool sur_audit = false;
+  SurModel hmodel{};
+  SurModel* d_model = nullptr;
+  float* sur_p = nullptr;              // FP32 master parameters
+  float* sur_m = nullptr;              // Adam moments
+  float* sur_v = nullptr;
+  float* sur_g = nullptr;              // gradient
+  uint16_t* sur_p16 = nullptr;         // bfloat16 copy
+  float* sur_Q = nullptr;              // own rollout joints [A][Hmax][Nmax][7]
+  uint8_t* sur_skip = nullptr;         // [A][A][Hmax][Nmax]
+  float* sur_pred = nullptr;           // optional predictions (debug capture)
+  unsigned long long* sur_counts = nullptr;  // [A][5]
+  SurItem* d_sur_items = nullptr;
+  int n_sur_items = 0;
+  int sur_grid = 0;
   std::string err;
   std::vector<void*> allocations;
 };
@@ -117,6 +136,7 @@ static int build_arm(mpc_ctx* c, const mpc_arm_desc& d, int layout, DevArm& o) {
   o.base[0] = d.base[0];
   o.base[1] = d.base[1];
   o.base[2] = d.base[2];
+  o.base[3] = d.base[3];  // yaw (the learned distance's canonical frame)
   o.cyaw = (float)std::cos((double)d.base[3]);
   o.syaw = (float)std::sin((double)d.base[3]);
   o.tool[0] = d.tool[0];
@@ -206,7 +226,9 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (p->iters < 1 || p->iters > 8) return fail(nullptr, MPC_EINVAL, "iters outside 1..8");
   if (p->max_obstacles < 0 || p->max_obstacles > MPC_MAX_OBSTACLES)
     return fail(nullptr, MPC_EINVAL, "max_obstacles outside 0..64");
-  if (p->collision_mode != 0) return fail(nullptr, MPC_EUNSUPPORTED, "collision_mode 1 needs a trained distance model");
+  if (p->collision_mode != 0 && p->collision_mode != 1) return fail(nullptr, MPC_EINVAL, "collision_mode must be 0 or 1");
+  if (p->collision_mode == 1 && !(p->surrogate_margin >= p->buf_dyn))
+    return fail(nullptr, MPC_EINVAL, "surrogate_margin must be at least buf_dyn");
 
   mpc_ctx* c = new mpc_ctx();
   c->A = n_arms;
@@ -263,6 +285,28 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (hipMemcpy(c->d_arms, c->harms.data(), A * sizeof(DevArm), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_P, &c->P, sizeof(Params), hipMemcpyHostToDevice) != hipSuccess) {
     fail(c, MPC_EHIP, "upload of arm tables failed");
+    mpc_destroy(c);
+    return MPC_EHIP;
+  }
+  // Learned-distance model state: joint normalisation of the (shared) arm
+  // model, parameters and the per-step buffers.
+  c->collision_mode = p->collision_mode;
+  for (int j = 0; j < 7; ++j) {
+    const double lo = arms[0].q_lim[2 * j], hi = arms[0].q_lim[2 * j + 1];
+    c->hmodel.mid[j] = (float)(0.5 * (lo + hi));
+    c->hmodel.inv_half[j] = (float)(hi > lo ? 2.0 / (hi - lo) : 1.0);
+  }
+  c->hmodel.margin = p->surrogate_margin > 0.f ? p->surrogate_margin : p->buf_dyn;
+  if ((rc = dalloc(c, &c->d_model, 1)) || (rc = dalloc(c, &c->sur_p, (size_t)kMlpParams)) ||
+      (rc = dalloc(c, &c->sur_m, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_v, (size_t)kMlpParams)) ||
+      (rc = dalloc(c, &c->sur_g, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_p16, (size_t)kMlpParams)) ||
+      (rc = dalloc(c, &c->sur_counts, 5 * A))) {
+    g_last_error = c->err;
+    mpc_destroy(c);
+    return rc;
+  }
+  if (hipMemcpy(c->d_model, &c->hmodel, sizeof(SurModel), hipMemcpyHostToDevice) != hipSuccess) {
+    fail(c, MPC_EHIP, "upload of the distance model failed");
     mpc_destroy(c);
     return MPC_EHIP;
   }
@@ -326,6 +370,9 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.dbg_sph = c->dbg_sph;
   R.dbg_stage = c->dbg_stage;
   R.dbg_pairs = c->dbg_pairs;
+  R.skip = c->collision_mode == 1 ? c->sur_skip : nullptr;
+  R.audit = c->sur_audit ? 1 : 0;
+  R.sur_counts = c->sur_counts;
   return R;
 }
 
@@ -424,6 +471,26 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
   ReduceArgs Rr = reduce_args(c);
   for (int k = 0; k < c->P.iters; ++k) {
     RolloutArgs R = rollout_args(c, k);
+    if (c->collision_mode == 1) {
+      // Learned distance: own joints of every rollout step, then the MLP's
+      // skip decision per (rollout, step, neighbour).
+      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, k, c->A, c->Nmax, c->sur_Q,
+                                  c->stream));
+      SurInferArgs I{};
+      I.arms = c->d_arms;
+      I.P = c->d_P;
+      I.model = c->d_model;
+      I.meta = c->d_meta;
+      I.W16 = c->sur_p16;
+      I.P32 = c->sur_p;
+      I.Q = c->sur_Q;
+      I.planq = c->planq[0];
+      I.items = c->d_sur_items;
+      I.n_items = c->n_sur_items;
+      I.skip = c->sur_skip;
+      I.pred = debug ? c->sur_pred : nullptr;
+      HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
+    }
     hipEvent_t e1 = nullptr;
     if (c->profile) {
       while (c->prof_events.size() < c->prof_used + 2) {
@@ -441,6 +508,32 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
     HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->stream));
   }
   HIPCHK(c, launch_toplan(Rr, c->A, c->stream));
+  return MPC_OK;
+}
+
+// Per-step buffers of the learned distance and its work items: every
+// (arm, neighbour, step within both horizons, 32-rollout block).
+static int ensure_sur_buffers(mpc_ctx* c) {
+  if (c->sur_Q) return MPC_OK;
+  const size_t A = c->A, H = c->Hmax, N = c->Nmax;
+  int rc;
+  if ((rc = dalloc(c, &c->sur_Q, A * H * N * 7)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
+      (rc = dalloc(c, &c->sur_pred, A * A * H * N)))
+    return rc;
+  std::vector<SurItem> items;
+  for (int a = 0; a < c->A; ++a)
+    for (int i = 0; i < c->A; ++i) {
+      if (i == a) continue;
+      const int H2 = std::min(c->harms[a].H, c->harms[i].H);
+      for (int h = 0; h < H2; ++h)
+        for (int n0 = 0; n0 < c->harms[a].Npad; n0 += 32) items.push_back(SurItem{a, i, h, n0});
+    }
+  c->n_sur_items = (int)items.size();
+  if (!items.empty()) {
+    if ((rc = dalloc(c, &c->d_sur_items, items.size()))) return rc;
+    HIPCHK(c, hipMemcpy(c->d_sur_items, items.data(), items.size() * sizeof(SurItem), hipMemcpyHostToDevice));
+  }
+  c->sur_grid = std::max(1, std::min((c->n_sur_items + 7) / 8, 1024));
   return MPC_OK;
 }
 
@@ -469,6 +562,11 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
   if (n_obstacles < 0 || n_obstacles > c->P.max_obs)
     return fail(c, MPC_EINVAL, "n_obstacles outside [0, max_obstacles]");
   if (n_obstacles > 0 && !obstacles) return fail(c, MPC_EINVAL, "obstacles is NULL");
+  if (c->collision_mode == 1) {
+    if (!c->sur_ready) return fail(c, MPC_ESTATE, "collision mode 1 needs trained or set distance-model parameters");
+    const int rc0 = ensure_sur_buffers(c);
+    if (rc0) return rc0;
+  }
   SenseArgs S{};
   S.arms = c->d_arms;
   S.P = c->d_P;
@@ -622,6 +720,11 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
     case MPC_DBG_PAIRS:
       HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + 4 * arm, sizeof(unsigned long long), hipMemcpyDeviceToDevice, c->stream));
       break;
+    case MPC_DBG_PRED:
+      if (!c->sur_pred) return fail(c, MPC_ESTATE, "no learned-distance step has run");
+      HIPCHK(c, launch_copy3d(c->sur_pred + (size_t)arm * c->A * H * N, H * N, N, 1, out, (long long)d.H * d.N, d.N,
+                              1, c->A, d.H, d.N, c->stream));
+      break;
     case MPC_DBG_PASSES:
       HIPCHK(c, hipMemcpyAsync(out, c->dbg_pairs + 4 * arm + 1, 3 * sizeof(unsigned long long),
                                hipMemcpyDeviceToDevice, c->stream));
@@ -745,5 +848,385 @@ extern "C" int mpc_philox(const unsigned int* ctr, const unsigned int* key, unsi
   if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(nullptr, MPC_EINVAL, "bad philox arguments");
   hipError_t e = launch_philox(ctr, key, out, n, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(nullptr, MPC_EHIP, hipGetErrorString(e));
+  return MPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned arm-pair distance: exact distance, features, training, parameters.
+
+static int check_shared_model(mpc_ctx* c) {
+  for (int a = 0; a < c->A; ++a) {
+    const DevArm& x = c->harms[a];
+    const DevArm& y = c->harms[0];
+    if (x.a[0] != 0.f || x.sal[0] != 0.f)
+      return fail(c, MPC_EUNSUPPORTED, "the learned distance needs a first joint about the base z axis");
+    if (memcmp(x.a, y.a, sizeof(x.a)) || memcmp(x.cal, y.cal, sizeof(x.cal)) || memcmp(x.sal, y.sal, sizeof(x.sal)) ||
+        memcmp(x.d, y.d, sizeof(x.d)) || memcmp(x.off, y.off, sizeof(x.off)) ||
+        memcmp(x.slot, y.slot, sizeof(x.slot)) || memcmp(x.qlo, y.qlo, sizeof(x.qlo)) ||
+        memcmp(x.qhi, y.qhi, sizeof(x.qhi)))
+      return fail(c, MPC_EUNSUPPORTED, "the learned distance needs every arm to be the same model");
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_pair_distance(mpc_ctx* c, int arm_i, int arm_j, const float* q_i, const float* q_j, int m,
+                                 float* rho) {
+  if (!c) return MPC_EINVAL;
+  if (arm_i < 0 || arm_i >= c->A || arm_j < 0 || arm_j >= c->A || m < 0 || (m > 0 && (!q_i || !q_j || !rho)))
+    return fail(c, MPC_EINVAL, "bad pair-distance arguments");
+  HIPCHK(c, launch_pair_distance(c->layout, c->d_arms, arm_i, arm_j, q_i, q_j, m, rho, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_pair_features(mpc_ctx* c, int arm_i, int arm_j, const float* q_i, const float* q_j, int m,
+                                 float* features) {
+  if (!c) return MPC_EINVAL;
+  if (arm_i < 0 || arm_i >= c->A || arm_j < 0 || arm_j >= c->A || m < 0 || (m > 0 && (!q_i || !q_j || !features)))
+    return fail(c, MPC_EINVAL, "bad feature arguments");
+  HIPCHK(c, launch_features(c->d_arms, c->d_model, arm_i, arm_j, q_i, q_j, m, features, c->stream));
+  return MPC_OK;
+}
+
+// Scratch of one forward + backward pass over a batch of B samples.
+struct MlpScratch {
+  size_t B = 0;
+  float *Z[3] = {nullptr, nullptr, nullptr}, *y = nullptr, *dy = nullptr, *dZ = nullptr, *loss = nullptr;
+  uint16_t *A16[3] = {nullptr, nullptr, nullptr}, *dy16 = nullptr, *dZ16 = nullptr, *X16 = nullptr;
+  std::vector<void*> mem;
+  ~MlpScratch() {
+    for (void* p : mem) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t get(T** p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+    if (e == hipSuccess) {
+      mem.push_back(q);
+      *p = static_cast<T*>(q);
+    }
+    return e;
+  }
+  hipError_t alloc(size_t b) {
+    B = b;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+      e = get(&Z[l], B * kHid);
+      if (e == hipSuccess) e = get(&A16[l], B * kHid);
+    }
+    if (e == hipSuccess) e = get(&y, B);
+    if (e == hipSuccess) e = get(&dy, B);
+    if (e == hipSuccess) e = get(&dy16, B);
+    if (e == hipSuccess) e = get(&dZ, B * kHid);
+    if (e == hipSuccess) e = get(&dZ16, B * kHid);
+    if (e == hipSuccess) e = get(&loss, 1);
+    if (e == hipSuccess) e = get(&X16, B * kFeat);
+    return e;
+  }
+};
+
+static GemmArgs gemm(int M, int N, int K, const uint16_t* A, int lda, int ta, const uint16_t* B, int ldb, int tb) {
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.transA = ta;
+  g.B = B; g.ldb = ldb; g.transB = tb;
+  return g;
+}
+
+// Forward pass of B samples (X16 [B][17]) with the bfloat16 parameters:
+// Z_l = bf(A_{l-1}) bf(W_l)^T + b_l, A_l = bf(relu(Z_l)), y = Z_4.
+static hipError_t mlp_forward(mpc_ctx* c, MlpScratch& S, const uint16_t* X16, int B) {
+  const uint16_t* in = X16;
+  int K = kFeat;
+  for (int l = 0; l < 3; ++l) {
+    GemmArgs g = gemm(B, kHid, K, in, K, 0, c->sur_p16 + mlp_w_off(l), K, 1);
+    g.bias = c->sur_p + mlp_b_off(l);
+    g.C32 = S.Z[l]; g.ldc = kHid;
+    g.C16 = S.A16[l]; g.ldc16 = kHid; g.relu = 1;
+    hipError_t e = launch_gemm_bf16(g, c->stream);
+    if (e != hipSuccess) return e;
+    in = S.A16[l];
+    K = kHid;
+  }
+  GemmArgs g = gemm(B, 1, kHid, in, kHid, 0, c->sur_p16 + mlp_w_off(3), kHid, 1);
+  g.bias = c->sur_p + mlp_b_off(3);
+  g.C32 = S.y; g.ldc = 1;
+  return launch_gemm_bf16(g, c->stream);
+}
+
+// Backward pass into c->sur_g (after mlp_forward and the loss):
+// dW_l = bf(dZ_l)^T bf(A_{l-1}), db_l = sum dZ_l, dZ_{l-1} = (bf(dZ_l) bf(W_l)) * [Z_{l-1} > 0].
+static hipError_t mlp_backward(mpc_ctx* c, MlpScratch& S, const uint16_t* X16, int B) {
+  hipError_t e;
+  // output layer
+  GemmArgs g = gemm(1, kHid, B, S.dy16, 1, 1, S.A16[2], kHid, 0);
+  g.C32 = c->sur_g + mlp_w_off(3); g.ldc = kHid;
+  if ((e = launch_gemm_bf16(g, c->stream)) != hipSuccess) return e;
+  if ((e = launch_colsum(S.dy, B, 1, c->sur_g + mlp_b_off(3), c->stream)) != hipSuccess) return e;
+  g = gemm(B, kHid, 1, S.dy16, 1, 0, c->sur_p16 + mlp_w_off(3), kHid, 0);
+  g.mask = S.Z[2]; g.ldm = kHid;
+  g.C32 = S.dZ; g.ldc = kHid; g.C16 = S.dZ16; g.ldc16 = kHid;
+  if ((e = launch_gemm_bf16(g, c->stream)) != hipSuccess) return e;
+  for (int l = 2; l >= 0; --l) {
+    const uint16_t* in = l > 0 ? S.A16[l - 1] : X16;
+    const int K = l > 0 ? kHid : kFeat;
+    g = gemm(kHid, K, B, S.dZ16, kHid, 1, in, K, 0);
+    g.C32 = c->sur_g + mlp_w_off(l); g.ldc = K;
+    if ((e = launch_gemm_bf16(g, c->stream)) != hipSuccess) return e;
+    if ((e = launch_colsum(S.dZ, B, kHid, c->sur_g + mlp_b_off(l), c->stream)) != hipSuccess) return e;
+    if (l > 0) {
+      // dZ16 is read by this product and rewritten by it: stage through dZ first.
+      g = gemm(B, kHid, kHid, S.dZ16, kHid, 0, c->sur_p16 + mlp_w_off(l), kHid, 0);
+      g.mask = S.Z[l - 1]; g.ldm = kHid;
+      g.C32 = S.dZ; g.ldc = kHid;
+      if ((e = launch_gemm_bf16(g, c->stream)) != hipSuccess) return e;
+      if ((e = launch_f32_to_bf16(S.dZ, S.dZ16, (long long)B * kHid, c->stream)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+extern "C" int mpc_surrogate_grad(mpc_ctx* c, const float* features, const float* targets, int B, float over_w,
+                                  float* grad, float* loss) {
+  if (!c) return MPC_EINVAL;
+  if (B < 1 || !features || !targets || !grad) return fail(c, MPC_EINVAL, "bad gradient arguments");
+  MlpScratch S;
+  HIPCHK(c, S.alloc((size_t)B));
+  HIPCHK(c, launch_f32_to_bf16(features, S.X16, (long long)B * kFeat, c->stream));
+  HIPCHK(c, hipMemsetAsync(S.loss, 0, sizeof(float), c->stream));
+  HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  HIPCHK(c, mlp_forward(c, S, S.X16, B));
+  HIPCHK(c, launch_loss(S.y, targets, B, over_w, S.dy, S.dy16, S.loss, c->stream));
+  HIPCHK(c, mlp_backward(c, S, S.X16, B));
+  HIPCHK(c, hipMemcpyAsync(grad, c->sur_g, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, c->stream));
+  float l = 0.f;
+  HIPCHK(c, hipMemcpyAsync(&l, S.loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = l;
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_predict(mpc_ctx* c, const float* features, int m, float* y) {
+  if (!c) return MPC_EINVAL;
+  if (m < 0 || (m > 0 && (!features || !y))) return fail(c, MPC_EINVAL, "bad prediction arguments");
+  const int chunk = 65536;
+  MlpScratch S;
+  HIPCHK(c, S.alloc((size_t)std::min(m, chunk)));
+  HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  for (int m0 = 0; m0 < m; m0 += chunk) {
+    const int b = std::min(chunk, m - m0);
+    HIPCHK(c, launch_f32_to_bf16(features + (size_t)m0 * kFeat, S.X16, (long long)b * kFeat, c->stream));
+    HIPCHK(c, mlp_forward(c, S, S.X16, b));
+    HIPCHK(c, hipMemcpyAsync(y + m0, S.y, sizeof(float) * b, hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_get_params(mpc_ctx* c, float* params) {
+  if (!c || !params) return MPC_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(params, c->sur_p, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_set_params(mpc_ctx* c, const float* params) {
+  if (!c || !params) return MPC_EINVAL;
+  int rc = check_shared_model(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->sur_p, params, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  c->sur_ready = true;
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_train_report* rep) {
+  if (!c || !tp) return MPC_EINVAL;
+  if (c->A < 2) return fail(c, MPC_EINVAL, "the learned distance needs at least two arms");
+  if (tp->samples < 1024 || tp->batch < 64 || tp->batch > 65536 || tp->epochs < 1 ||
+      !(tp->val_fraction >= 0.f && tp->val_fraction < 0.5f) || !(tp->lr > 0.f) ||
+      !(tp->lr_final > 0.f && tp->lr_final <= tp->lr))
+    return fail(c, MPC_EINVAL, "bad training parameters");
+  int rc = check_shared_model(c);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  const int M = tp->samples;
+  const int n_val = (int)(M * tp->val_fraction);
+  const int n_train = M - n_val;
+  const int B = tp->batch;
+  // Training set: every directed arm pair of this context, joints uniform in the limits.
+  std::vector<int> pairs;
+  for (int a = 0; a < c->A; ++a)
+    for (int i = 0; i < c->A; ++i)
+      if (i != a) {
+        pairs.push_back(a);
+        pairs.push_back(i);
+      }
+  MlpScratch S;
+  HIPCHK(c, S.alloc((size_t)B));
+  uint16_t* X16 = nullptr;
+  float* T = nullptr;
+  int* d_pairs = nullptr;
+  HIPCHK(c, S.get(&X16, (size_t)M * kFeat));
+  HIPCHK(c, S.get(&T, (size_t)M));
+  HIPCHK(c, S.get(&d_pairs, pairs.size()));
+  HIPCHK(c, hipMemcpy(d_pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice));
+  const uint32_t slo = (uint32_t)(tp->seed & 0xffffffffull), shi = (uint32_t)(tp->seed >> 32);
+  for (int m0 = 0; m0 < M; m0 += (1 << 20)) {
+    const int n = std::min(1 << 20, M - m0);
+    HIPCHK(c, launch_sur_sample_layout(c->layout, c->d_arms, c->d_model, d_pairs, (int)pairs.size() / 2, slo, shi,
+                                       m0, n, tp->target_clip, X16 + (size_t)m0 * kFeat, T + m0, nullptr,
+                                       c->stream));
+  }
+  // Parameters uniform in +-1/sqrt(fan_in), zero Adam moments.
+  HIPCHK(c, launch_init_params(c->sur_p, slo ^ 0x9E3779B9u, shi, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->sur_m, 0, sizeof(float) * kMlpParams, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->sur_v, 0, sizeof(float) * kMlpParams, c->stream));
+  HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  long long step = 0;
+  float last_loss = 0.f;
+  const int nb = n_train / B;
+  for (int ep = 0; ep < tp->epochs; ++ep) {
+    HIPCHK(c, hipMemsetAsync(S.loss, 0, sizeof(float), c->stream));
+    for (int b = 0; b < nb; ++b) {
+      const uint16_t* xb = X16 + (size_t)b * B * kFeat;
+      HIPCHK(c, mlp_forward(c, S, xb, B));
+      HIPCHK(c, launch_loss(S.y, T + (size_t)b * B, B, tp->over_weight, S.dy, S.dy16, S.loss, c->stream));
+      HIPCHK(c, mlp_backward(c, S, xb, B));
+      ++step;
+      // step size: cosine from lr to lr_final over the run
+      const double total = (double)tp->epochs * nb;
+      const double cw = 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / total));
+      const float lr_t = (float)(tp->lr_final + (tp->lr - tp->lr_final) * cw);
+      HIPCHK(c, launch_adam(c->sur_p, c->sur_m, c->sur_v, c->sur_g, kMlpParams, lr_t, tp->beta1, tp->beta2,
+                            tp->adam_eps, (int)std::min<long long>(step, 1 << 30), c->stream));
+      HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+    }
+    float l = 0.f;
+    HIPCHK(c, hipMemcpyAsync(&l, S.loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    last_loss = nb > 0 ? l / nb : 0.f;
+  }
+  // Held-out error of the trained network (same bfloat16 dataflow).
+  float mae = 0.f, rmse = 0.f, p99 = 0.f, max_over = 0.f, min_err = 0.f;
+  if (n_val > 0) {
+    std::vector<float> pred(n_val), tgt(n_val);
+    float* yv = nullptr;
+    HIPCHK(c, S.get(&yv, (size_t)n_val));
+    for (int m0 = 0; m0 < n_val; m0 += B) {
+      const int b = std::min(B, n_val - m0);
+      HIPCHK(c, mlp_forward(c, S, X16 + (size_t)(n_train + m0) * kFeat, b));
+      HIPCHK(c, hipMemcpyAsync(yv + m0, S.y, sizeof(float) * b, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(pred.data(), yv, sizeof(float) * n_val, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(tgt.data(), T + n_train, sizeof(float) * n_val, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<float> ae(n_val);
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < n_val; ++i) {
+      const float e = pred[i] - tgt[i];
+      ae[i] = std::fabs(e);
+      s1 += ae[i];
+      s2 += (double)e * e;
+      max_over = std::max(max_over, e);
+      min_err = std::min(min_err, e);
+    }
+    std::sort(ae.begin(), ae.end());
+    mae = (float)(s1 / n_val);
+    rmse = (float)std::sqrt(s2 / n_val);
+    p99 = ae[(size_t)(0.99 * (n_val - 1))];
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->sur_ready = true;
+  if (rep) {
+    rep->final_loss = last_loss;
+    rep->val_mae = mae;
+    rep->val_rmse = rmse;
+    rep->val_p99 = p99;
+    rep->val_max_over = max_over;
+    rep->val_min_err = min_err;
+    rep->steps = step;
+    rep->seconds = ms * 1e-3f;
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_samples(mpc_ctx* c, unsigned long long seed, long long first, int m, float clip,
+                                     float* features, float* targets, float* joints) {
+  if (!c) return MPC_EINVAL;
+  if (c->A < 2 || m < 0 || (m > 0 && (!features || !targets)))
+    return fail(c, MPC_EINVAL, "bad sample arguments");
+  int rc = check_shared_model(c);
+  if (rc) return rc;
+  std::vector<int> pairs;
+  for (int a = 0; a < c->A; ++a)
+    for (int i = 0; i < c->A; ++i)
+      if (i != a) {
+        pairs.push_back(a);
+        pairs.push_back(i);
+      }
+  MlpScratch S;
+  int* d_pairs = nullptr;
+  uint16_t* X16 = nullptr;
+  HIPCHK(c, S.get(&d_pairs, pairs.size()));
+  HIPCHK(c, S.get(&X16, (size_t)m * kFeat));
+  HIPCHK(c, hipMemcpy(d_pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(c, launch_sur_sample_layout(c->layout, c->d_arms, c->d_model, d_pairs, (int)pairs.size() / 2,
+                                     (uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32), first, m, clip, X16,
+                                     targets, joints, c->stream));
+  // features back to FP32 (they are exactly the bfloat16 values the network sees)
+  std::vector<uint16_t> h((size_t)m * kFeat);
+  std::vector<float> f((size_t)m * kFeat);
+  HIPCHK(c, hipMemcpyAsync(h.data(), X16, h.size() * 2, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < h.size(); ++i) {
+    const uint32_t u = (uint32_t)h[i] << 16;
+    memcpy(&f[i], &u, 4);
+  }
+  HIPCHK(c, hipMemcpy(features, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  return MPC_OK;
+}
+
+extern "C" int mpc_set_collision_mode(mpc_ctx* c, int mode) {
+  if (!c) return MPC_EINVAL;
+  if (mode != 0 && mode != 1) return fail(c, MPC_EINVAL, "mode must be 0 or 1");
+  if (mode == 1) {
+    int rc = check_shared_model(c);
+    if (rc) return rc;
+  }
+  if (mode != c->collision_mode) {
+    c->collision_mode = mode;
+    c->tuned = false;  // re-tune and re-capture for the new step body
+    c->n_items = 0;
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_audit(mpc_ctx* c, int on) {
+  if (!c) return MPC_EINVAL;
+  if ((on != 0) != c->sur_audit) {
+    c->sur_audit = on != 0;
+    c->tuned = false;
+    c->n_items = 0;
+  }
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_stats(mpc_ctx* c, unsigned long long* out, int reset) {
+  if (!c || !out) return MPC_EINVAL;
+  std::vector<unsigned long long> h(5 * c->A);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(h.data(), c->sur_counts, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  for (int k = 0; k < 5; ++k) {
+    out[k] = 0;
+    for (int a = 0; a < c->A; ++a) out[k] += h[5 * a + k];
+  }
+  if (reset) HIPCHK(c, hipMemset(c->sur_counts, 0, h.size() * sizeof(unsigned long long)));
   return MPC_OK;
 }

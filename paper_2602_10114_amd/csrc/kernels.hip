@@ -33,7 +33,7 @@ struct LdsSets {
   float4 raw[kLdsSpheres];
   float F[kLdsSpheres];
   float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
-  int set_k0[kMaxSets], set_n[kMaxSets];
+  int set_k0[kMaxSets], set_n[kMaxSets], set_arm[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
 };
 
@@ -345,6 +345,9 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
     float acc = 0.f;
     unsigned long long pairs = 0;
     unsigned set_passes = 0, set_refines = 0, self_refines = 0;
+    // learned-distance counters: queries, predicted far, waves skipped,
+    // audited misses (exact gap < B), audited missed collisions (gap < 0)
+    unsigned sq = 0, sf = 0, sw = 0, sm1 = 0, sm2 = 0;
     for (int h = item.h0; h < item.h1; ++h) {
       float z[8];
       normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
@@ -368,6 +371,7 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
         if (lane == 0) {
           L.set_k0[0] = 0;
           L.set_n[0] = n_obs;
+          L.set_arm[0] = -1;
           L.set_buf[0] = P.buf_env;
           L.set_wt[0] = P.w_coll;
         }
@@ -383,6 +387,7 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
           if (lane == 0) {
             L.set_k0[nsets] = off;
             L.set_n[nsets] = nb.S;
+            L.set_arm[nsets] = nb.arm;
             L.set_buf[nsets] = P.buf_dyn;
             L.set_wt[nsets] = P.w_dyn * nb.alpha;
           }
@@ -432,6 +437,18 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
         const int k0 = L.set_k0[si], K = L.set_n[si];
+        // Learned distance: a neighbour predicted beyond the margin skips the
+        // exact check (all lanes of the wave, or its hinge is taken as 0).
+        bool sk = false;
+        if (A.skip && L.set_arm[si] >= 0) {
+          sk = A.skip[(((size_t)a * P.A + L.set_arm[si]) * P.Hmax + h) * P.Nmax + n] != 0;
+          sq += live ? 1u : 0u;
+          sf += (live && sk) ? 1u : 0u;
+          if (!A.audit && __ballot(sk) == ~0ull) {
+            ++sw;
+            continue;
+          }
+        }
         unsigned nearb = 0;
         {
           Frame W;
@@ -446,7 +463,12 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
           Frame W;
           frame_base(W, arm);
           set_refine<LAY, 0>(W, arm, C, L, k0, K, nearb, best);
-          const float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
+          float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
+          if (sk) {
+            if (live && near && best < (double)L.set_buf[si]) ++sm1;
+            if (live && near && best < 0.0) ++sm2;
+            hv = 0.f;
+          }
           c = fmaf_(L.set_wt[si], hv, c);
         }
       }
@@ -479,6 +501,19 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
     }
     if (live) A.partial[((size_t)a * kMaxH + item.h0 / A.h_tile) * P.Nmax + n] = acc;
     if (DBG && live) atomicAdd(A.dbg_pairs + 4 * a, pairs);
+    if (A.skip) {
+      // wave sums of the lane counters, one atomic per counter
+      unsigned v[5] = {sq, sf, sw, sm1, sm2};
+#pragma unroll
+      for (int c2 = 0; c2 < 5; ++c2) {
+        unsigned x = v[c2];
+        if (c2 != 2) {  // the skipped-wave count is already a per-wave value
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        }
+        if (lane == 0 && x) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)x);
+      }
+    }
     if (DBG && lane == 0) {
       atomicAdd(A.dbg_pairs + 4 * a + 1, (unsigned long long)set_passes);
       atomicAdd(A.dbg_pairs + 4 * a + 2, (unsigned long long)set_refines);

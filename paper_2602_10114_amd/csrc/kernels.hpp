@@ -30,6 +30,11 @@ struct RolloutArgs {
   float* dbg_sph;              // [A][Nmax][Hmax][Smax][4]
   float* dbg_stage;            // [A][Hmax][Nmax]
   unsigned long long* dbg_pairs;  // [A][4]: queries, set filter passes, set exact passes, self exact passes (per wave)
+  // learned distance (collision mode 1): skip mask [A][A][Hmax][Nmax] and counters [A][5]
+  const uint8_t* skip;
+  int audit;
+  int pad2;
+  unsigned long long* sur_counts;
 };
 
 struct SenseArgs {

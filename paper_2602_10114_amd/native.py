@@ -17,12 +17,17 @@ LIB_PATH = os.path.join(HERE, "libmrstorm.so")
 
 MPC_OK, MPC_EINVAL, MPC_ENOMEM, MPC_EHIP, MPC_ESTATE, MPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DBG = dict(NOISE=0, Q=1, QD=2, SPHERES=3, STAGE_COST=4, COST=5, WEIGHTS=6, MEAN=7, ALPHA=8,
-           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12)
+           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12, PRED=13)
 EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destroy",
            "mpc_last_error", "mpc_sync", "mpc_debug_enable", "mpc_debug_get", "mpc_get_board",
            "mpc_set_board", "mpc_set_mean", "mpc_get_step", "mpc_set_step", "mpc_sim_execute",
            "mpc_get_tuning", "mpc_set_tuning", "mpc_philox", "mpc_profile_enable",
-           "mpc_profile_read"]
+           "mpc_profile_read", "mpc_pair_distance", "mpc_pair_features", "mpc_surrogate_samples",
+           "mpc_surrogate_train", "mpc_surrogate_get_params", "mpc_surrogate_set_params",
+           "mpc_surrogate_predict", "mpc_surrogate_grad", "mpc_set_collision_mode",
+           "mpc_surrogate_audit", "mpc_surrogate_stats"]
+MLP_WIDTHS = [17, 256, 256, 256, 1]
+MLP_PARAMS = 136449
 
 
 class MpcError(RuntimeError):
@@ -36,6 +41,19 @@ class MpcArmDesc(C.Structure):
                 ("dh", C.POINTER(C.c_float)), ("q_lim", C.POINTER(C.c_float)),
                 ("qd_max", C.POINTER(C.c_float)), ("spheres", C.POINTER(C.c_float)),
                 ("sphere_link", C.POINTER(C.c_int)), ("base", C.c_float * 4), ("tool", C.c_float * 3)]
+
+
+class MpcTrainParams(C.Structure):
+    _fields_ = [("samples", C.c_int), ("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
+                ("over_weight", C.c_float), ("target_clip", C.c_float), ("val_fraction", C.c_float),
+                ("seed", C.c_ulonglong), ("lr_final", C.c_float)]
+
+
+class MpcTrainReport(C.Structure):
+    _fields_ = [("final_loss", C.c_float), ("val_mae", C.c_float), ("val_rmse", C.c_float),
+                ("val_p99", C.c_float), ("val_max_over", C.c_float), ("val_min_err", C.c_float),
+                ("steps", C.c_longlong), ("seconds", C.c_float)]
 
 
 class MpcParams(C.Structure):
@@ -81,6 +99,17 @@ def lib():
         L.mpc_get_tuning.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
         L.mpc_set_tuning.argtypes = [vp, ip, ip, ip]
         L.mpc_philox.argtypes = [vp, vp, vp, ip, vp]
+        L.mpc_pair_distance.argtypes = [vp, ip, ip, vp, vp, ip, vp]
+        L.mpc_pair_features.argtypes = [vp, ip, ip, vp, vp, ip, vp]
+        L.mpc_surrogate_samples.argtypes = [vp, C.c_ulonglong, C.c_longlong, ip, fp, vp, vp, vp]
+        L.mpc_surrogate_train.argtypes = [vp, C.POINTER(MpcTrainParams), C.POINTER(MpcTrainReport)]
+        L.mpc_surrogate_get_params.argtypes = [vp, vp]
+        L.mpc_surrogate_set_params.argtypes = [vp, vp]
+        L.mpc_surrogate_predict.argtypes = [vp, vp, ip, vp]
+        L.mpc_surrogate_grad.argtypes = [vp, vp, vp, ip, fp, vp, C.POINTER(fp)]
+        L.mpc_set_collision_mode.argtypes = [vp, ip]
+        L.mpc_surrogate_audit.argtypes = [vp, ip]
+        L.mpc_surrogate_stats.argtypes = [vp, vp, ip]
         L.mpc_profile_enable.argtypes = [vp, ip]
         L.mpc_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ip)]
         _lib = L
@@ -201,7 +230,7 @@ class Controller:
         t = self.torch
         shapes = dict(NOISE=(H, 7, N), Q=(N, H, 7), QD=(N, H, 7), SPHERES=(N, H, S, 4),
                       STAGE_COST=(H, N), COST=(N,), WEIGHTS=(N,), MEAN=(H, 7), ALPHA=(self.A,),
-                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,))
+                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,), PRED=(self.A, H, N))
         dtype = dict(PAIRS=t.int64, ARGMIN=t.int32, PASSES=t.int64).get(what, t.float32)
         out = t.empty(shapes[what], dtype=dtype, device=self.dev)
         _check(lib().mpc_debug_get(self.h, DBG[what], arm, _ptr(out)), self.h)
@@ -255,6 +284,76 @@ class Controller:
         ms, n = C.c_double(), C.c_int()
         _check(lib().mpc_profile_read(self.h, C.byref(ms), C.byref(n)), self.h)
         return ms.value, n.value
+
+
+    # ---- learned arm-pair distance ----
+    def pair_distance(self, arm_i, arm_j, q_i, q_j):
+        q_i, q_j = self._f32(q_i), self._f32(q_j)
+        m = int(q_i.shape[0])
+        out = self.torch.empty(m, dtype=self.torch.float32, device=self.dev)
+        _check(lib().mpc_pair_distance(self.h, arm_i, arm_j, _ptr(q_i), _ptr(q_j), m, _ptr(out)), self.h)
+        return out
+
+    def pair_features(self, arm_i, arm_j, q_i, q_j):
+        q_i, q_j = self._f32(q_i), self._f32(q_j)
+        m = int(q_i.shape[0])
+        out = self.torch.empty((m, 17), dtype=self.torch.float32, device=self.dev)
+        _check(lib().mpc_pair_features(self.h, arm_i, arm_j, _ptr(q_i), _ptr(q_j), m, _ptr(out)), self.h)
+        return out
+
+    def surrogate_samples(self, seed, first, m, clip=0.5):
+        t = self.torch
+        f = t.empty((m, 17), dtype=t.float32, device=self.dev)
+        y = t.empty(m, dtype=t.float32, device=self.dev)
+        q = t.empty((m, 14), dtype=t.float32, device=self.dev)
+        _check(lib().mpc_surrogate_samples(self.h, int(seed), int(first), m, float(clip), _ptr(f), _ptr(y),
+                                           _ptr(q)), self.h)
+        return f, y, q
+
+    def surrogate_train(self, samples=2_000_000, epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
+                        adam_eps=1e-8, over_weight=4.0, target_clip=0.5, val_fraction=0.05, seed=7,
+                        lr_final=None):
+        tp = MpcTrainParams(samples, epochs, batch, lr, beta1, beta2, adam_eps, over_weight, target_clip,
+                            val_fraction, seed, lr if lr_final is None else lr_final)
+        rep = MpcTrainReport()
+        _check(lib().mpc_surrogate_train(self.h, C.byref(tp), C.byref(rep)), self.h)
+        return {k: getattr(rep, k) for k, _ in MpcTrainReport._fields_}
+
+    def surrogate_params(self):
+        out = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.dev)
+        _check(lib().mpc_surrogate_get_params(self.h, _ptr(out)), self.h)
+        return out
+
+    def set_surrogate_params(self, params):
+        params = self._f32(params)
+        _check(lib().mpc_surrogate_set_params(self.h, _ptr(params)), self.h)
+
+    def surrogate_predict(self, features):
+        features = self._f32(features)
+        m = int(features.shape[0])
+        out = self.torch.empty(m, dtype=self.torch.float32, device=self.dev)
+        _check(lib().mpc_surrogate_predict(self.h, _ptr(features), m, _ptr(out)), self.h)
+        return out
+
+    def surrogate_grad(self, features, targets, over_weight=4.0):
+        features, targets = self._f32(features), self._f32(targets)
+        g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.dev)
+        loss = C.c_float()
+        _check(lib().mpc_surrogate_grad(self.h, _ptr(features), _ptr(targets), int(features.shape[0]),
+                                        float(over_weight), _ptr(g), C.byref(loss)), self.h)
+        return g, loss.value
+
+    def set_collision_mode(self, mode):
+        _check(lib().mpc_set_collision_mode(self.h, int(mode)), self.h)
+
+    def surrogate_audit(self, on=True):
+        _check(lib().mpc_surrogate_audit(self.h, 1 if on else 0), self.h)
+
+    def surrogate_stats(self, reset=False):
+        out = (C.c_ulonglong * 5)()
+        _check(lib().mpc_surrogate_stats(self.h, C.cast(out, C.c_void_p), 1 if reset else 0), self.h)
+        return dict(zip(["queries", "predicted_far", "waves_skipped", "misses", "missed_collisions"],
+                        [int(x) for x in out]))
 
 
 def philox(ctr, key, stream=None):

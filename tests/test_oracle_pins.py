@@ -445,3 +445,69 @@ def test_adam_first_step_is_signed_lr(orc):
     g = np.array([0.3, -4.0, 1e-3])
     orc.adam(p, m, v, g, 0.01, 0.9, 0.999, 1e-12, 1)
     np.testing.assert_allclose(p, [0.99, -1.99, 0.49], atol=1e-8)
+
+
+def test_bf16_rounding_matches_torch(orc):
+    """Round-to-nearest-even bfloat16 against torch's own conversion."""
+    import torch
+    rng = np.random.default_rng(13)
+    xs = np.concatenate([rng.normal(size=2000) * 10 ** rng.uniform(-6, 6, size=2000),
+                         [1 + 2 ** -8, 1 + 3 * 2 ** -8, -1 - 2 ** -8, 0.0, 3.14159265]]).astype(np.float32)
+    ref = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([orc.bf16(float(x)) for x in xs])
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_bf16_gradient_exact_when_nothing_rounds(orc):
+    """A linear layer with small integer weights, inputs and targets: every
+    product operand is bfloat16-exact, so the reduced-precision gradient
+    equals the FP64 one exactly; with non-representable operands it does not."""
+    widths = [3, 1]
+    p = np.array([1.0, -1.0, 0.0, 2.0])
+    x = np.array([[1.0, 0.0, -1.0], [1.0, 1.0, 1.0]])
+    t = np.array([1.0, -2.0])
+    l1, g1 = orc.mlp_loss_grad(widths, p, x, t, 4.0)
+    l2, g2 = orc.mlp_loss_grad_bf16(widths, p, x, t, 4.0)
+    assert l1 == l2
+    np.testing.assert_array_equal(g1, g2)
+    _, g3 = orc.mlp_loss_grad(widths, p + 1e-3, x * 1.001, t, 4.0)
+    _, g4 = orc.mlp_loss_grad_bf16(widths, p + 1e-3, x * 1.001, t, 4.0)
+    assert np.any(g3 != g4)
+
+
+def test_bf16_gradient_close_to_fp64(orc):
+    widths = [17, 32, 32, 1]
+    rng = np.random.default_rng(15)
+    n = orc.mlp_param_count(widths)
+    p = rng.normal(size=n) * 0.3
+    x = rng.uniform(-1, 1, size=(64, 17))
+    t = rng.uniform(-0.1, 0.5, size=64)
+    _, g1 = orc.mlp_loss_grad(widths, p, x, t, 4.0)
+    _, g2 = orc.mlp_loss_grad_bf16(widths, p, x, t, 4.0)
+    assert np.linalg.norm(g2 - g1) / np.linalg.norm(g1) < 3e-2
+
+
+def test_pair_features_reproduce_the_distance(orc):
+    """The canonical frame of the features preserves the exact distance: both
+    arms rebuilt from the features alone (own arm at the origin, the other at
+    the feature offset with its yaw folded into its first joint) are exactly
+    as far apart as in the world."""
+    sc = scenes.make_scene(5, collision_mode=0)
+    rng = np.random.default_rng(16)
+    for a, i in [(0, 4), (1, 2), (6, 3), (7, 0)]:
+        A, I = sc.arms[a], sc.arms[i]
+        qa = scenes.random_plan_inputs(rng, A, 1)[0].astype(np.float64)
+        qi = scenes.random_plan_inputs(rng, I, 1)[0].astype(np.float64)
+        f = orc.pair_features(orc.make_arm(A), qa, orc.make_arm(I), qi)
+        lo, hi = A.q_lim[:, 0].astype(np.float64), A.q_lim[:, 1].astype(np.float64)
+        mid, half = (lo + hi) / 2, (hi - lo) / 2
+        np.testing.assert_allclose(mid + half * f[:7], qa, atol=1e-12)
+        qi2 = np.concatenate([[f[7] * math.pi], mid[1:] + half[1:] * f[8:14]])
+        A0 = scenes.Arm(**{**A.__dict__, "base": np.zeros(4, np.float32)})
+        I0 = scenes.Arm(**{**I.__dict__, "base": np.array([0, 0, 0, 0], np.float32)})
+        oa0, oi0 = orc.make_arm(A0), orc.make_arm(I0)
+        oi0.base[0], oi0.base[1], oi0.base[2] = f[14], f[15], f[16]
+        world = orc.arm_pair_rho(orc.make_arm(A), qa, orc.make_arm(I), qi)
+        canon = orc.arm_pair_rho(oa0, qa, oi0, qi2)
+        assert abs(world - canon) < 1e-9
+        assert -1 <= f[7] < 1
