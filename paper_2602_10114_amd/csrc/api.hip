@@ -72,7 +72,7 @@ struct mpc_ctx {
   float* sur_v = nullptr;
   float* sur_g = nullptr;              // gradient
   uint16_t* sur_p16 = nullptr;         // bfloat16 copy
-  float* sur_Q = nullptr;              // own rollout joints [A][Hmax][Nmax][7]
+  uint16_t* sur_F = nullptr;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16)
   uint8_t* sur_skip = nullptr;         // [A][A][Hmax][Nmax]
   float* sur_pred = nullptr;           // optional predictions (debug capture)
   unsigned long long* sur_counts = nullptr;  // [A][5]
@@ -472,9 +472,9 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
   for (int k = 0; k < c->P.iters; ++k) {
     RolloutArgs R = rollout_args(c, k);
     if (c->collision_mode == 1) {
-      // Learned distance: own joints of every rollout step, then the MLP's
+      // Learned distance: own-joint features of every rollout step, then the MLP's
       // skip decision per (rollout, step, neighbour).
-      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, k, c->A, c->Nmax, c->sur_Q,
+      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, k, c->A, c->Nmax, c->sur_F,
                                   c->stream));
       SurInferArgs I{};
       I.arms = c->d_arms;
@@ -483,7 +483,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       I.meta = c->d_meta;
       I.W16 = c->sur_p16;
       I.P32 = c->sur_p;
-      I.Q = c->sur_Q;
+      I.F = c->sur_F;
       I.planq = c->planq[0];
       I.items = c->d_sur_items;
       I.n_items = c->n_sur_items;
@@ -514,10 +514,10 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
 // Per-step buffers of the learned distance and its work items: every
 // (arm, neighbour, step within both horizons, 32-rollout block).
 static int ensure_sur_buffers(mpc_ctx* c) {
-  if (c->sur_Q) return MPC_OK;
+  if (c->sur_F) return MPC_OK;
   const size_t A = c->A, H = c->Hmax, N = c->Nmax;
   int rc;
-  if ((rc = dalloc(c, &c->sur_Q, A * H * N * 7)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
+  if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
       (rc = dalloc(c, &c->sur_pred, A * A * H * N)))
     return rc;
   std::vector<SurItem> items;
@@ -533,7 +533,11 @@ static int ensure_sur_buffers(mpc_ctx* c) {
     if ((rc = dalloc(c, &c->d_sur_items, items.size()))) return rc;
     HIPCHK(c, hipMemcpy(c->d_sur_items, items.data(), items.size() * sizeof(SurItem), hipMemcpyHostToDevice));
   }
-  c->sur_grid = std::max(1, std::min((c->n_sur_items + 7) / 8, 1024));
+  // One inference block per compute unit (its LDS and registers fill one).
+  int dev = 0, n_cu = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  c->sur_grid = std::max(1, std::min(c->n_sur_items, std::max(n_cu, 1)));
   return MPC_OK;
 }
 

@@ -12,15 +12,24 @@
 
 namespace mrs {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-// FP32 -> bfloat16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+__device__ __forceinline__ bf16x8_t load_bf16x8(const uint16_t* p) {  // 16-byte aligned
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  bf16x8_t r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// FP32 -> bfloat16 with gfx950's conversion instruction (round to nearest
+// even); the pair form packs a (low half) and b (high half) in one instruction.
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  const bf16x2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -186,45 +195,70 @@ __global__ __launch_bounds__(kWave) void k_sur_sample(const DevArm* __restrict__
 
 // ---------------------------------------------------------------------------
 // bfloat16 MFMA GEMM, 64x64 tile per 256-thread block (4 waves, one 32x32
-// sub-tile each), K in steps of 32 through LDS, every operand access
-// bounds-checked (zero fill), FP32 accumulation.
+// sub-tile each), K in steps of 32 through LDS, FP32 accumulation.  Both
+// operands are staged k-contiguous ([row][k] and [col][k]) so that every MFMA
+// operand is one 16-byte LDS read; global reads are 16-byte vectors along
+// the contiguous dimension when the tile is in bounds and aligned, element
+// reads with zero fill otherwise.
+constexpr int kGemmLd = 32 + 8;
+
+__device__ __forceinline__ bool vec_ok(const uint16_t* base, int ld, int lim_row, int lim_col, int row, int col) {
+  return ((reinterpret_cast<uintptr_t>(base) & 15) == 0) && (ld & 7) == 0 && row < lim_row && col + 8 <= lim_col;
+}
+
+// Stage a 64 (rows r) x 32 (k) tile of X(r, k) into S[r][k].  X(r, k) =
+// trans ? X[k*ld + r] : X[r*ld + k]; R, Kd bound r and k.
+__device__ __forceinline__ void stage_tile(uint16_t (*S)[kGemmLd], const uint16_t* __restrict__ X, int ld, int trans,
+                                           int r0, int k0, int R, int Kd, int tid) {
+  if (!trans) {
+    // 64 rows x 4 vectors of 8 k
+    const int r = tid >> 2, kv = (tid & 3) * 8;
+    const int gr = r0 + r, gk = k0 + kv;
+    if (vec_ok(X, ld, R, Kd, gr, gk)) {
+      *reinterpret_cast<uint4*>(&S[r][kv]) = *reinterpret_cast<const uint4*>(X + (size_t)gr * ld + gk);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        S[r][kv + e] = (gr < R && gk + e < Kd) ? X[(size_t)gr * ld + gk + e] : (uint16_t)0;
+    }
+  } else {
+    // 32 k x 8 vectors of 8 rows
+    const int k = tid >> 3, rv = (tid & 7) * 8;
+    const int gk = k0 + k, gr = r0 + rv;
+    uint16_t v[8];
+    if (vec_ok(X, ld, Kd, R, gk, gr)) {
+      const uint4 u = *reinterpret_cast<const uint4*>(X + (size_t)gk * ld + gr);
+      const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (uint16_t)(w4[e >> 1] >> ((e & 1) * 16));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (gk < Kd && gr + e < R) ? X[(size_t)gk * ld + gr + e] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) S[rv + e][k] = v[e];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[64][40];
-  __shared__ uint16_t Bs[32][72];
+  __shared__ uint16_t As[64][kGemmLd];
+  __shared__ uint16_t Bs[64][kGemmLd];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f32x16_t acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  // B(k, n): stored [n][k] when transB, so it stages like a non-transposed A.
   for (int k0 = 0; k0 < g.K; k0 += 32) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      int r, c;
-      if (g.transA) { r = e % 64; c = e / 64; } else { r = e / 32; c = e % 32; }
-      const int m = m0 + r, k = k0 + c;
-      uint16_t v = 0;
-      if (m < g.M && k < g.K) v = g.transA ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-      As[r][c] = v;
-    }
-    for (int e = tid; e < 32 * 64; e += 256) {
-      int r, c;
-      if (g.transB) { r = e % 32; c = e / 32; } else { r = e / 64; c = e % 64; }
-      const int k = k0 + r, n = n0 + c;
-      uint16_t v = 0;
-      if (k < g.K && n < g.N) v = g.transB ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
-      Bs[r][c] = v;
-    }
+    stage_tile(As, g.A, g.lda, g.transA, m0, k0, g.M, g.K, tid);
+    stage_tile(Bs, g.B, g.ldb, !g.transB, n0, k0, g.N, g.K, tid);
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 8) {
-      bf16x4_t a, b;
-      const int kb = kk + (lane >> 5) * 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = (short)As[wm + (lane & 31)][kb + i];
-        b[i] = (short)Bs[kb + i][wn + (lane & 31)];
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < 32; kk += 16) {
+      const bf16x8_t a = load_bf16x8(&As[wm + (lane & 31)][kk + (lane >> 5) * 8]);
+      const bf16x8_t b = load_bf16x8(&Bs[wn + (lane & 31)][kk + (lane >> 5) * 8]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -267,13 +301,25 @@ __global__ __launch_bounds__(1024) void k_loss(const float* __restrict__ y, cons
   if (tid == 0) *loss_acc += red[0] * invB;
 }
 
-// out[n] = sum over rows of X[m][n] (bias gradients), rows in order.
-__global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// out[n] = sum over rows of X[m][n] (bias gradients).  A block owns 64
+// columns; its 16 row groups each sum every 16th row in order, then the 16
+// partial sums are added in group order (fixed reduction order).
+constexpr int kColsumCols = 64, kColsumGroups = 16;
+__global__ __launch_bounds__(kColsumCols * kColsumGroups) void k_colsum(const float* __restrict__ X, int M, int N,
+                                                                         float* __restrict__ out) {
+  __shared__ float part[kColsumGroups][kColsumCols];
+  const int c = threadIdx.x % kColsumCols, r = threadIdx.x / kColsumCols;
+  const int n = blockIdx.x * kColsumCols + c;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += X[(size_t)m * N + n];
-  out[n] = s;
+  if (n < N)
+    for (int m = r; m < M; m += kColsumGroups) s += X[(size_t)m * N + n];
+  part[r][c] = s;
+  __syncthreads();
+  if (r == 0 && n < N) {
+    float t = 0.f;
+    for (int g = 0; g < kColsumGroups; ++g) t += part[g][c];
+    out[n] = t;
+  }
 }
 
 // Adam (Kingma and Ba), bias-corrected, step counted from 1.
@@ -309,14 +355,17 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 }
 
 // ---------------------------------------------------------------------------
-// Own rollout joint positions of every (arm, step, rollout) for the learned
-// distance: the same noise and integration as the rollout kernel.
+// Own-joint features of every (arm, step, rollout) for the learned distance:
+// the same noise and integration as the rollout kernel, then the normalised
+// joints as one 16-byte row of bfloat16 [f0..f6, in-box flag] (flag 1.0 when
+// all seven lie within the training box, else 0.0).
 __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__ arms,
                                                       const Params* __restrict__ Pp,
+                                                      const SurModel* __restrict__ sm,
                                                       const StepState* __restrict__ ssp,
                                                       const float* __restrict__ mu_all,
                                                       const float* __restrict__ state, int k_iter,
-                                                      float* __restrict__ Q) {
+                                                      uint16_t* __restrict__ F) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
   const DevArm* arm = arms + a;
@@ -324,64 +373,108 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
   if (n >= arm->Npad) return;
   const uint32_t t = ssp->t;
   const float* mu = mu_all + (size_t)a * P.Hmax * 7;
-  float q[7], qd[7];
+  float q[7], qd[7], mid[7], ih[7];
   for (int j = 0; j < 7; ++j) {
     q[j] = state[(a * 7 + j) * 3 + 0];
     qd[j] = state[(a * 7 + j) * 3 + 1];
+    mid[j] = sm->mid[j];
+    ih[j] = sm->inv_half[j];
   }
   for (int h = 0; h < arm->H; ++h) {
     float z[8];
     normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
-    float* out = Q + (((size_t)a * P.Hmax + h) * P.Nmax + n) * 7;
+    uint16_t f[8];
+    bool inbox = true;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
       const float u = P.sigma * z[j] + mu[h * 7 + j];
       qd[j] = fmaf_(P.dt, u, qd[j]);
       q[j] = fmaf_(P.dt, qd[j], q[j]);
-      out[j] = q[j];
+      const float x = (q[j] - mid[j]) * ih[j];
+      inbox = inbox && fabsf(x) <= 1.0f + 1e-3f;
+      f[j] = f2bf(x);
     }
+    f[7] = inbox ? (uint16_t)0x3F80u : (uint16_t)0u;
+    uint4 v;
+    v.x = (uint32_t)f[0] | ((uint32_t)f[1] << 16);
+    v.y = (uint32_t)f[2] | ((uint32_t)f[3] << 16);
+    v.z = (uint32_t)f[4] | ((uint32_t)f[5] << 16);
+    v.w = (uint32_t)f[6] | ((uint32_t)f[7] << 16);
+    *reinterpret_cast<uint4*>(F + (((size_t)a * P.Hmax + h) * P.Nmax + n) * 8) = v;
   }
 }
 
-// Fused MLP inference, transposed so features run along the MFMA rows and
-// queries along the columns: a 32x32 accumulator block of layer l holds, for
-// lane l, 16 features of query l%32 in exactly the K order the next layer's
-// B operand needs, so activations never leave registers.  One wave = 32
-// queries (one rollout block of one (arm, neighbour, step)); a 512-thread
-// block shares each layer's weights through LDS.
-constexpr int kW1Ld = 32 + 4;    // bf16 per staged row (17 inputs padded to 32, +4 against bank conflicts)
-constexpr int kWLd = kHid + 4;
+// Fused MLP inference, weight-stationary.  A 512-thread block (one per CU)
+// streams blocks of 32 queries (32 rollouts of one arm at one step against
+// one neighbour's plan) through a three-stage pipeline:
+//   waves 0-3 ("group A") hold 64 rows each of the second layer's weights in
+//   registers and run that layer;
+//   waves 4-7 ("group B") hold 64 rows each of the third layer's weights (and
+//   of the first layer's) and run the features + first layer of the newest
+//   query block and the third layer + output partial sums of an older one;
+//   wave 0 then adds the four partial sums, the output bias and decides.
+// Activations pass between the groups through LDS as bfloat16 rows
+// [query][feature]; one barrier per stage.  The products are gfx950's
+// 32x32x16 bfloat16 MFMAs with features along the rows and queries along the
+// columns: A = weight rows, B = activation rows of 32 queries.
+constexpr int kActLd = kHid + 8;  // bfloat16 per LDS row: +16 bytes so consecutive rows start 4 banks apart
+constexpr int kInferThreads = 512;
+
+// What the inference loop needs of each arm, copied to LDS once.
+struct InferArm {
+  int N, Npad, H, valid;         // valid: the arm's plan is on the read side of the board
+  float bx, by, bz, byaw, cyaw, syaw;
+};
 
 struct InferLds {
-  uint16_t W1[kHid][kW1Ld];
-  uint16_t W[kHid][kWLd];          // layer 2, then layer 3
-  float b[3][kHid];
-  float w4[kHid];
+  uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
+  uint16_t act2[2][32][kActLd];  // second-layer outputs
+  float bias[3][kHid];
+  float w4[kHid];                // output weights (bfloat16 values)
+  float part[2][4][32];          // third-layer partial output sums per wave
+  int ok[4][32];                 // query live and inside the training box
+  long long out_row[4];          // skip / prediction offset of the block's first query
+  int n_rows[4];                 // rows of the block below the arm's padded rollout count
+  InferArm arm[kMaxArms];
+  float mid[7], inv_half[7];
   float b4;
 };
 
-template <int NKB>
-__device__ __forceinline__ void mfma_block_row(const uint16_t* wrow, const bf16x4_t* act, f32x16_t& acc, int lane) {
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) {
-    const uint16_t* p = wrow + kb * 8 + (lane >> 5) * 4;
-    const uint2 raw = *reinterpret_cast<const uint2*>(p);
-    bf16x4_t a;
-    a[0] = (short)(raw.x & 0xffffu);
-    a[1] = (short)(raw.x >> 16);
-    a[2] = (short)(raw.y & 0xffffu);
-    a[3] = (short)(raw.y >> 16);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, act[kb], acc, 0, 0, 0);
-  }
+// First-layer K slots: chunk 0 = [own f0..f6, flag slot (zero weight)] for
+// lanes 0-31 and [neighbour f7..f13, f14] for lanes 32-63; chunk 1 = [f15,
+// f16, zeros] for lanes 0-31 and zeros for lanes 32-63.
+__device__ __forceinline__ int first_layer_feature(int c, int half, int e) {
+  if (c == 0) return half ? 7 + e : (e < 7 ? e : -1);
+  return (half == 0 && e < 2) ? 15 + e : -1;
 }
 
-// Accumulator block fb starts from the bias of its features: element
-// q4*4 + r holds feature fb*32 + q4*8 + (lane/32)*4 + r.  `bl` points at
-// bias[(lane/32)*4], so every read is that lane base plus a constant.
-__device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl, int fb) {
+// Neighbour part of the features (identical for the 32 queries of a block):
+// f7..f16 as in pair_features, and whether its joints lie in the box.
+__device__ __forceinline__ bool neighbour_features(const InferArm& a, const InferArm& i, const float* qi,
+                                                   const float* mid, const float* inv_half, float g[10]) {
+  const float kPi = 3.14159265358979f;
+  float q0 = qi[0] + (i.byaw - a.byaw);
+  q0 = q0 - 6.28318530717959f * floorf((q0 + kPi) * 0.159154943091895f);
+  g[0] = q0 * 0.318309886183791f;
+  bool inbox = fabsf(g[0]) <= 1.0f + 1e-3f;
+#pragma unroll
+  for (int j = 1; j < 7; ++j) {
+    g[j] = (qi[j] - mid[j]) * inv_half[j];
+    inbox = inbox && fabsf(g[j]) <= 1.0f + 1e-3f;
+  }
+  const float dx = i.bx - a.bx, dy = i.by - a.by, dz = i.bz - a.bz;
+  g[7] = fmaf_(a.cyaw, dx, a.syaw * dy);
+  g[8] = fmaf_(-a.syaw, dx, a.cyaw * dy);
+  g[9] = dz;
+  return inbox;
+}
+
+// Accumulator block starts from the bias of its features: element q4*4 + r
+// holds feature base + q4*8 + (lane/32)*4 + r (`bl` = bias + base + (lane/32)*4).
+__device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl) {
 #pragma unroll
   for (int q4 = 0; q4 < 4; ++q4) {
-    const float4 b = *reinterpret_cast<const float4*>(bl + fb * 32 + q4 * 8);
+    const float4 b = *reinterpret_cast<const float4*>(bl + q4 * 8);
     acc[q4 * 4 + 0] = b.x;
     acc[q4 * 4 + 1] = b.y;
     acc[q4 * 4 + 2] = b.z;
@@ -389,121 +482,203 @@ __device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl, int f
   }
 }
 
-// One accumulator block -> four B operands of the next layer: relu in bfloat16.
-__device__ __forceinline__ void block_to_operands(const f32x16_t& acc, bf16x4_t* dst) {
+// 256-wide layer for this wave's 64 output features over 32 queries.
+__device__ __forceinline__ void layer256(const bf16x8_t (&w)[2][16], const uint16_t (*act)[kActLd],
+                                         const float* bl, f32x16_t (&acc)[2], int lane) {
+  init_block(acc[0], bl);
+  init_block(acc[1], bl + 32);
+  const uint16_t* row = act[lane & 31] + (lane >> 5) * 8;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const bf16x8_t b = load_bf16x8(row + c * 16);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[0][c], b, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[1][c], b, acc[1], 0, 0, 0);
+  }
+}
+
+// relu, bfloat16, into the LDS rows of this lane's query (`dst` = row +
+// base + (lane/32)*4).
+__device__ __forceinline__ void store_block(const f32x16_t& acc, uint16_t* dst) {
 #pragma unroll
   for (int q4 = 0; q4 < 4; ++q4) {
-    bf16x4_t v;
+    uint2 v;
+    v.x = f2bf2(fmaxf(acc[q4 * 4 + 0], 0.f), fmaxf(acc[q4 * 4 + 1], 0.f));
+    v.y = f2bf2(fmaxf(acc[q4 * 4 + 2], 0.f), fmaxf(acc[q4 * 4 + 3], 0.f));
+    *reinterpret_cast<uint2*>(dst + q4 * 8) = v;
+  }
+}
+
+// The global reads of one query block, issued a stage before they are used.
+struct BlockIn {
+  SurItem item;
+  uint4 fown;     // this lane's own-feature row (lanes 0-31 use it)
+  float pq[7];    // neighbour's planned joints at the block's step
+};
+
+__device__ __forceinline__ void fetch_block(const SurInferArgs& A, const InferLds& L, int Hmax, int Nmax,
+                                            const SurItem& it, int q, BlockIn& b) {
+  b.item = it;
+  const int n = min(it.n0 + q, L.arm[it.arm].Npad - 1);
+  b.fown = *reinterpret_cast<const uint4*>(A.F + (((size_t)it.arm * Hmax + it.h) * Nmax + n) * 8);
+  const float* pq = A.planq + ((size_t)it.nbr * Hmax + it.h) * 7;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = (short)f2bf(fmaxf(acc[q4 * 4 + r], 0.f));
-    dst[q4] = v;
-  }
+  for (int j = 0; j < 7; ++j) b.pq[j] = pq[j];
 }
 
-// Stage one 256x256 layer into the shared buffer (all waves done with the
-// previous contents first).
-__device__ __forceinline__ void stage_weights(InferLds& L, const uint16_t* W, int tid, int nthr) {
-  __syncthreads();
-  for (int e = tid; e < kHid * kHid / 4; e += nthr) {
-    const int f2 = e / (kHid / 4), k4 = (e % (kHid / 4)) * 4;
-    *reinterpret_cast<uint2*>(&L.W[f2][k4]) = *reinterpret_cast<const uint2*>(W + (long long)f2 * kHid + k4);
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(512) void k_sur_infer(SurInferArgs A) {
+__global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
   __shared__ InferLds L;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const Params& P = *A.P;
-  const SurModel& sm = *A.model;
-  // Resident: layer 1 (inputs padded to 32 with zeros), biases, output layer.
-  for (int e = tid; e < kHid * 32; e += blockDim.x) {
-    const int f = e / 32, k = e % 32;
-    L.W1[f][k] = k < kFeat ? A.W16[mlp_w_off(0) + (long long)f * kFeat + k] : (uint16_t)0;
+  const int grp = wave >> 2, wq = wave & 3, half = lane >> 5, q = lane & 31;
+  // Loop invariants in registers and LDS: the loop's only global reads are
+  // the prefetched query blocks.
+  const int nA = A.P->A, Hmax = A.P->Hmax, Nmax = A.P->Nmax;
+  const float margin = A.model->margin;
+  if (tid < nA) {
+    const DevArm& d = A.arms[tid];
+    InferArm& m = L.arm[tid];
+    m.N = d.N;
+    m.Npad = d.Npad;
+    m.H = d.H;
+    m.valid = A.meta->valid[0][tid];
+    m.bx = d.base[0];
+    m.by = d.base[1];
+    m.bz = d.base[2];
+    m.byaw = d.base[3];
+    m.cyaw = d.cyaw;
+    m.syaw = d.syaw;
   }
-  for (int e = tid; e < kHid; e += blockDim.x) {
-    L.b[0][e] = A.P32[mlp_b_off(0) + e];
-    L.b[1][e] = A.P32[mlp_b_off(1) + e];
-    L.b[2][e] = A.P32[mlp_b_off(2) + e];
+  if (tid < 7) {
+    L.mid[tid] = A.model->mid[tid];
+    L.inv_half[tid] = A.model->inv_half[tid];
+  }
+  for (int e = tid; e < kHid; e += kInferThreads) {
+    L.bias[0][e] = A.P32[mlp_b_off(0) + e];
+    L.bias[1][e] = A.P32[mlp_b_off(1) + e];
+    L.bias[2][e] = A.P32[mlp_b_off(2) + e];
     L.w4[e] = bf2f(A.W16[mlp_w_off(3) + e]);
   }
   if (tid == 0) L.b4 = A.P32[mlp_b_off(3)];
-  __syncthreads();
-  const int groups = (A.n_items + 7) / 8;
-  for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-    const int it = g * 8 + wave;
-    const bool have = it < A.n_items;
-    SurItem item = have ? A.items[it] : A.items[0];
-    const DevArm* arm = A.arms + item.arm;
-    const DevArm* nbr = A.arms + item.nbr;
-    const int q = lane & 31;
-    const int n = item.n0 + q;
-    const bool valid = A.meta->valid[0][item.nbr] != 0 && item.h < nbr->H;
-    const bool live = have && valid && n < arm->N;
-    // Features of this lane's query.
-    float qa[8], qb[8], f[kFeat];
-    const float* src = A.Q + (((size_t)item.arm * P.Hmax + item.h) * P.Nmax + (n < arm->Npad ? n : 0)) * 7;
-    const float* pq = A.planq + ((size_t)item.nbr * P.Hmax + item.h) * 7;
+  // Stationary weights: rows wq*64 + fb*32 + q, K slots c*16 + half*8 + 0..7.
+  const int row0 = wq * 64 + q;
+  bf16x8_t w[2][16];
+  {
+    const uint16_t* src = A.W16 + mlp_w_off(grp == 0 ? 1 : 2) + (long long)row0 * kHid + half * 8;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      qa[j] = src[j];
-      qb[j] = pq[j];
-    }
-    qa[7] = qb[7] = 0.f;
-    pair_features(arm, qa, nbr, qb, A.model, f);
-    bool inbox = true;
+    for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-    for (int k = 0; k < 14; ++k) inbox = inbox && fabsf(f[k]) <= 1.0f + 1e-3f;
-    // Layer 1: K = 32 (17 features + zeros): B operand kb holds features
-    // kb*8 + (lane/32)*4 + 0..3 of query lane%32.
-    bf16x4_t x[4];
+      for (int c = 0; c < 16; ++c) w[fb][c] = load_bf16x8(src + fb * 32 * kHid + c * 16);
+  }
+  bf16x8_t w1[2][2];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
+  for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k0 = kb * 8 + r, k1 = kb * 8 + 4 + r;
-        const float v0 = k0 < kFeat ? f[k0 < kFeat ? k0 : 0] : 0.f;
-        const float v1 = k1 < kFeat ? f[k1 < kFeat ? k1 : 0] : 0.f;
-        x[kb][r] = (short)f2bf((lane >> 5) ? v1 : v0);
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = first_layer_feature(c, half, e);
+        uint16_t v = 0;
+        if (grp == 1 && k >= 0) v = A.W16[mlp_w_off(0) + (long long)(row0 + fb * 32) * kFeat + k];
+        w1[fb][c][e] = __builtin_bit_cast(__bf16, v);
       }
-    bf16x4_t act[32], nxt[32];
-    const int lb = (lane >> 5) * 4;
+
+  const int G = gridDim.x;
+  const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+  const int fcol = wq * 64 + half * 4;  // this lane's first feature within an accumulator block
+  // Group B keeps the reads of the next block and the item after it in flight.
+  BlockIn cur, nxt;
+  SurItem item2{};
+  __syncthreads();
+  if (grp == 1 && n_my > 0) {
+    fetch_block(A, L, Hmax, Nmax, A.items[blockIdx.x], q, nxt);
+    if (n_my > 1) item2 = A.items[blockIdx.x + G];
+  }
+  for (int s = 0; s < n_my + 3; ++s) {
+    if (grp == 1) {
+      if (s < n_my) {
+        cur = nxt;
+        if (s + 1 < n_my) {
+          fetch_block(A, L, Hmax, Nmax, item2, q, nxt);
+          if (s + 2 < n_my) item2 = A.items[blockIdx.x + (long long)(s + 2) * G];
+        }
+        // Features and first layer of query block s.
+        const SurItem& it = cur.item;
+        const InferArm& arm = L.arm[it.arm];
+        const InferArm& nbr = L.arm[it.nbr];
+        const bool valid = nbr.valid != 0 && it.h < nbr.H;
+        const bool live = valid && it.n0 + q < arm.N;
+        float g[10];
+        const bool nbr_in = neighbour_features(arm, nbr, cur.pq, L.mid, L.inv_half, g);
+        const bool own_in = (cur.fown.w >> 16) != 0u;
+        bf16x8_t x0, x1;
+        {
+          const uint32_t hm = 0u - (uint32_t)half;
+          const uint32_t ow[4] = {cur.fown.x, cur.fown.y, cur.fown.z, cur.fown.w};
 #pragma unroll
-    for (int fb = 0; fb < 8; ++fb) {
-      f32x16_t acc;
-      init_block(acc, &L.b[0][lb], fb);
-      mfma_block_row<4>(&L.W1[fb * 32 + (lane & 31)][0], x, acc, lane);
-      block_to_operands(acc, &act[fb * 4]);
-    }
-    // Layer 2 (weights staged through the shared buffer).
-    stage_weights(L, A.W16 + mlp_w_off(1), tid, blockDim.x);
+          for (int e = 0; e < 8; ++e) {
+            const uint16_t own = (uint16_t)(ow[e >> 1] >> ((e & 1) * 16));
+            const uint16_t nb = f2bf(g[e]);
+            x0[e] = __builtin_bit_cast(__bf16, (uint16_t)((own & ~hm) | (nb & hm)));
+            const uint16_t t = e < 2 ? f2bf(g[8 + e]) : (uint16_t)0;
+            x1[e] = __builtin_bit_cast(__bf16, (uint16_t)(t & ~hm));
+          }
+        }
+        f32x16_t acc[2];
 #pragma unroll
-    for (int fb = 0; fb < 8; ++fb) {
-      f32x16_t acc;
-      init_block(acc, &L.b[1][lb], fb);
-      mfma_block_row<32>(&L.W[fb * 32 + (lane & 31)][0], act, acc, lane);
-      block_to_operands(acc, &nxt[fb * 4]);
-    }
-    // Layer 3, folded straight into the output dot product; its activations
-    // are rounded to bfloat16 first, as the output layer's operand is in training.
-    stage_weights(L, A.W16 + mlp_w_off(2), tid, blockDim.x);
-    float part = 0.f;
+        for (int fb = 0; fb < 2; ++fb) {
+          init_block(acc[fb], &L.bias[0][fcol + fb * 32]);
+          acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][0], x0, acc[fb], 0, 0, 0);
+          acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc[fb], 0, 0, 0);
+          store_block(acc[fb], &L.act1[s & 1][q][fcol + fb * 32]);
+        }
+        if (wq == 0 && half == 0) {
+          L.ok[s & 3][q] = (live && own_in && nbr_in) ? 1 : 0;
+          if (q == 0) {
+            L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
+            L.n_rows[s & 3] = arm.Npad - it.n0;
+          }
+        }
+      }
+      if (s >= 2 && s - 2 < n_my) {
+        // Third layer and the output partial sums of query block s-2.
+        f32x16_t acc[2];
+        layer256(w, L.act2[(s - 2) & 1], &L.bias[2][fcol], acc, lane);
+        float part = 0.f;
 #pragma unroll
-    for (int fb = 0; fb < 8; ++fb) {
-      f32x16_t acc;
-      init_block(acc, &L.b[2][lb], fb);
-      mfma_block_row<32>(&L.W[fb * 32 + (lane & 31)][0], nxt, acc, lane);
-      f32x16_t w4;
-      init_block(w4, &L.w4[lb], fb);
+        for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) part = fmaf_(w4[i], bf2f(f2bf(fmaxf(acc[i], 0.f))), part);
+          for (int q4 = 0; q4 < 4; ++q4) {
+            const float4 w4 = *reinterpret_cast<const float4*>(&L.w4[fcol + fb * 32 + q4 * 8]);
+            const uint32_t u01 = f2bf2(fmaxf(acc[fb][q4 * 4 + 0], 0.f), fmaxf(acc[fb][q4 * 4 + 1], 0.f));
+            const uint32_t u23 = f2bf2(fmaxf(acc[fb][q4 * 4 + 2], 0.f), fmaxf(acc[fb][q4 * 4 + 3], 0.f));
+            part = fmaf_(w4.x, __uint_as_float(u01 << 16), part);
+            part = fmaf_(w4.y, __uint_as_float(u01 & 0xffff0000u), part);
+            part = fmaf_(w4.z, __uint_as_float(u23 << 16), part);
+            part = fmaf_(w4.w, __uint_as_float(u23 & 0xffff0000u), part);
+          }
+        part += __shfl_xor(part, 32);
+        if (half == 0) L.part[s & 1][wq][q] = part;
+      }
+    } else {
+      if (s >= 1 && s - 1 < n_my) {
+        // Second layer of query block s-1.
+        f32x16_t acc[2];
+        layer256(w, L.act1[(s - 1) & 1], &L.bias[1][fcol], acc, lane);
+        store_block(acc[0], &L.act2[(s - 1) & 1][q][fcol]);
+        store_block(acc[1], &L.act2[(s - 1) & 1][q][fcol + 32]);
+      }
+      if (wq == 0 && half == 0 && s >= 3) {
+        // Output and decision of query block s-3.
+        const int r = (s - 3) & 3;
+        const float* pp = &L.part[(s - 1) & 1][0][q];
+        const float y = (((pp[0] + pp[32]) + pp[64]) + pp[96]) + L.b4;
+        if (q < L.n_rows[r]) {
+          const long long o = L.out_row[r] + q;
+          A.skip[o] = (L.ok[r][q] != 0 && y >= margin) ? 1 : 0;
+          if (A.pred) A.pred[o] = y;
+        }
+      }
     }
-    const float y = part + __shfl_xor(part, 32) + L.b4;
-    if (lane < 32 && have && n < arm->Npad) {
-      const bool skip = live && inbox && y >= sm.margin;
-      A.skip[(((size_t)item.arm * P.A + item.nbr) * P.Hmax + item.h) * P.Nmax + n] = skip ? 1 : 0;
-      if (A.pred) A.pred[(((size_t)item.arm * P.A + item.nbr) * P.Hmax + item.h) * P.Nmax + n] = y;
-    }
+    __syncthreads();
   }
 }
 
@@ -556,7 +731,8 @@ hipError_t launch_loss(const float* y, const float* t, int B, float over_w, floa
 }
 
 hipError_t launch_colsum(const float* X, int M, int N, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, X, M, N, out);
+  hipLaunchKernelGGL(k_colsum, dim3((N + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumGroups), 0, s, X,
+                     M, N, out);
   return hipGetLastError();
 }
 
@@ -579,16 +755,17 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_sur_states(const DevArm* arms, const Params* P, const StepState* ss, const float* mu,
-                             const float* state, int k_iter, int n_arms, int npad_max, float* Q, hipStream_t s) {
-  hipLaunchKernelGGL(k_sur_states, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, ss, mu,
-                     state, k_iter, Q);
+hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
+                             const float* mu, const float* state, int k_iter, int n_arms, int npad_max, uint16_t* F,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_states, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, model,
+                     ss, mu, state, k_iter, F);
   return hipGetLastError();
 }
 
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s) {
   if (A.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sur_infer, dim3(grid), dim3(512), 0, s, A);
+  hipLaunchKernelGGL(k_sur_infer, dim3(grid), dim3(kInferThreads), 0, s, A);
   return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ struct SurInferArgs {
   const BoardMeta* meta;
   const uint16_t* W16;         // bfloat16 parameters (same packing as the FP32 master)
   const float* P32;            // FP32 parameters (biases are taken in FP32)
-  const float* Q;              // own rollout joints [A][Hmax][Nmax][7]
+  const uint16_t* F;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16, slot 7 = in-box flag)
   const float* planq;          // read-side planned joints [A][Hmax][7]
   const SurItem* items;
   int n_items;
@@ -76,8 +76,9 @@ struct SurInferArgs {
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, const float* qi, const float* qj,
                                 int M, float* out, hipStream_t s);
-hipError_t launch_sur_states(const DevArm* arms, const Params* P, const StepState* ss, const float* mu,
-                             const float* state, int k_iter, int n_arms, int npad_max, float* Q, hipStream_t s);
+hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
+                             const float* mu, const float* state, int k_iter, int n_arms, int npad_max, uint16_t* F,
+                             hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);
