@@ -10,7 +10,13 @@ every step are precomputed and uploaded before the timed region.
 
 Prints one JSON line: rollout-steps/s, p50/p99 step latency, the roofline of
 the fused rollout kernel (FP32 ALU bound, achieved algorithmic TFLOP/s over
-its HIP-event-timed launches) and the CPU oracle baseline.
+its HIP-event-timed launches) and the CPU oracle baseline.  With the learned
+arm-pair distance (unless --no-surrogate): the network trained on this
+workload's arms, the same steps with the exact check only below the margin
+(throughput, latency, speedup, share of exact checks skipped), and on the
+4-arm scene the same comparison plus an audited closed loop of --audit-steps
+steps that counts every query the network passed whose exact distance was
+below the buffer or below zero.
 """
 import argparse
 import json
@@ -22,6 +28,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_2602_10114_amd import scenes  # noqa: E402  (seeded inputs; no GPU use at import)
 
 METRIC = "rollout-steps/s (arms×rollouts×horizon) + p50/p99 step latency, exact vs surrogate"
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, 256 CUs at 2.4 GHz
@@ -131,12 +139,130 @@ def cpu_baseline(scene, seconds_hint=True):
                       f"({rs} rollout-steps, {dt:.1f} s on one host thread, FP64)"}
 
 
+# Training recipe of the learned distance: 2M exact-kernel samples, Adam;
+# the loss weighs over-prediction (the unsafe direction) 256x and samples
+# within 0.15 m of contact 5x, with targets clipped to [-0.1, 0.5] m.
+SURROGATE_RECIPE = dict(samples=2_000_000, epochs=20, batch=4096, lr=1e-3, over_weight=256.0, near_weight=4.0,
+                        near_band=0.15, target_floor=-0.1, target_clip=0.5, val_fraction=0.05, seed=7)
+
+
+def obstacle_track(scene, n):
+    """Obstacle positions for n consecutive control steps (scene is advanced)."""
+    out = []
+    for _ in range(n):
+        out.append(scene.obstacles.copy())
+        scenes.move_obstacles(scene, float(scene.params["dt"]))
+    return np.stack(out)
+
+
+def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
+    """Closed-loop control steps (Publish + mpc_step + plant) on inputs resident
+    in HBM; returns wall seconds of the timed steps, per-step latencies (ms)
+    from HIP events, and the rollout-kernel event time per launch."""
+    import torch
+    A = scene.n_arms
+    obs = torch.as_tensor(obstacle_track(scene, warmup + 2 * steps), device=dev)
+    with torch.cuda.stream(stream):
+        state = torch.as_tensor(scene.state, device=dev).contiguous()
+        goal = torch.as_tensor(scene.goal, device=dev).contiguous()
+        u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
+        ctl.set_collision_mode(mode)
+        k = 0
+
+        def one_step():
+            nonlocal k
+            ctl.share_plans()
+            ctl.step(state, goal, obs[k], u_out=u)
+            ctl.sim_execute(state, u)
+            k += 1
+
+        for _ in range(warmup):
+            one_step()
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        ctl.surrogate_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ev[i][0].record(stream)
+            one_step()
+            ev[i][1].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stats = ctl.surrogate_stats()
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        # Same steps again with the rollout launches bracketed by HIP events.
+        ctl.profile_enable(True)
+        for i in range(steps):
+            one_step()
+        ms_roll, n_roll = ctl.profile_read()
+        ctl.profile_enable(False)
+        stream.synchronize()
+    return wall, lat, ms_roll / max(n_roll, 1), stats
+
+
+def audit_run(scene, params, steps, dev, goal_age=50):
+    """Learned-distance closed loop with every query also checked exactly:
+    counts of predictions at or beyond the margin whose exact distance is below
+    buf_dyn (misses) or below zero (missed collisions), and the smallest exact
+    gap between the arms as executed.  Goals are reset every goal_age steps
+    (staggered per arm) so that the arms keep crossing the shared workspace."""
+    import torch
+    from paper_2602_10114_amd import native
+    A = scene.n_arms
+    rng = np.random.default_rng(scene.seed + 99)
+    ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
+    ctl.set_surrogate_params(params)
+    ctl.set_collision_mode(1)
+    ctl.surrogate_audit(True)
+    state = torch.as_tensor(scene.state, device=dev).contiguous()
+    goal = torch.as_tensor(scene.goal, device=dev).contiguous()
+    u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
+    age = np.arange(A) * (goal_age // A)
+    qs = torch.empty((steps, A, 7), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        m = scenes.reset_goals(scene, rng, np.full(A, np.inf), age, max_age=goal_age)
+        age = np.where(m, 0, age + 1)
+        if m.any():
+            goal.copy_(torch.as_tensor(scene.goal))
+        ctl.share_plans()
+        ctl.step(state, goal, scene.obstacles, u_out=u)
+        ctl.sim_execute(state, u)
+        qs[k].copy_(state[:, :, 0])
+        scenes.move_obstacles(scene, float(scene.params["dt"]))
+        if (k + 1) % 2000 == 0:
+            print(f"bench: audit step {k + 1}/{steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctl.surrogate_stats()
+    gap = min(float(ctl.pair_distance(i, j, qs[:, i].contiguous(), qs[:, j].contiguous()).min())
+              for i in range(A) for j in range(i + 1, A))
+    ctl.close()
+    return {"steps": steps, "queries": st["queries"], "predicted_far": st["predicted_far"],
+            "misses_below_buffer": st["misses"], "missed_collisions": st["missed_collisions"],
+            "executed_min_arm_gap_m": gap, "seconds": wall}
+
+
+def train_surrogate(scene):
+    from paper_2602_10114_amd import native
+    ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
+    rep = ctl.surrogate_train(**SURROGATE_RECIPE)
+    params = ctl.surrogate_params().clone()
+    ctl.close()
+    return params, rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-distance legs")
+    ap.add_argument("--audit-steps", type=int, default=10000,
+                    help="closed-loop steps of the audited learned-distance run on the 4-arm scene (0: skip)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a summary of rocprofv3 output of a bench run and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -151,63 +277,19 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2602_10114_amd import native, scenes
+    from paper_2602_10114_amd import native
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    scene = scenes.make_scene(5, collision_mode=0)
-    A = scene.n_arms
-    total_steps = args.warmup + 2 * args.steps
-    # Obstacle trajectories for every step, uploaded once.
-    obs_traj = []
-    for _ in range(total_steps):
-        obs_traj.append(scene.obstacles.copy())
-        scenes.move_obstacles(scene, float(scene.params["dt"]))
-    obs_dev = torch.as_tensor(np.stack(obs_traj), device=dev)
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        state = torch.as_tensor(scene.state, device=dev).contiguous()
-        goal = torch.as_tensor(scene.goal, device=dev).contiguous()
-        u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
-        ctl = native.Controller(scene.arms, scene.params, stream=stream)
-        k = 0
-
-        def one_step():
-            nonlocal k
-            ctl.share_plans()
-            ctl.step(state, goal, obs_dev[k], u_out=u)
-            ctl.sim_execute(state, u)
-            k += 1
-
-        for _ in range(args.warmup):
-            one_step()
-        stream.synchronize()
-        print(f"bench: warmup done, tuning {ctl.tuning()}", file=sys.stderr, flush=True)
-        # Timed region: graph-launched steps, one event pair per step.
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            ev[i][0].record(stream)
-            one_step()
-            ev[i][1].record(stream)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        lat = np.array([a.elapsed_time(b) for a, b in ev])
-        print(f"bench: timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
-        # Same steps again with the rollout launches bracketed by HIP events.
-        ctl.profile_enable(True)
-        for i in range(args.steps):
-            one_step()
-        ms_roll, n_roll = ctl.profile_read()
-        ctl.profile_enable(False)
-        stream.synchronize()
+    scene = scenes.make_scene(5, collision_mode=0)
+    ctl = native.Controller(scene.arms, scene.params, stream=stream)
+    wall, lat, roll_ms, _ = timed_loop(ctl, scene, stream, args.steps, args.warmup, 0, dev)
+    tuning = list(ctl.tuning())
+    print(f"bench: exact {args.steps} steps in {wall:.3f} s, tuning {tuning}", file=sys.stderr, flush=True)
+    scene = scenes.make_scene(5, collision_mode=0)
     rs_per_step = scene.rollout_steps()
-    ms_per_step = 1e3 * wall / args.steps
     flops = algorithmic_flops_per_step(scene)
-    roll_ms = ms_roll / max(n_roll, 1)
     achieved = flops / (roll_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -216,7 +298,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -224,8 +306,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "8 arms (two facing rows of 4, 0.5 m pitch) x 4096 rollouts x 40 steps, "
                                "64 spheres/arm, 20 moving obstacles, exact coordination distances, K=1",
-                   "arms": A, "rollouts": 4096, "horizon": 40, "spheres": 64, "obstacles": 20,
-                   "mode": "exact", "tuning": list(ctl.tuning())},
+                   "arms": scene.n_arms, "rollouts": 4096, "horizon": 40, "spheres": 64, "obstacles": 20,
+                   "mode": "exact", "tuning": tuning},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "roofline": {"kernel": "k_rollout", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
@@ -233,6 +315,45 @@ def main():
                      "traffic": TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_digest() else None,
                      "kernel_ms": roll_ms, "algorithmic_flop_per_launch": flops},
     }
+    if not args.no_surrogate:
+        # Learned arm-pair distance on the same workload: exact check only
+        # below the margin, same inputs and step count.
+        params, rep = train_surrogate(scenes.make_scene(5, collision_mode=0))
+        print(f"bench: surrogate trained in {rep['seconds']:.1f} s", file=sys.stderr, flush=True)
+        scene = scenes.make_scene(5, collision_mode=0)
+        ctl2 = native.Controller(scene.arms, {**scene.params, "collision_mode": 0}, stream=stream)
+        ctl2.set_surrogate_params(params)
+        w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev)
+        ctl2.close()
+        q = max(st["queries"], 1)
+        out["surrogate"] = {
+            "value": rs_per_step / (w2 / args.steps), "unit": "rollout-steps/s",
+            "ms_per_step": 1e3 * w2 / args.steps, "speedup_vs_exact": wall / w2,
+            "latency_ms": {"p50": float(np.percentile(lat2, 50)), "p99": float(np.percentile(lat2, 99))},
+            "rollout_kernel_ms": roll2, "queries_predicted_far": st["predicted_far"] / q,
+            "exact_checks_skipped": st["waves_skipped"] * 64 / q,
+            "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()},
+            "recipe": SURROGATE_RECIPE,
+        }
+        if args.audit_steps > 0:
+            sc4 = scenes.make_scene(4, collision_mode=0)
+            p4, rep4 = train_surrogate(scenes.make_scene(4, collision_mode=0))
+            ctl4 = native.Controller(sc4.arms, {**sc4.params, "collision_mode": 0}, stream=stream)
+            ctl4.set_surrogate_params(p4)
+            w4e, _, _, _ = timed_loop(ctl4, scenes.make_scene(4, collision_mode=0), stream, args.steps,
+                                      args.warmup, 0, dev)
+            w4l, lat4, _, st4 = timed_loop(ctl4, scenes.make_scene(4, collision_mode=0), stream, args.steps,
+                                           args.warmup, 1, dev)
+            ctl4.close()
+            aud = audit_run(sc4, p4, args.audit_steps, dev)
+            out["surrogate_4arm"] = {
+                "workload": "4 arms on a 1.2 m square, 1024 rollouts x 30 steps each, 8 moving obstacles",
+                "exact_ms_per_step": 1e3 * w4e / args.steps, "surrogate_ms_per_step": 1e3 * w4l / args.steps,
+                "speedup_vs_exact": w4e / w4l,
+                "exact_checks_skipped": st4["waves_skipped"] * 64 / max(st4["queries"], 1),
+                "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep4.items()},
+                "audit": aud,
+            }
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -241,7 +362,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene)
+        out["cpu_baseline"] = cpu_baseline(scenes.make_scene(5, collision_mode=0))
     ctl.close()
     print(json.dumps(out))
 

@@ -197,11 +197,16 @@ int mpc_profile_read(mpc_ctx *c, double *total_ms, int *launches);
  *
  * An MLP 17 -> 256 -> 256 -> 256 -> 1 (ReLU) predicts the signed minimum
  * sphere distance (Eq. 6) between two arms of the same model from their joint
- * positions and base offset.  In collision mode 1, every (rollout, step,
- * neighbour) query whose prediction is at least surrogate_margin (and whose
- * inputs lie inside the training box) skips the exact sphere-pair check of
- * the coordination cost (its hinge is taken as zero); every other query is
- * checked exactly.  The margin must be at least buf_dyn.  Inputs, in the
+ * positions and base offset.  In collision mode 1 the network scores every
+ * (rollout, step, neighbour) query; a query is "far" when its prediction is
+ * at least surrogate_margin and its inputs lie inside the training box.  The
+ * rollouts are scored in blocks of 64 (rollouts 64b .. 64b+63 of an arm):
+ * when all 64 queries of a block against a neighbour at a step are far, that
+ * neighbour's coordination term is dropped for them (hinge zero) and its
+ * exact sphere-pair check is not run; otherwise all 64 are checked exactly.
+ * So every query predicted below the margin is checked exactly, and a far
+ * query is checked exactly unless its whole block is far.  The margin must
+ * be at least buf_dyn.  Inputs, in the
  * first arm's base frame: its 7 joints normalised to [-1, 1] by the limits,
  * the other arm's first joint plus the yaw difference (wrapped, / pi), the
  * other arm's 6 further normalised joints, and the base offset (metres).
@@ -212,11 +217,14 @@ typedef struct {
   int epochs;
   int batch;               /* 64..65536 */
   float lr, beta1, beta2, adam_eps;
-  float over_weight;       /* loss = mean (y-t)^2 + over_weight * max(0, y-t)^2 */
-  float target_clip;       /* targets min(rho, clip), metres */
+  float over_weight;       /* loss = mean om(t) [(y-t)^2 + over_weight * max(0, y-t)^2] */
+  float target_clip;       /* targets max(min(rho, clip), target_floor), metres */
   float val_fraction;      /* held-out share, [0, 0.5) */
   unsigned long long seed;
   float lr_final;          /* step size at the end of the cosine schedule, (0, lr] */
+  float near_weight;       /* om(t) = 1 + near_weight if t < near_band, else 1 (>= 0) */
+  float near_band;         /* metres */
+  float target_floor;      /* below target_clip; use a large negative value for none */
 } mpc_train_params;
 
 typedef struct {
@@ -226,6 +234,9 @@ typedef struct {
   float val_min_err;       /* most negative error */
   long long steps;         /* optimiser steps */
   float seconds;           /* device time of sampling + training + validation */
+  float val_skip_rate;     /* share of held-out samples predicted >= surrogate_margin */
+  float val_miss_rate;     /* share of held-out samples with target < 0 predicted >= the margin */
+  float val_max_over_near; /* largest over-prediction among held-out targets below the margin */
 } mpc_train_report;
 
 /* Exact signed distance (Eq. 6, min over all sphere pairs) between arm_i at
@@ -237,8 +248,9 @@ int mpc_pair_features(mpc_ctx *c, int arm_i, int arm_j, const float *q_i, const 
 /* Draw training samples (every directed arm pair of the context, joints
  * uniform in the limits, counter-based draws keyed by seed, sample indices
  * first..first+m-1): features [m][17] (the bfloat16 values the network sees),
- * targets [m] = min(rho, clip), joints [m][14] (q_i, q_j; may be NULL).  Device. */
-int mpc_surrogate_samples(mpc_ctx *c, unsigned long long seed, long long first, int m, float clip,
+ * targets [m] = max(min(rho, clip), floor), joints [m][14] (q_i, q_j; may be
+ * NULL).  Device. */
+int mpc_surrogate_samples(mpc_ctx *c, unsigned long long seed, long long first, int m, float clip, float floor,
                           float *features, float *targets, float *joints);
 /* Train the network from scratch on freshly drawn samples (weights and biases
  * uniform in +-1/sqrt(fan_in), Adam, step size on a cosine from lr to
@@ -250,18 +262,20 @@ int mpc_surrogate_set_params(mpc_ctx *c, const float *params);
 /* Network output for features [m][17]; y [m].  Device; waits for the GPU. */
 int mpc_surrogate_predict(mpc_ctx *c, const float *features, int m, float *y);
 /* One forward + backward pass of the training dataflow on a batch
- * (features [B][17], targets [B]): gradient [136449] (device), loss (host). */
+ * (features [B][17], targets [B]) with the training loss (over_weight,
+ * near_weight, near_band as in mpc_train_params): gradient [136449]
+ * (device), loss (host). */
 int mpc_surrogate_grad(mpc_ctx *c, const float *features, const float *targets, int B, float over_weight,
-                       float *grad, float *loss);
+                       float near_weight, float near_band, float *grad, float *loss);
 /* Switch between exact (0) and learned (1) coordination distances. */
 int mpc_set_collision_mode(mpc_ctx *c, int mode);
-/* Audit: in mode 1 also run the exact check of every query and count the
- * queries predicted beyond the margin whose exact distance is below buf_dyn
- * (misses) or below zero (missed collisions). */
+/* Audit: in mode 1 also run the exact checks of the dropped blocks (the
+ * costs stay those of mode 1) and count their queries whose exact distance
+ * is below buf_dyn (misses) or below zero (missed collisions). */
 int mpc_surrogate_audit(mpc_ctx *c, int on);
-/* Counters summed over arms since the last reset: out[5] = queries,
- * predicted beyond the margin, wave-level skips (64 rollouts), misses,
- * missed collisions.  Waits for the GPU. */
+/* Counters summed over arms since the last reset: out[5] = queries, far
+ * queries, dropped (block, neighbour, step) checks of 64 rollouts, misses,
+ * missed collisions (the last two only while auditing).  Waits for the GPU. */
 int mpc_surrogate_stats(mpc_ctx *c, unsigned long long *out, int reset);
 
 /* Device Philox4x32-10 (the noise generator) on n counters: ctr [n][4],

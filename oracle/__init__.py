@@ -116,13 +116,15 @@ def lib():
         L.orc_mlp_param_count.argtypes = [C.c_int, _ip]
         L.orc_mlp_param_count.restype = C.c_longlong
         L.orc_mlp_forward.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp]
-        L.orc_mlp_loss_grad.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp, C.c_double, _dp]
+        L.orc_mlp_loss_grad.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                        _dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_adam.argtypes = [C.c_longlong, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int]
         L.orc_bf16.argtypes = [C.c_double]
         L.orc_bf16.restype = C.c_double
-        L.orc_mlp_loss_grad_bf16.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp, C.c_double, _dp]
+        L.orc_mlp_loss_grad_bf16.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double,
+                                             C.c_double, _dp]
         L.orc_mlp_loss_grad_bf16.restype = C.c_double
         L.orc_pair_features.argtypes = [C.POINTER(OrcArm), _dp, C.POINTER(OrcArm), _dp, _dp]
         _lib = L
@@ -333,12 +335,12 @@ def mlp_forward(widths, params, x):
     return y
 
 
-def mlp_loss_grad(widths, params, x, t, over_w):
+def mlp_loss_grad(widths, params, x, t, over_w, near_w=0.0, near_band=0.0):
     w = np.ascontiguousarray(widths, dtype=np.int32)
     x = _f64(x)
     g = np.zeros(mlp_param_count(widths))
     loss = lib().orc_mlp_loss_grad(len(widths) - 1, w, _f64(params), x.shape[0], x, _f64(t),
-                                   over_w, g)
+                                   over_w, near_w, near_band, g)
     return loss, g
 
 
@@ -346,12 +348,12 @@ def bf16(x):
     return lib().orc_bf16(float(x))
 
 
-def mlp_loss_grad_bf16(widths, params, x, t, over_w):
+def mlp_loss_grad_bf16(widths, params, x, t, over_w, near_w=0.0, near_band=0.0):
     w = np.ascontiguousarray(widths, dtype=np.int32)
     x = _f64(x)
     g = np.zeros(mlp_param_count(widths))
     loss = lib().orc_mlp_loss_grad_bf16(len(widths) - 1, w, _f64(params), x.shape[0], x, _f64(t),
-                                        over_w, g)
+                                        over_w, near_w, near_band, g)
     return loss, g
 
 

@@ -659,9 +659,15 @@ void orc_mlp_forward(int L, const int *w, const double *params, int B, const dou
 
 /* Loss (reading): mean squared error plus an extra penalty on
  * over-prediction (a predicted distance larger than the true one is the
- * unsafe direction).  Backpropagation by the chain rule, layer by layer. */
+ * unsafe direction), each sample weighted by 1 + near_w when its target lies
+ * below near_band (the region where the skip decision is taken).
+ * Backpropagation by the chain rule, layer by layer. */
+static double sample_weight(double t, double near_w, double near_band) {
+  return t < near_band ? 1.0 + near_w : 1.0;
+}
+
 double orc_mlp_loss_grad(int L, const int *w, const double *params, int B, const double *x,
-                         const double *t, double over_w, double *grad) {
+                         const double *t, double over_w, double near_w, double near_band, double *grad) {
   long long np = orc_mlp_param_count(L, w);
   memset(grad, 0, sizeof(double) * np);
   size_t acts = 0;
@@ -689,8 +695,9 @@ double orc_mlp_loss_grad(int L, const int *w, const double *params, int B, const
     }
     double yv = A[off[L]], e = yv - t[s];
     double pos = e > 0.0 ? e : 0.0;
-    loss += e * e + over_w * pos * pos;
-    D[off[L]] = (2.0 * e + 2.0 * over_w * pos) / B;
+    double om = sample_weight(t[s], near_w, near_band);
+    loss += om * (e * e + over_w * pos * pos);
+    D[off[L]] = om * (2.0 * e + 2.0 * over_w * pos) / B;
     for (int l = L - 1; l >= 0; --l) {
       const double *W = params + po[l];
       double *gW = grad + po[l], *gb = gW + (size_t)w[l + 1] * w[l];
@@ -741,7 +748,7 @@ double orc_bf16(double x) {
  * dZ_L = dy; dW_l = bf(dZ_l)^T bf(A_{l-1}); db_l = sum dZ_l;
  * dA_{l-1} = bf(dZ_l) bf(W_l); dZ_{l-1} = dA_{l-1} * [Z_{l-1} > 0]. */
 double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
-                              const double *t, double over_w, double *grad) {
+                              const double *t, double over_w, double near_w, double near_band, double *grad) {
   long long np = orc_mlp_param_count(L, w);
   memset(grad, 0, sizeof(double) * np);
   double *pb = (double *)malloc(sizeof(double) * np);
@@ -770,8 +777,9 @@ double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, 
       }
     }
     double e = A[off[L]] - t[s], pos = e > 0.0 ? e : 0.0;
-    loss += e * e + over_w * pos * pos;
-    D[off[L]] = (2.0 * e + 2.0 * over_w * pos) / B;
+    double om = sample_weight(t[s], near_w, near_band);
+    loss += om * (e * e + over_w * pos * pos);
+    D[off[L]] = om * (2.0 * e + 2.0 * over_w * pos) / B;
     for (int l = L - 1; l >= 0; --l) {
       const double *W = pb + po[l];
       double *gW = grad + po[l], *gb = gW + (size_t)w[l + 1] * w[l];

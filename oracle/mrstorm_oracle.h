@@ -116,10 +116,11 @@ double orc_arm_pair_rho(const orc_arm *ai, const double *qi, const orc_arm *aj, 
  * Parameters are packed per layer as W[out][in] then b[out]. */
 long long orc_mlp_param_count(int L, const int *w);
 void orc_mlp_forward(int L, const int *w, const double *params, int B, const double *x, double *y);
-/* Loss = mean over the batch of (y - t)^2 + over_w * max(0, y - t)^2, and
- * its gradient with respect to every parameter (same packing). */
+/* Loss = mean over the batch of om(t) [(y - t)^2 + over_w * max(0, y - t)^2]
+ * with om(t) = 1 + near_w if t < near_band else 1, and its gradient with
+ * respect to every parameter (same packing). */
 double orc_mlp_loss_grad(int L, const int *w, const double *params, int B, const double *x,
-                         const double *t, double over_w, double *grad);
+                         const double *t, double over_w, double near_w, double near_band, double *grad);
 void orc_adam(long long n, double *p, double *m, double *v, const double *g, double lr,
               double b1, double b2, double eps, int step);
 /* bfloat16 rounding (round to nearest, ties to even) of a double taken as FP32. */
@@ -128,7 +129,7 @@ double orc_bf16(double x);
  * written out: every product operand (inputs, weights, hidden activations,
  * back-propagated deltas) rounded to bfloat16, sums and biases exact. */
 double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
-                              const double *t, double over_w, double *grad);
+                              const double *t, double over_w, double near_w, double near_band, double *grad);
 /* Input features of the learned distance between arm a at q_a (own) and arm
  * i at q_i (neighbour), in arm a's base frame: 7 normalised own joints, the
  * neighbour's first joint plus the yaw difference (wrapped, / pi), its other

@@ -489,6 +489,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       I.n_items = c->n_sur_items;
       I.skip = c->sur_skip;
       I.pred = debug ? c->sur_pred : nullptr;
+      I.counts = c->sur_counts;
       HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
     }
     hipEvent_t e1 = nullptr;
@@ -990,7 +991,7 @@ static hipError_t mlp_backward(mpc_ctx* c, MlpScratch& S, const uint16_t* X16, i
 }
 
 extern "C" int mpc_surrogate_grad(mpc_ctx* c, const float* features, const float* targets, int B, float over_w,
-                                  float* grad, float* loss) {
+                                  float near_w, float near_band, float* grad, float* loss) {
   if (!c) return MPC_EINVAL;
   if (B < 1 || !features || !targets || !grad) return fail(c, MPC_EINVAL, "bad gradient arguments");
   MlpScratch S;
@@ -999,7 +1000,7 @@ extern "C" int mpc_surrogate_grad(mpc_ctx* c, const float* features, const float
   HIPCHK(c, hipMemsetAsync(S.loss, 0, sizeof(float), c->stream));
   HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
   HIPCHK(c, mlp_forward(c, S, S.X16, B));
-  HIPCHK(c, launch_loss(S.y, targets, B, over_w, S.dy, S.dy16, S.loss, c->stream));
+  HIPCHK(c, launch_loss(S.y, targets, B, over_w, near_w, near_band, S.dy, S.dy16, S.loss, c->stream));
   HIPCHK(c, mlp_backward(c, S, S.X16, B));
   HIPCHK(c, hipMemcpyAsync(grad, c->sur_g, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, c->stream));
   float l = 0.f;
@@ -1047,7 +1048,8 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
   if (c->A < 2) return fail(c, MPC_EINVAL, "the learned distance needs at least two arms");
   if (tp->samples < 1024 || tp->batch < 64 || tp->batch > 65536 || tp->epochs < 1 ||
       !(tp->val_fraction >= 0.f && tp->val_fraction < 0.5f) || !(tp->lr > 0.f) ||
-      !(tp->lr_final > 0.f && tp->lr_final <= tp->lr))
+      !(tp->lr_final > 0.f && tp->lr_final <= tp->lr) || !(tp->near_weight >= 0.f) ||
+      !(tp->target_floor < tp->target_clip))
     return fail(c, MPC_EINVAL, "bad training parameters");
   int rc = check_shared_model(c);
   if (rc) return rc;
@@ -1080,8 +1082,8 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
   for (int m0 = 0; m0 < M; m0 += (1 << 20)) {
     const int n = std::min(1 << 20, M - m0);
     HIPCHK(c, launch_sur_sample_layout(c->layout, c->d_arms, c->d_model, d_pairs, (int)pairs.size() / 2, slo, shi,
-                                       m0, n, tp->target_clip, X16 + (size_t)m0 * kFeat, T + m0, nullptr,
-                                       c->stream));
+                                       m0, n, tp->target_clip, tp->target_floor, X16 + (size_t)m0 * kFeat, T + m0,
+                                       nullptr, c->stream));
   }
   // Parameters uniform in +-1/sqrt(fan_in), zero Adam moments.
   HIPCHK(c, launch_init_params(c->sur_p, slo ^ 0x9E3779B9u, shi, c->stream));
@@ -1096,7 +1098,8 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
     for (int b = 0; b < nb; ++b) {
       const uint16_t* xb = X16 + (size_t)b * B * kFeat;
       HIPCHK(c, mlp_forward(c, S, xb, B));
-      HIPCHK(c, launch_loss(S.y, T + (size_t)b * B, B, tp->over_weight, S.dy, S.dy16, S.loss, c->stream));
+      HIPCHK(c, launch_loss(S.y, T + (size_t)b * B, B, tp->over_weight, tp->near_weight, tp->near_band, S.dy, S.dy16,
+                            S.loss, c->stream));
       HIPCHK(c, mlp_backward(c, S, xb, B));
       ++step;
       // step size: cosine from lr to lr_final over the run
@@ -1112,8 +1115,13 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
     HIPCHK(c, hipStreamSynchronize(c->stream));
     last_loss = nb > 0 ? l / nb : 0.f;
   }
-  // Held-out error of the trained network (same bfloat16 dataflow).
+  // Held-out error of the trained network (same bfloat16 dataflow), and the
+  // skip decision at the context's margin: share of samples predicted at or
+  // beyond it, share of colliding samples (target < 0) among them, largest
+  // over-prediction of a sample whose target is below the margin.
   float mae = 0.f, rmse = 0.f, p99 = 0.f, max_over = 0.f, min_err = 0.f;
+  float skip_rate = 0.f, miss_rate = 0.f, max_over_near = 0.f;
+  const float margin = c->hmodel.margin;
   if (n_val > 0) {
     std::vector<float> pred(n_val), tgt(n_val);
     float* yv = nullptr;
@@ -1128,6 +1136,7 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<float> ae(n_val);
     double s1 = 0.0, s2 = 0.0;
+    long long n_skip = 0, n_coll = 0, n_miss = 0;
     for (int i = 0; i < n_val; ++i) {
       const float e = pred[i] - tgt[i];
       ae[i] = std::fabs(e);
@@ -1135,7 +1144,16 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
       s2 += (double)e * e;
       max_over = std::max(max_over, e);
       min_err = std::min(min_err, e);
+      const bool skip = pred[i] >= margin;
+      n_skip += skip;
+      if (tgt[i] < 0.f) {
+        ++n_coll;
+        n_miss += skip;
+      }
+      if (tgt[i] < margin) max_over_near = std::max(max_over_near, e);
     }
+    skip_rate = (float)((double)n_skip / n_val);
+    miss_rate = n_coll ? (float)((double)n_miss / n_coll) : 0.f;
     std::sort(ae.begin(), ae.end());
     mae = (float)(s1 / n_val);
     rmse = (float)std::sqrt(s2 / n_val);
@@ -1155,6 +1173,9 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
     rep->val_p99 = p99;
     rep->val_max_over = max_over;
     rep->val_min_err = min_err;
+    rep->val_skip_rate = skip_rate;
+    rep->val_miss_rate = miss_rate;
+    rep->val_max_over_near = max_over_near;
     rep->steps = step;
     rep->seconds = ms * 1e-3f;
   }
@@ -1162,7 +1183,7 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
 }
 
 extern "C" int mpc_surrogate_samples(mpc_ctx* c, unsigned long long seed, long long first, int m, float clip,
-                                     float* features, float* targets, float* joints) {
+                                     float floor, float* features, float* targets, float* joints) {
   if (!c) return MPC_EINVAL;
   if (c->A < 2 || m < 0 || (m > 0 && (!features || !targets)))
     return fail(c, MPC_EINVAL, "bad sample arguments");
@@ -1182,8 +1203,8 @@ extern "C" int mpc_surrogate_samples(mpc_ctx* c, unsigned long long seed, long l
   HIPCHK(c, S.get(&X16, (size_t)m * kFeat));
   HIPCHK(c, hipMemcpy(d_pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(c, launch_sur_sample_layout(c->layout, c->d_arms, c->d_model, d_pairs, (int)pairs.size() / 2,
-                                     (uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32), first, m, clip, X16,
-                                     targets, joints, c->stream));
+                                     (uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32), first, m, clip, floor,
+                                     X16, targets, joints, c->stream));
   // features back to FP32 (they are exactly the bfloat16 values the network sees)
   std::vector<uint16_t> h((size_t)m * kFeat);
   std::vector<float> f((size_t)m * kFeat);

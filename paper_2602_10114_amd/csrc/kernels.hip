@@ -33,8 +33,13 @@ struct LdsSets {
   float4 raw[kLdsSpheres];
   float F[kLdsSpheres];
   float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
-  int set_k0[kMaxSets], set_n[kMaxSets], set_arm[kMaxSets];
+  int set_k0[kMaxSets], set_n[kMaxSets], set_drop[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
+  // learned-distance counters of the current item (lane 0 only), in the
+  // layout of the per-arm counter rows (slots 0 and 1, queries and predicted
+  // far, are the inference kernel's): waves skipped, audited misses (exact
+  // gap < B), audited missed collisions (gap < 0)
+  unsigned sur[5];
 };
 
 __device__ __forceinline__ void stage_sphere(LdsSets& L, int dst, float4 s, float buf) {
@@ -287,8 +292,8 @@ __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, cons
 }
 
 // ---------------------------------------------------------------------------
-template <int LAY, bool DBG>
-__global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ arms,
+template <int LAY, bool DBG, int SURM>
+__global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__ arms,
                                                    const Params* __restrict__ Pp,
                                                    const StepState* __restrict__ ssp,
                                                    const Item* __restrict__ items,
@@ -345,9 +350,8 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
     float acc = 0.f;
     unsigned long long pairs = 0;
     unsigned set_passes = 0, set_refines = 0, self_refines = 0;
-    // learned-distance counters: queries, predicted far, waves skipped,
-    // audited misses (exact gap < B), audited missed collisions (gap < 0)
-    unsigned sq = 0, sf = 0, sw = 0, sm1 = 0, sm2 = 0;
+    if (SURM && lane == 0)
+      for (int c2 = 0; c2 < 5; ++c2) L.sur[c2] = 0u;
     for (int h = item.h0; h < item.h1; ++h) {
       float z[8];
       normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
@@ -371,7 +375,7 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
         if (lane == 0) {
           L.set_k0[0] = 0;
           L.set_n[0] = n_obs;
-          L.set_arm[0] = -1;
+          L.set_drop[0] = 0;
           L.set_buf[0] = P.buf_env;
           L.set_wt[0] = P.w_coll;
         }
@@ -382,12 +386,22 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
         for (int i = 0; i < nnb; ++i) {
           const Nb nb = SS.nb[a][i];
           if (h >= nb.H) continue;
+          // Learned distance: the neighbour is dropped from this step's sets
+          // when every rollout of the wave is predicted beyond the margin
+          // (SURM 1); the audit (SURM 2) keeps it and marks it.
+          bool dropped = false;
+          if (SURM) {
+            const bool sk = A.skip[(((size_t)a * P.A + nb.arm) * P.Hmax + h) * P.Nmax + n] != 0;
+            dropped = __ballot(sk) == ~0ull;
+            if (dropped && lane == 0) L.sur[2] += 1u;
+            if (SURM == 1 && dropped) continue;
+          }
           const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
           for (int s = lane; s < nb.S; s += kWave) stage_sphere(L, off + s, src[s], P.buf_dyn);
           if (lane == 0) {
             L.set_k0[nsets] = off;
             L.set_n[nsets] = nb.S;
-            L.set_arm[nsets] = nb.arm;
+            L.set_drop[nsets] = dropped ? 1 : 0;
             L.set_buf[nsets] = P.buf_dyn;
             L.set_wt[nsets] = P.w_dyn * nb.alpha;
           }
@@ -437,18 +451,6 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
         const int k0 = L.set_k0[si], K = L.set_n[si];
-        // Learned distance: a neighbour predicted beyond the margin skips the
-        // exact check (all lanes of the wave, or its hinge is taken as 0).
-        bool sk = false;
-        if (A.skip && L.set_arm[si] >= 0) {
-          sk = A.skip[(((size_t)a * P.A + L.set_arm[si]) * P.Hmax + h) * P.Nmax + n] != 0;
-          sq += live ? 1u : 0u;
-          sf += (live && sk) ? 1u : 0u;
-          if (!A.audit && __ballot(sk) == ~0ull) {
-            ++sw;
-            continue;
-          }
-        }
         unsigned nearb = 0;
         {
           Frame W;
@@ -464,9 +466,14 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
           frame_base(W, arm);
           set_refine<LAY, 0>(W, arm, C, L, k0, K, nearb, best);
           float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
-          if (sk) {
-            if (live && near && best < (double)L.set_buf[si]) ++sm1;
-            if (live && near && best < 0.0) ++sm2;
+          if (SURM == 2 && L.set_drop[si]) {
+            const bool hit = live && near;
+            const unsigned m1 = (unsigned)__popcll(__ballot(hit && best < (double)L.set_buf[si]));
+            const unsigned m2 = (unsigned)__popcll(__ballot(hit && best < 0.0));
+            if (lane == 0) {
+              L.sur[3] += m1;
+              L.sur[4] += m2;
+            }
             hv = 0.f;
           }
           c = fmaf_(L.set_wt[si], hv, c);
@@ -501,18 +508,11 @@ __global__ __launch_bounds__(kWave) void k_rollout(const DevArm* __restrict__ ar
     }
     if (live) A.partial[((size_t)a * kMaxH + item.h0 / A.h_tile) * P.Nmax + n] = acc;
     if (DBG && live) atomicAdd(A.dbg_pairs + 4 * a, pairs);
-    if (A.skip) {
-      // wave sums of the lane counters, one atomic per counter
-      unsigned v[5] = {sq, sf, sw, sm1, sm2};
+    if (SURM && lane == 0) {
+      // one atomic per counter and item
 #pragma unroll
-      for (int c2 = 0; c2 < 5; ++c2) {
-        unsigned x = v[c2];
-        if (c2 != 2) {  // the skipped-wave count is already a per-wave value
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        }
-        if (lane == 0 && x) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)x);
-      }
+      for (int c2 = 0; c2 < 5; ++c2)
+        if (L.sur[c2]) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)L.sur[c2]);
     }
     if (DBG && lane == 0) {
       atomicAdd(A.dbg_pairs + 4 * a + 1, (unsigned long long)set_passes);
@@ -783,16 +783,24 @@ __global__ void k_set_meta(BoardMeta* meta, int arm, float dist, int valid) {
 
 // ---------------------------------------------------------------------------
 // Launchers.
-template <int LAY, bool DBG>
+template <int LAY, bool DBG, int SURM>
 static hipError_t launch_rollout_t(const RolloutArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_rollout<LAY, DBG>), dim3(grid), dim3(kWave), 0, s, A.arms, A.P, A.ss, A.items,
+  hipLaunchKernelGGL((k_rollout<LAY, DBG, SURM>), dim3(grid), dim3(kWave), 0, s, A.arms, A.P, A.ss, A.items,
                      A.mu, A.state, A.goal, A.goalR, A.obs, A.plan_read, A);
   return hipGetLastError();
 }
 
+template <int LAY, bool DBG>
+static hipError_t launch_rollout_s(const RolloutArgs& A, int grid, hipStream_t s) {
+  if (!A.skip) return launch_rollout_t<LAY, DBG, 0>(A, grid, s);
+  return A.audit ? launch_rollout_t<LAY, DBG, 2>(A, grid, s) : launch_rollout_t<LAY, DBG, 1>(A, grid, s);
+}
+
+// The learned-distance variants (A.skip set; audited or not) are separate
+// instantiations so that the exact kernel carries none of their bookkeeping.
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s) {
-  if (layout == 0) return debug ? launch_rollout_t<0, true>(A, grid, s) : launch_rollout_t<0, false>(A, grid, s);
-  return debug ? launch_rollout_t<1, true>(A, grid, s) : launch_rollout_t<1, false>(A, grid, s);
+  if (layout == 0) return debug ? launch_rollout_s<0, true>(A, grid, s) : launch_rollout_s<0, false>(A, grid, s);
+  return debug ? launch_rollout_s<1, true>(A, grid, s) : launch_rollout_s<1, false>(A, grid, s);
 }
 
 hipError_t launch_sense(const SenseArgs& A, hipStream_t s) {

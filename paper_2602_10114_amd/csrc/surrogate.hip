@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kWave) void k_sur_sample(const DevArm* __restrict__
                                                       const SurModel* __restrict__ sm,
                                                       const int* __restrict__ pairs, int n_pairs,
                                                       uint32_t slo, uint32_t shi, long long first, int M,
-                                                      float clip, uint16_t* __restrict__ X16,
+                                                      float clip, float floor_, uint16_t* __restrict__ X16,
                                                       float* __restrict__ T, float* __restrict__ Q) {
   __shared__ float4 col[kMaxSpheres][kWave];
   const int lane = threadIdx.x;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kWave) void k_sur_sample(const DevArm* __restrict__
   if (m < M) {
 #pragma unroll
     for (int k = 0; k < kFeat; ++k) X16[m * kFeat + k] = f2bf(f[k]);
-    T[m] = fminf(r, clip);
+    T[m] = fmaxf(fminf(r, clip), floor_);
     if (Q) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
@@ -276,19 +276,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   }
 }
 
-// Loss (mean of e^2 + w max(e,0)^2, e = y - t) and dLoss/dy; one block,
-// fixed reduction order.
+// Loss (mean of om(t) [e^2 + w max(e,0)^2], e = y - t, om = 1 + near_w below
+// near_band) and dLoss/dy; one block, fixed reduction order.
 __global__ __launch_bounds__(1024) void k_loss(const float* __restrict__ y, const float* __restrict__ t, int B,
-                                               float over_w, float* __restrict__ dy, uint16_t* __restrict__ dy16,
-                                               float* __restrict__ loss_acc) {
+                                               float over_w, float near_w, float near_band, float* __restrict__ dy,
+                                               uint16_t* __restrict__ dy16, float* __restrict__ loss_acc) {
   __shared__ float red[1024];
   const int tid = threadIdx.x;
   float acc = 0.f;
   const float invB = 1.0f / (float)B;
   for (int i = tid; i < B; i += blockDim.x) {
     const float e = y[i] - t[i], pos = fmaxf(e, 0.f);
-    acc = fmaf_(e, e, fmaf_(over_w * pos, pos, acc));
-    const float d = (2.f * e + 2.f * over_w * pos) * invB;
+    const float om = t[i] < near_band ? 1.f + near_w : 1.f;
+    acc = fmaf_(om, fmaf_(e, e, over_w * pos * pos), acc);
+    const float d = om * (2.f * e + 2.f * over_w * pos) * invB;
     dy[i] = d;
     dy16[i] = f2bf(d);
   }
@@ -406,17 +407,17 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
 
 // Fused MLP inference, weight-stationary.  A 512-thread block (one per CU)
 // streams blocks of 32 queries (32 rollouts of one arm at one step against
-// one neighbour's plan) through a three-stage pipeline:
-//   waves 0-3 ("group A") hold 64 rows each of the second layer's weights in
-//   registers and run that layer;
+// one neighbour's plan) through a pipeline with one barrier per stage:
 //   waves 4-7 ("group B") hold 64 rows each of the third layer's weights (and
-//   of the first layer's) and run the features + first layer of the newest
-//   query block and the third layer + output partial sums of an older one;
-//   wave 0 then adds the four partial sums, the output bias and decides.
+//   of the first layer's) in registers; at stage s they run the features and
+//   first layer of query block s and the third layer of block s-2;
+//   waves 0-3 ("group A") hold 64 rows each of the second layer's weights and
+//   run that layer on block s-1, then the output layer and the skip decision
+//   of block s-3 (8 lanes per query, reduced in the wave).
 // Activations pass between the groups through LDS as bfloat16 rows
-// [query][feature]; one barrier per stage.  The products are gfx950's
-// 32x32x16 bfloat16 MFMAs with features along the rows and queries along the
-// columns: A = weight rows, B = activation rows of 32 queries.
+// [query][feature].  The products are gfx950's 32x32x16 bfloat16 MFMAs with
+// features along the rows and queries along the columns: A = weight rows,
+// B = activation rows of 32 queries.
 constexpr int kActLd = kHid + 8;  // bfloat16 per LDS row: +16 bytes so consecutive rows start 4 banks apart
 constexpr int kInferThreads = 512;
 
@@ -426,14 +427,16 @@ struct InferArm {
   float bx, by, bz, byaw, cyaw, syaw;
 };
 
-struct InferLds {
+struct alignas(16) InferLds {
   uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
   uint16_t act2[2][32][kActLd];  // second-layer outputs
+  uint16_t act3[2][32][kActLd];  // third-layer outputs
   float bias[3][kHid];
-  float w4[kHid];                // output weights (bfloat16 values)
-  float part[2][4][32];          // third-layer partial output sums per wave
-  int ok[4][32];                 // query live and inside the training box
+  uint16_t w4[kHid];             // output weights, bfloat16
+  int ok[4][32];                 // bit 0: query live; bit 1: live and inside the training box
   long long out_row[4];          // skip / prediction offset of the block's first query
+  int out_arm[4];                // own arm of the block
+  unsigned cnt[kMaxArms][2];     // queries and predicted-far queries of this block, per arm
   int n_rows[4];                 // rows of the block below the arm's padded rollout count
   InferArm arm[kMaxArms];
   float mid[7], inv_half[7];
@@ -496,14 +499,24 @@ __device__ __forceinline__ void layer256(const bf16x8_t (&w)[2][16], const uint1
   }
 }
 
+// Lane exchange by DPP control `ctrl` (all rows and banks enabled).
+template <int ctrl>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
+// max(x, 0) as one integer max on the bit pattern (equal to fmaxf(x, 0) for
+// every non-NaN x, -0 included up to the sign of zero).
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // relu, bfloat16, into the LDS rows of this lane's query (`dst` = row +
 // base + (lane/32)*4).
 __device__ __forceinline__ void store_block(const f32x16_t& acc, uint16_t* dst) {
 #pragma unroll
   for (int q4 = 0; q4 < 4; ++q4) {
     uint2 v;
-    v.x = f2bf2(fmaxf(acc[q4 * 4 + 0], 0.f), fmaxf(acc[q4 * 4 + 1], 0.f));
-    v.y = f2bf2(fmaxf(acc[q4 * 4 + 2], 0.f), fmaxf(acc[q4 * 4 + 3], 0.f));
+    v.x = f2bf2(relu_bits(acc[q4 * 4 + 0]), relu_bits(acc[q4 * 4 + 1]));
+    v.y = f2bf2(relu_bits(acc[q4 * 4 + 2]), relu_bits(acc[q4 * 4 + 3]));
     *reinterpret_cast<uint2*>(dst + q4 * 8) = v;
   }
 }
@@ -551,11 +564,12 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
     L.mid[tid] = A.model->mid[tid];
     L.inv_half[tid] = A.model->inv_half[tid];
   }
+  if (tid < 2 * kMaxArms) L.cnt[tid >> 1][tid & 1] = 0u;
   for (int e = tid; e < kHid; e += kInferThreads) {
     L.bias[0][e] = A.P32[mlp_b_off(0) + e];
     L.bias[1][e] = A.P32[mlp_b_off(1) + e];
     L.bias[2][e] = A.P32[mlp_b_off(2) + e];
-    L.w4[e] = bf2f(A.W16[mlp_w_off(3) + e]);
+    L.w4[e] = A.W16[mlp_w_off(3) + e];
   }
   if (tid == 0) L.b4 = A.P32[mlp_b_off(3)];
   // Stationary weights: rows wq*64 + fb*32 + q, K slots c*16 + half*8 + 0..7.
@@ -609,19 +623,14 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
         float g[10];
         const bool nbr_in = neighbour_features(arm, nbr, cur.pq, L.mid, L.inv_half, g);
         const bool own_in = (cur.fown.w >> 16) != 0u;
-        bf16x8_t x0, x1;
-        {
-          const uint32_t hm = 0u - (uint32_t)half;
-          const uint32_t ow[4] = {cur.fown.x, cur.fown.y, cur.fown.z, cur.fown.w};
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const uint16_t own = (uint16_t)(ow[e >> 1] >> ((e & 1) * 16));
-            const uint16_t nb = f2bf(g[e]);
-            x0[e] = __builtin_bit_cast(__bf16, (uint16_t)((own & ~hm) | (nb & hm)));
-            const uint16_t t = e < 2 ? f2bf(g[8 + e]) : (uint16_t)0;
-            x1[e] = __builtin_bit_cast(__bf16, (uint16_t)(t & ~hm));
-          }
-        }
+        // B operands: lanes 0-31 take their own-feature row (its flag slot
+        // meets a zero weight), lanes 32-63 the neighbour features f7..f14;
+        // the second chunk holds f15, f16 for lanes 0-31 and zeros.
+        const uint4 nbw = make_uint4(f2bf2(g[0], g[1]), f2bf2(g[2], g[3]), f2bf2(g[4], g[5]), f2bf2(g[6], g[7]));
+        const uint4 xw0 = half ? nbw : cur.fown;
+        const uint4 xw1 = make_uint4(half ? 0u : f2bf2(g[8], g[9]), 0u, 0u, 0u);
+        const bf16x8_t x0 = __builtin_bit_cast(bf16x8_t, xw0);
+        const bf16x8_t x1 = __builtin_bit_cast(bf16x8_t, xw1);
         f32x16_t acc[2];
 #pragma unroll
         for (int fb = 0; fb < 2; ++fb) {
@@ -631,32 +640,20 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
           store_block(acc[fb], &L.act1[s & 1][q][fcol + fb * 32]);
         }
         if (wq == 0 && half == 0) {
-          L.ok[s & 3][q] = (live && own_in && nbr_in) ? 1 : 0;
+          L.ok[s & 3][q] = (live ? 1 : 0) | ((live && own_in && nbr_in) ? 2 : 0);
           if (q == 0) {
             L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
             L.n_rows[s & 3] = arm.Npad - it.n0;
+            L.out_arm[s & 3] = it.arm;
           }
         }
       }
       if (s >= 2 && s - 2 < n_my) {
-        // Third layer and the output partial sums of query block s-2.
+        // Third layer of query block s-2.
         f32x16_t acc[2];
         layer256(w, L.act2[(s - 2) & 1], &L.bias[2][fcol], acc, lane);
-        float part = 0.f;
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb)
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4) {
-            const float4 w4 = *reinterpret_cast<const float4*>(&L.w4[fcol + fb * 32 + q4 * 8]);
-            const uint32_t u01 = f2bf2(fmaxf(acc[fb][q4 * 4 + 0], 0.f), fmaxf(acc[fb][q4 * 4 + 1], 0.f));
-            const uint32_t u23 = f2bf2(fmaxf(acc[fb][q4 * 4 + 2], 0.f), fmaxf(acc[fb][q4 * 4 + 3], 0.f));
-            part = fmaf_(w4.x, __uint_as_float(u01 << 16), part);
-            part = fmaf_(w4.y, __uint_as_float(u01 & 0xffff0000u), part);
-            part = fmaf_(w4.z, __uint_as_float(u23 << 16), part);
-            part = fmaf_(w4.w, __uint_as_float(u23 & 0xffff0000u), part);
-          }
-        part += __shfl_xor(part, 32);
-        if (half == 0) L.part[s & 1][wq][q] = part;
+        store_block(acc[0], &L.act3[(s - 2) & 1][q][fcol]);
+        store_block(acc[1], &L.act3[(s - 2) & 1][q][fcol + 32]);
       }
     } else {
       if (s >= 1 && s - 1 < n_my) {
@@ -666,19 +663,55 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
         store_block(acc[0], &L.act2[(s - 1) & 1][q][fcol]);
         store_block(acc[1], &L.act2[(s - 1) & 1][q][fcol + 32]);
       }
-      if (wq == 0 && half == 0 && s >= 3) {
-        // Output and decision of query block s-3.
-        const int r = (s - 3) & 3;
-        const float* pp = &L.part[(s - 1) & 1][0][q];
-        const float y = (((pp[0] + pp[32]) + pp[64]) + pp[96]) + L.b4;
-        if (q < L.n_rows[r]) {
-          const long long o = L.out_row[r] + q;
-          A.skip[o] = (L.ok[r][q] != 0 && y >= margin) ? 1 : 0;
+      if (s >= 3) {
+        // Output layer and decision of query block s-3: query wq*8 + lane/8;
+        // the 8 lanes of a query take 16-byte chunks j, j+8, j+16, j+24
+        // (j = lane%8), so each 8-lane group reads 128 contiguous bytes.
+        const int r = (s - 3) & 3, qq = wq * 8 + (lane >> 3), j = lane & 7;
+        const uint16_t* row = &L.act3[(s - 3) & 1][qq][0];
+        float pi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = (j + 8 * i) * 8;
+          const uint4 a = *reinterpret_cast<const uint4*>(row + k);
+          const uint4 wv = *reinterpret_cast<const uint4*>(&L.w4[k]);
+          float t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.x),
+                                                    __builtin_bit_cast(bf16x2_t, wv.x), 0.f, false);
+          t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.y), __builtin_bit_cast(bf16x2_t, wv.y), t,
+                                              false);
+          t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.z), __builtin_bit_cast(bf16x2_t, wv.z), t,
+                                              false);
+          pi[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.w), __builtin_bit_cast(bf16x2_t, wv.w),
+                                                  t, false);
+        }
+        // sum over the 8 lanes of the query: swaps within quads, then the
+        // mirrored lane of the other quad of the row of 8
+        float part = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+        part += dpp_f32<0xB1>(part);   // quad_perm [1,0,3,2]
+        part += dpp_f32<0x4E>(part);   // quad_perm [2,3,0,1]
+        part += dpp_f32<0x141>(part);  // row_half_mirror
+        const bool writer = (lane & 7) == 0 && qq < L.n_rows[r];
+        const int okv = L.ok[r][qq];
+        const float y = part + L.b4;
+        const bool far = (okv & 2) != 0 && y >= margin;
+        if (writer) {
+          const long long o = L.out_row[r] + qq;
+          A.skip[o] = far ? 1 : 0;
           if (A.pred) A.pred[o] = y;
+        }
+        const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
+        const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
+        if (lane == 0 && (nq | nf)) {
+          atomicAdd(&L.cnt[L.out_arm[r]][0], nq);
+          atomicAdd(&L.cnt[L.out_arm[r]][1], nf);
         }
       }
     }
     __syncthreads();
+  }
+  if (A.counts && tid < 2 * nA) {
+    const unsigned v = L.cnt[tid >> 1][tid & 1];
+    if (v) atomicAdd(A.counts + 5 * (tid >> 1) + (tid & 1), (unsigned long long)v);
   }
 }
 
@@ -700,14 +733,14 @@ hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, 
 
 hipError_t launch_sur_sample_layout(int layout, const DevArm* arms, const SurModel* model, const int* pairs,
                                     int n_pairs, uint32_t slo, uint32_t shi, long long first, int M, float clip,
-                                    uint16_t* X16, float* T, float* Q, hipStream_t s) {
+                                    float floor_, uint16_t* X16, float* T, float* Q, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   if (layout == 0)
     hipLaunchKernelGGL(k_sur_sample<0>, dim3((M + kWave - 1) / kWave), dim3(kWave), 0, s, arms, model, pairs,
-                       n_pairs, slo, shi, first, M, clip, X16, T, Q);
+                       n_pairs, slo, shi, first, M, clip, floor_, X16, T, Q);
   else
     hipLaunchKernelGGL(k_sur_sample<1>, dim3((M + kWave - 1) / kWave), dim3(kWave), 0, s, arms, model, pairs,
-                       n_pairs, slo, shi, first, M, clip, X16, T, Q);
+                       n_pairs, slo, shi, first, M, clip, floor_, X16, T, Q);
   return hipGetLastError();
 }
 
@@ -724,9 +757,10 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_loss(const float* y, const float* t, int B, float over_w, float* dy, uint16_t* dy16,
+hipError_t launch_loss(const float* y, const float* t, int B, float over_w, float near_w, float near_band, float* dy,
+                       uint16_t* dy16,
                        float* loss_acc, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, y, t, B, over_w, dy, dy16, loss_acc);
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, y, t, B, over_w, near_w, near_band, dy, dy16, loss_acc);
   return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct SurInferArgs {
   int pad;
   uint8_t* skip;               // [A][A][Hmax][Nmax]: 1 = predicted beyond the margin
   float* pred;                 // optional predictions, same layout
+  unsigned long long* counts;  // per-arm counter rows [A][5]: adds queries (slot 0) and predicted far (slot 1)
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
@@ -82,15 +83,15 @@ hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);
-// features (bfloat16 [M][17]), FP32 targets min(rho, clip), and the joints
-// (FP32 [M][14], optional).
+// features (bfloat16 [M][17]), FP32 targets max(min(rho, clip), floor), and
+// the joints (FP32 [M][14], optional).
 hipError_t launch_sur_sample_layout(int layout, const DevArm* arms, const SurModel* model, const int* pairs,
                                     int n_pairs, uint32_t seed_lo, uint32_t seed_hi, long long first, int M,
-                                    float clip, uint16_t* X16, float* T, float* Q, hipStream_t s);
+                                    float clip, float floor_, uint16_t* X16, float* T, float* Q, hipStream_t s);
 hipError_t launch_features(const DevArm* arms, const SurModel* model, int ai, int aj, const float* qi,
                            const float* qj, int M, float* F, hipStream_t s);
-hipError_t launch_loss(const float* y, const float* t, int B, float over_w, float* dy, uint16_t* dy16,
-                       float* loss_acc, hipStream_t s);
+hipError_t launch_loss(const float* y, const float* t, int B, float over_w, float near_w, float near_band, float* dy,
+                       uint16_t* dy16, float* loss_acc, hipStream_t s);
 hipError_t launch_colsum(const float* X, int M, int N, float* out, hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, long long n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);

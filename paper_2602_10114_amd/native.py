@@ -47,13 +47,15 @@ class MpcTrainParams(C.Structure):
     _fields_ = [("samples", C.c_int), ("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
                 ("over_weight", C.c_float), ("target_clip", C.c_float), ("val_fraction", C.c_float),
-                ("seed", C.c_ulonglong), ("lr_final", C.c_float)]
+                ("seed", C.c_ulonglong), ("lr_final", C.c_float), ("near_weight", C.c_float),
+                ("near_band", C.c_float), ("target_floor", C.c_float)]
 
 
 class MpcTrainReport(C.Structure):
     _fields_ = [("final_loss", C.c_float), ("val_mae", C.c_float), ("val_rmse", C.c_float),
                 ("val_p99", C.c_float), ("val_max_over", C.c_float), ("val_min_err", C.c_float),
-                ("steps", C.c_longlong), ("seconds", C.c_float)]
+                ("steps", C.c_longlong), ("seconds", C.c_float), ("val_skip_rate", C.c_float),
+                ("val_miss_rate", C.c_float), ("val_max_over_near", C.c_float)]
 
 
 class MpcParams(C.Structure):
@@ -101,12 +103,12 @@ def lib():
         L.mpc_philox.argtypes = [vp, vp, vp, ip, vp]
         L.mpc_pair_distance.argtypes = [vp, ip, ip, vp, vp, ip, vp]
         L.mpc_pair_features.argtypes = [vp, ip, ip, vp, vp, ip, vp]
-        L.mpc_surrogate_samples.argtypes = [vp, C.c_ulonglong, C.c_longlong, ip, fp, vp, vp, vp]
+        L.mpc_surrogate_samples.argtypes = [vp, C.c_ulonglong, C.c_longlong, ip, fp, fp, vp, vp, vp]
         L.mpc_surrogate_train.argtypes = [vp, C.POINTER(MpcTrainParams), C.POINTER(MpcTrainReport)]
         L.mpc_surrogate_get_params.argtypes = [vp, vp]
         L.mpc_surrogate_set_params.argtypes = [vp, vp]
         L.mpc_surrogate_predict.argtypes = [vp, vp, ip, vp]
-        L.mpc_surrogate_grad.argtypes = [vp, vp, vp, ip, fp, vp, C.POINTER(fp)]
+        L.mpc_surrogate_grad.argtypes = [vp, vp, vp, ip, fp, fp, fp, vp, C.POINTER(fp)]
         L.mpc_set_collision_mode.argtypes = [vp, ip]
         L.mpc_surrogate_audit.argtypes = [vp, ip]
         L.mpc_surrogate_stats.argtypes = [vp, vp, ip]
@@ -301,20 +303,21 @@ class Controller:
         _check(lib().mpc_pair_features(self.h, arm_i, arm_j, _ptr(q_i), _ptr(q_j), m, _ptr(out)), self.h)
         return out
 
-    def surrogate_samples(self, seed, first, m, clip=0.5):
+    def surrogate_samples(self, seed, first, m, clip=0.5, floor=-1e30):
         t = self.torch
         f = t.empty((m, 17), dtype=t.float32, device=self.dev)
         y = t.empty(m, dtype=t.float32, device=self.dev)
         q = t.empty((m, 14), dtype=t.float32, device=self.dev)
-        _check(lib().mpc_surrogate_samples(self.h, int(seed), int(first), m, float(clip), _ptr(f), _ptr(y),
-                                           _ptr(q)), self.h)
+        _check(lib().mpc_surrogate_samples(self.h, int(seed), int(first), m, float(clip), float(floor), _ptr(f),
+                                           _ptr(y), _ptr(q)), self.h)
         return f, y, q
 
     def surrogate_train(self, samples=2_000_000, epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
                         adam_eps=1e-8, over_weight=4.0, target_clip=0.5, val_fraction=0.05, seed=7,
-                        lr_final=None):
+                        lr_final=None, near_weight=0.0, near_band=0.0, target_floor=-1e30):
         tp = MpcTrainParams(samples, epochs, batch, lr, beta1, beta2, adam_eps, over_weight, target_clip,
-                            val_fraction, seed, lr if lr_final is None else lr_final)
+                            val_fraction, seed, lr if lr_final is None else lr_final, near_weight, near_band,
+                            target_floor)
         rep = MpcTrainReport()
         _check(lib().mpc_surrogate_train(self.h, C.byref(tp), C.byref(rep)), self.h)
         return {k: getattr(rep, k) for k, _ in MpcTrainReport._fields_}
@@ -335,12 +338,13 @@ class Controller:
         _check(lib().mpc_surrogate_predict(self.h, _ptr(features), m, _ptr(out)), self.h)
         return out
 
-    def surrogate_grad(self, features, targets, over_weight=4.0):
+    def surrogate_grad(self, features, targets, over_weight=4.0, near_weight=0.0, near_band=0.0):
         features, targets = self._f32(features), self._f32(targets)
         g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.dev)
         loss = C.c_float()
         _check(lib().mpc_surrogate_grad(self.h, _ptr(features), _ptr(targets), int(features.shape[0]),
-                                        float(over_weight), _ptr(g), C.byref(loss)), self.h)
+                                        float(over_weight), float(near_weight), float(near_band), _ptr(g),
+                                        C.byref(loss)), self.h)
         return g, loss.value
 
     def set_collision_mode(self, mode):

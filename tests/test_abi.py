@@ -39,6 +39,10 @@ int main(void) {
          offsetof(mpc_arm_desc, base), offsetof(mpc_arm_desc, tool), sizeof(mpc_params));
   printf("%zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
          offsetof(mpc_params, collision_mode), offsetof(mpc_params, surrogate_margin));
+  printf("%zu %zu %zu %zu\\n", sizeof(mpc_train_params), offsetof(mpc_train_params, seed),
+         offsetof(mpc_train_params, lr_final), offsetof(mpc_train_params, target_floor));
+  printf("%zu %zu %zu\\n", sizeof(mpc_train_report), offsetof(mpc_train_report, steps),
+         offsetof(mpc_train_report, val_max_over_near));
   return 0;
 }
 """)
@@ -46,8 +50,11 @@ int main(void) {
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     A, P = native.MpcArmDesc, native.MpcParams
+    T, R = native.MpcTrainParams, native.MpcTrainReport
     expect = [C.sizeof(A), A.sphere_link.offset, A.base.offset, A.tool.offset, C.sizeof(P),
-              P.iters.offset, P.seed.offset, P.collision_mode.offset, P.surrogate_margin.offset]
+              P.iters.offset, P.seed.offset, P.collision_mode.offset, P.surrogate_margin.offset,
+              C.sizeof(T), T.seed.offset, T.lr_final.offset, T.target_floor.offset,
+              C.sizeof(R), R.steps.offset, R.val_max_over_near.offset]
     assert [int(x) for x in out] == expect
 
 

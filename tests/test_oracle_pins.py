@@ -439,6 +439,38 @@ def test_mlp_gradient_finite_difference(orc):
     assert abs(loss - np.mean(e * e + 4.0 * np.maximum(e, 0) ** 2)) < 1e-12
 
 
+def test_mlp_near_weighted_loss(orc):
+    """Samples whose target lies below the band count (1 + near_w) times: the
+    loss and gradient equal those of the unweighted loss over a batch in which
+    each such sample is repeated 1 + near_w times (rescaled to the batch size);
+    finite differences agree with the gradient."""
+    widths = [4, 6, 1]
+    rng = np.random.default_rng(21)
+    n = orc.mlp_param_count(widths)
+    p = rng.normal(size=n) * 0.5
+    x = rng.normal(size=(6, 4))
+    t = np.array([-0.2, 0.01, 0.3, 0.04, 0.6, -0.05])
+    band, near_w = 0.05, 2.0
+    loss, g = orc.mlp_loss_grad(widths, p, x, t, 4.0, near_w, band)
+    rep = np.concatenate([np.repeat(np.arange(6)[t < band], 3), np.arange(6)[t >= band]])
+    l_rep, g_rep = orc.mlp_loss_grad(widths, p, x[rep], t[rep], 4.0)
+    scale = len(rep) / 6.0
+    assert abs(loss - l_rep * scale) < 1e-12
+    np.testing.assert_allclose(g, g_rep * scale, rtol=1e-12, atol=1e-14)
+    h = 1e-6
+    for i in range(0, n, 3):
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (orc.mlp_loss_grad(widths, pp, x, t, 4.0, near_w, band)[0]
+              - orc.mlp_loss_grad(widths, pm, x, t, 4.0, near_w, band)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
+    # the reduced-precision dataflow applies the same weights
+    lb, _ = orc.mlp_loss_grad_bf16(widths, p, x, t, 4.0, near_w, band)
+    lb0, _ = orc.mlp_loss_grad_bf16(widths, p, x, t, 4.0)
+    assert lb > lb0
+
+
 def test_adam_first_step_is_signed_lr(orc):
     p = np.array([1.0, -2.0, 0.5])
     m, v = np.zeros(3), np.zeros(3)
