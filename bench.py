@@ -33,13 +33,14 @@ from paper_2602_10114_amd import scenes  # noqa: E402  (seeded inputs; no GPU us
 
 METRIC = "rollout-steps/s (arms×rollouts×horizon) + p50/p99 step latency, exact vs surrogate"
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, 256 CUs at 2.4 GHz
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bfloat16 MFMA
 KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd/csrc/device.hpp",
                   "paper_2602_10114_amd/csrc/common.hpp"]
 # HBM bytes per k_rollout launch on this workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes, each scaled by the same counter's reading for a 256 MiB
 # device copy (fetch x2.000, write x1.000); valid only for the kernel sources
 # with this digest (see profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "9a1119d1865e7c11", "bytes_per_launch": 44653772}
+TRAFFIC = {"sources_sha256": "0b55b427a07cfe74", "bytes_per_launch": 44633812}
 
 
 def sources_digest():
@@ -98,6 +99,30 @@ def summarize(trace_dir, fetch_dir, write_dir, steps):
     return "\n".join(out)
 
 
+def summarize_pmc(pmc_dir):
+    """Text summary of a rocprofv3 --pmc pass (CSV, each counter already summed
+    over its instances): per kernel, the counters of its last dispatch and the
+    MFMA busy share SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 1024
+    SIMDs), GRBM_GUI_ACTIVE being the sum of the 8 XCDs' active cycles."""
+    import csv
+    import glob
+    from collections import defaultdict
+    f = glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0]
+    per = defaultdict(lambda: defaultdict(dict))
+    for r in csv.DictReader(open(f)):
+        per[r["Kernel_Name"].split("(")[0]][int(r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    out = [f"counter collection: {f}"]
+    for name, disp in sorted(per.items()):
+        vals = disp[max(disp)]
+        out.append(f"{name[:60]} (dispatches {len(disp)}, last):")
+        for c in sorted(vals):
+            out.append(f"  {c:28s} {vals[c]:16.6g}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in vals and vals.get("GRBM_GUI_ACTIVE"):
+            share = vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (vals["GRBM_GUI_ACTIVE"] / 8 * 1024)
+            out.append(f"  MFMA busy share             {share:16.4f}")
+    return "\n".join(out)
+
+
 def algorithmic_flops_per_step(scene, active_neighbours=True):
     """Algorithmic work of one rollout launch: 11 FLOP per sphere pair (3 sub,
     5 for the dot product, sqrt, minus radii, min) plus the per rollout-step
@@ -137,13 +162,6 @@ def cpu_baseline(scene, seconds_hint=True):
     return {"value": rs / dt, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"one control step of all 8 arms restricted to {window} of 4096 rollouts each "
                       f"({rs} rollout-steps, {dt:.1f} s on one host thread, FP64)"}
-
-
-# Training recipe of the learned distance: 2M exact-kernel samples, Adam;
-# the loss weighs over-prediction (the unsafe direction) 256x and samples
-# within 0.15 m of contact 5x, with targets clipped to [-0.1, 0.5] m.
-SURROGATE_RECIPE = dict(samples=2_000_000, epochs=20, batch=4096, lr=1e-3, over_weight=256.0, near_weight=4.0,
-                        near_band=0.15, target_floor=-0.1, target_clip=0.5, val_fraction=0.05, seed=7)
 
 
 def obstacle_track(scene, n):
@@ -197,8 +215,10 @@ def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
         for i in range(steps):
             one_step()
         ms_roll, n_roll = ctl.profile_read()
+        ms_inf, n_inf = ctl.profile_read_surrogate()
         ctl.profile_enable(False)
         stream.synchronize()
+    stats["infer_ms"] = ms_inf / n_inf if n_inf else None
     return wall, lat, ms_roll / max(n_roll, 1), stats
 
 
@@ -248,7 +268,7 @@ def audit_run(scene, params, steps, dev, goal_age=50):
 def train_surrogate(scene):
     from paper_2602_10114_amd import native
     ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
-    rep = ctl.surrogate_train(**SURROGATE_RECIPE)
+    rep = ctl.surrogate_train(**native.TRAINING_RECIPE)
     params = ctl.surrogate_params().clone()
     ctl.close()
     return params, rep
@@ -265,11 +285,16 @@ def main():
                     help="closed-loop steps of the audited learned-distance run on the 4-arm scene (0: skip)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a summary of rocprofv3 output of a bench run and exit")
+    ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
+                    help="print a summary of a rocprofv3 --pmc pass (per-kernel counters, MFMA busy share) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.summarize:
         print(summarize(*args.summarize, steps=args.steps))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU plan all-gather "
@@ -326,14 +351,23 @@ def main():
         w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev)
         ctl2.close()
         q = max(st["queries"], 1)
+        # Inference roofline: every (rollout, step, neighbour) query costs the
+        # network's multiply-adds (17*256 + 2*256*256 + 256) x 2 FLOP.
+        n_queries = sum(a.n_rollouts * min(a.horizon, b.horizon) for i, a in enumerate(scene.arms)
+                        for j, b in enumerate(scene.arms) if i != j)
+        mlp_flops = n_queries * 2 * (17 * 256 + 2 * 256 * 256 + 256)
+        inf_ach = mlp_flops / (st["infer_ms"] * 1e-3) / 1e12
         out["surrogate"] = {
             "value": rs_per_step / (w2 / args.steps), "unit": "rollout-steps/s",
             "ms_per_step": 1e3 * w2 / args.steps, "speedup_vs_exact": wall / w2,
             "latency_ms": {"p50": float(np.percentile(lat2, 50)), "p99": float(np.percentile(lat2, 99))},
             "rollout_kernel_ms": roll2, "queries_predicted_far": st["predicted_far"] / q,
+            "roofline": {"kernel": "k_sur_infer", "bound": "mfma", "achieved": inf_ach, "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": inf_ach / BF16_PEAK_TFLOPS, "traffic": None,
+                         "kernel_ms": st["infer_ms"], "algorithmic_flop_per_launch": mlp_flops},
             "exact_checks_skipped": st["waves_skipped"] * 64 / q,
             "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()},
-            "recipe": SURROGATE_RECIPE,
+            "recipe": native.TRAINING_RECIPE,
         }
         if args.audit_steps > 0:
             sc4 = scenes.make_scene(4, collision_mode=0)

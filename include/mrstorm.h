@@ -186,12 +186,14 @@ int mpc_set_tuning(mpc_ctx *c, int rollouts_per_block, int h_tile, int grid);
 
 /* Kernel timing for measurement: while on, mpc_step launches its kernels
  * directly (no graph) and brackets every rollout launch (the fused sampling,
- * dynamics, kinematics and scoring kernel) with HIP events on the context's
- * stream. */
+ * dynamics, kinematics and scoring kernel) and, in collision mode 1, every
+ * learned-distance inference launch with HIP events on the context's stream. */
 int mpc_profile_enable(mpc_ctx *c, int on);
 /* Total and count of the bracketed rollout-launch durations since the last
  * read; waits for them and clears the record. */
 int mpc_profile_read(mpc_ctx *c, double *total_ms, int *launches);
+/* The same for the learned-distance inference launches. */
+int mpc_profile_read_surrogate(mpc_ctx *c, double *total_ms, int *launches);
 
 /* ---- learned arm-pair distance (collision_mode 1) ----
  *

@@ -18,6 +18,44 @@ using namespace mrs;
 
 static thread_local std::string g_last_error;
 
+// (start, end) HIP event pairs recorded around launches while profiling.
+struct EventLog {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  // Records the start event; returns the end event to record after the launch.
+  hipError_t begin(hipStream_t s, hipEvent_t* end) {
+    while (ev.size() < used + 2) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    hipError_t r = hipEventRecord(ev[used], s);
+    if (r != hipSuccess) return r;
+    *end = ev[used + 1];
+    used += 2;
+    return hipSuccess;
+  }
+  // Sum of the recorded durations (ms) and their count; clears the record.
+  hipError_t read(double* total_ms, int* n) {
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float ms = 0.f;
+      hipError_t r = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      if (r != hipSuccess) return r;
+      tot += ms;
+    }
+    *total_ms = tot;
+    *n = (int)(used / 2);
+    used = 0;
+    return hipSuccess;
+  }
+  void destroy() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+};
+
 struct mpc_ctx {
   int A = 0, Hmax = 0, Smax = 0, Nmax = 0, layout = 0;
   hipStream_t stream = nullptr;
@@ -59,8 +97,8 @@ struct mpc_ctx {
   uint32_t t = 0;
   bool stepped = false;
   bool profile = false;
-  std::vector<hipEvent_t> prof_events;  // pairs (start, end) of recorded rollout launches
-  size_t prof_used = 0;
+  EventLog prof_roll;                   // bracketed rollout launches
+  EventLog prof_infer;                  // bracketed learned-distance inference launches
   // learned arm-pair distance
   int collision_mode = 0;
   bool sur_ready = false;              // trained or set parameters present
@@ -318,7 +356,8 @@ extern "C" void mpc_destroy(mpc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+  c->prof_roll.destroy();
+  c->prof_infer.destroy();
   for (void* p : c->allocations) (void)hipFree(p);
   delete c;
 }
@@ -490,19 +529,13 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       I.skip = c->sur_skip;
       I.pred = debug ? c->sur_pred : nullptr;
       I.counts = c->sur_counts;
+      hipEvent_t ei = nullptr;
+      if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
       HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
+      if (ei) HIPCHK(c, hipEventRecord(ei, c->stream));
     }
     hipEvent_t e1 = nullptr;
-    if (c->profile) {
-      while (c->prof_events.size() < c->prof_used + 2) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->prof_events.push_back(e);
-      }
-      HIPCHK(c, hipEventRecord(c->prof_events[c->prof_used], c->stream));
-      e1 = c->prof_events[c->prof_used + 1];
-      c->prof_used += 2;
-    }
+    if (c->profile) HIPCHK(c, c->prof_roll.begin(c->stream, &e1));
     HIPCHK(c, launch_rollout(R, c->layout, debug, c->grid, c->stream));
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, launch_softmax(Rr, c->A, c->stream));
@@ -836,15 +869,14 @@ extern "C" int mpc_profile_enable(mpc_ctx* c, int on) {
 extern "C" int mpc_profile_read(mpc_ctx* c, double* total_ms, int* launches) {
   if (!c || !total_ms || !launches) return MPC_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double tot = 0.0;
-  for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->prof_events[i], c->prof_events[i + 1]));
-    tot += ms;
-  }
-  *total_ms = tot;
-  *launches = (int)(c->prof_used / 2);
-  c->prof_used = 0;
+  HIPCHK(c, c->prof_roll.read(total_ms, launches));
+  return MPC_OK;
+}
+
+extern "C" int mpc_profile_read_surrogate(mpc_ctx* c, double* total_ms, int* launches) {
+  if (!c || !total_ms || !launches) return MPC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, c->prof_infer.read(total_ms, launches));
   return MPC_OK;
 }
 

@@ -405,21 +405,29 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
   }
 }
 
-// Fused MLP inference, weight-stationary.  A 512-thread block (one per CU)
-// streams blocks of 32 queries (32 rollouts of one arm at one step against
-// one neighbour's plan) through a pipeline with one barrier per stage:
-//   waves 4-7 ("group B") hold 64 rows each of the third layer's weights (and
-//   of the first layer's) in registers; at stage s they run the features and
-//   first layer of query block s and the third layer of block s-2;
-//   waves 0-3 ("group A") hold 64 rows each of the second layer's weights and
-//   run that layer on block s-1, then the output layer and the skip decision
-//   of block s-3 (8 lanes per query, reduced in the wave).
+// Fused MLP inference, weight-stationary.  A block of 2 x kGroupWaves waves
+// (one block per CU) streams blocks of 32 queries (32 rollouts of one arm at
+// one step against one neighbour's plan) through a pipeline with one barrier
+// per stage:
+//   group B (the upper kGroupWaves waves) holds kWaveRows rows each of the
+//   third layer's weights (and of the first layer's) in registers; at stage
+//   s it runs the features and first layer of query block s and the third
+//   layer of block s-2;
+//   group A holds kWaveRows rows each of the second layer's weights and runs
+//   that layer on block s-1, then the output layer and the skip decision of
+//   block s-3 (8 lanes per query, reduced in the wave).
 // Activations pass between the groups through LDS as bfloat16 rows
 // [query][feature].  The products are gfx950's 32x32x16 bfloat16 MFMAs with
 // features along the rows and queries along the columns: A = weight rows,
-// B = activation rows of 32 queries.
+// B = activation rows of 32 queries; each B operand read from LDS feeds
+// kFB = kWaveRows / 32 independent accumulators.  kGroupWaves = 4 (two waves
+// per SIMD, 64 rows each) measured faster than 2 (one wave per SIMD with 128
+// rows, whose accumulators then live in AGPRs and cost a move per element).
+constexpr int kGroupWaves = 4;
+constexpr int kWaveRows = kHid / kGroupWaves;
+constexpr int kFB = kWaveRows / 32;
+constexpr int kInferThreads = 2 * kGroupWaves * kWave;
 constexpr int kActLd = kHid + 8;  // bfloat16 per LDS row: +16 bytes so consecutive rows start 4 banks apart
-constexpr int kInferThreads = 512;
 
 // What the inference loop needs of each arm, copied to LDS once.
 struct InferArm {
@@ -485,17 +493,18 @@ __device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl) {
   }
 }
 
-// 256-wide layer for this wave's 64 output features over 32 queries.
-__device__ __forceinline__ void layer256(const bf16x8_t (&w)[2][16], const uint16_t (*act)[kActLd],
-                                         const float* bl, f32x16_t (&acc)[2], int lane) {
-  init_block(acc[0], bl);
-  init_block(acc[1], bl + 32);
+// 256-wide layer for this wave's kWaveRows output features over 32 queries
+// (`bl` = bias + the lane's first feature).
+__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const uint16_t (*act)[kActLd],
+                                         const float* bl, f32x16_t (&acc)[kFB], int lane) {
+#pragma unroll
+  for (int fb = 0; fb < kFB; ++fb) init_block(acc[fb], bl + fb * 32);
   const uint16_t* row = act[lane & 31] + (lane >> 5) * 8;
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     const bf16x8_t b = load_bf16x8(row + c * 16);
-    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[0][c], b, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[1][c], b, acc[1], 0, 0, 0);
+#pragma unroll
+    for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b, acc[fb], 0, 0, 0);
   }
 }
 
@@ -538,10 +547,10 @@ __device__ __forceinline__ void fetch_block(const SurInferArgs& A, const InferLd
   for (int j = 0; j < 7; ++j) b.pq[j] = pq[j];
 }
 
-__global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
+__global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) {
   __shared__ InferLds L;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int grp = wave >> 2, wq = wave & 3, half = lane >> 5, q = lane & 31;
+  const int grp = wave / kGroupWaves, wq = wave % kGroupWaves, half = lane >> 5, q = lane & 31;
   // Loop invariants in registers and LDS: the loop's only global reads are
   // the prefetched query blocks.
   const int nA = A.P->A, Hmax = A.P->Hmax, Nmax = A.P->Nmax;
@@ -572,19 +581,19 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
     L.w4[e] = A.W16[mlp_w_off(3) + e];
   }
   if (tid == 0) L.b4 = A.P32[mlp_b_off(3)];
-  // Stationary weights: rows wq*64 + fb*32 + q, K slots c*16 + half*8 + 0..7.
-  const int row0 = wq * 64 + q;
-  bf16x8_t w[2][16];
+  // Stationary weights: rows wq*kWaveRows + fb*32 + q, K slots c*16 + half*8 + 0..7.
+  const int row0 = wq * kWaveRows + q;
+  bf16x8_t w[kFB][16];
   {
     const uint16_t* src = A.W16 + mlp_w_off(grp == 0 ? 1 : 2) + (long long)row0 * kHid + half * 8;
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb)
+    for (int fb = 0; fb < kFB; ++fb)
 #pragma unroll
       for (int c = 0; c < 16; ++c) w[fb][c] = load_bf16x8(src + fb * 32 * kHid + c * 16);
   }
-  bf16x8_t w1[2][2];
+  bf16x8_t w1[kFB][2];
 #pragma unroll
-  for (int fb = 0; fb < 2; ++fb)
+  for (int fb = 0; fb < kFB; ++fb)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -597,7 +606,7 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
 
   const int G = gridDim.x;
   const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
-  const int fcol = wq * 64 + half * 4;  // this lane's first feature within an accumulator block
+  const int fcol = wq * kWaveRows + half * 4;  // this lane's first feature within an accumulator block
   // Group B keeps the reads of the next block and the item after it in flight.
   BlockIn cur, nxt;
   SurItem item2{};
@@ -631,9 +640,9 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
         const uint4 xw1 = make_uint4(half ? 0u : f2bf2(g[8], g[9]), 0u, 0u, 0u);
         const bf16x8_t x0 = __builtin_bit_cast(bf16x8_t, xw0);
         const bf16x8_t x1 = __builtin_bit_cast(bf16x8_t, xw1);
-        f32x16_t acc[2];
+        f32x16_t acc[kFB];
 #pragma unroll
-        for (int fb = 0; fb < 2; ++fb) {
+        for (int fb = 0; fb < kFB; ++fb) {
           init_block(acc[fb], &L.bias[0][fcol + fb * 32]);
           acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][0], x0, acc[fb], 0, 0, 0);
           acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc[fb], 0, 0, 0);
@@ -650,60 +659,65 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_infer(SurInferArgs A) {
       }
       if (s >= 2 && s - 2 < n_my) {
         // Third layer of query block s-2.
-        f32x16_t acc[2];
+        f32x16_t acc[kFB];
         layer256(w, L.act2[(s - 2) & 1], &L.bias[2][fcol], acc, lane);
-        store_block(acc[0], &L.act3[(s - 2) & 1][q][fcol]);
-        store_block(acc[1], &L.act3[(s - 2) & 1][q][fcol + 32]);
+#pragma unroll
+        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act3[(s - 2) & 1][q][fcol + fb * 32]);
       }
     } else {
       if (s >= 1 && s - 1 < n_my) {
         // Second layer of query block s-1.
-        f32x16_t acc[2];
+        f32x16_t acc[kFB];
         layer256(w, L.act1[(s - 1) & 1], &L.bias[1][fcol], acc, lane);
-        store_block(acc[0], &L.act2[(s - 1) & 1][q][fcol]);
-        store_block(acc[1], &L.act2[(s - 1) & 1][q][fcol + 32]);
+#pragma unroll
+        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][q][fcol + fb * 32]);
       }
       if (s >= 3) {
-        // Output layer and decision of query block s-3: query wq*8 + lane/8;
-        // the 8 lanes of a query take 16-byte chunks j, j+8, j+16, j+24
-        // (j = lane%8), so each 8-lane group reads 128 contiguous bytes.
-        const int r = (s - 3) & 3, qq = wq * 8 + (lane >> 3), j = lane & 7;
-        const uint16_t* row = &L.act3[(s - 3) & 1][qq][0];
-        float pi[4];
+        // Output layer and decision of query block s-3: 8 lanes per query
+        // (queries wq*32/kGroupWaves + pass*8 + lane/8); the 8 lanes take
+        // 16-byte chunks j, j+8, j+16, j+24 (j = lane%8), so each 8-lane group
+        // reads 128 contiguous bytes.
+        const int r = (s - 3) & 3, j = lane & 7;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int k = (j + 8 * i) * 8;
-          const uint4 a = *reinterpret_cast<const uint4*>(row + k);
-          const uint4 wv = *reinterpret_cast<const uint4*>(&L.w4[k]);
-          float t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.x),
-                                                    __builtin_bit_cast(bf16x2_t, wv.x), 0.f, false);
-          t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.y), __builtin_bit_cast(bf16x2_t, wv.y), t,
-                                              false);
-          t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.z), __builtin_bit_cast(bf16x2_t, wv.z), t,
-                                              false);
-          pi[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.w), __builtin_bit_cast(bf16x2_t, wv.w),
-                                                  t, false);
-        }
-        // sum over the 8 lanes of the query: swaps within quads, then the
-        // mirrored lane of the other quad of the row of 8
-        float part = (pi[0] + pi[1]) + (pi[2] + pi[3]);
-        part += dpp_f32<0xB1>(part);   // quad_perm [1,0,3,2]
-        part += dpp_f32<0x4E>(part);   // quad_perm [2,3,0,1]
-        part += dpp_f32<0x141>(part);  // row_half_mirror
-        const bool writer = (lane & 7) == 0 && qq < L.n_rows[r];
-        const int okv = L.ok[r][qq];
-        const float y = part + L.b4;
-        const bool far = (okv & 2) != 0 && y >= margin;
-        if (writer) {
-          const long long o = L.out_row[r] + qq;
-          A.skip[o] = far ? 1 : 0;
-          if (A.pred) A.pred[o] = y;
-        }
-        const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
-        const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
-        if (lane == 0 && (nq | nf)) {
-          atomicAdd(&L.cnt[L.out_arm[r]][0], nq);
-          atomicAdd(&L.cnt[L.out_arm[r]][1], nf);
+        for (int pass = 0; pass < 4 / kGroupWaves; ++pass) {
+          const int qq = wq * (32 / kGroupWaves) + pass * 8 + (lane >> 3);
+          const uint16_t* row = &L.act3[(s - 3) & 1][qq][0];
+          float pi[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = (j + 8 * i) * 8;
+            const uint4 a = *reinterpret_cast<const uint4*>(row + k);
+            const uint4 wv = *reinterpret_cast<const uint4*>(&L.w4[k]);
+            float t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.x),
+                                                      __builtin_bit_cast(bf16x2_t, wv.x), 0.f, false);
+            t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.y), __builtin_bit_cast(bf16x2_t, wv.y),
+                                                t, false);
+            t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.z), __builtin_bit_cast(bf16x2_t, wv.z),
+                                                t, false);
+            pi[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.w),
+                                                    __builtin_bit_cast(bf16x2_t, wv.w), t, false);
+          }
+          // sum over the 8 lanes of the query: swaps within quads, then the
+          // mirrored lane of the other quad of the row of 8
+          float part = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+          part += dpp_f32<0xB1>(part);   // quad_perm [1,0,3,2]
+          part += dpp_f32<0x4E>(part);   // quad_perm [2,3,0,1]
+          part += dpp_f32<0x141>(part);  // row_half_mirror
+          const bool writer = j == 0 && qq < L.n_rows[r];
+          const int okv = L.ok[r][qq];
+          const float y = part + L.b4;
+          const bool far = (okv & 2) != 0 && y >= margin;
+          if (writer) {
+            const long long o = L.out_row[r] + qq;
+            A.skip[o] = far ? 1 : 0;
+            if (A.pred) A.pred[o] = y;
+          }
+          const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
+          const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
+          if (lane == 0 && (nq | nf)) {
+            atomicAdd(&L.cnt[L.out_arm[r]][0], nq);
+            atomicAdd(&L.cnt[L.out_arm[r]][1], nf);
+          }
         }
       }
     }

@@ -25,9 +25,14 @@ EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destr
            "mpc_profile_read", "mpc_pair_distance", "mpc_pair_features", "mpc_surrogate_samples",
            "mpc_surrogate_train", "mpc_surrogate_get_params", "mpc_surrogate_set_params",
            "mpc_surrogate_predict", "mpc_surrogate_grad", "mpc_set_collision_mode",
-           "mpc_surrogate_audit", "mpc_surrogate_stats"]
+           "mpc_surrogate_audit", "mpc_surrogate_stats", "mpc_profile_read_surrogate"]
 MLP_WIDTHS = [17, 256, 256, 256, 1]
 MLP_PARAMS = 136449
+# Default training recipe of the learned distance: 2M exact-kernel samples,
+# Adam; the loss weighs over-prediction (the unsafe direction) 256x and
+# samples within 0.15 m of contact 5x, with targets clipped to [-0.1, 0.5] m.
+TRAINING_RECIPE = dict(samples=2_000_000, epochs=40, batch=4096, lr=1e-3, over_weight=256.0, near_weight=4.0,
+                       near_band=0.15, target_floor=-0.1, target_clip=0.5, val_fraction=0.05, seed=7)
 
 
 class MpcError(RuntimeError):
@@ -114,6 +119,7 @@ def lib():
         L.mpc_surrogate_stats.argtypes = [vp, vp, ip]
         L.mpc_profile_enable.argtypes = [vp, ip]
         L.mpc_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ip)]
+        L.mpc_profile_read_surrogate.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ip)]
         _lib = L
     return _lib
 
@@ -285,6 +291,12 @@ class Controller:
         """(total ms, launches) of the rollout kernels bracketed since the last read."""
         ms, n = C.c_double(), C.c_int()
         _check(lib().mpc_profile_read(self.h, C.byref(ms), C.byref(n)), self.h)
+        return ms.value, n.value
+
+    def profile_read_surrogate(self):
+        """(total ms, launches) of the learned-distance inference kernels bracketed since the last read."""
+        ms, n = C.c_double(), C.c_int()
+        _check(lib().mpc_profile_read_surrogate(self.h, C.byref(ms), C.byref(n)), self.h)
         return ms.value, n.value
 
 

@@ -251,8 +251,7 @@ def trained4():
     _say("case: training on the 4-arm scene (2M samples)")
     sc = scenes.make_scene(4, collision_mode=0)
     ctl = native.Controller(sc.arms, sc.params)
-    rep = ctl.surrogate_train(samples=2_000_000, epochs=20, batch=4096, lr=1e-3, over_weight=256.0,
-                              near_weight=4.0, near_band=0.15, target_floor=-0.1, seed=7)
+    rep = ctl.surrogate_train(**native.TRAINING_RECIPE)
     _say(f"  report {rep}")
     params = ctl.surrogate_params().clone()
     yield sc, ctl, params, rep
