@@ -223,19 +223,22 @@ def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
 
 
 def audit_run(scene, params, steps, dev, goal_age=50):
-    """Learned-distance closed loop with every query also checked exactly:
-    counts of predictions at or beyond the margin whose exact distance is below
-    buf_dyn (misses) or below zero (missed collisions), and the smallest exact
-    gap between the arms as executed.  Goals are reset every goal_age steps
-    (staggered per arm) so that the arms keep crossing the shared workspace."""
+    """Closed loop with goals reset every goal_age steps (staggered per arm)
+    so that the arms keep crossing the shared workspace.  With params: the
+    learned distance, audited (the dropped checks are also computed exactly):
+    counts of dropped queries whose exact distance is below buf_dyn (misses)
+    or below zero (missed collisions).  Without: the exact controller on the
+    same goal sequence.  Both report the smallest exact gap between the arms
+    as executed."""
     import torch
     from paper_2602_10114_amd import native
     A = scene.n_arms
     rng = np.random.default_rng(scene.seed + 99)
     ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
-    ctl.set_surrogate_params(params)
-    ctl.set_collision_mode(1)
-    ctl.surrogate_audit(True)
+    if params is not None:
+        ctl.set_surrogate_params(params)
+        ctl.set_collision_mode(1)
+        ctl.surrogate_audit(True)
     state = torch.as_tensor(scene.state, device=dev).contiguous()
     goal = torch.as_tensor(scene.goal, device=dev).contiguous()
     u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
@@ -380,6 +383,7 @@ def main():
                                            args.warmup, 1, dev)
             ctl4.close()
             aud = audit_run(sc4, p4, args.audit_steps, dev)
+            aud_exact = audit_run(scenes.make_scene(4, collision_mode=0), None, args.audit_steps, dev)
             out["surrogate_4arm"] = {
                 "workload": "4 arms on a 1.2 m square, 1024 rollouts x 30 steps each, 8 moving obstacles",
                 "exact_ms_per_step": 1e3 * w4e / args.steps, "surrogate_ms_per_step": 1e3 * w4l / args.steps,
@@ -387,6 +391,8 @@ def main():
                 "exact_checks_skipped": st4["waves_skipped"] * 64 / max(st4["queries"], 1),
                 "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep4.items()},
                 "audit": aud,
+                "exact_same_goals": {"executed_min_arm_gap_m": aud_exact["executed_min_arm_gap_m"],
+                                     "seconds": aud_exact["seconds"]},
             }
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
