@@ -268,6 +268,48 @@ def audit_run(scene, params, steps, dev, goal_age=50):
             "executed_min_arm_gap_m": gap, "seconds": wall}
 
 
+def ablation_run(variant, steps, dev):
+    """Closed loop on the two facing arms (0.8 m apart, goals drawn in the
+    shared middle region): MR-STORM (tau = 3, shared plans), M_tau (tau = 0:
+    no priority) or S_d (no plans: each arm sees the other's current spheres
+    as a static obstacle).  Goals are re-drawn when reached (5 cm) or after
+    150 steps (3 s).  Returns goals reached and their mean time, steps where
+    both arms are stalled away from their goals (joint speed below 0.05
+    rad/s, more than 10 cm from the goal: the livelock signature), and the
+    smallest executed gap after the first step (the start pose is shared)."""
+    import torch
+    from paper_2602_10114_amd import native
+    over = {"M": {}, "M_tau": {"tau": 0.0}, "S_d": {"plan_mode": 1}}[variant]
+    sc = scenes.make_scene(2, collision_mode=0, **over)
+    A = sc.n_arms
+    rng = np.random.default_rng(sc.seed + 7)
+    ctl = native.Controller(sc.arms, sc.params)
+    state = torch.as_tensor(sc.state, device=dev).contiguous()
+    u = torch.zeros((A, 7), dtype=torch.float32, device=dev)
+    age = np.zeros(A, dtype=int)
+    reached, stalled, t_reach = 0, 0, []
+    qs = torch.empty((steps, A, 7), dtype=torch.float32, device=dev)
+    for k in range(steps):
+        ctl.share_plans()
+        ctl.step(state, sc.goal, None, u_out=u)
+        ctl.sim_execute(state, u)
+        qs[k].copy_(state[:, :, 0])
+        dist = np.array([float(ctl.debug_get("DIST", a)[0]) for a in range(A)])
+        speed = state[:, :, 1].abs().max(dim=1).values.cpu().numpy()
+        if np.all((speed < 0.05) & (dist > 0.10)):
+            stalled += 1
+        m = scenes.reset_goals(sc, rng, dist, age, tol=0.05, max_age=150)
+        hit = m & (dist < 0.05)
+        reached += int(np.sum(hit))
+        t_reach += [int(age[a]) + 1 for a in np.nonzero(hit)[0]]
+        age = np.where(m, 0, age + 1)
+    gaps = ctl.pair_distance(0, 1, qs[:, 0].contiguous(), qs[:, 1].contiguous())
+    ctl.close()
+    return {"goals_reached": reached, "mean_steps_to_goal": float(np.mean(t_reach)) if t_reach else None,
+            "stalled_steps": stalled, "executed_min_arm_gap_m": float(gaps[1:].min()),
+            "start_gap_m": float(gaps[0]), "steps": steps}
+
+
 def train_surrogate(scene):
     from paper_2602_10114_amd import native
     ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
@@ -286,6 +328,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-distance legs")
     ap.add_argument("--audit-steps", type=int, default=10000,
                     help="closed-loop steps of the audited learned-distance run on the 4-arm scene (0: skip)")
+    ap.add_argument("--ablation-steps", type=int, default=1500,
+                    help="closed-loop steps of each variant of the two-arm ablation (0: skip)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a summary of rocprofv3 output of a bench run and exit")
     ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
@@ -394,6 +438,8 @@ def main():
                 "exact_same_goals": {"executed_min_arm_gap_m": aud_exact["executed_min_arm_gap_m"],
                                      "seconds": aud_exact["seconds"]},
             }
+    if args.ablation_steps > 0:
+        out["ablation_2arm"] = {v: ablation_run(v, args.ablation_steps, dev) for v in ("M", "M_tau", "S_d")}
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -83,6 +83,10 @@ typedef struct {
   int max_obstacles;       /* capacity for obstacle spheres per step, <= MPC_MAX_OBSTACLES */
   int collision_mode;      /* 0: exact coordination distances; 1: learned distance with exact fallback */
   float surrogate_margin;  /* mode 1: predictions below this (metres) are checked exactly */
+  float alpha_sigma;       /* covariance step size (Eqs. 3-4), [0, 1]; 0 keeps Sigma = sigma^2 I */
+  float sigma_floor;       /* floor of the Cholesky pivots of the adapted Sigma (std. dev. units), > 0 */
+  int plan_mode;           /* 0: publish the predicted plan (Sec. IV-A); 1: publish the current
+                              spheres at every step, a static obstacle (the paper's S_d ablation) */
 } mpc_params;
 
 /* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).
@@ -150,8 +154,11 @@ enum {
   MPC_DBG_PASSES = 12,     /* unsigned long long [3]: per-wave count of distance filter
                               passes over obstacle/neighbour sets, of exact (FP64) passes
                               over such sets, and of exact self-collision passes */
-  MPC_DBG_PRED = 13        /* float [n_arms][horizon][n_rollouts]: learned-distance
+  MPC_DBG_PRED = 13,       /* float [n_arms][horizon][n_rollouts]: learned-distance
                               prediction against each neighbour (collision mode 1) */
+  MPC_DBG_SIGMA = 14,      /* float [horizon][28]: sampling covariance Sigma_h (Eqs. 3-4), packed
+                              lower triangle, row j holds (j, 0..j); always available */
+  MPC_DBG_CHOL = 15        /* float [horizon][28]: its Cholesky factor L_h (eps = L_h z); always available */
 };
 /* Copy one captured quantity of one arm into dev_out (device). */
 int mpc_debug_get(mpc_ctx *c, int what, int arm, void *dev_out);

@@ -42,7 +42,8 @@ class OrcParams(C.Structure):
         "dt", "sigma", "lam", "gamma", "alpha_mu", "w_pose", "w_rot", "w_stop", "w_joint",
         "w_coll", "w_dyn", "buf_env", "buf_self", "buf_dyn", "tau", "prio_min", "prio_max",
         "dist_floor", "joint_margin")] + [("seed", C.c_ulonglong), ("iters", C.c_int),
-                                          ("pad_", C.c_int)]
+                                          ("plan_mode", C.c_int), ("alpha_sigma", C.c_double),
+                                          ("sigma_floor", C.c_double)]
 
 
 _lib = None
@@ -86,6 +87,9 @@ def lib():
         L.orc_weights.argtypes = [C.c_int, C.c_double, _dp, _dp]
         L.orc_weighted_mean.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_ema.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp]
+        L.orc_weighted_cov.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_cholesky_floor.argtypes = [C.c_int, _dp, C.c_double, _dp]
+        L.orc_get_sigma.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_argmin.argtypes = [C.c_int, _dp]
         L.orc_argmin.restype = C.c_int
         L.orc_shift.argtypes = [C.c_int, C.c_int, _dp]
@@ -159,11 +163,12 @@ def make_arm(arm) -> OrcArm:
 def make_params(p: dict) -> OrcParams:
     o = OrcParams()
     for name, _ in OrcParams._fields_:
-        if name in ("seed", "iters", "pad_"):
+        if name in ("seed", "iters", "plan_mode"):
             continue
-        setattr(o, name, float(np.float32(p[name])))
+        setattr(o, name, float(np.float32(p.get(name, 0.0 if name == "alpha_sigma" else 1e-3))))
     o.seed = int(p["seed"])
     o.iters = int(p["iters"])
+    o.plan_mode = int(p.get("plan_mode", 0))
     return o
 
 
@@ -264,6 +269,22 @@ def weighted_mean(w, U):
     mt = np.zeros((H, d))
     lib().orc_weighted_mean(N, H, d, _f64(w), U, mt)
     return mt
+
+
+def weighted_cov(w, U, mt):
+    U = _f64(U)
+    N, H, d = U.shape
+    out = np.zeros((H, d, d))
+    lib().orc_weighted_cov(N, H, d, _f64(w), U, _f64(mt), out)
+    return out
+
+
+def cholesky_floor(S, floor_var):
+    S = _f64(S)
+    d = S.shape[0]
+    L = np.zeros((d, d))
+    lib().orc_cholesky_floor(d, S, float(floor_var), L)
+    return L
 
 
 def ema(mu, mt, a):
@@ -415,6 +436,13 @@ class Controller:
 
     def set_mean(self, a, mu):
         lib().orc_set_mean(self.h, a, _f64(mu))
+
+    def sigma(self, a):
+        """(covariances, Cholesky factors) of arm a, [Hmax][d][d] each."""
+        H, d = self.Hmax, self.d
+        sig, chol = np.zeros((H, d, d)), np.zeros((H, d, d))
+        lib().orc_get_sigma(self.h, a, sig.ctypes.data_as(C.c_void_p), chol.ctypes.data_as(C.c_void_p))
+        return sig, chol
 
     def plan(self, a, side=0):
         p = np.zeros((self.Hmax, self.Smax, 4))

@@ -367,6 +367,39 @@ void orc_ema(int H, int dof, double a, const double *mt, double *mu) {
   for (int i = 0; i < H * dof; ++i) mu[i] = (1.0 - a) * mu[i] + a * mt[i];
 }
 
+/* Eq. 3, second half: Sigma~_h = sum_n w_n (U_{n,h} - mu~_h)(U_{n,h} - mu~_h)^T.
+ * U: [N][H][d], mt: [H][d] (the weighted mean), out: [H][d][d]. */
+void orc_weighted_cov(int N, int H, int dof, const double *w, const double *U, const double *mt, double *out) {
+  for (int h = 0; h < H; ++h)
+    for (int i = 0; i < dof; ++i)
+      for (int j = 0; j < dof; ++j) {
+        double s = 0.0;
+        for (int n = 0; n < N; ++n) {
+          const double *u = U + ((size_t)n * H + h) * dof;
+          s += w[n] * (u[i] - mt[h * dof + i]) * (u[j] - mt[h * dof + j]);
+        }
+        out[((size_t)h * dof + i) * dof + j] = s;
+      }
+}
+
+/* Cholesky factor L (lower, row-major d x d) of the symmetric S, each pivot
+ * floored at floor_var (reading: keeps the sampling distribution proper when
+ * the weights collapse onto one rollout). */
+void orc_cholesky_floor(int dof, const double *S, double floor_var, double *L) {
+  for (int i = 0; i < dof * dof; ++i) L[i] = 0.0;
+  for (int j = 0; j < dof; ++j) {
+    double d = S[j * dof + j];
+    for (int m = 0; m < j; ++m) d -= L[j * dof + m] * L[j * dof + m];
+    if (d < floor_var) d = floor_var;
+    L[j * dof + j] = sqrt(d);
+    for (int i = j + 1; i < dof; ++i) {
+      double v = S[i * dof + j];
+      for (int m = 0; m < j; ++m) v -= L[i * dof + m] * L[j * dof + m];
+      L[i * dof + j] = v / L[j * dof + j];
+    }
+  }
+}
+
 /* Act: n* = argmin_n C_n, lowest index on ties (reading of the argmin). */
 int orc_argmin(int N, const double *C) {
   int best = 0;
@@ -402,6 +435,7 @@ struct orc_ctx {
   uint32_t t;
   int n_lo, n_hi;
   double *mu;           /* [A][Hmax][d] */
+  double *sig, *chol;   /* [A][Hmax][d][d]: sampling covariance (Eqs. 3-4) and its factor */
   double *plan[2];      /* [A][Hmax][Smax][4]; side 0 = read, 1 = write */
   double *plan_q[2];    /* [A][Hmax][d] */
   double dist[2][ORC_MAX_ARMS];
@@ -426,6 +460,13 @@ orc_ctx *orc_create(const orc_arm *arms, int n_arms, const orc_params *p) {
   c->n_lo = 0; c->n_hi = 1 << 30;
   size_t A = n_arms, H = c->Hmax, S = c->Smax, N = c->Nmax, d = c->dof;
   c->mu = (double *)calloc(A * H * d, sizeof(double));
+  c->sig = (double *)calloc(A * H * d * d, sizeof(double));
+  c->chol = (double *)calloc(A * H * d * d, sizeof(double));
+  for (size_t i = 0; i < A * H; ++i)
+    for (size_t j = 0; j < d; ++j) {
+      c->sig[(i * d + j) * d + j] = p->sigma * p->sigma;  /* Sigma = sigma^2 I ... */
+      c->chol[(i * d + j) * d + j] = p->sigma;            /* ... whose factor is sigma I */
+    }
   for (int s = 0; s < 2; ++s) {
     c->plan[s] = (double *)calloc(A * H * S * 4, sizeof(double));
     c->plan_q[s] = (double *)calloc(A * H * d, sizeof(double));
@@ -439,7 +480,7 @@ orc_ctx *orc_create(const orc_arm *arms, int n_arms, const orc_params *p) {
 
 void orc_destroy(orc_ctx *c) {
   if (!c) return;
-  free(c->mu);
+  free(c->mu); free(c->sig); free(c->chol);
   for (int s = 0; s < 2; ++s) { free(c->plan[s]); free(c->plan_q[s]); }
   free(c->last_total); free(c->last_w); free(c->last_stage); free(c->last_eps);
   free(c);
@@ -469,7 +510,14 @@ static void to_plan(orc_ctx *c, int a, const double *state) {
   double q0[ORC_MAX_DOF], qd0[ORC_MAX_DOF];
   for (int j = 0; j < d; ++j) { q0[j] = state[3 * j]; qd0[j] = state[3 * j + 1]; }
   double *q = (double *)malloc(sizeof(double) * H * d), *qd = (double *)malloc(sizeof(double) * H * d);
-  orc_integrate(d, H, c->p.dt, q0, qd0, c->mu + a * Hm * d, q, qd);
+  if (c->p.plan_mode == 1) {
+    /* S_d ablation: the arm's current configuration at every step (its
+     * spheres act as a static obstacle for the others). */
+    for (int h = 0; h < H; ++h)
+      for (int j = 0; j < d; ++j) q[h * d + j] = q0[j];
+  } else {
+    orc_integrate(d, H, c->p.dt, q0, qd0, c->mu + a * Hm * d, q, qd);
+  }
   double *out = c->plan[1] + a * Hm * Sm * 4;
   double *outq = c->plan_q[1] + a * Hm * d;
   memset(out, 0, Hm * Sm * 4 * sizeof(double));
@@ -513,6 +561,10 @@ void orc_step(orc_ctx *c, const double *state, const double *goal, const double 
     double q0[ORC_MAX_DOF], qd0[ORC_MAX_DOF];
     for (int j = 0; j < d; ++j) { q0[j] = st[3 * j]; qd0[j] = st[3 * j + 1]; }
     orc_shift(H, d, mu);
+    /* phi = (mu, Sigma): the covariances (and their factors) shift too. */
+    double *sig = c->sig + a * Hm * d * d, *chol = c->chol + a * Hm * d * d;
+    orc_shift(H, d * d, sig);
+    orc_shift(H, d * d, chol);
     double *U = (double *)malloc(sizeof(double) * N * H * d);
     double *q = (double *)malloc(sizeof(double) * H * d);
     double *qd = (double *)malloc(sizeof(double) * H * d);
@@ -530,8 +582,11 @@ void orc_step(orc_ctx *c, const double *state, const double *goal, const double 
         for (int h = 0; h < H; ++h) {
           double z[ORC_MAX_DOF];
           orc_normals(p->seed, a, c->t, k, n0 + n, h, d, z);
+          const double *L = chol + (size_t)h * d * d;
           for (int j = 0; j < d; ++j) {
-            double e = p->sigma * z[j];
+            /* eps ~ N(0, Sigma_h): eps = L_h z (sigma z while Sigma = sigma^2 I) */
+            double e = 0.0;
+            for (int m = 0; m <= j; ++m) e += L[j * d + m] * z[m];
             U[((size_t)n * H + h) * d + j] = mu[h * d + j] + e;
             if (k == p->iters - 1) c->last_eps[(((size_t)a * Nm + n) * Hm + h) * d + j] = e;
           }
@@ -568,6 +623,15 @@ void orc_step(orc_ctx *c, const double *state, const double *goal, const double 
         int nb = orc_argmin(N, Ctot);
         for (int j = 0; j < d; ++j) u_out[a * c->dof + j] = U[(size_t)nb * H * d + j];
       }
+      if (p->alpha_sigma > 0.0) {
+        /* Eq. 3 (Sigma~), Eq. 4 (EMA), then the factor used by the next draw. */
+        double *st = (double *)malloc(sizeof(double) * H * d * d);
+        orc_weighted_cov(N, H, d, w, U, mt, st);
+        for (int i = 0; i < H * d * d; ++i) sig[i] = (1.0 - p->alpha_sigma) * sig[i] + p->alpha_sigma * st[i];
+        for (int h = 0; h < H; ++h)
+          orc_cholesky_floor(d, sig + (size_t)h * d * d, p->sigma_floor * p->sigma_floor, chol + (size_t)h * d * d);
+        free(st);
+      }
       orc_ema(H, d, p->alpha_mu, mt, mu);
     }
     to_plan(c, a, st);
@@ -577,6 +641,11 @@ void orc_step(orc_ctx *c, const double *state, const double *goal, const double 
   c->t += 1;
 }
 
+void orc_get_sigma(const orc_ctx *c, int a, double *sig, double *chol) {
+  size_t n = (size_t)c->Hmax * c->dof * c->dof;
+  if (sig) memcpy(sig, c->sig + a * n, sizeof(double) * n);
+  if (chol) memcpy(chol, c->chol + a * n, sizeof(double) * n);
+}
 void orc_get_mean(const orc_ctx *c, int a, double *mu) {
   memcpy(mu, c->mu + (size_t)a * c->Hmax * c->dof, sizeof(double) * c->Hmax * c->dof);
 }

@@ -36,7 +36,8 @@ typedef struct {
   double buf_env, buf_self, buf_dyn, tau, prio_min, prio_max, dist_floor, joint_margin;
   unsigned long long seed;
   int iters;
-  int pad_;
+  int plan_mode;                  /* 0: predicted plan; 1: current spheres at every step (S_d) */
+  double alpha_sigma, sigma_floor;
 } orc_params;
 
 /* ---- primitives ---- */
@@ -60,6 +61,11 @@ double orc_total_cost(int H, double gamma, const double *stage /*[H]*/);
 void orc_weights(int N, double lambda, const double *C, double *w);
 void orc_weighted_mean(int N, int H, int dof, const double *w, const double *U /*[N][H][d]*/, double *mu_tilde);
 void orc_ema(int H, int dof, double alpha_mu, const double *mu_tilde, double *mu);
+/* Eq. 3, second half: Sigma~_h = sum_n w_n (U_{n,h} - mu~_h)(U_{n,h} - mu~_h)^T;
+ * U [N][H][d], mt [H][d], out [H][d][d]. */
+void orc_weighted_cov(int N, int H, int dof, const double *w, const double *U, const double *mt, double *out);
+/* Lower Cholesky factor of a symmetric d x d matrix, pivots floored at floor_var. */
+void orc_cholesky_floor(int dof, const double *S, double floor_var, double *L);
 int orc_argmin(int N, const double *C);
 void orc_shift(int H, int dof, double *mu);
 long long orc_pair_count(int H, int N, int S_own, const int *S_nb, int n_nb);
@@ -97,6 +103,8 @@ void orc_step(orc_ctx *c, const double *state, const double *goal, const double 
 void orc_set_rollout_window(orc_ctx *c, int n_lo, int n_hi);
 /* Accessors for the last step (arm a). */
 void orc_get_mean(const orc_ctx *c, int a, double *mu /*[H][d]*/);
+/* Sampling covariances and their factors of arm a, [Hmax][d][d] each (either may be NULL). */
+void orc_get_sigma(const orc_ctx *c, int a, double *sig, double *chol);
 void orc_set_mean(orc_ctx *c, int a, const double *mu);
 void orc_get_plan(const orc_ctx *c, int a, int side, double *plan /*[H][S][4]*/,
                   double *plan_q /*[H][d]*/, double *dist, int *valid);

@@ -67,6 +67,8 @@ struct mpc_ctx {
   BoardMeta* d_meta = nullptr;
   float* mu = nullptr;
   float* eps = nullptr;
+  float* sig = nullptr;                // [A][Hmax][28] adapted covariances (packed lower triangles)
+  float* chol = nullptr;               // their Cholesky factors
   float* partial = nullptr;
   float* cost = nullptr;
   float* w = nullptr;
@@ -265,6 +267,9 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (p->max_obstacles < 0 || p->max_obstacles > MPC_MAX_OBSTACLES)
     return fail(nullptr, MPC_EINVAL, "max_obstacles outside 0..64");
   if (p->collision_mode != 0 && p->collision_mode != 1) return fail(nullptr, MPC_EINVAL, "collision_mode must be 0 or 1");
+  if (!(p->alpha_sigma >= 0.f && p->alpha_sigma <= 1.f)) return fail(nullptr, MPC_EINVAL, "alpha_sigma outside [0, 1]");
+  if (!(p->sigma_floor > 0.f && p->sigma_floor < 1e3f)) return fail(nullptr, MPC_EINVAL, "sigma_floor must be positive");
+  if (p->plan_mode != 0 && p->plan_mode != 1) return fail(nullptr, MPC_EINVAL, "plan_mode must be 0 or 1");
   if (p->collision_mode == 1 && !(p->surrogate_margin >= p->buf_dyn))
     return fail(nullptr, MPC_EINVAL, "surrogate_margin must be at least buf_dyn");
 
@@ -299,6 +304,8 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   P.w_coll = p->w_coll; P.w_dyn = p->w_dyn; P.buf_env = p->buf_env; P.buf_self = p->buf_self;
   P.buf_dyn = p->buf_dyn; P.tau = p->tau; P.prio_min = p->prio_min; P.prio_max = p->prio_max;
   P.dist_floor = p->dist_floor; P.joint_margin = p->joint_margin;
+  P.alpha_sigma = p->alpha_sigma; P.sigma_floor = p->sigma_floor;
+  P.plan_mode = p->plan_mode; P.cov = p->alpha_sigma > 0.f ? 1 : 0;
   P.seed_lo = (uint32_t)(p->seed & 0xffffffffull);
   P.seed_hi = (uint32_t)(p->seed >> 32);
   P.iters = p->iters; P.A = n_arms; P.dof = 7; P.Hmax = c->Hmax; P.Smax = c->Smax; P.Nmax = c->Nmax;
@@ -315,13 +322,24 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
       (rc = dalloc(c, &c->st_goalR, A * 9)) || (rc = dalloc(c, &c->st_obs, (size_t)kMaxObs * 4)) ||
       (rc = dalloc(c, &c->plan[0], A * H * S * 4)) || (rc = dalloc(c, &c->plan[1], A * H * S * 4)) ||
       (rc = dalloc(c, &c->planq[0], A * H * 7)) || (rc = dalloc(c, &c->planq[1], A * H * 7)) ||
-      (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A))) {
+      (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A)) ||
+      (rc = dalloc(c, &c->sig, A * H * kTri)) || (rc = dalloc(c, &c->chol, A * H * kTri))) {
     g_last_error = c->err;
     mpc_destroy(c);
     return rc;
   }
+  // Sigma_h = sigma^2 I and its factor sigma I (set directly, not factorised,
+  // so that without adaptation the noise is exactly sigma z).
+  std::vector<float> sig0(A * H * kTri, 0.f), chol0(A * H * kTri, 0.f);
+  for (size_t i = 0; i < A * H; ++i)
+    for (int j = 0; j < 7; ++j) {
+      sig0[i * kTri + tri7(j, j)] = p->sigma * p->sigma;
+      chol0[i * kTri + tri7(j, j)] = p->sigma;
+    }
   if (hipMemcpy(c->d_arms, c->harms.data(), A * sizeof(DevArm), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_P, &c->P, sizeof(Params), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->d_P, &c->P, sizeof(Params), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->sig, sig0.data(), sig0.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->chol, chol0.data(), chol0.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
     fail(c, MPC_EHIP, "upload of arm tables failed");
     mpc_destroy(c);
     return MPC_EHIP;
@@ -412,6 +430,7 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.skip = c->collision_mode == 1 ? c->sur_skip : nullptr;
   R.audit = c->sur_audit ? 1 : 0;
   R.sur_counts = c->sur_counts;
+  R.eps_in = c->P.cov ? c->eps : nullptr;
   return R;
 }
 
@@ -432,6 +451,8 @@ static ReduceArgs reduce_args(const mpc_ctx* c) {
   R.plan_write = c->plan[1];
   R.planq_write = c->planq[1];
   R.meta = c->d_meta;
+  R.sig = c->sig;
+  R.chol = c->chol;
   return R;
 }
 
@@ -479,6 +500,7 @@ static int tune(mpc_ctx* c) {
       for (int g : {1024, 2048, 4096})
         if (g < c->n_items) grids.push_back(g);
     }
+    if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
     for (int g : grids) {
       RolloutArgs R = rollout_args(c, 0);
       HIPCHK(c, launch_rollout(R, c->layout, false, g, c->stream));
@@ -510,11 +532,13 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
   ReduceArgs Rr = reduce_args(c);
   for (int k = 0; k < c->P.iters; ++k) {
     RolloutArgs R = rollout_args(c, k);
+    if (c->P.cov)
+      HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, k, c->A, c->Nmax, c->stream));
     if (c->collision_mode == 1) {
       // Learned distance: own-joint features of every rollout step, then the MLP's
       // skip decision per (rollout, step, neighbour).
-      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, k, c->A, c->Nmax, c->sur_F,
-                                  c->stream));
+      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A,
+                                  c->Nmax, c->sur_F, c->stream));
       SurInferArgs I{};
       I.arms = c->d_arms;
       I.P = c->d_P;
@@ -620,6 +644,8 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
   S.st_obs = c->st_obs;
   S.goalR = c->st_goalR;
   S.mu = c->mu;
+  S.sig = c->sig;
+  S.chol = c->chol;
   HIPCHK(c, launch_sense(S, c->stream));
   int rc;
   if (!c->tuned) {
@@ -769,6 +795,11 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
       break;
     case MPC_DBG_ARGMIN:
       HIPCHK(c, hipMemcpyAsync(out, c->argmin + arm, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+      break;
+    case MPC_DBG_SIGMA:
+    case MPC_DBG_CHOL:
+      HIPCHK(c, hipMemcpyAsync(out, (what == MPC_DBG_SIGMA ? c->sig : c->chol) + (size_t)arm * H * kTri,
+                               sizeof(float) * d.H * kTri, hipMemcpyDeviceToDevice, c->stream));
       break;
     default:
       return fail(c, MPC_EINVAL, "unknown debug quantity");

@@ -52,10 +52,16 @@ struct Params {
   float dt, sigma, lambda, gamma, alpha_mu;
   float w_pose, w_rot, w_stop, w_joint, w_coll, w_dyn;
   float buf_env, buf_self, buf_dyn, tau, prio_min, prio_max, dist_floor, joint_margin;
+  float alpha_sigma, sigma_floor;
   uint32_t seed_lo, seed_hi;
   int iters, A, dof, Hmax, Smax, Nmax, max_obs;
+  int plan_mode, cov;          // cov: covariance adaptation on (alpha_sigma > 0)
   float gpow[kMaxH];           // gamma^h rounded to FP32
 };
+
+// Packed lower triangle of a 7x7 symmetric matrix: entry (j, m), m <= j.
+__host__ __device__ constexpr int tri7(int j, int m) { return j * (j + 1) / 2 + m; }
+constexpr int kTri = 28;
 
 // Per-step device scalars written at Sense.
 struct StepState {

@@ -336,10 +336,17 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
     // Integration prefix of this horizon tile (noise regenerated, not stored).
     for (int h = 0; h < item.h0; ++h) {
       float z[8];
-      normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+      if (A.eps_in) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) z[j] = A.eps_in[arm->eps_off + ((size_t)h * 7 + j) * Npad + n];
+      } else {
+        normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
+      }
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const float u = P.sigma * z[j] + mu[h * 7 + j];
+        const float u = z[j] + mu[h * 7 + j];
         qd[j] = fmaf_(P.dt, u, qd[j]);
         q[j] = fmaf_(P.dt, qd[j], q[j]);
       }
@@ -354,12 +361,21 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
       for (int c2 = 0; c2 < 5; ++c2) L.sur[c2] = 0u;
     for (int h = item.h0; h < item.h1; ++h) {
       float z[8];
-      normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+      if (A.eps_in) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) z[j] = A.eps_in[arm->eps_off + ((size_t)h * 7 + j) * Npad + n];
+      } else {
+        normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          z[j] *= P.sigma;
+          if (live) eps[((size_t)h * 7 + j) * Npad + n] = z[j];
+        }
+      }
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const float e = P.sigma * z[j];
+        const float e = z[j];
         const float u = e + mu[h * 7 + j];
-        if (live) eps[((size_t)h * 7 + j) * Npad + n] = e;
         qd[j] = fmaf_(P.dt, u, qd[j]);
         q[j] = fmaf_(P.dt, qd[j], q[j]);
       }
@@ -542,6 +558,14 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
     const int H = A.arms[a].H;
     if (h + 1 < H) A.mu[i] = s_mu[i + 7];
   }
+  // The adapted covariances and their factors shift with the means (one
+  // thread per (arm, entry), steps in increasing order).
+  if (P.cov && tid < nA * 2 * kTri) {
+    const int a = tid / (2 * kTri), e = tid % (2 * kTri);
+    float* m = (e < kTri ? A.sig : A.chol) + (size_t)a * P.Hmax * kTri + e % kTri;
+    const int H = A.arms[a].H;
+    for (int h = 0; h + 1 < H; ++h) m[(size_t)h * kTri] = m[(size_t)(h + 1) * kTri];
+  }
   if (tid < nA) {
     const int a = tid;
     const DevArm* arm = A.arms + a;
@@ -650,29 +674,78 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
 }
 
 // Eq. 3 (weighted mean) and Eq. 4 (mean update), one block per (arm, step).
+// Noise with the adapted covariance (Eqs. 3-4): eps_{n,h} = L_h z_{n,h}, L_h
+// the Cholesky factor of Sigma_h, z the same standard normals as the rollout
+// kernel draws; written in its [H][7][Npad] per-arm layout.
+__global__ __launch_bounds__(kWave) void k_noise(const DevArm* __restrict__ arms, const Params* __restrict__ Pp,
+                                                 const StepState* __restrict__ ssp, const float* __restrict__ chol,
+                                                 float* __restrict__ eps, int k) {
+  const Params& P = *Pp;
+  const int a = blockIdx.y;
+  const DevArm* arm = arms + a;
+  const int n = blockIdx.x * kWave + threadIdx.x;
+  if (n >= arm->Npad) return;
+  const uint32_t t = ssp->t;
+  const int Npad = arm->Npad;
+  float* out = eps + arm->eps_off;
+  for (int h = 0; h < arm->H; ++h) {
+    float z[8];
+    normals8(P.seed_lo, P.seed_hi, a, t, k, n, h, z);
+    const float* L = chol + ((size_t)a * P.Hmax + h) * kTri;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      float e = 0.f;
+#pragma unroll
+      for (int m = 0; m <= j; ++m) e = fmaf_(L[tri7(j, m)], z[m], e);
+      out[((size_t)h * 7 + j) * Npad + n] = e;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
-  __shared__ float s_r[7][256];
+  // 7 weighted noise sums (Eq. 3, first half) and, with covariance
+  // adaptation, the 28 weighted second moments of the noise.
+  __shared__ float s_r[7 + kTri][256];
   const int a = blockIdx.y, h = blockIdx.x, tid = threadIdx.x;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   if (h >= arm->H) return;
   const int N = arm->N, Npad = arm->Npad;
+  const bool cov = P.cov != 0;
   const float* w = A.w + (size_t)a * P.Nmax;
   const float* eps = A.eps + arm->eps_off + (size_t)h * 7 * Npad;
   float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float s2[kTri];
+#pragma unroll
+  for (int e = 0; e < kTri; ++e) s2[e] = 0.f;
   for (int n = tid; n < N; n += blockDim.x) {
     const float wn = w[n];
+    float en[7];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) s[j] = fmaf_(wn, eps[(size_t)j * Npad + n], s[j]);
+    for (int j = 0; j < 7; ++j) {
+      en[j] = eps[(size_t)j * Npad + n];
+      s[j] = fmaf_(wn, en[j], s[j]);
+    }
+    if (cov) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float we = wn * en[j];
+#pragma unroll
+        for (int m = 0; m <= j; ++m) s2[tri7(j, m)] = fmaf_(we, en[m], s2[tri7(j, m)]);
+      }
+    }
   }
+  const int nsum = cov ? 7 + kTri : 7;
 #pragma unroll
   for (int j = 0; j < 7; ++j) s_r[j][tid] = s[j];
+  if (cov) {
+#pragma unroll
+    for (int e = 0; e < kTri; ++e) s_r[7 + e][tid] = s2[e];
+  }
   __syncthreads();
   for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (tid < st) {
-#pragma unroll
-      for (int j = 0; j < 7; ++j) s_r[j][tid] += s_r[j][tid + st];
-    }
+    if (tid < st)
+      for (int j = 0; j < nsum; ++j) s_r[j][tid] += s_r[j][tid + st];
     __syncthreads();
   }
   if (tid < 7) {
@@ -680,6 +753,36 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
     const float m0 = *mu;
     const float mt = m0 + s_r[tid][0];
     *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
+  }
+  if (cov && tid == 64) {
+    // Eq. 3: Sigma~ = sum_n w_n (U_n - mu~)(U_n - mu~)^T = sum_n w_n eps eps^T - ebar ebar^T
+    // (U_n - mu~ = eps_n - ebar, ebar = sum_n w_n eps_n); Eq. 4: EMA; then the
+    // Cholesky factor, pivots floored at sigma_floor^2.
+    float* sg = A.sig + ((size_t)a * P.Hmax + h) * kTri;
+    float* L = A.chol + ((size_t)a * P.Hmax + h) * kTri;
+    float eb[7], S[kTri], Lc[kTri];
+    for (int j = 0; j < 7; ++j) eb[j] = s_r[j][0];
+    for (int j = 0; j < 7; ++j)
+      for (int m = 0; m <= j; ++m) {
+        const float st = s_r[7 + tri7(j, m)][0] - eb[j] * eb[m];
+        S[tri7(j, m)] = fmaf_(P.alpha_sigma, st, (1.0f - P.alpha_sigma) * sg[tri7(j, m)]);
+      }
+    const float f2 = P.sigma_floor * P.sigma_floor;
+    for (int j = 0; j < 7; ++j) {
+      float d = S[tri7(j, j)];
+      for (int m = 0; m < j; ++m) d -= Lc[tri7(j, m)] * Lc[tri7(j, m)];
+      const float ljj = sqrtf(fmaxf(d, f2));
+      Lc[tri7(j, j)] = ljj;
+      for (int i = j + 1; i < 7; ++i) {
+        float v = S[tri7(i, j)];
+        for (int m = 0; m < j; ++m) v -= Lc[tri7(i, m)] * Lc[tri7(j, m)];
+        Lc[tri7(i, j)] = v / ljj;
+      }
+    }
+    for (int e = 0; e < kTri; ++e) {
+      sg[e] = S[e];
+      L[e] = Lc[e];
+    }
   }
 }
 
@@ -700,8 +803,11 @@ __global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
     const float* mu = A.mu + (size_t)a * P.Hmax * 7;
     for (int h = 0; h < H; ++h)
       for (int j = 0; j < 7; ++j) {
-        qd[j] = fmaf_(P.dt, mu[h * 7 + j], qd[j]);
-        q[j] = fmaf_(P.dt, qd[j], q[j]);
+        if (P.plan_mode == 0) {
+          qd[j] = fmaf_(P.dt, mu[h * 7 + j], qd[j]);
+          q[j] = fmaf_(P.dt, qd[j], q[j]);
+        }
+        // plan_mode 1 (the S_d ablation): the current configuration at every step
         s_q[h][j] = q[j];
       }
   }
@@ -825,6 +931,13 @@ hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s) {
 
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s) {
   hipLaunchKernelGGL(k_publish, dim3(n_arms), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise(const DevArm* arms, const Params* P, const StepState* ss, const float* chol, float* eps, int k,
+                        int n_arms, int npad_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_noise, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, ss, chol, eps,
+                     k);
   return hipGetLastError();
 }
 

@@ -35,6 +35,9 @@ struct RolloutArgs {
   int audit;
   int pad2;
   unsigned long long* sur_counts;
+  // adapted covariance: the iteration's noise, precomputed (same layout as
+  // eps); NULL = draw sigma z in the kernel
+  const float* eps_in;
 };
 
 struct SenseArgs {
@@ -52,6 +55,8 @@ struct SenseArgs {
   float* st_obs;
   float* goalR;
   float* mu;
+  float* sig;                  // [A][Hmax][28] packed lower triangles (covariance adaptation)
+  float* chol;                 // their Cholesky factors
 };
 
 struct ReduceArgs {
@@ -71,6 +76,8 @@ struct ReduceArgs {
   float* plan_write;
   float* planq_write;
   BoardMeta* meta;
+  float* sig;                  // [A][Hmax][28] packed lower triangles (covariance adaptation)
+  float* chol;                 // their Cholesky factors
 };
 
 struct PublishArgs {
@@ -89,6 +96,9 @@ hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s);
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
+// Noise of iteration k from the adapted covariances: eps = L_h z.
+hipError_t launch_noise(const DevArm* arms, const Params* P, const StepState* ss, const float* chol, float* eps, int k,
+                        int n_arms, int npad_max, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n, hipStream_t s);
 hipError_t launch_sim_execute(float* state, const float* u, int n, float dt, hipStream_t s);
 hipError_t launch_copy3d(const float* src, long long s0, long long s1, long long s2, float* dst,

@@ -365,7 +365,8 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
                                                       const SurModel* __restrict__ sm,
                                                       const StepState* __restrict__ ssp,
                                                       const float* __restrict__ mu_all,
-                                                      const float* __restrict__ state, int k_iter,
+                                                      const float* __restrict__ state,
+                                                      const float* __restrict__ eps_in, int k_iter,
                                                       uint16_t* __restrict__ F) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
@@ -383,12 +384,17 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
   }
   for (int h = 0; h < arm->H; ++h) {
     float z[8];
-    normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
+    if (eps_in) {
+      for (int j = 0; j < 7; ++j) z[j] = eps_in[arm->eps_off + ((size_t)h * 7 + j) * arm->Npad + n];
+    } else {
+      normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
+      for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
+    }
     uint16_t f[8];
     bool inbox = true;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-      const float u = P.sigma * z[j] + mu[h * 7 + j];
+      const float u = z[j] + mu[h * 7 + j];
       qd[j] = fmaf_(P.dt, u, qd[j]);
       q[j] = fmaf_(P.dt, qd[j], q[j]);
       const float x = (q[j] - mid[j]) * ih[j];
@@ -607,31 +613,39 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   const int G = gridDim.x;
   const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
   const int fcol = wq * kWaveRows + half * 4;  // this lane's first feature within an accumulator block
+  // The pipeline body is straight-line code: edge stages (before the first
+  // block reaches a layer, after the last one has left it) compute on
+  // in-bounds stand-in data (zeroed activations, the last block's inputs) and
+  // only their writes are suppressed, so the compiler may interleave each
+  // wave's MFMA and VALU work freely.
+  for (int e = tid; e < (int)(3 * sizeof(L.act1) / sizeof(uint4)); e += kInferThreads)
+    reinterpret_cast<uint4*>(&L.act1[0][0][0])[e] = make_uint4(0u, 0u, 0u, 0u);
   // Group B keeps the reads of the next block and the item after it in flight.
   BlockIn cur, nxt;
   SurItem item2{};
   __syncthreads();
   if (grp == 1 && n_my > 0) {
     fetch_block(A, L, Hmax, Nmax, A.items[blockIdx.x], q, nxt);
-    if (n_my > 1) item2 = A.items[blockIdx.x + G];
+    item2 = A.items[blockIdx.x + (long long)min(1, n_my - 1) * G];
   }
   for (int s = 0; s < n_my + 3; ++s) {
     if (grp == 1) {
-      if (s < n_my) {
-        cur = nxt;
-        if (s + 1 < n_my) {
-          fetch_block(A, L, Hmax, Nmax, item2, q, nxt);
-          if (s + 2 < n_my) item2 = A.items[blockIdx.x + (long long)(s + 2) * G];
-        }
-        // Features and first layer of query block s.
-        const SurItem& it = cur.item;
-        const InferArm& arm = L.arm[it.arm];
-        const InferArm& nbr = L.arm[it.nbr];
-        const bool valid = nbr.valid != 0 && it.h < nbr.H;
-        const bool live = valid && it.n0 + q < arm.N;
+      // Features and first layer of query block s (the last block again
+      // past the end), then the third layer of block s-2; the block's
+      // bookkeeping for the decision three stages later is stored last so
+      // that both layers form one straight-line sequence.
+      cur = nxt;
+      fetch_block(A, L, Hmax, Nmax, item2, q, nxt);
+      item2 = A.items[blockIdx.x + (long long)min(s + 2, n_my - 1) * G];
+      const SurItem it = cur.item;
+      const InferArm& arm = L.arm[it.arm];
+      const InferArm& nbr = L.arm[it.nbr];
+      const bool live = nbr.valid != 0 && it.h < nbr.H && it.n0 + q < arm.N;
+      bool inbox;
+      {
         float g[10];
         const bool nbr_in = neighbour_features(arm, nbr, cur.pq, L.mid, L.inv_half, g);
-        const bool own_in = (cur.fown.w >> 16) != 0u;
+        inbox = nbr_in && (cur.fown.w >> 16) != 0u;
         // B operands: lanes 0-31 take their own-feature row (its flag slot
         // meets a zero weight), lanes 32-63 the neighbour features f7..f14;
         // the second chunk holds f15, f16 for lanes 0-31 and zeros.
@@ -648,31 +662,30 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc[fb], 0, 0, 0);
           store_block(acc[fb], &L.act1[s & 1][q][fcol + fb * 32]);
         }
-        if (wq == 0 && half == 0) {
-          L.ok[s & 3][q] = (live ? 1 : 0) | ((live && own_in && nbr_in) ? 2 : 0);
-          if (q == 0) {
-            L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
-            L.n_rows[s & 3] = arm.Npad - it.n0;
-            L.out_arm[s & 3] = it.arm;
-          }
-        }
       }
-      if (s >= 2 && s - 2 < n_my) {
-        // Third layer of query block s-2.
+      {
         f32x16_t acc[kFB];
         layer256(w, L.act2[(s - 2) & 1], &L.bias[2][fcol], acc, lane);
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act3[(s - 2) & 1][q][fcol + fb * 32]);
       }
+      if (s < n_my && wq == 0 && half == 0) {
+        L.ok[s & 3][q] = (live ? 1 : 0) | ((live && inbox) ? 2 : 0);
+        if (q == 0) {
+          L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
+          L.n_rows[s & 3] = arm.Npad - it.n0;
+          L.out_arm[s & 3] = it.arm;
+        }
+      }
     } else {
-      if (s >= 1 && s - 1 < n_my) {
+      {
         // Second layer of query block s-1.
         f32x16_t acc[kFB];
         layer256(w, L.act1[(s - 1) & 1], &L.bias[1][fcol], acc, lane);
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][q][fcol + fb * 32]);
       }
-      if (s >= 3) {
+      {
         // Output layer and decision of query block s-3: 8 lanes per query
         // (queries wq*32/kGroupWaves + pass*8 + lane/8); the 8 lanes take
         // 16-byte chunks j, j+8, j+16, j+24 (j = lane%8), so each 8-lane group
@@ -703,7 +716,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           part += dpp_f32<0xB1>(part);   // quad_perm [1,0,3,2]
           part += dpp_f32<0x4E>(part);   // quad_perm [2,3,0,1]
           part += dpp_f32<0x141>(part);  // row_half_mirror
-          const bool writer = j == 0 && qq < L.n_rows[r];
+          const bool writer = s >= 3 && j == 0 && qq < L.n_rows[r];
           const int okv = L.ok[r][qq];
           const float y = part + L.b4;
           const bool far = (okv & 2) != 0 && y >= margin;
@@ -804,10 +817,10 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
 }
 
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, int k_iter, int n_arms, int npad_max, uint16_t* F,
-                             hipStream_t s) {
+                             const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
+                             int npad_max, uint16_t* F, hipStream_t s) {
   hipLaunchKernelGGL(k_sur_states, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, model,
-                     ss, mu, state, k_iter, F);
+                     ss, mu, state, eps_in, k_iter, F);
   return hipGetLastError();
 }
 

@@ -77,9 +77,10 @@ struct SurInferArgs {
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, const float* qi, const float* qj,
                                 int M, float* out, hipStream_t s);
+// eps_in: the iteration's precomputed noise (adapted covariance), or NULL to draw sigma z.
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, int k_iter, int n_arms, int npad_max, uint16_t* F,
-                             hipStream_t s);
+                             const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
+                             int npad_max, uint16_t* F, hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrstorm.so")
 
 MPC_OK, MPC_EINVAL, MPC_ENOMEM, MPC_EHIP, MPC_ESTATE, MPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DBG = dict(NOISE=0, Q=1, QD=2, SPHERES=3, STAGE_COST=4, COST=5, WEIGHTS=6, MEAN=7, ALPHA=8,
-           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12, PRED=13)
+           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12, PRED=13, SIGMA=14, CHOL=15)
 EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destroy",
            "mpc_last_error", "mpc_sync", "mpc_debug_enable", "mpc_debug_get", "mpc_get_board",
            "mpc_set_board", "mpc_set_mean", "mpc_get_step", "mpc_set_step", "mpc_sim_execute",
@@ -72,7 +72,8 @@ class MpcParams(C.Structure):
                 ("tau", C.c_float), ("prio_min", C.c_float), ("prio_max", C.c_float),
                 ("dist_floor", C.c_float), ("joint_margin", C.c_float), ("seed", C.c_ulonglong),
                 ("max_obstacles", C.c_int), ("collision_mode", C.c_int),
-                ("surrogate_margin", C.c_float)]
+                ("surrogate_margin", C.c_float), ("alpha_sigma", C.c_float), ("sigma_floor", C.c_float),
+                ("plan_mode", C.c_int)]
 
 
 _lib = None
@@ -137,7 +138,7 @@ def _ptr(t):
 def params_struct(p: dict) -> MpcParams:
     s = MpcParams()
     for name, _ in MpcParams._fields_:
-        if name in ("iters", "max_obstacles", "collision_mode"):
+        if name in ("iters", "max_obstacles", "collision_mode", "plan_mode"):
             setattr(s, name, int(p[name]))
         elif name == "seed":
             s.seed = int(p["seed"])
@@ -238,7 +239,8 @@ class Controller:
         t = self.torch
         shapes = dict(NOISE=(H, 7, N), Q=(N, H, 7), QD=(N, H, 7), SPHERES=(N, H, S, 4),
                       STAGE_COST=(H, N), COST=(N,), WEIGHTS=(N,), MEAN=(H, 7), ALPHA=(self.A,),
-                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,), PRED=(self.A, H, N))
+                      DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,), PRED=(self.A, H, N),
+                      SIGMA=(H, 28), CHOL=(H, 28))
         dtype = dict(PAIRS=t.int64, ARGMIN=t.int32, PASSES=t.int64).get(what, t.float32)
         out = t.empty(shapes[what], dtype=dtype, device=self.dev)
         _check(lib().mpc_debug_get(self.h, DBG[what], arm, _ptr(out)), self.h)

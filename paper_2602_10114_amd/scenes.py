@@ -99,7 +99,8 @@ def default_params(**over) -> dict:
              w_dyn=5000.0, buf_env=0.03, buf_self=0.03, buf_dyn=0.03,
              tau=3.0, prio_min=0.5, prio_max=2.0, dist_floor=1e-3,
              joint_margin=0.05, seed=0, max_obstacles=32,
-             collision_mode=0, surrogate_margin=0.05)
+             collision_mode=0, surrogate_margin=0.05,
+             alpha_sigma=0.0, sigma_floor=1e-3, plan_mode=0)
     p.update(over)
     return p
 

@@ -1,0 +1,121 @@
+"""GPU parity of the covariance adaptation (Eqs. 3-4) and of the static-plan
+ablation (S_d) against the FP64 oracle.  Covariance update and factor are
+checked stage-isolated (the oracle is fed the GPU's FP32 weights and noise);
+the next step's noise against the oracle's normals times the GPU's shifted
+factor; K = 2 end to end within the softmax conditioning of FP32."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2602_10114_amd import native
+from helpers import small_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+    yield
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _unpack(tri):
+    """[..., 28] packed lower triangles -> [..., 7, 7] symmetric matrices."""
+    out = np.zeros(tri.shape[:-1] + (7, 7))
+    k = 0
+    for j in range(7):
+        for m in range(j + 1):
+            out[..., j, m] = tri[..., k]
+            out[..., m, j] = tri[..., k]
+            k += 1
+    return out
+
+
+def _lower(tri):
+    out = _unpack(tri)
+    return np.tril(out)
+
+
+def test_covariance_update_and_factor_stage_isolated():
+    _say("case: covariance adaptation, 2 arms, 96 rollouts x 6 steps, alpha_sigma 0.5")
+    sc = small_scene(2, n=96, h=6)
+    p = {**sc.params, "alpha_sigma": 0.5}
+    ctl = native.Controller(sc.arms, p)
+    ctl.debug_enable(True)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    s2 = float(np.float32(0.3)) ** 2
+    chol1 = []
+    for a in range(2):
+        eps = ctl.debug_get("NOISE", a).cpu().numpy().astype(np.float64)     # [H][7][N]
+        w = ctl.debug_get("WEIGHTS", a).cpu().numpy().astype(np.float64)
+        sig = _unpack(ctl.debug_get("SIGMA", a).cpu().numpy().astype(np.float64))
+        L = _lower(ctl.debug_get("CHOL", a).cpu().numpy().astype(np.float64))
+        U = eps.transpose(2, 0, 1)                                            # mu = 0 at the first step
+        St = oracle.weighted_cov(w, U, oracle.weighted_mean(w, U))
+        ref = 0.5 * s2 * np.eye(7) + 0.5 * St
+        assert np.abs(sig - ref).max() < 1e-6
+        for h in range(6):
+            Lr = oracle.cholesky_floor(sig[h], float(np.float32(1e-3)) ** 2)
+            assert np.abs(L[h] - Lr).max() < 1e-5 * np.abs(Lr).max()
+        chol1.append(L)
+    # The next step draws eps = L_h z with the factors shifted by one step.
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    seed = int(p["seed"])
+    for a in range(2):
+        eps2 = ctl.debug_get("NOISE", a).cpu().numpy().astype(np.float64)
+        Lu = np.concatenate([chol1[a][1:], chol1[a][-1:]])
+        for n in (0, 31, 63, 64, 95):
+            for h in range(6):
+                z = oracle.normals(seed, a, 1, 0, n, h, 7)
+                ref = Lu[h] @ z
+                assert np.abs(eps2[h, :, n] - ref).max() < 2e-6
+
+
+def test_covariance_two_iterations_end_to_end():
+    _say("case: covariance adaptation with K = 2, 1 arm, 128 rollouts x 8 steps")
+    sc = small_scene(1, n=128, h=8, iters=2)
+    p = {**sc.params, "alpha_sigma": 0.7}
+    ctl = native.Controller(sc.arms, p)
+    ctl.debug_enable(True)
+    orc = oracle.Controller(sc.arms, p)
+    for t in range(2):
+        ctl.step(sc.state, sc.goal, sc.obstacles)
+        orc.step(sc.state, sc.goal, sc.obstacles)
+    ctl.sync()
+    sig = _unpack(ctl.debug_get("SIGMA", 0).cpu().numpy().astype(np.float64))
+    so, _ = orc.sigma(0)
+    # FP32 costs move the weights by up to |dC|/lambda: compare at the
+    # conditioning of the update, not at rounding
+    rel = np.abs(sig - so[:8]).max() / np.abs(so[:8]).max()
+    _say(f"  Sigma after two steps of K = 2: max relative difference {rel:.2e}")
+    assert rel < 5e-2
+    eps = ctl.debug_get("NOISE", 0).cpu().numpy().astype(np.float64)        # [H][7][N]
+    eo = orc.noise(0)[:128, :8].transpose(1, 2, 0)
+    assert np.abs(eps - eo).max() < 5e-2 * np.abs(eo).max()
+
+
+def test_static_plans_are_current_spheres():
+    _say("case: S_d ablation (plan_mode 1), 2 arms")
+    sc = small_scene(2, n=64, h=8, plan_mode=1)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.share_plans()
+    ctl.sync()
+    for a in range(2):
+        plan, pq, _, valid = ctl.get_board(a)
+        ref = oracle.spheres(oracle.make_arm(sc.arms[a]), sc.state[a, :, 0].astype(np.float64))
+        assert valid == 1
+        plan = plan.cpu().numpy().astype(np.float64)
+        for h in range(8):
+            assert np.abs(plan[h] - ref).max() < 1e-5
+        assert np.abs(pq.cpu().numpy() - sc.state[a, :, 0]).max() == 0.0

@@ -300,6 +300,94 @@ def test_update_limits(orc):
     assert orc.argmin(np.array([3.0, 1.0, 1.0, 2.0])) == 1
 
 
+def test_weighted_covariance_limits(orc):
+    """Eq. 3's covariance: uniform weights give numpy's population covariance
+    of the samples; one dominant rollout gives zero; a pair with weights
+    (p, 1-p) gives p(1-p) (a-b)(a-b)^T."""
+    rng = np.random.default_rng(31)
+    N, H, d = 200, 3, 7
+    U = rng.normal(size=(N, H, d)) * rng.uniform(0.1, 2.0, size=d)
+    w = np.full(N, 1.0 / N)
+    S = orc.weighted_cov(w, U, orc.weighted_mean(w, U))
+    for h in range(H):
+        np.testing.assert_allclose(S[h], np.cov(U[:, h, :].T, bias=True), atol=1e-12)
+    w1 = np.zeros(N)
+    w1[17] = 1.0
+    np.testing.assert_allclose(orc.weighted_cov(w1, U, orc.weighted_mean(w1, U)), 0.0, atol=1e-15)
+    p = 0.3
+    w2 = np.zeros(N)
+    w2[3], w2[8] = p, 1 - p
+    dlt = U[3] - U[8]
+    S2 = orc.weighted_cov(w2, U, orc.weighted_mean(w2, U))
+    for h in range(H):
+        np.testing.assert_allclose(S2[h], p * (1 - p) * np.outer(dlt[h], dlt[h]), atol=1e-12)
+
+
+def test_cholesky_floor(orc):
+    """Factor of an SPD matrix equals numpy's; a singular matrix gets its
+    pivots floored (L L^T = S + the floor on the null direction)."""
+    rng = np.random.default_rng(32)
+    M = rng.normal(size=(7, 7))
+    S = M @ M.T + 0.1 * np.eye(7)
+    np.testing.assert_allclose(orc.cholesky_floor(S, 1e-12), np.linalg.cholesky(S), atol=1e-12)
+    v = rng.normal(size=7)
+    Z = np.outer(v, v)                      # rank one: pivots 2..7 vanish
+    L = orc.cholesky_floor(Z, 1e-6)
+    assert abs(L[0, 0] - abs(v[0])) < 1e-12
+    np.testing.assert_allclose(np.diag(L)[1:], 1e-3, rtol=1e-9)
+    np.testing.assert_allclose((L @ L.T)[:, 0], Z[:, 0], atol=1e-12)
+
+
+def test_covariance_adaptation_in_the_controller(orc):
+    """alpha_Sigma = 0 keeps Sigma = sigma^2 I; alpha_Sigma = 1 at infinite
+    temperature makes Sigma_h the population covariance of the step's
+    controls (numpy), its factor numpy's Cholesky; the next step's noise then
+    has that covariance (sampling pin over 4096 rollouts, 5 standard errors)."""
+    sc = scenes.make_scene(1)
+    sc.arms[0].n_rollouts = 4096
+    sc.arms[0].horizon = 4
+    sig = float(np.float32(0.3))
+    c0 = orc.Controller(sc.arms, {**sc.params, "alpha_sigma": 0.0})
+    c0.step(sc.state, sc.goal, sc.obstacles)
+    S0, L0 = c0.sigma(0)
+    for h in range(4):
+        np.testing.assert_array_equal(S0[h], sig * sig * np.eye(7))
+        np.testing.assert_array_equal(L0[h], sig * np.eye(7))
+    ctl = orc.Controller(sc.arms, {**sc.params, "alpha_sigma": 1.0, "lam": 1e30})
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    eps = ctl.noise(0)                       # [N][H][d]; U = mu + eps with mu = 0 here
+    S, L = ctl.sigma(0)
+    for h in range(4):
+        ref = np.cov(eps[:, h, :].T, bias=True)
+        np.testing.assert_allclose(S[h], ref, atol=1e-12)
+        np.testing.assert_allclose(L[h], np.linalg.cholesky(ref), atol=1e-10)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    eps2 = ctl.noise(0)
+    for h in range(3):                       # step h uses Sigma_{h+1} after the shift
+        Sh = S[h + 1]
+        emp = np.cov(eps2[:, h, :].T, bias=True)
+        se = np.sqrt((np.outer(np.diag(Sh), np.diag(Sh)) + Sh ** 2) / 4096)
+        assert np.all(np.abs(emp - Sh) < 5 * se + 1e-12)
+
+
+def test_static_plans_are_current_spheres(orc):
+    """plan_mode 1 (the S_d ablation): every published step holds the
+    spheres of the arm's current configuration."""
+    sc = scenes.make_scene(2, plan_mode=1)
+    for a in sc.arms:
+        a.n_rollouts = 16
+    ctl = orc.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    ctl.share_plans()
+    for a in range(2):
+        p, pq, _, valid = ctl.plan(a, 0)
+        ref = orc.spheres(ctl.arms[a], sc.state[a, :, 0].astype(np.float64))
+        assert valid == 1
+        for h in range(sc.arms[a].horizon):
+            np.testing.assert_allclose(p[h, :sc.arms[a].n_spheres], ref, atol=1e-12)
+            np.testing.assert_allclose(pq[h], sc.state[a, :, 0], atol=1e-7)
+
+
 def test_total_cost_geometric(orc):
     # constant stage cost c: sum_{h<H} gamma^h c = c (1 - gamma^H) / (1 - gamma)
     g, H = 0.99, 30
