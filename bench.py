@@ -144,24 +144,48 @@ def algorithmic_flops_per_step(scene, active_neighbours=True):
     return total * int(scene.params["iters"])
 
 
-def cpu_baseline(scene, seconds_hint=True):
-    """The FP64 oracle on a bounded sample of the same workload: one control
-    step of all 8 arms restricted to their first `window` rollouts, after one
-    warm step that publishes plans (so every neighbour term is active)."""
+def _oracle_window_step(args):
+    """One control step of the oracle on rollouts [lo, hi) of every arm, after
+    an untimed step that publishes plans; returns (start, end) wall times."""
+    config, lo, hi = args
     import oracle
-    window = 320
+    scene = scenes.make_scene(config, collision_mode=0)
     orc = oracle.Controller(scene.arms, scene.params)
     orc.set_window(0, 1)
     orc.step(scene.state, scene.goal, scene.obstacles)
     orc.share_plans()
-    orc.set_window(0, window)
-    t0 = time.perf_counter()
+    orc.set_window(lo, hi)
+    t0 = time.time()
     orc.step(scene.state, scene.goal, scene.obstacles)
-    dt = time.perf_counter() - t0
-    rs = window * sum(a.horizon for a in scene.arms)
-    return {"value": rs / dt, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one control step of all 8 arms restricted to {window} of 4096 rollouts each "
-                      f"({rs} rollout-steps, {dt:.1f} s on one host thread, FP64)"}
+    return t0, time.time()
+
+
+def cpu_baseline(scene):
+    """The FP64 oracle, as it stands, on the host cores, on bounded samples of
+    one control step: (1) one thread on the first 320 rollouts of every arm;
+    (2) the first 640 rollouts of every arm split over worker processes, one
+    per available core (at most 16), each running the unmodified oracle on a
+    disjoint rollout window; value = rollout-steps / wall time of (2)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    window = 320
+    t0, t1 = _oracle_window_step((5, 0, window))
+    rs1 = window * sum(a.horizon for a in scene.arms)
+    single = {"value": rs1 / (t1 - t0), "cores": 1,
+              "sample": f"first {window} of 4096 rollouts of every arm, {t1 - t0:.1f} s"}
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    N = 640
+    bounds = [(5, N * i // cores, N * (i + 1) // cores) for i in range(cores)]
+    # (a worker that dies raises BrokenProcessPool here rather than hanging)
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        spans = list(ex.map(_oracle_window_step, bounds, timeout=600))
+    wall = max(e for _, e in spans) - min(b for b, _ in spans)
+    rs = N * sum(a.horizon for a in scene.arms)
+    return {"value": rs / wall, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one control step of all 8 arms restricted to their first {N} of 4096 rollouts "
+                      f"({rs} rollout-steps, FP64), split into {cores} rollout windows run by {cores} "
+                      f"processes in {wall:.1f} s",
+            "single_thread": single}
 
 
 def obstacle_track(scene, n):
