@@ -87,6 +87,8 @@ typedef struct {
   float sigma_floor;       /* floor of the Cholesky pivots of the adapted Sigma (std. dev. units), > 0 */
   int plan_mode;           /* 0: publish the predicted plan (Sec. IV-A); 1: publish the current
                               spheres at every step, a static obstacle (the paper's S_d ablation) */
+  float w_manip;           /* weight of C_manip (Eq. 5), >= 0; 0 leaves the term out */
+  float manip_thresh;      /* C_manip = max(0, 1 - sqrt(det(J J^T)) / manip_thresh), > 0 */
 } mpc_params;
 
 /* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).

@@ -43,7 +43,8 @@ class OrcParams(C.Structure):
         "w_coll", "w_dyn", "buf_env", "buf_self", "buf_dyn", "tau", "prio_min", "prio_max",
         "dist_floor", "joint_margin")] + [("seed", C.c_ulonglong), ("iters", C.c_int),
                                           ("plan_mode", C.c_int), ("alpha_sigma", C.c_double),
-                                          ("sigma_floor", C.c_double)]
+                                          ("sigma_floor", C.c_double), ("w_manip", C.c_double),
+                                          ("manip_thresh", C.c_double)]
 
 
 _lib = None
@@ -89,6 +90,9 @@ def lib():
         L.orc_ema.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp]
         L.orc_weighted_cov.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L.orc_cholesky_floor.argtypes = [C.c_int, _dp, C.c_double, _dp]
+        L.orc_jacobian.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_manip_cost.argtypes = [C.c_void_p, _dp, C.c_double]
+        L.orc_manip_cost.restype = C.c_double
         L.orc_get_sigma.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_argmin.argtypes = [C.c_int, _dp]
         L.orc_argmin.restype = C.c_int
@@ -165,7 +169,7 @@ def make_params(p: dict) -> OrcParams:
     for name, _ in OrcParams._fields_:
         if name in ("seed", "iters", "plan_mode"):
             continue
-        setattr(o, name, float(np.float32(p.get(name, 0.0 if name == "alpha_sigma" else 1e-3))))
+        setattr(o, name, float(np.float32(p[name])))
     o.seed = int(p["seed"])
     o.iters = int(p["iters"])
     o.plan_mode = int(p.get("plan_mode", 0))
@@ -279,6 +283,16 @@ def weighted_cov(w, U, mt):
     return out
 
 
+def jacobian(oarm, q):
+    J = np.zeros((6, oarm.dof))
+    lib().orc_jacobian(C.byref(oarm), _f64(q), J)
+    return J
+
+
+def manip_cost(oarm, q, thresh):
+    return lib().orc_manip_cost(C.byref(oarm), _f64(q), float(thresh))
+
+
 def cholesky_floor(S, floor_var):
     S = _f64(S)
     d = S.shape[0]
@@ -314,7 +328,8 @@ def pair_count(H, N, S_own, S_nb):
 def stage_costs_batch(oarm, oparams, q, qd, sph, goal, obs, plans, nb_S, nb_H, nb_valid,
                       alpha_row, want_terms=False):
     """q, qd: [N][H][d]; sph: [N][H][S][4]; plans: [n_nb][Hmax][Smax][4].
-    Returns stage costs [H][N] (and terms [H][N][7])."""
+    Returns stage costs [H][N] (and terms [H][N][8]: pose, stop, joint, coll,
+    self, dyn, total, manip)."""
     q, qd, sph = _f64(q), _f64(qd), _f64(sph)
     N, H, _ = q.shape
     obs = _f64(obs).reshape(-1, 4)
@@ -328,7 +343,7 @@ def stage_costs_batch(oarm, oparams, q, qd, sph, goal, obs, plans, nb_S, nb_H, n
         plans = np.zeros((1, 1, 1, 4))
     n_nb = len(nb_S)
     out = np.zeros((H, N))
-    terms = np.zeros((H, N, 7)) if want_terms else None
+    terms = np.zeros((H, N, 8)) if want_terms else None
     lib().orc_stage_costs_batch(
         C.byref(oarm), C.byref(oparams), N, H, q, qd, sph, _f64(goal), obs, n_obs, plans, n_nb,
         plans.shape[1], plans.shape[2], np.ascontiguousarray(nb_S, dtype=np.int32) if n_nb else np.zeros(1, np.int32),

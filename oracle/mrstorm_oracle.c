@@ -162,6 +162,60 @@ void orc_ee_pose(const orc_arm *arm, const double *q, double *Tee) {
   mat4_mul(frames + 16 * arm->dof, M, Tee);
 }
 
+/* Geometric Jacobian of the end-effector point (reading of C_manip's
+ * "Jacobian ellipsoid"): column k = (z_k x (p_ee - o_k), z_k), z_k the axis
+ * of joint k (z of frame k in modified DH) and o_k a point on it (the origin
+ * of frame k).  Pinned by central differences of the forward kinematics. */
+void orc_jacobian(const orc_arm *arm, const double *q, double *J) {
+  double frames[(ORC_MAX_DOF + 1) * 16], Tee[16];
+  orc_fk(arm, q, frames);
+  orc_ee_pose(arm, q, Tee);
+  int d = arm->dof;
+  for (int k = 0; k < d; ++k) {
+    const double *T = frames + 16 * k;
+    double z[3] = {T[2], T[6], T[10]}, r[3] = {Tee[3] - T[3], Tee[7] - T[7], Tee[11] - T[11]};
+    J[0 * d + k] = z[1] * r[2] - z[2] * r[1];
+    J[1 * d + k] = z[2] * r[0] - z[0] * r[2];
+    J[2 * d + k] = z[0] * r[1] - z[1] * r[0];
+    J[3 * d + k] = z[0];
+    J[4 * d + k] = z[1];
+    J[5 * d + k] = z[2];
+  }
+}
+
+/* C_manip (Eq. 5; form a reading, following STORM's manipulability score):
+ * the volume of the manipulability ellipsoid sqrt(det(J J^T)), penalised
+ * linearly below thresh.  det by Gaussian elimination with partial pivoting. */
+double orc_manip_cost(const orc_arm *arm, const double *q, double thresh) {
+  int d = arm->dof;
+  double J[6 * ORC_MAX_DOF], G[36];
+  orc_jacobian(arm, q, J);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += J[i * d + k] * J[j * d + k];
+      G[i * 6 + j] = s;
+    }
+  double det = 1.0;
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r) if (fabs(G[r * 6 + c]) > fabs(G[piv * 6 + c])) piv = r;
+    if (G[piv * 6 + c] == 0.0) { det = 0.0; break; }
+    if (piv != c) {
+      for (int j = 0; j < 6; ++j) { double t = G[c * 6 + j]; G[c * 6 + j] = G[piv * 6 + j]; G[piv * 6 + j] = t; }
+      det = -det;
+    }
+    det *= G[c * 6 + c];
+    for (int r = c + 1; r < 6; ++r) {
+      double f = G[r * 6 + c] / G[c * 6 + c];
+      for (int j = c; j < 6; ++j) G[r * 6 + j] -= f * G[c * 6 + j];
+    }
+  }
+  double m = sqrt(det > 0.0 ? det : 0.0);
+  double v = 1.0 - m / thresh;
+  return v > 0.0 ? v : 0.0;
+}
+
 /* Rotation of a unit quaternion given as (w, x, y, z); the input is
  * normalised first.  Pinned by: orthonormality and the quaternion-inner-
  * product identity of the orientation term. */
@@ -292,11 +346,12 @@ double orc_stage_cost(const orc_arm *arm, const orc_params *p, int H, int h,
     double rho = orc_rho_sets(spheres, arm->n_spheres, nb_plan[i], nb_S[i]);
     dyn += alpha_row[i] * orc_hinge(rho, p->buf_dyn);
   }
+  double manip = p->w_manip > 0.0 ? orc_manip_cost(arm, q, p->manip_thresh) : 0.0;
   double total = p->w_pose * pose + p->w_stop * stop + p->w_joint * joint +
-                 p->w_coll * (coll + self) + p->w_dyn * dyn;
+                 p->w_coll * (coll + self) + p->w_dyn * dyn + p->w_manip * manip;
   if (terms) {
     terms[0] = pose; terms[1] = stop; terms[2] = joint; terms[3] = coll;
-    terms[4] = self; terms[5] = dyn; terms[6] = total;
+    terms[4] = self; terms[5] = dyn; terms[6] = total; terms[7] = manip;
   }
   return total;
 }
@@ -317,11 +372,11 @@ void orc_stage_costs_batch(const orc_arm *arm, const orc_params *p, int N, int H
     }
     for (int n = 0; n < N; ++n) {
       size_t nh = (size_t)n * H + h;
-      double terms[7];
+      double terms[8];
       out[(size_t)h * N + n] = orc_stage_cost(arm, p, H, h, q + nh * d, qd + nh * d,
                                               spheres + nh * S * 4, goal, obs, n_obs, ptrs,
                                               nb_S, active, alpha_row, n_nb, terms);
-      if (terms_out) memcpy(terms_out + ((size_t)h * N + n) * 7, terms, sizeof(terms));
+      if (terms_out) memcpy(terms_out + ((size_t)h * N + n) * 8, terms, sizeof(terms));
     }
   }
 }

@@ -38,6 +38,7 @@ typedef struct {
   int iters;
   int plan_mode;                  /* 0: predicted plan; 1: current spheres at every step (S_d) */
   double alpha_sigma, sigma_floor;
+  double w_manip, manip_thresh;
 } orc_params;
 
 /* ---- primitives ---- */
@@ -71,10 +72,15 @@ void orc_shift(int H, int dof, double *mu);
 long long orc_pair_count(int H, int N, int S_own, const int *S_nb, int n_nb);
 
 /* ---- stage-level entry points (fed upstream values from elsewhere) ---- */
+/* Geometric Jacobian J [6][dof] (linear rows, then angular) of the
+ * end-effector point at q, and the manipulability cost of Eq. 5:
+ * max(0, 1 - sqrt(det(J J^T)) / thresh). */
+void orc_jacobian(const orc_arm *arm, const double *q, double *J);
+double orc_manip_cost(const orc_arm *arm, const double *q, double thresh);
 /* Stage cost of one rollout step (Eq. 5 with Eqs. 6-10).  nb_plan[i] points
  * at neighbour i's plan spheres for this h ([S_i][4]); nb_active[i] = 0 skips
- * it (unpublished plan, or h beyond its horizon).  terms[7] receives
- * pose, stop, joint, coll, self, dyn-sum(alpha*hinge), total. */
+ * it (unpublished plan, or h beyond its horizon).  terms[8] receives
+ * pose, stop, joint, coll, self, dyn-sum(alpha*hinge), total, manip. */
 double orc_stage_cost(const orc_arm *arm, const orc_params *p, int H, int h,
                       const double *q, const double *qd, const double *spheres,
                       const double *goal, const double *obs, int n_obs,
@@ -82,7 +88,7 @@ double orc_stage_cost(const orc_arm *arm, const orc_params *p, int H, int h,
                       const double *alpha_row, int n_nb, double *terms);
 /* Batched form over all (n, h) of one arm.  q, qd: [N][H][d]; spheres:
  * [N][H][S][4]; plans: [n_nb][H_max][S_max][4] with nb_H[i] steps valid;
- * out: [H][N]. */
+ * out: [H][N]; terms_out (optional): [H][N][8]. */
 void orc_stage_costs_batch(const orc_arm *arm, const orc_params *p, int N, int H,
                            const double *q, const double *qd, const double *spheres,
                            const double *goal, const double *obs, int n_obs,

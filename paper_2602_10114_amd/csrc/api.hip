@@ -67,6 +67,7 @@ struct mpc_ctx {
   BoardMeta* d_meta = nullptr;
   float* mu = nullptr;
   float* eps = nullptr;
+  float* manip = nullptr;              // [A][Hmax][Nmax] C_manip of the iteration (w_manip > 0)
   float* sig = nullptr;                // [A][Hmax][28] adapted covariances (packed lower triangles)
   float* chol = nullptr;               // their Cholesky factors
   float* partial = nullptr;
@@ -270,6 +271,8 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (!(p->alpha_sigma >= 0.f && p->alpha_sigma <= 1.f)) return fail(nullptr, MPC_EINVAL, "alpha_sigma outside [0, 1]");
   if (!(p->sigma_floor > 0.f && p->sigma_floor < 1e3f)) return fail(nullptr, MPC_EINVAL, "sigma_floor must be positive");
   if (p->plan_mode != 0 && p->plan_mode != 1) return fail(nullptr, MPC_EINVAL, "plan_mode must be 0 or 1");
+  if (!(p->w_manip >= 0.f && p->w_manip < 1e30f) || !(p->manip_thresh > 0.f && p->manip_thresh < 1e30f))
+    return fail(nullptr, MPC_EINVAL, "w_manip must be >= 0 and manip_thresh > 0");
   if (p->collision_mode == 1 && !(p->surrogate_margin >= p->buf_dyn))
     return fail(nullptr, MPC_EINVAL, "surrogate_margin must be at least buf_dyn");
 
@@ -306,6 +309,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   P.dist_floor = p->dist_floor; P.joint_margin = p->joint_margin;
   P.alpha_sigma = p->alpha_sigma; P.sigma_floor = p->sigma_floor;
   P.plan_mode = p->plan_mode; P.cov = p->alpha_sigma > 0.f ? 1 : 0;
+  P.w_manip = p->w_manip; P.manip_thresh = p->manip_thresh;
   P.seed_lo = (uint32_t)(p->seed & 0xffffffffull);
   P.seed_hi = (uint32_t)(p->seed >> 32);
   P.iters = p->iters; P.A = n_arms; P.dof = 7; P.Hmax = c->Hmax; P.Smax = c->Smax; P.Nmax = c->Nmax;
@@ -323,7 +327,8 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
       (rc = dalloc(c, &c->plan[0], A * H * S * 4)) || (rc = dalloc(c, &c->plan[1], A * H * S * 4)) ||
       (rc = dalloc(c, &c->planq[0], A * H * 7)) || (rc = dalloc(c, &c->planq[1], A * H * 7)) ||
       (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A)) ||
-      (rc = dalloc(c, &c->sig, A * H * kTri)) || (rc = dalloc(c, &c->chol, A * H * kTri))) {
+      (rc = dalloc(c, &c->sig, A * H * kTri)) || (rc = dalloc(c, &c->chol, A * H * kTri)) ||
+      (p->w_manip > 0.f && (rc = dalloc(c, &c->manip, A * H * N)))) {
     g_last_error = c->err;
     mpc_destroy(c);
     return rc;
@@ -431,6 +436,7 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.audit = c->sur_audit ? 1 : 0;
   R.sur_counts = c->sur_counts;
   R.eps_in = c->P.cov ? c->eps : nullptr;
+  R.manip = c->manip;
   return R;
 }
 
@@ -534,6 +540,9 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
     RolloutArgs R = rollout_args(c, k);
     if (c->P.cov)
       HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, k, c->A, c->Nmax, c->stream));
+    if (c->manip)
+      HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A, c->Nmax, c->manip,
+                             c->stream));
     if (c->collision_mode == 1) {
       // Learned distance: own-joint features of every rollout step, then the MLP's
       // skip decision per (rollout, step, neighbour).

@@ -53,6 +53,7 @@ struct Params {
   float w_pose, w_rot, w_stop, w_joint, w_coll, w_dyn;
   float buf_env, buf_self, buf_dyn, tau, prio_min, prio_max, dist_floor, joint_margin;
   float alpha_sigma, sigma_floor;
+  float w_manip, manip_thresh;
   uint32_t seed_lo, seed_hi;
   int iters, A, dof, Hmax, Smax, Nmax, max_obs;
   int plan_mode, cov;          // cov: covariance adaptation on (alpha_sigma > 0)

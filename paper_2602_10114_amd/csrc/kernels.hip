@@ -459,6 +459,7 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
         c = P.w_pose * pose;
         c = fmaf_(P.w_stop, stop, c);
         c = fmaf_(P.w_joint, joint, c);
+        if (A.manip) c = fmaf_(P.w_manip, A.manip[((size_t)a * P.Hmax + h) * P.Nmax + n], c);
       }
       // Self collision.
       c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_refines), c);
@@ -674,6 +675,85 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
 }
 
 // Eq. 3 (weighted mean) and Eq. 4 (mean update), one block per (arm, step).
+// Manipulability term of Eq. 5 for every rollout step: the rollout's joints
+// (the same noise and integration as the rollout kernel), the end-effector
+// point by the same walking frame, the geometric Jacobian (column k = (z_k x
+// (p_ee - o_k), z_k) from frame k), J J^T and its Cholesky factor, whose
+// pivot product is sqrt(det(J J^T)); C_manip = max(0, 1 - that / thresh).
+__global__ __launch_bounds__(kWave) void k_manip(const DevArm* __restrict__ arms, const Params* __restrict__ Pp,
+                                                 const StepState* __restrict__ ssp, const float* __restrict__ mu_all,
+                                                 const float* __restrict__ state, const float* __restrict__ eps_in,
+                                                 int k_iter, float* __restrict__ out) {
+  const Params& P = *Pp;
+  const int a = blockIdx.y;
+  const DevArm* arm = arms + a;
+  const int n = blockIdx.x * kWave + threadIdx.x;
+  if (n >= arm->Npad) return;
+  const uint32_t t = ssp->t;
+  const float* mu = mu_all + (size_t)a * P.Hmax * 7;
+  float q[8], qd[8];
+  for (int j = 0; j < 7; ++j) {
+    q[j] = state[(a * 7 + j) * 3 + 0];
+    qd[j] = state[(a * 7 + j) * 3 + 1];
+  }
+  q[7] = qd[7] = 0.f;
+  for (int h = 0; h < arm->H; ++h) {
+    float z[8];
+    if (eps_in) {
+      for (int j = 0; j < 7; ++j) z[j] = eps_in[arm->eps_off + ((size_t)h * 7 + j) * arm->Npad + n];
+    } else {
+      normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
+      for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
+    }
+    for (int j = 0; j < 7; ++j) {
+      const float u = z[j] + mu[h * 7 + j];
+      qd[j] = fmaf_(P.dt, u, qd[j]);
+      q[j] = fmaf_(P.dt, qd[j], q[j]);
+    }
+    Chain C;
+    chain_angles(C, arm, q);
+    Frame W;
+    frame_base(W, arm);
+    for (int k = 0; k < 7; ++k) walk(W, arm, C, k);
+    float ee[3];
+    frame_point(W, arm->tool[0], arm->tool[1], arm->tool[2], ee[0], ee[1], ee[2]);
+    float G[21];  // J J^T, packed lower triangle of a 6x6
+    for (int e = 0; e < 21; ++e) G[e] = 0.f;
+    frame_base(W, arm);
+    for (int k = 0; k < 7; ++k) {
+      walk(W, arm, C, k);
+      const float rx = ee[0] - W.t[0], ry = ee[1] - W.t[1], rz = ee[2] - W.t[2];
+      float col[6];
+      col[0] = W.z[1] * rz - W.z[2] * ry;
+      col[1] = W.z[2] * rx - W.z[0] * rz;
+      col[2] = W.z[0] * ry - W.z[1] * rx;
+      col[3] = W.z[0];
+      col[4] = W.z[1];
+      col[5] = W.z[2];
+      for (int i = 0; i < 6; ++i)
+        for (int j = 0; j <= i; ++j) G[i * (i + 1) / 2 + j] = fmaf_(col[i], col[j], G[i * (i + 1) / 2 + j]);
+    }
+    float L[21], vol = 1.f;
+    for (int j = 0; j < 6; ++j) {
+      float d = G[j * (j + 1) / 2 + j];
+      for (int m = 0; m < j; ++m) d -= L[j * (j + 1) / 2 + m] * L[j * (j + 1) / 2 + m];
+      if (!(d > 0.f)) {
+        vol = 0.f;
+        break;
+      }
+      const float ljj = sqrtf(d);
+      L[j * (j + 1) / 2 + j] = ljj;
+      vol *= ljj;
+      for (int i = j + 1; i < 6; ++i) {
+        float v = G[i * (i + 1) / 2 + j];
+        for (int m = 0; m < j; ++m) v -= L[i * (i + 1) / 2 + m] * L[j * (j + 1) / 2 + m];
+        L[i * (i + 1) / 2 + j] = v / ljj;
+      }
+    }
+    out[((size_t)a * P.Hmax + h) * P.Nmax + n] = fmaxf(0.f, 1.f - vol / P.manip_thresh);
+  }
+}
+
 // Noise with the adapted covariance (Eqs. 3-4): eps_{n,h} = L_h z_{n,h}, L_h
 // the Cholesky factor of Sigma_h, z the same standard normals as the rollout
 // kernel draws; written in its [H][7][Npad] per-arm layout.
@@ -931,6 +1011,13 @@ hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s) {
 
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s) {
   hipLaunchKernelGGL(k_publish, dim3(n_arms), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_manip(const DevArm* arms, const Params* P, const StepState* ss, const float* mu, const float* state,
+                        const float* eps_in, int k, int n_arms, int npad_max, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_manip, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, ss, mu, state,
+                     eps_in, k, out);
   return hipGetLastError();
 }
 

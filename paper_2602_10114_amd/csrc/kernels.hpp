@@ -38,6 +38,8 @@ struct RolloutArgs {
   // adapted covariance: the iteration's noise, precomputed (same layout as
   // eps); NULL = draw sigma z in the kernel
   const float* eps_in;
+  // C_manip of every (arm, step, rollout) [A][Hmax][Nmax], or NULL (w_manip = 0)
+  const float* manip;
 };
 
 struct SenseArgs {
@@ -96,6 +98,9 @@ hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s);
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
+// C_manip (Eq. 5) of every rollout step of iteration k: out [A][Hmax][Nmax].
+hipError_t launch_manip(const DevArm* arms, const Params* P, const StepState* ss, const float* mu, const float* state,
+                        const float* eps_in, int k, int n_arms, int npad_max, float* out, hipStream_t s);
 // Noise of iteration k from the adapted covariances: eps = L_h z.
 hipError_t launch_noise(const DevArm* arms, const Params* P, const StepState* ss, const float* chol, float* eps, int k,
                         int n_arms, int npad_max, hipStream_t s);

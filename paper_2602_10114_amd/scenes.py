@@ -100,7 +100,8 @@ def default_params(**over) -> dict:
              tau=3.0, prio_min=0.5, prio_max=2.0, dist_floor=1e-3,
              joint_margin=0.05, seed=0, max_obstacles=32,
              collision_mode=0, surrogate_margin=0.05,
-             alpha_sigma=0.0, sigma_floor=1e-3, plan_mode=0)
+             alpha_sigma=0.0, sigma_floor=1e-3, plan_mode=0,
+             w_manip=0.0, manip_thresh=0.1)
     p.update(over)
     return p
 

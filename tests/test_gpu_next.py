@@ -119,3 +119,28 @@ def test_static_plans_are_current_spheres():
         for h in range(8):
             assert np.abs(plan[h] - ref).max() < 1e-5
         assert np.abs(pq.cpu().numpy() - sc.state[a, :, 0]).max() == 0.0
+
+
+def test_manipulability_term_stage_isolated():
+    """C_manip in the stage cost (w_manip 50, threshold 0.15): the oracle's
+    stage costs on the GPU's own joints, spheres and plans, 1e-4 relative."""
+    from helpers import Capture, oracle_stage, read_boards, rel_err
+    _say("case: C_manip, 2 arms, 96 rollouts x 6 steps")
+    sc = small_scene(2, n=96, h=6, w_manip=50.0, manip_thresh=0.15)
+    ctl = native.Controller(sc.arms, sc.params)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.share_plans()
+    ctl.debug_enable(True)
+    boards = read_boards(ctl, sc)
+    ctl.step(sc.state, sc.goal, None)
+    ctl.sync()
+    manip_active = 0
+    for a in range(2):
+        cap = Capture(ctl, a)
+        ref = oracle_stage(sc, a, cap, np.zeros((0, 4)), boards)
+        assert rel_err(cap.stage, ref) < 1e-4
+        oa = oracle.make_arm(sc.arms[a])
+        manip_active += sum(oracle.manip_cost(oa, cap.q[n, h], float(np.float32(0.15))) > 0
+                            for n in range(0, 96, 7) for h in range(6))
+    _say(f"  sampled rollout steps with an active manipulability term: {manip_active}")
+    assert manip_active > 0

@@ -388,6 +388,39 @@ def test_static_plans_are_current_spheres(orc):
             np.testing.assert_allclose(pq[h], sc.state[a, :, 0], atol=1e-7)
 
 
+def _fd_jacobian(orc, oa, q, h=1e-6):
+    """Jacobian by central differences of the forward kinematics: linear rows
+    from the end-effector point, angular rows from R(q+h) R(q-h)^T."""
+    J = np.zeros((6, 7))
+    for k in range(7):
+        qp, qm = q.copy(), q.copy()
+        qp[k] += h
+        qm[k] -= h
+        Tp, Tm = orc.ee_pose(oa, qp), orc.ee_pose(oa, qm)
+        J[:3, k] = (Tp[:3, 3] - Tm[:3, 3]) / (2 * h)
+        W = Tp[:3, :3] @ Tm[:3, :3].T
+        J[3:, k] = np.array([W[2, 1] - W[1, 2], W[0, 2] - W[2, 0], W[1, 0] - W[0, 1]]) / (4 * h)
+    return J
+
+
+def test_jacobian_and_manipulability(orc):
+    """C_manip's Jacobian against central differences of the kinematics, its
+    cost against numpy's determinant; the zero configuration (joint axes 1
+    and 3, 5 and 7 aligned) is singular; the threshold limits."""
+    oa = orc.make_arm(_arm())
+    rng = np.random.default_rng(41)
+    lo, hi = _arm().q_lim[:, 0].astype(np.float64), _arm().q_lim[:, 1].astype(np.float64)
+    for _ in range(5):
+        q = rng.uniform(lo, hi)
+        J = orc.jacobian(oa, q)
+        Jf = _fd_jacobian(orc, oa, q)
+        np.testing.assert_allclose(J, Jf, atol=1e-7)
+        m = np.sqrt(max(np.linalg.det(Jf @ Jf.T), 0.0))
+        assert abs(orc.manip_cost(oa, q, 0.1) - max(0.0, 1.0 - m / 0.1)) < 1e-6
+        assert orc.manip_cost(oa, q, 1e-9) == 0.0
+    assert abs(orc.manip_cost(oa, np.zeros(7), 0.1) - 1.0) < 1e-6
+
+
 def test_total_cost_geometric(orc):
     # constant stage cost c: sum_{h<H} gamma^h c = c (1 - gamma^H) / (1 - gamma)
     g, H = 0.99, 30
