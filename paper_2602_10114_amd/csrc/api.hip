@@ -16,6 +16,11 @@
 
 using namespace mrs;
 
+// Device-side tables (the per-step powers of gamma, the LDS copy of the
+// neighbours' planned joints in the inference kernel) are sized for the
+// largest valid problem.
+static_assert(kMaxH >= MPC_MAX_HORIZON && kMaxArms >= MPC_MAX_ARMS, "device tables cover every valid problem");
+
 static thread_local std::string g_last_error;
 
 // (start, end) HIP event pairs recorded around launches while profiling.
@@ -116,6 +121,7 @@ struct mpc_ctx {
   uint16_t* sur_F = nullptr;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16)
   uint8_t* sur_skip = nullptr;         // [A][A][Hmax][Nmax]
   float* sur_pred = nullptr;           // optional predictions (debug capture)
+  uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
   unsigned long long* sur_counts = nullptr;  // [A][5]
   SurItem* d_sur_items = nullptr;
   int n_sur_items = 0;
@@ -548,15 +554,15 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       // skip decision per (rollout, step, neighbour).
       HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A,
                                   c->Nmax, c->sur_F, c->stream));
+      HIPCHK(c, launch_sur_pairs(c->d_arms, c->d_model, c->d_meta, c->planq[0], c->A, c->Hmax, c->sur_nbrec,
+                                 c->stream));
       SurInferArgs I{};
-      I.arms = c->d_arms;
       I.P = c->d_P;
       I.model = c->d_model;
-      I.meta = c->d_meta;
       I.W16 = c->sur_p16;
       I.P32 = c->sur_p;
       I.F = c->sur_F;
-      I.planq = c->planq[0];
+      I.nbrec = c->sur_nbrec;
       I.items = c->d_sur_items;
       I.n_items = c->n_sur_items;
       I.skip = c->sur_skip;
@@ -585,7 +591,7 @@ static int ensure_sur_buffers(mpc_ctx* c) {
   const size_t A = c->A, H = c->Hmax, N = c->Nmax;
   int rc;
   if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
-      (rc = dalloc(c, &c->sur_pred, A * A * H * N)))
+      (rc = dalloc(c, &c->sur_pred, A * A * H * N)) || (rc = dalloc(c, &c->sur_nbrec, A * A * H * kNbrRec)))
     return rc;
   std::vector<SurItem> items;
   for (int a = 0; a < c->A; ++a)

@@ -143,6 +143,36 @@ __global__ void k_features(const DevArm* __restrict__ arms, const SurModel* __re
   for (int k = 0; k < kFeat; ++k) F[(size_t)m * kFeat + k] = f[k];
 }
 
+// Neighbour records of the fused inference, one per (arm a, neighbour i,
+// step h) of the read-side plans: the neighbour half of the features
+// (identical for every rollout of a at step h) and what the decision needs.
+__global__ __launch_bounds__(kWave) void k_sur_pairs(const DevArm* __restrict__ arms,
+                                                     const SurModel* __restrict__ sm,
+                                                     const BoardMeta* __restrict__ meta,
+                                                     const float* __restrict__ planq, int n_arms, int Hmax,
+                                                     uint32_t* __restrict__ rec) {
+  const int h = blockIdx.x * kWave + threadIdx.x;
+  const int a = blockIdx.y / n_arms, i = blockIdx.y % n_arms;
+  if (h >= Hmax) return;
+  uint32_t* r = rec + (((size_t)a * n_arms + i) * Hmax + h) * kNbrRec;
+  const DevArm* A = arms + a;
+  const DevArm* I = arms + i;
+  float qa[8], qi[8], f[kFeat];
+  for (int j = 0; j < 8; ++j) {
+    qa[j] = 0.f;
+    qi[j] = j < 7 ? planq[((size_t)i * Hmax + h) * 7 + j] : 0.f;
+  }
+  pair_features(A, qa, I, qi, sm, f);
+  bool inbox = true;
+  for (int j = 7; j < 14; ++j) inbox = inbox && fabsf(f[j]) <= 1.0f + 1e-3f;
+  const bool live = i != a && meta->valid[0][i] != 0 && h < I->H;
+  const uint4 v0 = make_uint4(f2bf2(f[7], f[8]), f2bf2(f[9], f[10]), f2bf2(f[11], f[12]), f2bf2(f[13], f[14]));
+  const uint4 v1 = make_uint4(f2bf2(f[15], f[16]), (inbox ? 1u : 0u) | (live ? 2u : 0u), (uint32_t)A->N,
+                              (uint32_t)A->Npad);
+  reinterpret_cast<uint4*>(r)[0] = v0;
+  reinterpret_cast<uint4*>(r)[1] = v1;
+}
+
 // Training samples.  Counter (sample low, sample high, draw c, 0x5A000000):
 // word 0 of draw 0 picks the pair, the other 15 words give the 14 joints.
 template <int LAY>
@@ -415,75 +445,62 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
 // (one block per CU) streams blocks of 32 queries (32 rollouts of one arm at
 // one step against one neighbour's plan) through a pipeline with one barrier
 // per stage:
-//   group B (the upper kGroupWaves waves) holds kWaveRows rows each of the
-//   third layer's weights (and of the first layer's) in registers; at stage
-//   s it runs the features and first layer of query block s and the third
-//   layer of block s-2;
-//   group A holds kWaveRows rows each of the second layer's weights and runs
-//   that layer on block s-1, then the output layer and the skip decision of
-//   block s-3 (8 lanes per query, reduced in the wave).
+//   group A (the lower kGroupWaves waves) holds kWaveRows rows each of the
+//   second layer's weights in registers; at stage s it runs the first layer
+//   of query block s (small weights read from LDS; its inputs, the own-
+//   feature rows and the neighbour record, were loaded a stage earlier) and
+//   then the second layer on block s-1;
+//   group B holds kWaveRows rows each of the third layer's weights; it runs
+//   that layer on block s-2 with the output layer folded into its epilogue
+//   (each lane takes its ReLU'd third-layer features, rounded to bfloat16,
+//   times the matching output weights, and leaves one partial sum per query,
+//   wave and lane half in LDS); its first wave then adds the partial sums of
+//   block s-3 and takes the skip decision.
+// Each SIMD holds one wave of each group, so one wave's MFMA chain runs
+// while the other does its latency-bound part (LDS round trips, VALU), and
+// the roles swap half-way through the stage.
 // Activations pass between the groups through LDS as bfloat16 rows
 // [query][feature].  The products are gfx950's 32x32x16 bfloat16 MFMAs with
 // features along the rows and queries along the columns: A = weight rows,
 // B = activation rows of 32 queries; each B operand read from LDS feeds
-// kFB = kWaveRows / 32 independent accumulators.  kGroupWaves = 4 (two waves
-// per SIMD, 64 rows each) measured faster than 2 (one wave per SIMD with 128
-// rows, whose accumulators then live in AGPRs and cost a move per element).
+// kFB = kWaveRows / 32 independent accumulators, and kInflight operand reads
+// stay in flight ahead of the MFMAs that use them.
 constexpr int kGroupWaves = 4;
 constexpr int kWaveRows = kHid / kGroupWaves;
 constexpr int kFB = kWaveRows / 32;
 constexpr int kInferThreads = 2 * kGroupWaves * kWave;
 constexpr int kActLd = kHid + 8;  // bfloat16 per LDS row: +16 bytes so consecutive rows start 4 banks apart
-
-// What the inference loop needs of each arm, copied to LDS once.
-struct InferArm {
-  int N, Npad, H, valid;         // valid: the arm's plan is on the read side of the board
-  float bx, by, bz, byaw, cyaw, syaw;
-};
+constexpr int kParts = 2 * kGroupWaves;  // output-layer partial sums per query
+constexpr int kPartLd = kParts + 4;      // floats per partial-sum row (16-byte aligned rows)
+constexpr int kInflight = 4;
+constexpr int kItemBatch = 64;           // query-block descriptors staged in LDS per batch
+static_assert(kParts % 4 == 0, "partial sums are read as float4");
+static_assert(kItemBatch <= kWave && kItemBatch >= 3, "one lane per staged descriptor; staged two stages early");
+static_assert(sizeof(SurItem) == 16, "descriptors are staged as 16-byte vectors");
 
 struct alignas(16) InferLds {
   uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
   uint16_t act2[2][32][kActLd];  // second-layer outputs
-  uint16_t act3[2][32][kActLd];  // third-layer outputs
+  uint4 w1[kGroupWaves][kFB][2][kWave];  // group A's first-layer A operands, per wave / block / chunk / lane
+  float part[2][32][kPartLd];    // output-layer partial sums [block][query][wave * 2 + lane half]
   float bias[3][kHid];
   uint16_t w4[kHid];             // output weights, bfloat16
   int ok[4][32];                 // bit 0: query live; bit 1: live and inside the training box
   long long out_row[4];          // skip / prediction offset of the block's first query
   int out_arm[4];                // own arm of the block
-  unsigned cnt[kMaxArms][2];     // queries and predicted-far queries of this block, per arm
   int n_rows[4];                 // rows of the block below the arm's padded rollout count
-  InferArm arm[kMaxArms];
-  float mid[7], inv_half[7];
+  unsigned cnt[kMaxArms][2];     // queries and predicted-far queries, per arm
+  alignas(16) SurItem items[2][kItemBatch];  // this block's query-block descriptors, two batches
   float b4;
 };
 
 // First-layer K slots: chunk 0 = [own f0..f6, flag slot (zero weight)] for
-// lanes 0-31 and [neighbour f7..f13, f14] for lanes 32-63; chunk 1 = [f15,
-// f16, zeros] for lanes 0-31 and zeros for lanes 32-63.
+// lanes 0-31 and [neighbour f7..f13, f14] for lanes 32-63 (the neighbour
+// record's first 16 bytes); chunk 1 = [f15, f16, zeros] for lanes 0-31 and
+// zeros for lanes 32-63.
 __device__ __forceinline__ int first_layer_feature(int c, int half, int e) {
   if (c == 0) return half ? 7 + e : (e < 7 ? e : -1);
   return (half == 0 && e < 2) ? 15 + e : -1;
-}
-
-// Neighbour part of the features (identical for the 32 queries of a block):
-// f7..f16 as in pair_features, and whether its joints lie in the box.
-__device__ __forceinline__ bool neighbour_features(const InferArm& a, const InferArm& i, const float* qi,
-                                                   const float* mid, const float* inv_half, float g[10]) {
-  const float kPi = 3.14159265358979f;
-  float q0 = qi[0] + (i.byaw - a.byaw);
-  q0 = q0 - 6.28318530717959f * floorf((q0 + kPi) * 0.159154943091895f);
-  g[0] = q0 * 0.318309886183791f;
-  bool inbox = fabsf(g[0]) <= 1.0f + 1e-3f;
-#pragma unroll
-  for (int j = 1; j < 7; ++j) {
-    g[j] = (qi[j] - mid[j]) * inv_half[j];
-    inbox = inbox && fabsf(g[j]) <= 1.0f + 1e-3f;
-  }
-  const float dx = i.bx - a.bx, dy = i.by - a.by, dz = i.bz - a.bz;
-  g[7] = fmaf_(a.cyaw, dx, a.syaw * dy);
-  g[8] = fmaf_(-a.syaw, dx, a.cyaw * dy);
-  g[9] = dz;
-  return inbox;
 }
 
 // Accumulator block starts from the bias of its features: element q4*4 + r
@@ -500,86 +517,104 @@ __device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl) {
 }
 
 // 256-wide layer for this wave's kWaveRows output features over 32 queries
-// (`bl` = bias + the lane's first feature).
-__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const uint16_t (*act)[kActLd],
-                                         const float* bl, f32x16_t (&acc)[kFB], int lane) {
+// (`row` = the input activation row of the lane's query + (lane/32)*8,
+// `bl` = bias + the lane's first feature).
+__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const uint16_t* row, const float* bl,
+                                         f32x16_t (&acc)[kFB]) {
+  __builtin_amdgcn_sched_barrier(0);
+  bf16x8_t b[16];
+#pragma unroll
+  for (int c = 0; c < kInflight; ++c) b[c] = load_bf16x8(row + c * 16);
 #pragma unroll
   for (int fb = 0; fb < kFB; ++fb) init_block(acc[fb], bl + fb * 32);
-  const uint16_t* row = act[lane & 31] + (lane >> 5) * 8;
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    const bf16x8_t b = load_bf16x8(row + c * 16);
+    if (c + kInflight < 16) b[c + kInflight] = load_bf16x8(row + (c + kInflight) * 16);
 #pragma unroll
-    for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b, acc[fb], 0, 0, 0);
+    for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b[c], acc[fb], 0, 0, 0);
   }
+  // Issue order: the first kInflight operand reads and the bias reads, then
+  // per chunk its kFB MFMAs and the read kInflight chunks ahead.
+  __builtin_amdgcn_sched_group_barrier(0x100, kInflight + 4 * kFB, 0);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    __builtin_amdgcn_sched_group_barrier(0x008, kFB, 0);
+    if (c + kInflight < 16) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
-// Lane exchange by DPP control `ctrl` (all rows and banks enabled).
-template <int ctrl>
-__device__ __forceinline__ float dpp_f32(float x) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+// ReLU of two packed bfloat16 values: a signed 16-bit max with 0 on each
+// half (a set sign bit reads as a negative integer), one VALU instruction.
+// ReLU after rounding equals rounding after ReLU, so the stored activations
+// are bfloat16(max(x, 0)).
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
+  uint32_t r;
+  asm("v_pk_max_i16 %0, %1, 0" : "=v"(r) : "v"(x));
+  return r;
 }
 
-// max(x, 0) as one integer max on the bit pattern (equal to fmaxf(x, 0) for
-// every non-NaN x, -0 included up to the sign of zero).
-__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
-
-// relu, bfloat16, into the LDS rows of this lane's query (`dst` = row +
+// ReLU, bfloat16, into the LDS rows of this lane's query (`dst` = row +
 // base + (lane/32)*4).
 __device__ __forceinline__ void store_block(const f32x16_t& acc, uint16_t* dst) {
 #pragma unroll
   for (int q4 = 0; q4 < 4; ++q4) {
     uint2 v;
-    v.x = f2bf2(relu_bits(acc[q4 * 4 + 0]), relu_bits(acc[q4 * 4 + 1]));
-    v.y = f2bf2(relu_bits(acc[q4 * 4 + 2]), relu_bits(acc[q4 * 4 + 3]));
+    v.x = relu_bf16x2(f2bf2(acc[q4 * 4 + 0], acc[q4 * 4 + 1]));
+    v.y = relu_bf16x2(f2bf2(acc[q4 * 4 + 2], acc[q4 * 4 + 3]));
     *reinterpret_cast<uint2*>(dst + q4 * 8) = v;
   }
 }
 
-// The global reads of one query block, issued a stage before they are used.
-struct BlockIn {
-  SurItem item;
-  uint4 fown;     // this lane's own-feature row (lanes 0-31 use it)
-  float pq[7];    // neighbour's planned joints at the block's step
-};
-
-__device__ __forceinline__ void fetch_block(const SurInferArgs& A, const InferLds& L, int Hmax, int Nmax,
-                                            const SurItem& it, int q, BlockIn& b) {
-  b.item = it;
-  const int n = min(it.n0 + q, L.arm[it.arm].Npad - 1);
-  b.fown = *reinterpret_cast<const uint4*>(A.F + (((size_t)it.arm * Hmax + it.h) * Nmax + n) * 8);
-  const float* pq = A.planq + ((size_t)it.nbr * Hmax + it.h) * 7;
+// The lane's share of the output layer for one accumulator block: its 16
+// third-layer features, ReLU'd and rounded to bfloat16, dotted with the
+// output weights of the same features (`w4` = output weights + the lane's
+// first feature), FP32 accumulation.
+__device__ __forceinline__ float out_partial(const f32x16_t& acc, const uint16_t* w4) {
+  float t = 0.f;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) b.pq[j] = pq[j];
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const uint2 wv = *reinterpret_cast<const uint2*>(w4 + q4 * 8);
+    const uint32_t h01 = relu_bf16x2(f2bf2(acc[q4 * 4 + 0], acc[q4 * 4 + 1]));
+    const uint32_t h23 = relu_bf16x2(f2bf2(acc[q4 * 4 + 2], acc[q4 * 4 + 3]));
+    t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, h01), __builtin_bit_cast(bf16x2_t, wv.x), t,
+                                        false);
+    t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, h23), __builtin_bit_cast(bf16x2_t, wv.y), t,
+                                        false);
+  }
+  return t;
+}
+
+// The lane's B operand of the first layer's first chunk for query block
+// `it` (lanes 0-31: the query's own-feature row; lanes 32-63: the neighbour
+// record's first 16 bytes) and the record's second 16 bytes.  Every query
+// block lies inside its arm's padded rollout range, so the row is in bounds.
+__device__ __forceinline__ void fetch_block(const SurInferArgs& A, int nA, int Hmax, int Nmax, const SurItem& it,
+                                            int half, int q, uint4& x0, uint4& r1) {
+  const uint32_t* rec = A.nbrec + (((size_t)it.arm * nA + it.nbr) * Hmax + it.h) * kNbrRec;
+  const uint16_t* own = A.F + (((size_t)it.arm * Hmax + it.h) * Nmax + it.n0 + q) * 8;
+  x0 = half ? *reinterpret_cast<const uint4*>(rec) : *reinterpret_cast<const uint4*>(own);
+  r1 = *reinterpret_cast<const uint4*>(rec + 4);
 }
 
 __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) {
   __shared__ InferLds L;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // Wave roles are wave-uniform: the group branch below is a scalar branch.
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int grp = wave / kGroupWaves, wq = wave % kGroupWaves, half = lane >> 5, q = lane & 31;
   // Loop invariants in registers and LDS: the loop's only global reads are
-  // the prefetched query blocks.
+  // the first-layer inputs (a stage ahead) and the descriptor batches (a
+  // batch ahead).
   const int nA = A.P->A, Hmax = A.P->Hmax, Nmax = A.P->Nmax;
   const float margin = A.model->margin;
-  if (tid < nA) {
-    const DevArm& d = A.arms[tid];
-    InferArm& m = L.arm[tid];
-    m.N = d.N;
-    m.Npad = d.Npad;
-    m.H = d.H;
-    m.valid = A.meta->valid[0][tid];
-    m.bx = d.base[0];
-    m.by = d.base[1];
-    m.bz = d.base[2];
-    m.byaw = d.base[3];
-    m.cyaw = d.cyaw;
-    m.syaw = d.syaw;
-  }
-  if (tid < 7) {
-    L.mid[tid] = A.model->mid[tid];
-    L.inv_half[tid] = A.model->inv_half[tid];
-  }
   if (tid < 2 * kMaxArms) L.cnt[tid >> 1][tid & 1] = 0u;
+  if (tid < 4) {
+    L.out_row[tid] = 0;
+    L.out_arm[tid] = 0;
+    L.n_rows[tid] = 0;
+  }
+  for (int e = tid; e < 4 * 32; e += kInferThreads) L.ok[e >> 5][e & 31] = 0;
   for (int e = tid; e < kHid; e += kInferThreads) {
     L.bias[0][e] = A.P32[mlp_b_off(0) + e];
     L.bias[1][e] = A.P32[mlp_b_off(1) + e];
@@ -597,18 +632,21 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
       for (int c = 0; c < 16; ++c) w[fb][c] = load_bf16x8(src + fb * 32 * kHid + c * 16);
   }
-  bf16x8_t w1[kFB][2];
+  if (grp == 0) {
 #pragma unroll
-  for (int fb = 0; fb < kFB; ++fb)
+    for (int fb = 0; fb < kFB; ++fb)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c) {
+        uint16_t v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = first_layer_feature(c, half, e);
-        uint16_t v = 0;
-        if (grp == 1 && k >= 0) v = A.W16[mlp_w_off(0) + (long long)(row0 + fb * 32) * kFeat + k];
-        w1[fb][c][e] = __builtin_bit_cast(__bf16, v);
+        for (int e = 0; e < 8; ++e) {
+          const int k = first_layer_feature(c, half, e);
+          v[e] = k >= 0 ? A.W16[mlp_w_off(0) + (long long)(row0 + fb * 32) * kFeat + k] : (uint16_t)0;
+        }
+        L.w1[wq][fb][c][lane] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                                           v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
       }
+  }
 
   const int G = gridDim.x;
   const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
@@ -618,119 +656,124 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   // in-bounds stand-in data (zeroed activations, the last block's inputs) and
   // only their writes are suppressed, so the compiler may interleave each
   // wave's MFMA and VALU work freely.
-  for (int e = tid; e < (int)(3 * sizeof(L.act1) / sizeof(uint4)); e += kInferThreads)
+  for (int e = tid; e < (int)(2 * sizeof(L.act1) / sizeof(uint4)); e += kInferThreads)
     reinterpret_cast<uint4*>(&L.act1[0][0][0])[e] = make_uint4(0u, 0u, 0u, 0u);
-  // Group B keeps the reads of the next block and the item after it in flight.
-  BlockIn cur, nxt;
-  SurItem item2{};
+  for (int e = tid; e < (int)(sizeof(L.part) / sizeof(float)); e += kInferThreads) (&L.part[0][0][0])[e] = 0.f;
+  // Descriptors of this block's query blocks (block k at stage k is item
+  // blockIdx.x + k*G): the first batch now; later batches are loaded by the
+  // first wave of group A at the start of the batch before and written two
+  // stages before they are first needed.
+  for (int e = tid; e < min(kItemBatch, n_my); e += kInferThreads)
+    L.items[0][e] = A.items[blockIdx.x + (long long)e * G];
+  auto item_at = [&](int k) -> SurItem {
+    const int c = min(k, n_my - 1);
+    return L.items[(c / kItemBatch) & 1][c % kItemBatch];
+  };
+  uint4 batch_next = make_uint4(0u, 0u, 0u, 0u);  // a descriptor, kept as a vector in registers
+  // Group A's inputs of the next query block, loaded a stage ahead.
+  SurItem it_next{};
+  uint4 x0_next = make_uint4(0u, 0u, 0u, 0u), r1_next = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
-  if (grp == 1 && n_my > 0) {
-    fetch_block(A, L, Hmax, Nmax, A.items[blockIdx.x], q, nxt);
-    item2 = A.items[blockIdx.x + (long long)min(1, n_my - 1) * G];
+  if (grp == 0 && n_my > 0) {
+    it_next = item_at(0);
+    fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
   }
+  // Each SIMD holds one wave of each group, and the two alternate between
+  // MFMA-bound and latency-bound work within a stage: group B starts its
+  // third-layer chain at the barrier while group A runs the first layer of
+  // the next block, then group A runs its second-layer chain while group B
+  // finishes the output layer and the decision.
   for (int s = 0; s < n_my + 3; ++s) {
-    if (grp == 1) {
-      // Features and first layer of query block s (the last block again
-      // past the end), then the third layer of block s-2; the block's
-      // bookkeeping for the decision three stages later is stored last so
-      // that both layers form one straight-line sequence.
-      cur = nxt;
-      fetch_block(A, L, Hmax, Nmax, item2, q, nxt);
-      item2 = A.items[blockIdx.x + (long long)min(s + 2, n_my - 1) * G];
-      const SurItem it = cur.item;
-      const InferArm& arm = L.arm[it.arm];
-      const InferArm& nbr = L.arm[it.nbr];
-      const bool live = nbr.valid != 0 && it.h < nbr.H && it.n0 + q < arm.N;
-      bool inbox;
+    if (grp == 0) {
+      // First layer of query block s (the last block again past the end) and
+      // its bookkeeping for the decision three stages later, then the second
+      // layer of block s-1.  Block s's inputs arrived during the last stage;
+      // block s+1's are requested now.
+      const SurItem it = it_next;
+      const uint4 x0w = x0_next, r1 = r1_next;
+      it_next = item_at(s + 1);
+      fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
+      if (wq == 0 && lane < kItemBatch) {
+        const int k = s % kItemBatch, nb = s / kItemBatch + 1, e = nb * kItemBatch + lane;
+        if (k == 0 && e < n_my)
+          batch_next = *reinterpret_cast<const uint4*>(A.items + blockIdx.x + (long long)e * G);
+        if (k == kItemBatch - 2 && e < n_my) *reinterpret_cast<uint4*>(&L.items[nb & 1][lane]) = batch_next;
+      }
       {
-        float g[10];
-        const bool nbr_in = neighbour_features(arm, nbr, cur.pq, L.mid, L.inv_half, g);
-        inbox = nbr_in && (cur.fown.w >> 16) != 0u;
-        // B operands: lanes 0-31 take their own-feature row (its flag slot
-        // meets a zero weight), lanes 32-63 the neighbour features f7..f14;
-        // the second chunk holds f15, f16 for lanes 0-31 and zeros.
-        const uint4 nbw = make_uint4(f2bf2(g[0], g[1]), f2bf2(g[2], g[3]), f2bf2(g[4], g[5]), f2bf2(g[6], g[7]));
-        const uint4 xw0 = half ? nbw : cur.fown;
-        const uint4 xw1 = make_uint4(half ? 0u : f2bf2(g[8], g[9]), 0u, 0u, 0u);
-        const bf16x8_t x0 = __builtin_bit_cast(bf16x8_t, xw0);
-        const bf16x8_t x1 = __builtin_bit_cast(bf16x8_t, xw1);
-        f32x16_t acc[kFB];
+        // B operands: chunk 0 as loaded; chunk 1 holds f15, f16 (the record's
+        // fifth word) for lanes 0-31 and zeros.
+        const bf16x8_t x0 = __builtin_bit_cast(bf16x8_t, x0w);
+        const bf16x8_t x1 = __builtin_bit_cast(bf16x8_t, make_uint4(half ? 0u : r1.x, 0u, 0u, 0u));
+        f32x16_t acc1[kFB];
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) {
-          init_block(acc[fb], &L.bias[0][fcol + fb * 32]);
-          acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][0], x0, acc[fb], 0, 0, 0);
-          acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc[fb], 0, 0, 0);
-          store_block(acc[fb], &L.act1[s & 1][q][fcol + fb * 32]);
+          init_block(acc1[fb], &L.bias[0][fcol + fb * 32]);
+          const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, L.w1[wq][fb][0][lane]);
+          const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, L.w1[wq][fb][1][lane]);
+          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, x0, acc1[fb], 0, 0, 0);
+          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, x1, acc1[fb], 0, 0, 0);
         }
-      }
-      {
-        f32x16_t acc[kFB];
-        layer256(w, L.act2[(s - 2) & 1], &L.bias[2][fcol], acc, lane);
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act3[(s - 2) & 1][q][fcol + fb * 32]);
+        for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][q][fcol + fb * 32]);
       }
       if (s < n_my && wq == 0 && half == 0) {
+        // A query is live when the neighbour's plan is readable and covers
+        // the step and the rollout exists; inside the training box when both
+        // arms' joints are.
+        const bool live = (r1.y & 2u) != 0u && it.n0 + q < (int)r1.z;
+        const bool inbox = (r1.y & 1u) != 0u && (x0w.w >> 16) != 0u;
         L.ok[s & 3][q] = (live ? 1 : 0) | ((live && inbox) ? 2 : 0);
         if (q == 0) {
           L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
-          L.n_rows[s & 3] = arm.Npad - it.n0;
+          L.n_rows[s & 3] = (int)r1.w - it.n0;
           L.out_arm[s & 3] = it.arm;
         }
       }
-    } else {
       {
-        // Second layer of query block s-1.
         f32x16_t acc[kFB];
-        layer256(w, L.act1[(s - 1) & 1], &L.bias[1][fcol], acc, lane);
+        layer256(w, &L.act1[(s - 1) & 1][q][half * 8], &L.bias[1][fcol], acc);
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][q][fcol + fb * 32]);
       }
+    } else {
+      // Third layer of block s-2 with the output layer folded into its
+      // epilogue, then (first wave) the output and decision of block s-3.
       {
-        // Output layer and decision of query block s-3: 8 lanes per query
-        // (queries wq*32/kGroupWaves + pass*8 + lane/8); the 8 lanes take
-        // 16-byte chunks j, j+8, j+16, j+24 (j = lane%8), so each 8-lane group
-        // reads 128 contiguous bytes.
-        const int r = (s - 3) & 3, j = lane & 7;
+        f32x16_t acc3[kFB];
+        layer256(w, &L.act2[(s - 2) & 1][q][half * 8], &L.bias[2][fcol], acc3);
+        float t = 0.f;
 #pragma unroll
-        for (int pass = 0; pass < 4 / kGroupWaves; ++pass) {
-          const int qq = wq * (32 / kGroupWaves) + pass * 8 + (lane >> 3);
-          const uint16_t* row = &L.act3[(s - 3) & 1][qq][0];
-          float pi[4];
+        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], &L.w4[fcol + fb * 32]);
+        L.part[(s - 2) & 1][q][wq * 2 + half] = t;
+      }
+      if (wq == 0) {
+        // Lanes 0-31, one query each: the partial sums in a fixed order,
+        // then the bias.
+        // All LDS inputs are read up front (one round trip); the counts are
+        // return-less LDS atomics.
+        const int r = (s - 3) & 3;
+        const float* pr = &L.part[(s - 3) & 1][q][0];
+        float4 p[kParts / 4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int k = (j + 8 * i) * 8;
-            const uint4 a = *reinterpret_cast<const uint4*>(row + k);
-            const uint4 wv = *reinterpret_cast<const uint4*>(&L.w4[k]);
-            float t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.x),
-                                                      __builtin_bit_cast(bf16x2_t, wv.x), 0.f, false);
-            t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.y), __builtin_bit_cast(bf16x2_t, wv.y),
-                                                t, false);
-            t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.z), __builtin_bit_cast(bf16x2_t, wv.z),
-                                                t, false);
-            pi[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a.w),
-                                                    __builtin_bit_cast(bf16x2_t, wv.w), t, false);
-          }
-          // sum over the 8 lanes of the query: swaps within quads, then the
-          // mirrored lane of the other quad of the row of 8
-          float part = (pi[0] + pi[1]) + (pi[2] + pi[3]);
-          part += dpp_f32<0xB1>(part);   // quad_perm [1,0,3,2]
-          part += dpp_f32<0x4E>(part);   // quad_perm [2,3,0,1]
-          part += dpp_f32<0x141>(part);  // row_half_mirror
-          const bool writer = s >= 3 && j == 0 && qq < L.n_rows[r];
-          const int okv = L.ok[r][qq];
-          const float y = part + L.b4;
-          const bool far = (okv & 2) != 0 && y >= margin;
-          if (writer) {
-            const long long o = L.out_row[r] + qq;
-            A.skip[o] = far ? 1 : 0;
-            if (A.pred) A.pred[o] = y;
-          }
-          const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
-          const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
-          if (lane == 0 && (nq | nf)) {
-            atomicAdd(&L.cnt[L.out_arm[r]][0], nq);
-            atomicAdd(&L.cnt[L.out_arm[r]][1], nf);
-          }
+        for (int i = 0; i < kParts / 4; ++i) p[i] = *reinterpret_cast<const float4*>(pr + 4 * i);
+        const int n_rows = L.n_rows[r], okv = L.ok[r][q], out_arm = L.out_arm[r];
+        const long long out_row = L.out_row[r];
+        float y = 0.f;
+#pragma unroll
+        for (int i = 0; i < kParts / 4; ++i) y += (p[i].x + p[i].y) + (p[i].z + p[i].w);
+        y += L.b4;
+        const bool writer = s >= 3 && half == 0 && q < n_rows;
+        const bool far = (okv & 2) != 0 && y >= margin;
+        if (writer) {
+          const long long o = out_row + q;
+          A.skip[o] = far ? 1 : 0;
+          if (A.pred) A.pred[o] = y;
+        }
+        const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
+        const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
+        if (lane == 0 && (nq | nf)) {
+          atomicAdd(&L.cnt[out_arm][0], nq);
+          atomicAdd(&L.cnt[out_arm][1], nf);
         }
       }
     }
@@ -821,6 +864,13 @@ hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel
                              int npad_max, uint16_t* F, hipStream_t s) {
   hipLaunchKernelGGL(k_sur_states, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, model,
                      ss, mu, state, eps_in, k_iter, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_sur_pairs(const DevArm* arms, const SurModel* model, const BoardMeta* meta, const float* planq,
+                            int n_arms, int Hmax, uint32_t* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_pairs, dim3((Hmax + kWave - 1) / kWave, n_arms * n_arms), dim3(kWave), 0, s, arms, model,
+                     meta, planq, n_arms, Hmax, rec);
   return hipGetLastError();
 }
 

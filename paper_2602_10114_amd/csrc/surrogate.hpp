@@ -57,15 +57,20 @@ struct SurItem {
   int arm, nbr, h, n0;
 };
 
+// Neighbour record of the fused inference, kNbrRec words per (arm a,
+// neighbour i, step h) of the read-side plans: [0..3] bfloat16 pairs
+// (f7,f8) .. (f13,f14), [4] (f15,f16), [5] flags (bit 0: the neighbour's
+// joints lie in the training box; bit 1: i != a, its plan is on the read
+// side and covers step h), [6] N of arm a, [7] padded N of arm a.
+constexpr int kNbrRec = 8;
+
 struct SurInferArgs {
-  const DevArm* arms;
   const Params* P;
   const SurModel* model;
-  const BoardMeta* meta;
   const uint16_t* W16;         // bfloat16 parameters (same packing as the FP32 master)
   const float* P32;            // FP32 parameters (biases are taken in FP32)
   const uint16_t* F;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16, slot 7 = in-box flag)
-  const float* planq;          // read-side planned joints [A][Hmax][7]
+  const uint32_t* nbrec;       // neighbour records [A][A][Hmax][kNbrRec]
   const SurItem* items;
   int n_items;
   int pad;
@@ -81,6 +86,9 @@ hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, 
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
                              int npad_max, uint16_t* F, hipStream_t s);
+// Neighbour records for every (a, i, h < Hmax) from the read-side plans.
+hipError_t launch_sur_pairs(const DevArm* arms, const SurModel* model, const BoardMeta* meta, const float* planq,
+                            int n_arms, int Hmax, uint32_t* rec, hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);
