@@ -481,10 +481,7 @@ static_assert(sizeof(SurItem) == 16, "descriptors are staged as 16-byte vectors"
 struct alignas(16) InferLds {
   uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
   uint16_t act2[2][32][kActLd];  // second-layer outputs
-  uint4 w1[kGroupWaves][kFB][2][kWave];  // group A's first-layer A operands, per wave / block / chunk / lane
   float part[2][32][kPartLd];    // output-layer partial sums [block][query][wave * 2 + lane half]
-  float bias[3][kHid];
-  uint16_t w4[kHid];             // output weights, bfloat16
   int ok[4][32];                 // bit 0: query live; bit 1: live and inside the training box
   long long out_row[4];          // skip / prediction offset of the block's first query
   int out_arm[4];                // own arm of the block
@@ -496,46 +493,61 @@ struct alignas(16) InferLds {
 
 // First-layer K slots: chunk 0 = [own f0..f6, flag slot (zero weight)] for
 // lanes 0-31 and [neighbour f7..f13, f14] for lanes 32-63 (the neighbour
-// record's first 16 bytes); chunk 1 = [f15, f16, zeros] for lanes 0-31 and
-// zeros for lanes 32-63.
+// record's first 16 bytes); chunk 1 = [f15, f16, 1, 1, 1, zeros] for lanes
+// 0-31 (the three ones meet the bias split into three bfloat16 parts) and
+// zeros for lanes 32-63.  Returns the feature index, kFeat for the bias
+// slots, -1 for zero slots.
 __device__ __forceinline__ int first_layer_feature(int c, int half, int e) {
   if (c == 0) return half ? 7 + e : (e < 7 ? e : -1);
-  return (half == 0 && e < 2) ? 15 + e : -1;
+  if (half != 0) return -1;
+  return e < 2 ? 15 + e : (e < 5 ? kFeat : -1);
 }
 
-// Accumulator block starts from the bias of its features: element q4*4 + r
-// holds feature base + q4*8 + (lane/32)*4 + r (`bl` = bias + base + (lane/32)*4).
-__device__ __forceinline__ void init_block(f32x16_t& acc, const float* bl) {
-#pragma unroll
-  for (int q4 = 0; q4 < 4; ++q4) {
-    const float4 b = *reinterpret_cast<const float4*>(bl + q4 * 8);
-    acc[q4 * 4 + 0] = b.x;
-    acc[q4 * 4 + 1] = b.y;
-    acc[q4 * 4 + 2] = b.z;
-    acc[q4 * 4 + 3] = b.w;
-  }
+// A bias as three bfloat16 parts (high, middle, low) that sum to it exactly:
+// each part takes the next 8 significant bits of what remains, and the
+// remainders are exact in FP32.  MFMA products with 1.0 are exact and their
+// FP32 sum is the bias again, so a folded bias equals an FP32 one.
+__device__ __forceinline__ void split_bias(float b, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
+  hi = f2bf(b);
+  const float r1 = b - bf2f(hi);
+  mid = f2bf(r1);
+  lo = f2bf(r1 - bf2f(mid));
+}
+
+// K chunk that adds a layer's bias: A operand = the rows' three bias parts
+// on lanes 0-31 (slots 0-2), zeros elsewhere; B operand = ones_operand.
+__device__ __forceinline__ bf16x8_t bias_operand(const float* bias, int row, int half) {
+  uint16_t hi = 0, mid = 0, lo = 0;
+  if (half == 0) split_bias(bias[row], hi, mid, lo);
+  return __builtin_bit_cast(bf16x8_t, make_uint4(hi | ((uint32_t)mid << 16), lo, 0u, 0u));
+}
+__device__ __forceinline__ bf16x8_t ones_operand(int half) {
+  return __builtin_bit_cast(bf16x8_t, make_uint4(half ? 0u : 0x3F803F80u, half ? 0u : 0x3F80u, 0u, 0u));
 }
 
 // 256-wide layer for this wave's kWaveRows output features over 32 queries
-// (`row` = the input activation row of the lane's query + (lane/32)*8,
-// `bl` = bias + the lane's first feature).
-__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const uint16_t* row, const float* bl,
-                                         f32x16_t (&acc)[kFB]) {
+// (`row` = the input activation row of the lane's query + (lane/32)*8): the
+// bias enters as one more K chunk (`wb` against the ones operand), so the
+// accumulators start from zero and the chain's first MFMAs need no LDS data.
+__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const bf16x8_t (&wb)[kFB], bf16x8_t ones,
+                                         const uint16_t* row, f32x16_t (&acc)[kFB]) {
   __builtin_amdgcn_sched_barrier(0);
   bf16x8_t b[16];
 #pragma unroll
   for (int c = 0; c < kInflight; ++c) b[c] = load_bf16x8(row + c * 16);
+  const f32x16_t zero = {};
 #pragma unroll
-  for (int fb = 0; fb < kFB; ++fb) init_block(acc[fb], bl + fb * 32);
+  for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c + kInflight < 16) b[c + kInflight] = load_bf16x8(row + (c + kInflight) * 16);
 #pragma unroll
     for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b[c], acc[fb], 0, 0, 0);
   }
-  // Issue order: the first kInflight operand reads and the bias reads, then
-  // per chunk its kFB MFMAs and the read kInflight chunks ahead.
-  __builtin_amdgcn_sched_group_barrier(0x100, kInflight + 4 * kFB, 0);
+  // Issue order: the first kInflight operand reads, the bias MFMAs, then per
+  // chunk its kFB MFMAs and the read kInflight chunks ahead.
+  __builtin_amdgcn_sched_group_barrier(0x100, kInflight, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, kFB, 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     __builtin_amdgcn_sched_group_barrier(0x008, kFB, 0);
@@ -568,13 +580,13 @@ __device__ __forceinline__ void store_block(const f32x16_t& acc, uint16_t* dst) 
 
 // The lane's share of the output layer for one accumulator block: its 16
 // third-layer features, ReLU'd and rounded to bfloat16, dotted with the
-// output weights of the same features (`w4` = output weights + the lane's
-// first feature), FP32 accumulation.
-__device__ __forceinline__ float out_partial(const f32x16_t& acc, const uint16_t* w4) {
+// output weights of the same features (`w4v`, four per quarter, in
+// registers), FP32 accumulation.
+__device__ __forceinline__ float out_partial(const f32x16_t& acc, const uint2 (&w4v)[4]) {
   float t = 0.f;
 #pragma unroll
   for (int q4 = 0; q4 < 4; ++q4) {
-    const uint2 wv = *reinterpret_cast<const uint2*>(w4 + q4 * 8);
+    const uint2 wv = w4v[q4];
     const uint32_t h01 = relu_bf16x2(f2bf2(acc[q4 * 4 + 0], acc[q4 * 4 + 1]));
     const uint32_t h23 = relu_bf16x2(f2bf2(acc[q4 * 4 + 2], acc[q4 * 4 + 3]));
     t = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, h01), __builtin_bit_cast(bf16x2_t, wv.x), t,
@@ -615,12 +627,6 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
     L.n_rows[tid] = 0;
   }
   for (int e = tid; e < 4 * 32; e += kInferThreads) L.ok[e >> 5][e & 31] = 0;
-  for (int e = tid; e < kHid; e += kInferThreads) {
-    L.bias[0][e] = A.P32[mlp_b_off(0) + e];
-    L.bias[1][e] = A.P32[mlp_b_off(1) + e];
-    L.bias[2][e] = A.P32[mlp_b_off(2) + e];
-    L.w4[e] = A.W16[mlp_w_off(3) + e];
-  }
   if (tid == 0) L.b4 = A.P32[mlp_b_off(3)];
   // Stationary weights: rows wq*kWaveRows + fb*32 + q, K slots c*16 + half*8 + 0..7.
   const int row0 = wq * kWaveRows + q;
@@ -632,21 +638,11 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
       for (int c = 0; c < 16; ++c) w[fb][c] = load_bf16x8(src + fb * 32 * kHid + c * 16);
   }
-  if (grp == 0) {
+  // The bias chunk of this wave's layer.
+  bf16x8_t wb[kFB];
 #pragma unroll
-    for (int fb = 0; fb < kFB; ++fb)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        uint16_t v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = first_layer_feature(c, half, e);
-          v[e] = k >= 0 ? A.W16[mlp_w_off(0) + (long long)(row0 + fb * 32) * kFeat + k] : (uint16_t)0;
-        }
-        L.w1[wq][fb][c][lane] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
-                                           v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
-      }
-  }
+  for (int fb = 0; fb < kFB; ++fb) wb[fb] = bias_operand(A.P32 + mlp_b_off(grp == 0 ? 1 : 2), row0 + fb * 32, half);
+  const bf16x8_t ones = ones_operand(half);
 
   const int G = gridDim.x;
   const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
@@ -682,9 +678,30 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   // MFMA-bound and latency-bound work within a stage: group B starts its
   // third-layer chain at the barrier while group A runs the first layer of
   // the next block, then group A runs its second-layer chain while group B
-  // finishes the output layer and the decision.
-  for (int s = 0; s < n_my + 3; ++s) {
-    if (grp == 0) {
+  // finishes the output layer and the decision.  Each group has a loop of
+  // its own (the same number of stages, one barrier per stage) and keeps
+  // its small weights in registers.
+  if (grp == 0) {
+    // First-layer A operands (bias folded into chunk 1).
+    bf16x8_t w1[kFB][2];
+#pragma unroll
+    for (int fb = 0; fb < kFB; ++fb)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint16_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = first_layer_feature(c, half, e);
+          const int r = row0 + fb * 32;
+          v[e] = 0;
+          if (k >= 0 && k < kFeat) v[e] = A.W16[mlp_w_off(0) + (long long)r * kFeat + k];
+        }
+        if (c == 1 && half == 0) split_bias(A.P32[mlp_b_off(0) + row0 + fb * 32], v[2], v[3], v[4]);
+        w1[fb][c] = __builtin_bit_cast(
+            bf16x8_t, make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                                 v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16)));
+      }
+    for (int s = 0; s < n_my + 3; ++s) {
       // First layer of query block s (the last block again past the end) and
       // its bookkeeping for the decision three stages later, then the second
       // layer of block s-1.  Block s's inputs arrived during the last stage;
@@ -700,57 +717,66 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
         if (k == kItemBatch - 2 && e < n_my) *reinterpret_cast<uint4*>(&L.items[nb & 1][lane]) = batch_next;
       }
       {
-        // B operands: chunk 0 as loaded; chunk 1 holds f15, f16 (the record's
-        // fifth word) for lanes 0-31 and zeros.
+        // B operands: chunk 0 as loaded; chunk 1 = [f15, f16, 1, 1, 1, 0..]
+        // (the record's fifth word, then the bias ones) for lanes 0-31 and
+        // zeros.
         const bf16x8_t x0 = __builtin_bit_cast(bf16x8_t, x0w);
-        const bf16x8_t x1 = __builtin_bit_cast(bf16x8_t, make_uint4(half ? 0u : r1.x, 0u, 0u, 0u));
+        const bf16x8_t x1 = __builtin_bit_cast(
+            bf16x8_t, make_uint4(half ? 0u : r1.x, half ? 0u : 0x3F803F80u, half ? 0u : 0x3F80u, 0u));
+        const f32x16_t zero = {};
         f32x16_t acc1[kFB];
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) {
-          init_block(acc1[fb], &L.bias[0][fcol + fb * 32]);
-          const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, L.w1[wq][fb][0][lane]);
-          const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, L.w1[wq][fb][1][lane]);
-          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, x0, acc1[fb], 0, 0, 0);
-          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, x1, acc1[fb], 0, 0, 0);
+          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][0], x0, zero, 0, 0, 0);
+          acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc1[fb], 0, 0, 0);
         }
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][q][fcol + fb * 32]);
-      }
-      if (s < n_my && wq == 0 && half == 0) {
-        // A query is live when the neighbour's plan is readable and covers
-        // the step and the rollout exists; inside the training box when both
-        // arms' joints are.
-        const bool live = (r1.y & 2u) != 0u && it.n0 + q < (int)r1.z;
-        const bool inbox = (r1.y & 1u) != 0u && (x0w.w >> 16) != 0u;
-        L.ok[s & 3][q] = (live ? 1 : 0) | ((live && inbox) ? 2 : 0);
-        if (q == 0) {
-          L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
-          L.n_rows[s & 3] = (int)r1.w - it.n0;
-          L.out_arm[s & 3] = it.arm;
+        if (s < n_my && wq == 0 && half == 0) {
+          // A query is live when the neighbour's plan is readable and covers
+          // the step and the rollout exists; inside the training box when
+          // both arms' joints are.
+          const bool live = (r1.y & 2u) != 0u && it.n0 + q < (int)r1.z;
+          const bool inbox = (r1.y & 1u) != 0u && (x0w.w >> 16) != 0u;
+          L.ok[s & 3][q] = (live ? 1 : 0) | ((live && inbox) ? 2 : 0);
+          if (q == 0) {
+            L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
+            L.n_rows[s & 3] = (int)r1.w - it.n0;
+            L.out_arm[s & 3] = it.arm;
+          }
         }
       }
       {
         f32x16_t acc[kFB];
-        layer256(w, &L.act1[(s - 1) & 1][q][half * 8], &L.bias[1][fcol], acc);
+        layer256(w, wb, ones, &L.act1[(s - 1) & 1][q][half * 8], acc);
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][q][fcol + fb * 32]);
       }
-    } else {
+      __syncthreads();
+    }
+  } else {
+    // Output weights of this lane's features.
+    uint2 w4v[kFB][4];
+#pragma unroll
+    for (int fb = 0; fb < kFB; ++fb)
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        w4v[fb][q4] = *reinterpret_cast<const uint2*>(A.W16 + mlp_w_off(3) + fcol + fb * 32 + q4 * 8);
+    for (int s = 0; s < n_my + 3; ++s) {
       // Third layer of block s-2 with the output layer folded into its
       // epilogue, then (first wave) the output and decision of block s-3.
       {
         f32x16_t acc3[kFB];
-        layer256(w, &L.act2[(s - 2) & 1][q][half * 8], &L.bias[2][fcol], acc3);
+        layer256(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], acc3);
         float t = 0.f;
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], &L.w4[fcol + fb * 32]);
+        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], w4v[fb]);
         L.part[(s - 2) & 1][q][wq * 2 + half] = t;
       }
       if (wq == 0) {
         // Lanes 0-31, one query each: the partial sums in a fixed order,
-        // then the bias.
-        // All LDS inputs are read up front (one round trip); the counts are
-        // return-less LDS atomics.
+        // then the bias.  All LDS inputs are read up front (one round trip);
+        // the counts are return-less LDS atomics.
         const int r = (s - 3) & 3;
         const float* pr = &L.part[(s - 3) & 1][q][0];
         float4 p[kParts / 4];
@@ -776,8 +802,8 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           atomicAdd(&L.cnt[out_arm][1], nf);
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (A.counts && tid < 2 * nA) {
     const unsigned v = L.cnt[tid >> 1][tid & 1];
