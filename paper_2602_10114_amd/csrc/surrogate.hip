@@ -657,8 +657,10 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   for (int e = tid; e < (int)(sizeof(L.part) / sizeof(float)); e += kInferThreads) (&L.part[0][0][0])[e] = 0.f;
   // Descriptors of this block's query blocks (block k at stage k is item
   // blockIdx.x + k*G): the first batch now; later batches are loaded by the
-  // first wave of group A at the start of the batch before and written two
-  // stages before they are first needed.
+  // third wave of group A at the start of the batch before and written two
+  // stages before they are first needed.  The staging, the bookkeeping and
+  // the decision sit on different waves (2 and 1 of group A, 0 of group B)
+  // so that no SIMD carries two of them.
   for (int e = tid; e < min(kItemBatch, n_my); e += kInferThreads)
     L.items[0][e] = A.items[blockIdx.x + (long long)e * G];
   auto item_at = [&](int k) -> SurItem {
@@ -710,7 +712,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
       const uint4 x0w = x0_next, r1 = r1_next;
       it_next = item_at(s + 1);
       fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
-      if (wq == 0 && lane < kItemBatch) {
+      if (wq == 2 && lane < kItemBatch) {
         const int k = s % kItemBatch, nb = s / kItemBatch + 1, e = nb * kItemBatch + lane;
         if (k == 0 && e < n_my)
           batch_next = *reinterpret_cast<const uint4*>(A.items + blockIdx.x + (long long)e * G);
@@ -732,7 +734,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
         }
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][q][fcol + fb * 32]);
-        if (s < n_my && wq == 0 && half == 0) {
+        if (s < n_my && wq == 1 && half == 0) {
           // A query is live when the neighbour's plan is readable and covers
           // the step and the rollout exists; inside the training box when
           // both arms' joints are.
@@ -763,16 +765,9 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
       for (int q4 = 0; q4 < 4; ++q4)
         w4v[fb][q4] = *reinterpret_cast<const uint2*>(A.W16 + mlp_w_off(3) + fcol + fb * 32 + q4 * 8);
     for (int s = 0; s < n_my + 3; ++s) {
-      // Third layer of block s-2 with the output layer folded into its
-      // epilogue, then (first wave) the output and decision of block s-3.
-      {
-        f32x16_t acc3[kFB];
-        layer256(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], acc3);
-        float t = 0.f;
-#pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], w4v[fb]);
-        L.part[(s - 2) & 1][q][wq * 2 + half] = t;
-      }
+      // First wave: the output and decision of block s-3 (its partial sums
+      // are complete at the barrier), before its chain; then the third layer
+      // of block s-2 with the output layer folded into its epilogue.
       if (wq == 0) {
         // Lanes 0-31, one query each: the partial sums in a fixed order,
         // then the bias.  All LDS inputs are read up front (one round trip);
@@ -801,6 +796,14 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           atomicAdd(&L.cnt[out_arm][0], nq);
           atomicAdd(&L.cnt[out_arm][1], nf);
         }
+      }
+      {
+        f32x16_t acc3[kFB];
+        layer256(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], acc3);
+        float t = 0.f;
+#pragma unroll
+        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], w4v[fb]);
+        L.part[(s - 2) & 1][q][wq * 2 + half] = t;
       }
       __syncthreads();
     }
