@@ -122,6 +122,7 @@ struct mpc_ctx {
   uint8_t* sur_skip = nullptr;         // [A][A][Hmax][Nmax]
   float* sur_pred = nullptr;           // optional predictions (debug capture)
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
+  float* sur_y = nullptr;              // predictions in descriptor order [items][32]
   unsigned long long* sur_counts = nullptr;  // [A][5]
   SurItem* d_sur_items = nullptr;
   int n_sur_items = 0;
@@ -565,13 +566,23 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       I.nbrec = c->sur_nbrec;
       I.items = c->d_sur_items;
       I.n_items = c->n_sur_items;
-      I.skip = c->sur_skip;
-      I.pred = debug ? c->sur_pred : nullptr;
-      I.counts = c->sur_counts;
+      I.y = c->sur_y;
       hipEvent_t ei = nullptr;
       if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
       HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
       if (ei) HIPCHK(c, hipEventRecord(ei, c->stream));
+      SurDecideArgs D{};
+      D.P = c->d_P;
+      D.model = c->d_model;
+      D.F = c->sur_F;
+      D.nbrec = c->sur_nbrec;
+      D.items = c->d_sur_items;
+      D.y = c->sur_y;
+      D.n_items = c->n_sur_items;
+      D.skip = c->sur_skip;
+      D.pred = debug ? c->sur_pred : nullptr;
+      D.counts = c->sur_counts;
+      HIPCHK(c, launch_sur_decide(D, c->stream));
     }
     hipEvent_t e1 = nullptr;
     if (c->profile) HIPCHK(c, c->prof_roll.begin(c->stream, &e1));
@@ -603,7 +614,7 @@ static int ensure_sur_buffers(mpc_ctx* c) {
     }
   c->n_sur_items = (int)items.size();
   if (!items.empty()) {
-    if ((rc = dalloc(c, &c->d_sur_items, items.size()))) return rc;
+    if ((rc = dalloc(c, &c->d_sur_items, items.size())) || (rc = dalloc(c, &c->sur_y, items.size() * 32))) return rc;
     HIPCHK(c, hipMemcpy(c->d_sur_items, items.data(), items.size() * sizeof(SurItem), hipMemcpyHostToDevice));
   }
   // One inference block per compute unit (its LDS and registers fill one).

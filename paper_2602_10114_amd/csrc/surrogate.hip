@@ -447,15 +447,16 @@ __global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__
 // per stage:
 //   group A (the lower kGroupWaves waves) holds kWaveRows rows each of the
 //   second layer's weights in registers; at stage s it runs the first layer
-//   of query block s (small weights read from LDS; its inputs, the own-
+//   of query block s (small weights in registers; its inputs, the own-
 //   feature rows and the neighbour record, were loaded a stage earlier) and
 //   then the second layer on block s-1;
 //   group B holds kWaveRows rows each of the third layer's weights; it runs
 //   that layer on block s-2 with the output layer folded into its epilogue
 //   (each lane takes its ReLU'd third-layer features, rounded to bfloat16,
 //   times the matching output weights, and leaves one partial sum per query,
-//   wave and lane half in LDS); its first wave then adds the partial sums of
-//   block s-3 and takes the skip decision.
+//   wave and lane half in LDS); its first wave adds the partial sums of
+//   block s-3 and stores the predictions.  The skip decision is a separate
+//   element-wise kernel (k_sur_decide), off the pipeline's critical path.
 // Each SIMD holds one wave of each group, so one wave's MFMA chain runs
 // while the other does its latency-bound part (LDS round trips, VALU), and
 // the roles swap half-way through the stage.
@@ -482,11 +483,6 @@ struct alignas(16) InferLds {
   uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
   uint16_t act2[2][32][kActLd];  // second-layer outputs
   float part[2][32][kPartLd];    // output-layer partial sums [block][query][wave * 2 + lane half]
-  int ok[4][32];                 // bit 0: query live; bit 1: live and inside the training box
-  long long out_row[4];          // skip / prediction offset of the block's first query
-  int out_arm[4];                // own arm of the block
-  int n_rows[4];                 // rows of the block below the arm's padded rollout count
-  unsigned cnt[kMaxArms][2];     // queries and predicted-far queries, per arm
   alignas(16) SurItem items[2][kItemBatch];  // this block's query-block descriptors, two batches
   float b4;
 };
@@ -619,14 +615,6 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   // the first-layer inputs (a stage ahead) and the descriptor batches (a
   // batch ahead).
   const int nA = A.P->A, Hmax = A.P->Hmax, Nmax = A.P->Nmax;
-  const float margin = A.model->margin;
-  if (tid < 2 * kMaxArms) L.cnt[tid >> 1][tid & 1] = 0u;
-  if (tid < 4) {
-    L.out_row[tid] = 0;
-    L.out_arm[tid] = 0;
-    L.n_rows[tid] = 0;
-  }
-  for (int e = tid; e < 4 * 32; e += kInferThreads) L.ok[e >> 5][e & 31] = 0;
   if (tid == 0) L.b4 = A.P32[mlp_b_off(3)];
   // Stationary weights: rows wq*kWaveRows + fb*32 + q, K slots c*16 + half*8 + 0..7.
   const int row0 = wq * kWaveRows + q;
@@ -658,9 +646,8 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   // Descriptors of this block's query blocks (block k at stage k is item
   // blockIdx.x + k*G): the first batch now; later batches are loaded by the
   // third wave of group A at the start of the batch before and written two
-  // stages before they are first needed.  The staging, the bookkeeping and
-  // the decision sit on different waves (2 and 1 of group A, 0 of group B)
-  // so that no SIMD carries two of them.
+  // stages before they are first needed.  The staging and the prediction
+  // store sit on waves of different SIMDs (2 of group A, 0 of group B).
   for (int e = tid; e < min(kItemBatch, n_my); e += kInferThreads)
     L.items[0][e] = A.items[blockIdx.x + (long long)e * G];
   auto item_at = [&](int k) -> SurItem {
@@ -680,7 +667,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   // MFMA-bound and latency-bound work within a stage: group B starts its
   // third-layer chain at the barrier while group A runs the first layer of
   // the next block, then group A runs its second-layer chain while group B
-  // finishes the output layer and the decision.  Each group has a loop of
+  // finishes the output layer.  Each group has a loop of
   // its own (the same number of stages, one barrier per stage) and keeps
   // its small weights in registers.
   if (grp == 0) {
@@ -704,11 +691,9 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
                                  v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16)));
       }
     for (int s = 0; s < n_my + 3; ++s) {
-      // First layer of query block s (the last block again past the end) and
-      // its bookkeeping for the decision three stages later, then the second
-      // layer of block s-1.  Block s's inputs arrived during the last stage;
-      // block s+1's are requested now.
-      const SurItem it = it_next;
+      // First layer of query block s (the last block again past the end),
+      // then the second layer of block s-1.  Block s's inputs arrived during
+      // the last stage; block s+1's are requested now.
       const uint4 x0w = x0_next, r1 = r1_next;
       it_next = item_at(s + 1);
       fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
@@ -734,19 +719,6 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
         }
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][q][fcol + fb * 32]);
-        if (s < n_my && wq == 1 && half == 0) {
-          // A query is live when the neighbour's plan is readable and covers
-          // the step and the rollout exists; inside the training box when
-          // both arms' joints are.
-          const bool live = (r1.y & 2u) != 0u && it.n0 + q < (int)r1.z;
-          const bool inbox = (r1.y & 1u) != 0u && (x0w.w >> 16) != 0u;
-          L.ok[s & 3][q] = (live ? 1 : 0) | ((live && inbox) ? 2 : 0);
-          if (q == 0) {
-            L.out_row[s & 3] = (((long long)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + it.n0;
-            L.n_rows[s & 3] = (int)r1.w - it.n0;
-            L.out_arm[s & 3] = it.arm;
-          }
-        }
       }
       {
         f32x16_t acc[kFB];
@@ -765,37 +737,21 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
       for (int q4 = 0; q4 < 4; ++q4)
         w4v[fb][q4] = *reinterpret_cast<const uint2*>(A.W16 + mlp_w_off(3) + fcol + fb * 32 + q4 * 8);
     for (int s = 0; s < n_my + 3; ++s) {
-      // First wave: the output and decision of block s-3 (its partial sums
-      // are complete at the barrier), before its chain; then the third layer
-      // of block s-2 with the output layer folded into its epilogue.
+      // First wave: the output of block s-3 (its partial sums are complete
+      // at the barrier), before its chain; then the third layer of block s-2
+      // with the output layer folded into its epilogue.
       if (wq == 0) {
         // Lanes 0-31, one query each: the partial sums in a fixed order,
-        // then the bias.  All LDS inputs are read up front (one round trip);
-        // the counts are return-less LDS atomics.
-        const int r = (s - 3) & 3;
+        // then the bias; one 128-byte line of predictions per block.
         const float* pr = &L.part[(s - 3) & 1][q][0];
         float4 p[kParts / 4];
 #pragma unroll
         for (int i = 0; i < kParts / 4; ++i) p[i] = *reinterpret_cast<const float4*>(pr + 4 * i);
-        const int n_rows = L.n_rows[r], okv = L.ok[r][q], out_arm = L.out_arm[r];
-        const long long out_row = L.out_row[r];
         float y = 0.f;
 #pragma unroll
         for (int i = 0; i < kParts / 4; ++i) y += (p[i].x + p[i].y) + (p[i].z + p[i].w);
         y += L.b4;
-        const bool writer = s >= 3 && half == 0 && q < n_rows;
-        const bool far = (okv & 2) != 0 && y >= margin;
-        if (writer) {
-          const long long o = out_row + q;
-          A.skip[o] = far ? 1 : 0;
-          if (A.pred) A.pred[o] = y;
-        }
-        const unsigned nq = (unsigned)__popcll(__ballot(writer && (okv & 1)));
-        const unsigned nf = (unsigned)__popcll(__ballot(writer && far));
-        if (lane == 0 && (nq | nf)) {
-          atomicAdd(&L.cnt[out_arm][0], nq);
-          atomicAdd(&L.cnt[out_arm][1], nf);
-        }
+        if (s >= 3 && half == 0) A.y[((long long)blockIdx.x + (long long)(s - 3) * G) * 32 + q] = y;
       }
       {
         f32x16_t acc3[kFB];
@@ -808,9 +764,61 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
       __syncthreads();
     }
   }
-  if (A.counts && tid < 2 * nA) {
-    const unsigned v = L.cnt[tid >> 1][tid & 1];
-    if (v) atomicAdd(A.counts + 5 * (tid >> 1) + (tid & 1), (unsigned long long)v);
+}
+
+// The skip decision of every query (one thread each, query blocks in
+// descriptor order): far when the query is live (the neighbour's plan is
+// readable and covers the step, the rollout exists), both arms' joints lie
+// inside the training box and the prediction reaches the margin.  Writes the
+// skip byte (and the prediction when asked) at the query's (arm, neighbour,
+// step, rollout) slot and adds per-arm counts of live and far queries.
+constexpr int kDecideThreads = 256;
+constexpr int kDecideBlocks = 1024;
+__global__ __launch_bounds__(kDecideThreads) void k_sur_decide(const SurDecideArgs D) {
+  // Per-block counts in LDS (return-less atomics), one global add per arm
+  // and block at the end.
+  __shared__ unsigned cnt[kMaxArms][2];
+  if (threadIdx.x < 2 * kMaxArms) cnt[threadIdx.x >> 1][threadIdx.x & 1] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, q = lane & 31;
+  const int nA = D.P->A, Hmax = D.P->Hmax, Nmax = D.P->Nmax;
+  const float margin = D.model->margin;
+  const long long total = (long long)D.n_items * 32;
+  // Every thread runs the same number of iterations (the ballots below are
+  // wave-wide); threads past the end take no part.
+  const long long stride = (long long)gridDim.x * kDecideThreads;
+  for (long long base = (long long)blockIdx.x * kDecideThreads; base < total; base += stride) {
+    const long long gid = base + threadIdx.x;
+    const long long item = gid >> 5;
+    bool live = false, far = false;
+    int arm = 0;
+    if (gid < total) {
+      const SurItem it = D.items[item];
+      arm = it.arm;
+      const uint32_t* rec = D.nbrec + (((size_t)it.arm * nA + it.nbr) * Hmax + it.h) * kNbrRec;
+      const uint32_t flags = rec[5];
+      const int n = it.n0 + q;
+      const float y = D.y[gid];
+      const uint16_t own_flag = D.F[(((size_t)it.arm * Hmax + it.h) * Nmax + n) * 8 + 7];
+      live = (flags & 2u) != 0u && n < (int)rec[6];
+      far = live && (flags & 1u) != 0u && own_flag != 0 && y >= margin;
+      const size_t o = (((size_t)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + n;
+      D.skip[o] = far ? 1 : 0;
+      if (D.pred) D.pred[o] = y;
+    }
+    // Each half-wave is one query block (one arm).
+    const unsigned long long mq = __ballot(live), mf = __ballot(far);
+    const unsigned long long half_mask = lane < 32 ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull;
+    const unsigned nq = (unsigned)__popcll(mq & half_mask), nf = (unsigned)__popcll(mf & half_mask);
+    if (q == 0 && (nq | nf)) {
+      atomicAdd(&cnt[arm][0], nq);
+      atomicAdd(&cnt[arm][1], nf);
+    }
+  }
+  __syncthreads();
+  if (D.counts && threadIdx.x < 2 * nA) {
+    const unsigned v = cnt[threadIdx.x >> 1][threadIdx.x & 1];
+    if (v) atomicAdd(D.counts + 5 * (threadIdx.x >> 1) + (threadIdx.x & 1), (unsigned long long)v);
   }
 }
 
@@ -900,6 +908,14 @@ hipError_t launch_sur_pairs(const DevArm* arms, const SurModel* model, const Boa
                             int n_arms, int Hmax, uint32_t* rec, hipStream_t s) {
   hipLaunchKernelGGL(k_sur_pairs, dim3((Hmax + kWave - 1) / kWave, n_arms * n_arms), dim3(kWave), 0, s, arms, model,
                      meta, planq, n_arms, Hmax, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_sur_decide(const SurDecideArgs& D, hipStream_t s) {
+  if (D.n_items <= 0) return hipSuccess;
+  const long long blocks = ((long long)D.n_items * 32 + kDecideThreads - 1) / kDecideThreads;
+  hipLaunchKernelGGL(k_sur_decide, dim3((unsigned)(blocks < kDecideBlocks ? blocks : kDecideBlocks)),
+                     dim3(kDecideThreads), 0, s, D);
   return hipGetLastError();
 }
 
