@@ -58,6 +58,20 @@ __device__ __forceinline__ void normals8(uint32_t slo, uint32_t shi, int arm, ui
   }
 }
 
+// Joint j's value of normals8 computed alone: the same counter, the same
+// Box-Muller word pair and the same cos / sin lane, so the result is
+// bit-identical.
+__device__ __forceinline__ float normal1(uint32_t slo, uint32_t shi, int arm, uint32_t t, int k, int n, int h,
+                                        int j) {
+  uint32_t c0 = (uint32_t)n, c1 = (uint32_t)(2 * h + (j >> 2)), c2 = t, c3 = ((uint32_t)arm << 8) | (uint32_t)k;
+  philox4x32_10(c0, c1, c2, c3, slo, shi);
+  const bool second = ((j >> 1) & 1) != 0;
+  const float r = sqrtf(-2.0f * logf(unit_open(second ? c2 : c0)));
+  float sn, cs;
+  sincospif(2.0f * unit_open(second ? c3 : c1), &sn, &cs);
+  return r * ((j & 1) ? sn : cs);
+}
+
 // ---------------------------------------------------------------------------
 // Rigid frame: rotation columns x, y, z and origin t.
 struct Frame {

@@ -389,55 +389,53 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 // Own-joint features of every (arm, step, rollout) for the learned distance:
 // the same noise and integration as the rollout kernel, then the normalised
 // joints as one 16-byte row of bfloat16 [f0..f6, in-box flag] (flag 1.0 when
-// all seven lie within the training box, else 0.0).
-__global__ __launch_bounds__(kWave) void k_sur_states(const DevArm* __restrict__ arms,
-                                                      const Params* __restrict__ Pp,
-                                                      const SurModel* __restrict__ sm,
-                                                      const StepState* __restrict__ ssp,
-                                                      const float* __restrict__ mu_all,
-                                                      const float* __restrict__ state,
-                                                      const float* __restrict__ eps_in, int k_iter,
-                                                      uint16_t* __restrict__ F) {
+// all seven lie within the training box, else 0.0).  Eight lanes per
+// rollout: lane j < 7 integrates joint j (the joints are independent) and
+// writes its feature; lane 7 writes the flag, the AND of the group's box
+// tests taken with a ballot.  The eight 2-byte writes form the row.
+constexpr int kStatesThreads = 256;
+__global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __restrict__ arms,
+                                                               const Params* __restrict__ Pp,
+                                                               const SurModel* __restrict__ sm,
+                                                               const StepState* __restrict__ ssp,
+                                                               const float* __restrict__ mu_all,
+                                                               const float* __restrict__ state,
+                                                               const float* __restrict__ eps_in, int k_iter,
+                                                               uint16_t* __restrict__ F) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
   const DevArm* arm = arms + a;
-  const int n = blockIdx.x * kWave + threadIdx.x;
+  const int j = threadIdx.x & 7, lane = threadIdx.x & 63;
+  const int n = blockIdx.x * (kStatesThreads / 8) + (threadIdx.x >> 3);
+  // A wave holds 8 rollouts; it leaves only when all of them are past the
+  // arm's padded count (Npad is a multiple of 64, so a wave is all in or all
+  // out and every lane takes part in the ballots below).
   if (n >= arm->Npad) return;
   const uint32_t t = ssp->t;
   const float* mu = mu_all + (size_t)a * P.Hmax * 7;
-  float q[7], qd[7], mid[7], ih[7];
-  for (int j = 0; j < 7; ++j) {
-    q[j] = state[(a * 7 + j) * 3 + 0];
-    qd[j] = state[(a * 7 + j) * 3 + 1];
-    mid[j] = sm->mid[j];
-    ih[j] = sm->inv_half[j];
-  }
+  const int jj = j < 7 ? j : 0;
+  float q = state[(a * 7 + jj) * 3 + 0], qd = state[(a * 7 + jj) * 3 + 1];
+  const float mid = sm->mid[jj], ih = sm->inv_half[jj];
+  const int group_shift = lane & ~7;
+  // Unrolled so that the noise of consecutive steps (independent Philox
+  // rounds) overlaps; only the two-FMA integration is sequential.
+#pragma unroll 4
   for (int h = 0; h < arm->H; ++h) {
-    float z[8];
+    float z;
     if (eps_in) {
-      for (int j = 0; j < 7; ++j) z[j] = eps_in[arm->eps_off + ((size_t)h * 7 + j) * arm->Npad + n];
+      z = eps_in[arm->eps_off + ((size_t)h * 7 + jj) * arm->Npad + n];
     } else {
-      normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
-      for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
+      z = normal1(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, jj) * P.sigma;
     }
-    uint16_t f[8];
-    bool inbox = true;
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      const float u = z[j] + mu[h * 7 + j];
-      qd[j] = fmaf_(P.dt, u, qd[j]);
-      q[j] = fmaf_(P.dt, qd[j], q[j]);
-      const float x = (q[j] - mid[j]) * ih[j];
-      inbox = inbox && fabsf(x) <= 1.0f + 1e-3f;
-      f[j] = f2bf(x);
-    }
-    f[7] = inbox ? (uint16_t)0x3F80u : (uint16_t)0u;
-    uint4 v;
-    v.x = (uint32_t)f[0] | ((uint32_t)f[1] << 16);
-    v.y = (uint32_t)f[2] | ((uint32_t)f[3] << 16);
-    v.z = (uint32_t)f[4] | ((uint32_t)f[5] << 16);
-    v.w = (uint32_t)f[6] | ((uint32_t)f[7] << 16);
-    *reinterpret_cast<uint4*>(F + (((size_t)a * P.Hmax + h) * P.Nmax + n) * 8) = v;
+    const float u = z + mu[h * 7 + jj];
+    qd = fmaf_(P.dt, u, qd);
+    q = fmaf_(P.dt, qd, q);
+    const float x = (q - mid) * ih;
+    const bool out_of_box = j < 7 && !(fabsf(x) <= 1.0f + 1e-3f);
+    const unsigned long long bad = __ballot(out_of_box);
+    const bool inbox = ((bad >> group_shift) & 0x7Full) == 0ull;
+    const uint16_t v = j < 7 ? f2bf(x) : (inbox ? (uint16_t)0x3F80u : (uint16_t)0u);
+    F[(((size_t)a * P.Hmax + h) * P.Nmax + n) * 8 + j] = v;
   }
 }
 
@@ -899,8 +897,9 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
                              int npad_max, uint16_t* F, hipStream_t s) {
-  hipLaunchKernelGGL(k_sur_states, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, model,
-                     ss, mu, state, eps_in, k_iter, F);
+  const int per_block = kStatesThreads / 8;
+  hipLaunchKernelGGL(k_sur_states, dim3((npad_max + per_block - 1) / per_block, n_arms), dim3(kStatesThreads), 0, s,
+                     arms, P, model, ss, mu, state, eps_in, k_iter, F);
   return hipGetLastError();
 }
 
