@@ -207,6 +207,39 @@ def test_mode1_always_skipping_drops_coordination_and_audit_counts():
     assert st["missed_collisions"] <= st["misses"] <= st["predicted_far"] <= st["queries"]
 
 
+def test_mode1_counts_on_ragged_rollouts_and_mixed_horizons():
+    _say("case: collision mode 1, 4 arms, ragged rollout counts and mixed horizons")
+    n, h = [40, 96, 70, 128], [5, 8, 6, 9]
+    sc = small_scene(3, n=n, h=h)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    # every ordered pair (a, i) has min(H_a, H_i) steps of N_a live queries
+    per_step = sum(min(h[a], h[i]) * n[a] for a in range(4) for i in range(4) if i != a)
+    for value in (1.0, -1.0):
+        ctl = native.Controller(sc.arms, {**sc.params, "collision_mode": 0})
+        ctl.set_surrogate_params(_const_params(value))
+        ctl.set_collision_mode(1)
+        ctl.step(sc.state, sc.goal, obst)
+        ctl.share_plans()
+        ctl.sync()
+        ctl.surrogate_stats(reset=True)
+        ctl.debug_enable(True)
+        ctl.step(sc.state, sc.goal, obst)
+        ctl.sync()
+        st = ctl.surrogate_stats()
+        _say(f"  value {value}: {st}, expected queries {per_step}")
+        assert st["queries"] == per_step
+        if value > 0:
+            assert 0 < st["predicted_far"] <= per_step
+        else:
+            assert st["predicted_far"] == 0 and st["waves_skipped"] == 0
+        for a in range(4):
+            pred = ctl.debug_get("PRED", a).cpu().numpy()  # [A][H_a][N_a]
+            for i in range(4):
+                if i != a:
+                    assert np.allclose(pred[i][: min(h[a], h[i]), : n[a]], value)
+        ctl.close()
+
+
 def test_fused_inference_matches_training_forward():
     _say("case: fused MFMA inference vs GEMM forward on the same queries")
     sc = small_scene(2, n=96, h=6)
