@@ -417,9 +417,6 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
   float q = state[(a * 7 + jj) * 3 + 0], qd = state[(a * 7 + jj) * 3 + 1];
   const float mid = sm->mid[jj], ih = sm->inv_half[jj];
   const int group_shift = lane & ~7;
-  // Unrolled so that the noise of consecutive steps (independent Philox
-  // rounds) overlaps; only the two-FMA integration is sequential.
-#pragma unroll 4
   for (int h = 0; h < arm->H; ++h) {
     float z;
     if (eps_in) {
