@@ -622,10 +622,23 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
 
 // ---------------------------------------------------------------------------
 // Eq. 1 totals, Eq. 2 weights and PickBest for one arm per block.
+// (value, index) minimum with ties to the lower index.
+__device__ __forceinline__ void argmin_merge(float& v, int& i, float v2, int i2) {
+  if (v2 < v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
-  __shared__ float s_v[1024];
-  __shared__ int s_i[1024];
-  const int a = blockIdx.x, tid = threadIdx.x;
+  // Reductions: shuffles inside each wave, then the 16 wave results in a
+  // fixed order (4 barriers in all).
+  constexpr int kWaves = 1024 / kWave;
+  __shared__ float s_v[kWaves];
+  __shared__ int s_i[kWaves];
+  __shared__ float s_bcast[2];
+  __shared__ int s_nstar;
+  const int a = blockIdx.x, tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int N = arm->N, H = arm->H;
@@ -640,31 +653,39 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
     cost[n] = c;
     if (c < best) { best = c; bi = n; }
   }
-  s_v[tid] = best;
-  s_i[tid] = bi;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const float v2 = s_v[tid + s];
-      const int i2 = s_i[tid + s];
-      if (v2 < s_v[tid] || (v2 == s_v[tid] && i2 < s_i[tid])) { s_v[tid] = v2; s_i[tid] = i2; }
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1)
+    argmin_merge(best, bi, __shfl_xor(best, off), __shfl_xor(bi, off));
+  if (lane == 0) {
+    s_v[wv] = best;
+    s_i[wv] = bi;
   }
-  const float m = s_v[0];
-  // All-NaN costs leave no minimum; fall back to rollout 0 so every index stays in range.
-  const int nstar = s_i[0] < N ? s_i[0] : 0;
   __syncthreads();
+  if (tid == 0) {
+    float v = s_v[0];
+    int i = s_i[0];
+    for (int k = 1; k < kWaves; ++k) argmin_merge(v, i, s_v[k], s_i[k]);
+    s_bcast[0] = v;
+    // All-NaN costs leave no minimum; fall back to rollout 0 so every index stays in range.
+    s_nstar = i < N ? i : 0;
+  }
+  __syncthreads();
+  const float m = s_bcast[0];
+  const int nstar = s_nstar;
   const float inv_lambda = 1.0f / P.lambda;
   float z = 0.f;
   for (int n = tid; n < N; n += blockDim.x) z += expf(-(cost[n] - m) * inv_lambda);
-  s_v[tid] = z;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) z += __shfl_xor(z, off);
+  if (lane == 0) s_v[wv] = z;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) s_v[tid] += s_v[tid + s];
-    __syncthreads();
+  if (tid == 0) {
+    float zs = s_v[0];
+    for (int k = 1; k < kWaves; ++k) zs += s_v[k];
+    s_bcast[1] = zs;
   }
-  const float zinv = 1.0f / s_v[0];
+  __syncthreads();
+  const float zinv = 1.0f / s_bcast[1];
   float* w = A.w + (size_t)a * P.Nmax;
   for (int n = tid; n < N; n += blockDim.x) w[n] = expf(-(cost[n] - m) * inv_lambda) * zinv;
   if (tid < 7) {
@@ -874,24 +895,22 @@ __global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int H = arm->H;
-  if (tid == 0) {
-    float q[7], qd[7];
-    for (int j = 0; j < 7; ++j) {
-      q[j] = A.st_state[(a * 7 + j) * 3 + 0];
-      qd[j] = A.st_state[(a * 7 + j) * 3 + 1];
-    }
+  if (tid < 7) {
+    // One thread per joint (the joints integrate independently).
+    const int j = tid;
+    float q = A.st_state[(a * 7 + j) * 3 + 0], qd = A.st_state[(a * 7 + j) * 3 + 1];
     const float* mu = A.mu + (size_t)a * P.Hmax * 7;
-    for (int h = 0; h < H; ++h)
-      for (int j = 0; j < 7; ++j) {
-        if (P.plan_mode == 0) {
-          qd[j] = fmaf_(P.dt, mu[h * 7 + j], qd[j]);
-          q[j] = fmaf_(P.dt, qd[j], q[j]);
-        }
-        // plan_mode 1 (the S_d ablation): the current configuration at every step
-        s_q[h][j] = q[j];
+    for (int h = 0; h < H; ++h) {
+      if (P.plan_mode == 0) {
+        qd = fmaf_(P.dt, mu[h * 7 + j], qd);
+        q = fmaf_(P.dt, qd, q);
       }
+      // plan_mode 1 (the S_d ablation): the current configuration at every step
+      s_q[h][j] = q;
+    }
   }
   __syncthreads();
+  const int lay = arm->layout;
   for (int h = tid; h < H; h += blockDim.x) {
     float q[8];
     for (int j = 0; j < 7; ++j) q[j] = s_q[h][j];
@@ -899,13 +918,20 @@ __global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
     Frame F[7];
     forward_kinematics(F, arm, q);
     float4* out = reinterpret_cast<float4*>(A.plan_write) + ((size_t)a * P.Hmax + h) * P.Smax;
-    for (int s = 0; s < arm->S; ++s) {
-      const int b = arm->link[s];
+    // Body by body (a static frame index keeps the frames in registers):
+    // each body's slots, written to their spheres' user positions; the
+    // hand is rigid with the last link.
+#pragma unroll
+    for (int b = 0; b < kBodies; ++b) {
       const Frame& Fb = F[b < 7 ? b : 6];
-      const float* p = arm->usph[s];
-      float x, y, z;
-      frame_point(Fb, p[0], p[1], p[2], x, y, z);
-      out[s] = make_float4(x, y, z, p[3]);
+      for (int jslot = kLayoutStart[lay][b]; jslot < kLayoutStart[lay][b + 1]; ++jslot) {
+        const int src = arm->slot_src[jslot];
+        if (src < 0) continue;
+        const float* p = arm->slot[jslot];
+        float x, y, z;
+        frame_point(Fb, p[0], p[1], p[2], x, y, z);
+        out[src] = make_float4(x, y, z, p[3]);
+      }
     }
     for (int j = 0; j < 7; ++j) A.planq_write[((size_t)a * P.Hmax + h) * 7 + j] = q[j];
   }
