@@ -103,23 +103,49 @@ def summarize_pmc(pmc_dir):
     """Text summary of a rocprofv3 --pmc pass (CSV, each counter already summed
     over its instances): per kernel, the counters of its last dispatch and the
     MFMA busy share SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 1024
-    SIMDs), GRBM_GUI_ACTIVE being the sum of the 8 XCDs' active cycles."""
+    SIMDs), GRBM_GUI_ACTIVE being the sum of the 8 XCDs' active cycles, and,
+    where the VALU counters were taken, the active-lane share, the issue rates
+    per SIMD and clock and the FP32 operations the instruction counts imply."""
     import csv
     import glob
     from collections import defaultdict
     f = glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0]
     per = defaultdict(lambda: defaultdict(dict))
+    dur = {}
     for r in csv.DictReader(open(f)):
         per[r["Kernel_Name"].split("(")[0]][int(r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+        if r.get("End_Timestamp"):
+            dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     out = [f"counter collection: {f}"]
     for name, disp in sorted(per.items()):
         vals = disp[max(disp)]
-        out.append(f"{name[:60]} (dispatches {len(disp)}, last):")
+        t = dur.get(max(disp), 0.0)
+        out.append(f"{name[:60]} (dispatches {len(disp)}, last: {t * 1e6:.1f} us):")
         for c in sorted(vals):
             out.append(f"  {c:28s} {vals[c]:16.6g}")
         if "SQ_VALU_MFMA_BUSY_CYCLES" in vals and vals.get("GRBM_GUI_ACTIVE"):
             share = vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (vals["GRBM_GUI_ACTIVE"] / 8 * 1024)
             out.append(f"  MFMA busy share             {share:16.4f}")
+        if vals.get("SQ_ACTIVE_INST_VALU") and vals.get("SQ_THREAD_CYCLES_VALU"):
+            util = vals["SQ_THREAD_CYCLES_VALU"] / (vals["SQ_ACTIVE_INST_VALU"] * 64)
+            out.append(f"  VALU active-lane share      {util:16.4f}")
+        if vals.get("SQ_INSTS_VALU") and t > 0:
+            # wave-level VALU instructions per SIMD per clock (1024 SIMDs,
+            # 2.4 GHz); non-packed FP32 FMA on 16 lanes caps FMAs at 0.25
+            rate = vals["SQ_INSTS_VALU"] / (1024 * t * 2.4e9)
+            out.append(f"  VALU wave-insts/SIMD-cycle  {rate:16.4f}")
+        if "SQ_INSTS_VALU_FMA_F32" in vals:
+            ops = 64 * (2 * vals["SQ_INSTS_VALU_FMA_F32"] + vals.get("SQ_INSTS_VALU_ADD_F32", 0)
+                        + vals.get("SQ_INSTS_VALU_MUL_F32", 0) + vals.get("SQ_INSTS_VALU_TRANS_F32", 0))
+            out.append(f"  FP32 VALU ops (64 lanes)    {ops:16.6g}")
+            if t > 0:
+                out.append(f"  FP32 VALU TFLOP/s           {ops / t / 1e12:16.4f}")
+                fma = vals["SQ_INSTS_VALU_FMA_F32"] / (1024 * t * 2.4e9)
+                out.append(f"  FMA wave-insts/SIMD-cycle   {fma:16.4f}")
+            if vals.get("SQ_INSTS_VALU"):
+                share = (vals["SQ_INSTS_VALU_FMA_F32"] + vals.get("SQ_INSTS_VALU_ADD_F32", 0)
+                         + vals.get("SQ_INSTS_VALU_MUL_F32", 0) + vals.get("SQ_INSTS_VALU_TRANS_F32", 0)) / vals["SQ_INSTS_VALU"]
+                out.append(f"  FP32 share of VALU insts    {share:16.4f}")
     return "\n".join(out)
 
 
