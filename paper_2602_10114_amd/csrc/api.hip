@@ -424,7 +424,6 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.ss = c->d_ss;
   R.items = c->d_items;
   R.n_items = c->n_items;
-  R.h_tile = c->h_tile;
   R.k = k;
   R.mu = c->mu;
   R.eps = c->eps;
@@ -452,7 +451,6 @@ static ReduceArgs reduce_args(const mpc_ctx* c) {
   R.arms = c->d_arms;
   R.P = c->d_P;
   R.ss = c->d_ss;
-  R.h_tile = c->h_tile;
   R.partial = c->partial;
   R.cost = c->cost;
   R.w = c->w;

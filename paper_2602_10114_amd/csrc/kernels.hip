@@ -4,7 +4,7 @@
 //   k_rollout    SampleControls + Rollout for every arm in one launch: noise,
 //                dynamics, forward kinematics over the collision spheres, the
 //                stage cost of Eq. 5 with the coordination term of Eqs. 6-9,
-//                discounted partial sums (Eq. 1).
+//                written per rollout step.
 //   k_softmax    Eq. 1 totals, Eq. 2 weights, PickBest (Act).
 //   k_wmean      Eq. 3 weighted mean and Eq. 4 update of the means.
 //   k_toplan     ToPlan: integrate the means, forward kinematics, plan spheres.
@@ -354,7 +354,6 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
     const float* __restrict__ gR = goalR + a * 9;
     const float* __restrict__ g = goal + a * 7;
     const int nnb = SS.nb_count[a];
-    float acc = 0.f;
     unsigned long long pairs = 0;
     unsigned set_passes = 0, set_refines = 0, self_refines = 0;
     if (SURM && lane == 0)
@@ -496,7 +495,9 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
           c = fmaf_(L.set_wt[si], hv, c);
         }
       }
-      acc = fmaf_(P.gpow[h], c, acc);
+      // The stage cost goes out per step; Eq. 1's discounted sum is formed in
+      // k_softmax over h in a fixed order, so it does not depend on the tiling.
+      if (live) A.partial[((size_t)a * kMaxH + h) * P.Nmax + n] = c;
 
       if (DBG && live) {
         const size_t row = ((size_t)a * P.Nmax + n) * P.Hmax + h;
@@ -523,7 +524,6 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
         A.dbg_stage[((size_t)a * P.Hmax + h) * P.Nmax + n] = c;
       }
     }
-    if (live) A.partial[((size_t)a * kMaxH + item.h0 / A.h_tile) * P.Nmax + n] = acc;
     if (DBG && live) atomicAdd(A.dbg_pairs + 4 * a, pairs);
     if (SURM && lane == 0) {
       // one atomic per counter and item
@@ -642,14 +642,15 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int N = arm->N, H = arm->H;
-  const int tiles = (H + A.h_tile - 1) / A.h_tile;
-  const float* part = A.partial + (size_t)a * kMaxH * P.Nmax;
+  const float* stage = A.partial + (size_t)a * kMaxH * P.Nmax;
   float* cost = A.cost + (size_t)a * P.Nmax;
   float best = 3.4e38f;
   int bi = 0x7fffffff;
   for (int n = tid; n < N; n += blockDim.x) {
+    // Eq. 1: C_n = sum_h gamma^h C_{n,h}, one FMA per step in step order
+    // (the same value for every horizon tiling of the rollout kernel).
     float c = 0.f;
-    for (int k = 0; k < tiles; ++k) c += part[(size_t)k * P.Nmax + n];
+    for (int h = 0; h < H; ++h) c = fmaf_(P.gpow[h], stage[(size_t)h * P.Nmax + n], c);
     cost[n] = c;
     if (c < best) { best = c; bi = n; }
   }

@@ -13,12 +13,11 @@ struct RolloutArgs {
   const StepState* ss;
   const Item* items;
   int n_items;
-  int h_tile;
   int k;                       // optimisation iteration
   int pad;
   const float* mu;             // [A][Hmax][7]
   float* eps;                  // per-arm [H][7][Npad] blocks
-  float* partial;              // [A][kMaxH][Nmax]
+  float* partial;              // stage costs [A][kMaxH][Nmax] (step-major)
   const float* state;          // staged [A][7][3]
   const float* goal;           // staged [A][7]
   const float* goalR;          // [A][9]
@@ -65,9 +64,8 @@ struct ReduceArgs {
   const DevArm* arms;
   const Params* P;
   const StepState* ss;
-  int h_tile;
   int pad;
-  const float* partial;
+  const float* partial;        // stage costs [A][kMaxH][Nmax]
   float* cost;                 // [A][Nmax]
   float* w;                    // [A][Nmax]
   const float* eps;

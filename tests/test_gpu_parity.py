@@ -273,21 +273,24 @@ def test_deterministic_repeat():
 
 
 def test_tiles_do_not_change_results():
-    _say("case: forced horizon tiles 1, 3, H give identical costs")
+    _say("case: forced horizon tiles 1, 3, H give identical costs, weights, means and actions")
     sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
     res = []
     for T in (1, 3, 16):
         ctl = native.Controller(sc.arms, sc.params)
         ctl.set_tuning(0, T, 0)
         ctl.debug_enable(True)
-        ctl.step(sc.state, sc.goal, sc.obstacles)
+        u = ctl.step(sc.state, sc.goal, sc.obstacles).cpu().numpy()
         ctl.sync()
-        res.append([ctl.debug_get("STAGE_COST", a).cpu().numpy() for a in range(4)])
+        res.append((u, [[ctl.debug_get(k, a).cpu().numpy() for k in ("STAGE_COST", "COST", "WEIGHTS", "MEAN")]
+                        for a in range(4)]))
         assert ctl.tuning()[1] == T
         ctl.close()
-    for r in res[1:]:
+    for u, r in res[1:]:
+        np.testing.assert_array_equal(u, res[0][0])
         for a in range(4):
-            np.testing.assert_array_equal(r[a], res[0][a])
+            for x, x0 in zip(r[a], res[0][1][a]):
+                np.testing.assert_array_equal(x, x0)
 
 
 # ------------------------------------------------------------- edge cases
