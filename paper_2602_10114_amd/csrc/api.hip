@@ -586,7 +586,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
     if (c->profile) HIPCHK(c, c->prof_roll.begin(c->stream, &e1));
     HIPCHK(c, launch_rollout(R, c->layout, debug, c->grid, c->stream));
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, launch_softmax(Rr, c->A, c->stream));
+    HIPCHK(c, launch_softmax(Rr, c->A, c->Nmax, c->stream));
     HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->stream));
   }
   HIPCHK(c, launch_toplan(Rr, c->A, c->stream));

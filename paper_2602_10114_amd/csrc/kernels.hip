@@ -5,7 +5,8 @@
 //                dynamics, forward kinematics over the collision spheres, the
 //                stage cost of Eq. 5 with the coordination term of Eqs. 6-9,
 //                written per rollout step.
-//   k_softmax    Eq. 1 totals, Eq. 2 weights, PickBest (Act).
+//   k_total      Eq. 1 totals from the per-step stage costs.
+//   k_softmax    Eq. 2 weights, PickBest (Act).
 //   k_wmean      Eq. 3 weighted mean and Eq. 4 update of the means.
 //   k_toplan     ToPlan: integrate the means, forward kinematics, plan spheres.
 //   k_publish    Publish: board write side -> read side.
@@ -630,6 +631,23 @@ __device__ __forceinline__ void argmin_merge(float& v, int& i, float v2, int i2)
   }
 }
 
+// Eq. 1 totals, one thread per rollout of every arm: C_n = sum_h gamma^h
+// C_{n,h} as one FMA chain in step order, so the value does not depend on the
+// rollout kernel's horizon tiling.
+__global__ __launch_bounds__(256) void k_total(ReduceArgs A) {
+  const int a = blockIdx.y;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const DevArm* arm = A.arms + a;
+  if (n >= arm->N) return;
+  const Params& P = *A.P;
+  const int H = arm->H;
+  const float* stage = A.partial + (size_t)a * kMaxH * P.Nmax + n;
+  float c = 0.f;
+#pragma unroll 8
+  for (int h = 0; h < H; ++h) c = fmaf_(P.gpow[h], stage[(size_t)h * P.Nmax], c);
+  A.cost[(size_t)a * P.Nmax + n] = c;
+}
+
 __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   // Reductions: shuffles inside each wave, then the 16 wave results in a
   // fixed order (4 barriers in all).
@@ -641,17 +659,12 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   const int a = blockIdx.x, tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
-  const int N = arm->N, H = arm->H;
-  const float* stage = A.partial + (size_t)a * kMaxH * P.Nmax;
-  float* cost = A.cost + (size_t)a * P.Nmax;
+  const int N = arm->N;
+  const float* cost = A.cost + (size_t)a * P.Nmax;
   float best = 3.4e38f;
   int bi = 0x7fffffff;
   for (int n = tid; n < N; n += blockDim.x) {
-    // Eq. 1: C_n = sum_h gamma^h C_{n,h}, one FMA per step in step order
-    // (the same value for every horizon tiling of the rollout kernel).
-    float c = 0.f;
-    for (int h = 0; h < H; ++h) c = fmaf_(P.gpow[h], stage[(size_t)h * P.Nmax + n], c);
-    cost[n] = c;
+    const float c = cost[n];
     if (c < best) { best = c; bi = n; }
   }
 #pragma unroll
@@ -1021,7 +1034,10 @@ hipError_t launch_sense(const SenseArgs& A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s) {
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_total, dim3((nmax + 255) / 256, n_arms), dim3(256), 0, s, A);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_softmax, dim3(n_arms), dim3(1024), 0, s, A);
   return hipGetLastError();
 }

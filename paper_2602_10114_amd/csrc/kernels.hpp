@@ -92,7 +92,7 @@ struct PublishArgs {
 
 hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s);
-hipError_t launch_softmax(const ReduceArgs& A, int n_arms, hipStream_t s);
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s);  // k_total, then k_softmax
 hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s);
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
