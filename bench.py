@@ -40,7 +40,7 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # WRITE_SIZE passes, each scaled by the same counter's reading for a 256 MiB
 # device copy (fetch x2.000, write x1.000); valid only for the kernel sources
 # with this digest (see profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "14bead9b1fa55c9b", "bytes_per_launch": 44650880}
+TRAFFIC = {"sources_sha256": "61228794059e349f", "bytes_per_launch": 47262336}
 
 
 def sources_digest():
@@ -129,18 +129,21 @@ def summarize_pmc(pmc_dir):
         if vals.get("SQ_ACTIVE_INST_VALU") and vals.get("SQ_THREAD_CYCLES_VALU"):
             util = vals["SQ_THREAD_CYCLES_VALU"] / (vals["SQ_ACTIVE_INST_VALU"] * 64)
             out.append(f"  VALU active-lane share      {util:16.4f}")
-        if vals.get("SQ_INSTS_VALU") and t > 0:
-            # wave-level VALU instructions per SIMD per clock (1024 SIMDs,
-            # 2.4 GHz); non-packed FP32 FMA on 16 lanes caps FMAs at 0.25
-            rate = vals["SQ_INSTS_VALU"] / (1024 * t * 2.4e9)
+        # Clock cycles of the dispatch: the busy cycles of one XCD
+        # (GRBM_GUI_ACTIVE sums the 8), else the duration at 2.4 GHz.
+        cyc = vals["GRBM_GUI_ACTIVE"] / 8 if vals.get("GRBM_GUI_ACTIVE") else t * 2.4e9
+        if vals.get("SQ_INSTS_VALU") and cyc > 0:
+            # wave-level VALU instructions per SIMD per clock (1024 SIMDs);
+            # non-packed FP32 FMA on 16 lanes caps FMAs at 0.25
+            rate = vals["SQ_INSTS_VALU"] / (1024 * cyc)
             out.append(f"  VALU wave-insts/SIMD-cycle  {rate:16.4f}")
         if "SQ_INSTS_VALU_FMA_F32" in vals:
             ops = 64 * (2 * vals["SQ_INSTS_VALU_FMA_F32"] + vals.get("SQ_INSTS_VALU_ADD_F32", 0)
                         + vals.get("SQ_INSTS_VALU_MUL_F32", 0) + vals.get("SQ_INSTS_VALU_TRANS_F32", 0))
             out.append(f"  FP32 VALU ops (64 lanes)    {ops:16.6g}")
-            if t > 0:
-                out.append(f"  FP32 VALU TFLOP/s           {ops / t / 1e12:16.4f}")
-                fma = vals["SQ_INSTS_VALU_FMA_F32"] / (1024 * t * 2.4e9)
+            if cyc > 0:
+                out.append(f"  FP32 VALU TFLOP/s at 2.4 GHz {ops / (cyc / 2.4e9) / 1e12:15.4f}")
+                fma = vals["SQ_INSTS_VALU_FMA_F32"] / (1024 * cyc)
                 out.append(f"  FMA wave-insts/SIMD-cycle   {fma:16.4f}")
             if vals.get("SQ_INSTS_VALU"):
                 share = (vals["SQ_INSTS_VALU_FMA_F32"] + vals.get("SQ_INSTS_VALU_ADD_F32", 0)
@@ -318,7 +321,7 @@ def audit_run(scene, params, steps, dev, goal_age=50):
             "executed_min_arm_gap_m": gap, "seconds": wall}
 
 
-def ablation_run(variant, steps, dev):
+def ablation_run(variant, steps, dev, seed=None):
     """Closed loop on the two facing arms (0.8 m apart, goals drawn in the
     shared middle region): MR-STORM (tau = 3, shared plans), M_tau (tau = 0:
     no priority) or S_d (no plans: each arm sees the other's current spheres
@@ -330,7 +333,7 @@ def ablation_run(variant, steps, dev):
     import torch
     from paper_2602_10114_amd import native
     over = {"M": {}, "M_tau": {"tau": 0.0}, "S_d": {"plan_mode": 1}}[variant]
-    sc = scenes.make_scene(2, collision_mode=0, **over)
+    sc = scenes.make_scene(2, seed=seed, collision_mode=0, **over)
     A = sc.n_arms
     rng = np.random.default_rng(sc.seed + 7)
     ctl = native.Controller(sc.arms, sc.params)
@@ -355,9 +358,28 @@ def ablation_run(variant, steps, dev):
         age = np.where(m, 0, age + 1)
     gaps = ctl.pair_distance(0, 1, qs[:, 0].contiguous(), qs[:, 1].contiguous())
     ctl.close()
-    return {"goals_reached": reached, "mean_steps_to_goal": float(np.mean(t_reach)) if t_reach else None,
+    return {"goals_reached": reached, "steps_to_goal": t_reach,
             "stalled_steps": stalled, "executed_min_arm_gap_m": float(gaps[1:].min()),
             "start_gap_m": float(gaps[0]), "steps": steps}
+
+
+def ablation(steps, seeds, dev):
+    """The three variants over the same scene seeds (start poses, goal
+    sequences, sphere radii): goals per seed, their total, the pooled mean
+    time to goal, stalled steps and the smallest executed gap."""
+    base = scenes.make_scene(2).seed
+    seed_list = [base + 100 * i for i in range(seeds)]
+    out = {"seeds": seed_list, "steps_per_seed": steps}
+    for v in ("M", "M_tau", "S_d"):
+        runs = [ablation_run(v, steps, dev, seed=sd) for sd in seed_list]
+        t = [x for r in runs for x in r["steps_to_goal"]]
+        out[v] = {"goals_per_seed": [r["goals_reached"] for r in runs],
+                  "goals_total": int(sum(r["goals_reached"] for r in runs)),
+                  "mean_steps_to_goal": float(np.mean(t)) if t else None,
+                  "stalled_steps": int(sum(r["stalled_steps"] for r in runs)),
+                  "executed_min_arm_gap_m": min(r["executed_min_arm_gap_m"] for r in runs),
+                  "start_gap_m": min(r["start_gap_m"] for r in runs)}
+    return out
 
 
 def train_surrogate(scene):
@@ -380,6 +402,8 @@ def main():
                     help="closed-loop steps of the audited learned-distance run on the 4-arm scene (0: skip)")
     ap.add_argument("--ablation-steps", type=int, default=1500,
                     help="closed-loop steps of each variant of the two-arm ablation (0: skip)")
+    ap.add_argument("--ablation-seeds", type=int, default=5,
+                    help="scene seeds of the two-arm ablation (start poses, goals, noise)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="print a summary of rocprofv3 output of a bench run and exit")
     ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
@@ -489,7 +513,7 @@ def main():
                                      "seconds": aud_exact["seconds"]},
             }
     if args.ablation_steps > 0:
-        out["ablation_2arm"] = {v: ablation_run(v, args.ablation_steps, dev) for v in ("M", "M_tau", "S_d")}
+        out["ablation_2arm"] = ablation(args.ablation_steps, args.ablation_seeds, dev)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
