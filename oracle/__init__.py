@@ -135,6 +135,7 @@ def lib():
                                              C.c_double, _dp]
         L.orc_mlp_loss_grad_bf16.restype = C.c_double
         L.orc_pair_features.argtypes = [C.POINTER(OrcArm), _dp, C.POINTER(OrcArm), _dp, _dp]
+        L.orc_mlp_forward_bf16.argtypes = [C.c_int, _ip, _dp, C.c_int, _dp, _dp]
         _lib = L
     return _lib
 
@@ -382,6 +383,14 @@ def mlp_loss_grad(widths, params, x, t, over_w, near_w=0.0, near_band=0.0):
 
 def bf16(x):
     return lib().orc_bf16(float(x))
+
+
+def mlp_forward_bf16(widths, params, x):
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    x = _f64(x)
+    y = np.zeros((x.shape[0], widths[-1]))
+    lib().orc_mlp_forward_bf16(len(widths) - 1, w, _f64(params), x.shape[0], x, y)
+    return y
 
 
 def mlp_loss_grad_bf16(widths, params, x, t, over_w, near_w=0.0, near_band=0.0):

@@ -867,6 +867,30 @@ double orc_bf16(double x) {
   return (double)f;
 }
 
+void orc_mlp_forward_bf16(int L, const int *w, const double *params, int B, const double *x, double *y) {
+  int maxw = 0;
+  for (int l = 0; l <= L; ++l) if (w[l] > maxw) maxw = w[l];
+  double *a = (double *)malloc(sizeof(double) * maxw), *b = (double *)malloc(sizeof(double) * maxw);
+  for (int s = 0; s < B; ++s) {
+    for (int i = 0; i < w[0]; ++i) a[i] = orc_bf16(x[(size_t)s * w[0] + i]);
+    const double *P = params;
+    for (int l = 0; l < L; ++l) {
+      const double *W = P, *bb = P + (size_t)w[l + 1] * w[l];
+      for (int o = 0; o < w[l + 1]; ++o) {
+        double z = 0.0;
+        for (int i = 0; i < w[l]; ++i) z += orc_bf16(W[(size_t)o * w[l] + i]) * a[i];
+        z += bb[o];
+        /* a hidden activation enters the next product as bfloat16 */
+        b[o] = (l + 1 < L) ? orc_bf16(z < 0.0 ? 0.0 : z) : z;
+      }
+      P += (size_t)w[l + 1] * w[l] + w[l + 1];
+      double *t = a; a = b; b = t;
+    }
+    for (int o = 0; o < w[L]; ++o) y[(size_t)s * w[L] + o] = a[o];
+  }
+  free(a); free(b);
+}
+
 /* Reduced-precision dataflow of the training kernels (definition above):
  * Z_l = bf(A_{l-1}) bf(W_l)^T + b_l, A_l = relu(Z_l), y = Z_L;
  * dZ_L = dy; dW_l = bf(dZ_l)^T bf(A_{l-1}); db_l = sum dZ_l;

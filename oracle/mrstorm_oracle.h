@@ -144,6 +144,11 @@ double orc_bf16(double x);
  * back-propagated deltas) rounded to bfloat16, sums and biases exact. */
 double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
                               const double *t, double over_w, double near_w, double near_band, double *grad);
+/* The forward pass of that reduced-precision dataflow alone (the network as
+ * the inference kernel computes it): inputs, weights and hidden activations
+ * rounded to bfloat16 before each product, sums and biases exact, ReLU
+ * between layers, linear output. */
+void orc_mlp_forward_bf16(int L, const int *w, const double *params, int B, const double *x, double *y);
 /* Input features of the learned distance between arm a at q_a (own) and arm
  * i at q_i (neighbour), in arm a's base frame: 7 normalised own joints, the
  * neighbour's first joint plus the yaw difference (wrapped, / pi), its other

@@ -628,6 +628,50 @@ def test_bf16_gradient_exact_when_nothing_rounds(orc):
     assert np.any(g3 != g4)
 
 
+def test_bf16_forward_exact_when_nothing_rounds(orc):
+    """Small integer weights, inputs and biases keep every product operand and
+    hidden activation bfloat16-exact: the reduced-precision forward equals the
+    hand-computed 2-2-1 network exactly."""
+    params = np.array([1, -1, 2, 0.5, 0, -1, 1, 3, 0.5], float)
+    x = np.array([[1.0, 2.0], [-1.0, 0.0]])
+    np.testing.assert_array_equal(orc.mlp_forward_bf16([2, 2, 1], params, x)[:, 0], [6.5, 0.5])
+
+
+def test_bf16_forward_rounds_each_operand(orc):
+    """Each rounding point of the dataflow on a 1-1-1 chain (W0, b0, W1, b1):
+    an input of 1 + 2^-9 enters as 1 and so does a weight of 1 + 2^-9 (the
+    bfloat16 spacing at 1 is 2^-7); a hidden activation 1 + 2^-7 + 2^-9 leaves
+    as 1 + 2^-7; a bias is added unrounded; a negative hidden value is cut to
+    0 while the output may be negative."""
+    def f(p, x):
+        return orc.mlp_forward_bf16([1, 1, 1], np.array(p, float), np.array([[x]], float))[0, 0]
+    e9, e7 = 2.0 ** -9, 2.0 ** -7
+    assert f([1, 0, 1, 0], 1 + e9) == 1.0
+    assert f([1 + e9, 0, 1, 0], 1.0) == 1.0
+    assert f([1 + e7, e9, 1, 0], 1.0) == 1 + e7
+    assert f([1, 0, 1, 2.0 ** -20], 1.0) == 1 + 2.0 ** -20
+    assert f([1, -2, 1, -0.25], 1.0) == -0.25
+    # the plain forward keeps the digits the reduced one drops
+    assert orc.mlp_forward([1, 1, 1], np.array([1 + e7, e9, 1, 0.0]), np.array([[1.0]]))[0, 0] == 1 + e7 + e9
+
+
+def test_bf16_forward_is_the_training_dataflow_forward(orc):
+    """The training dataflow's loss at target 0 without the asymmetric or
+    near weights is the batch mean of y^2, with y its own forward pass; the
+    standalone forward gives the same y.  Both stay within the bfloat16
+    operand error of the FP64 network."""
+    widths = [17, 32, 32, 1]
+    rng = np.random.default_rng(23)
+    p = rng.normal(size=orc.mlp_param_count(widths)) * 0.3
+    x = rng.uniform(-1, 1, size=(40, 17))
+    y = orc.mlp_forward_bf16(widths, p, x)[:, 0]
+    loss, _ = orc.mlp_loss_grad_bf16(widths, p, x, np.zeros(40), 0.0)
+    assert abs(loss - np.mean(y * y)) <= 1e-12 * max(1.0, loss)
+    y64 = orc.mlp_forward(widths, p, x)[:, 0]
+    assert np.linalg.norm(y - y64) / np.linalg.norm(y64) < 3e-2
+    assert np.any(y != y64)
+
+
 def test_bf16_gradient_close_to_fp64(orc):
     widths = [17, 32, 32, 1]
     rng = np.random.default_rng(15)
