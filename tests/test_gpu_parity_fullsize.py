@@ -3,15 +3,22 @@ rows of 4, 4096 rollouts x 40 steps each, 64 spheres per arm, 20 obstacle
 spheres), in the launch configuration the tuner picks for it (the one the
 throughput benchmark times).
 
-The production step (graph launch, no capture) and the capturing kernel
-must give bitwise-equal actions and plans; on the capture, sampled
-rollouts of every arm are checked one by one against the FP64 oracle:
-noise (1e-6), joint states (1e-5 rad: 40 FP32 additions of |q| < 4 rad,
-each rounded within 1.2e-7, plus the rate's rounding carried by dt), sphere
-centres from the GPU's joints (1e-5 m), stage and total costs (1e-4
-relative, floor 1), the query count (exact), and the weighted mean over all
-4096 rollouts from the GPU's costs and noise (1e-5).
+Exact mode: the production step (graph launch, no capture) and the
+capturing kernel must give bitwise-equal actions and plans; on the capture,
+sampled rollouts of every arm are checked one by one against the FP64
+oracle: noise (1e-6), joint states (1e-5 rad: 40 FP32 additions of
+|q| < 4 rad, each rounded within 1.2e-7, plus the rate's rounding carried
+by dt), sphere centres from the GPU's joints (1e-5 m), stage and total costs
+(1e-4 relative, floor 1), the query count (exact), and the weighted mean
+over all 4096 rollouts from the GPU's costs and noise (1e-5).
+
+Learned mode (a seeded random network, so both decisions occur): the query
+count is exact, the far count equals the host's rule on the GPU's own
+predictions and joints, and sampled predictions match the oracle's
+bfloat16-dataflow forward pass on the oracle's features.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -139,3 +146,95 @@ def test_full_size_workload_sampled_against_oracle():
         assert np.abs(g("MEAN").cpu().numpy() - mt).max() < 1e-5, a
         assert n_star == oracle.argmin(cost), a
     c2.close()
+
+
+def _random_params(seed):
+    """Uniform(+-sqrt(6 / fan_in)) weights and N(0, 0.05) biases."""
+    W = native.MLP_WIDTHS
+    rng = np.random.default_rng(seed)
+    p = np.zeros(native.MLP_PARAMS, np.float32)
+    o = 0
+    for l in range(len(W) - 1):
+        nw = W[l + 1] * W[l]
+        p[o:o + nw] = rng.uniform(-1, 1, nw) * math.sqrt(6 / W[l])
+        p[o + nw:o + nw + W[l + 1]] = rng.normal(size=W[l + 1]) * 0.05
+        o += nw + W[l + 1]
+    return p
+
+
+def _normalised(q, lim):
+    """Joints scaled to [-1, 1] over their limits (the network's input)."""
+    mid = 0.5 * (lim[:, 0] + lim[:, 1])
+    half = 0.5 * (lim[:, 1] - lim[:, 0])
+    return (q - mid) / half
+
+
+def test_full_size_learned_step_sampled_against_oracle():
+    sc = scenes.make_scene(5, collision_mode=0)
+    A = sc.n_arms
+    N, H = 4096, 40
+    params = _random_params(31)
+    _say("case: full-size eight-arm workload, learned distance (seeded random network), tuned launch")
+    c = native.Controller(sc.arms, sc.params)
+    c.set_surrogate_params(params)
+    c.set_collision_mode(1)
+    for _ in range(STEPS - 1):
+        c.step(sc.state, sc.goal, sc.obstacles)
+        c.share_plans()
+    c.sync()
+    boards = [c.get_board(i) for i in range(A)]
+    assert all(b[3] == 1 for b in boards)
+    c.surrogate_stats(reset=True)
+    c.debug_enable(True)
+    c.step(sc.state, sc.goal, sc.obstacles)
+    c.sync()
+    st = c.surrogate_stats()
+    _say(f"  tuned launch {c.tuning()}, counts {st}")
+    # every ordered arm pair, every step, every rollout
+    assert st["queries"] == A * (A - 1) * H * N
+
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    margin = np.float32(sc.params["surrogate_margin"])
+    box = 1.0 + 1e-3
+    pq = [b[1].cpu().numpy().astype(np.float64) for b in boards]                 # [H][7] planned joints
+    nb_in = [np.all(np.abs(_normalised(p, lim)[:, 1:]) <= box, axis=1) for p in pq]
+    nb_edge = [np.any(np.abs(np.abs(_normalised(p, lim)[:, 1:]) - box) < 1e-5, axis=1) for p in pq]
+    far, edge = 0, 0
+    W = native.MLP_WIDTHS
+    rng = np.random.default_rng(20261204)
+    oas = [oracle.make_arm(a) for a in sc.arms]
+    diffs = []
+    for a in range(A):
+        q = c.debug_get("Q", a).cpu().numpy().astype(np.float64)               # [N][H][7]
+        pred = c.debug_get("PRED", a).cpu().numpy()                            # [A][H][N]
+        f = np.abs(_normalised(q, lim))
+        own_in = np.all(f <= box, axis=2).T                                    # [H][N]
+        own_edge = np.any(np.abs(f - box) < 1e-5, axis=2).T
+        for i in range(A):
+            if i == a:
+                continue
+            ok = own_in & nb_in[i][:, None]
+            far += int(np.sum(ok & (pred[i] >= margin)))
+            edge += int(np.sum((own_edge | nb_edge[i][:, None]) & (pred[i] >= margin)))
+        # sampled predictions against the oracle's forward pass
+        for n in (0, int(rng.integers(1, N))):
+            feats, got = [], []
+            for i in range(A):
+                if i == a:
+                    continue
+                for h in range(H):
+                    feats.append(oracle.pair_features(oas[a], q[n, h], oas[i], pq[i][h]))
+                    got.append(pred[i][h, n])
+            ref = oracle.mlp_forward_bf16(W, params.astype(np.float64), np.array(feats))[:, 0]
+            diffs.append(np.abs(np.array(got, np.float64) - ref))
+    _say(f"  far: GPU {st['predicted_far']}, host rule {far} (at the box edge: {edge})")
+    assert abs(st["predicted_far"] - far) <= edge
+    assert 0 < st["predicted_far"] < st["queries"]
+    d = np.concatenate(diffs)
+    _say(f"  sampled predictions: {d.size}, max |diff| {d.max():.3g}, share above 1e-5 {np.mean(d > 1e-5):.3f}")
+    # Same bfloat16 dataflow; the GPU sums in FP32 and the oracle in FP64, so
+    # a feature or hidden activation near a bfloat16 rounding boundary can
+    # round the other way and move the output by well under a millimetre.
+    assert np.mean(d > 1e-5) < 0.1
+    assert d.max() < 2e-3
+    c.close()
