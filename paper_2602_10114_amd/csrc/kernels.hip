@@ -98,16 +98,20 @@ __device__ __forceinline__ void body_spheres(const Frame& Fb, const LdsSets& L, 
 }
 
 // min over the body's spheres and the staged spheres [k0, k0+K) of the
-// squared-gap expansion (two staged spheres per iteration).
+// squared-gap expansion (two staged spheres per iteration), with every own
+// sphere of the body given the body's largest radius rmax: E = |c|^2 - rmax^2
+// and, per staged sphere, G = F_k + rmax w_r, so a pair costs three FMAs.
+// The value is never above the per-sphere one (r_s <= rmax, r_k + B >= 0),
+// so every body with a pair whose gap is below B still falls below the slack.
 template <int C>
-__device__ __forceinline__ float filter_range(const float ux[8], const float uy[8], const float uz[8],
-                                              const float ur[8], const float E[8], const LdsSets& L,
-                                              int k0, int K, float g) {
+__device__ __forceinline__ float filter_range_rmax(const float ux[8], const float uy[8], const float uz[8],
+                                                   const float E[8], float rmax, const LdsSets& L, int k0,
+                                                   int K, float g) {
   const int kend = k0 + K;
   int k = k0;
   for (; k + 1 < kend; k += 2) {
     const float4 w0 = L.w[k], w1 = L.w[k + 1];
-    const float F0 = L.F[k], F1 = L.F[k + 1];
+    const float G0 = fmaf_(rmax, w0.w, L.F[k]), G1 = fmaf_(rmax, w1.w, L.F[k + 1]);
     float m0 = 3.0e38f, m1 = 3.0e38f;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
@@ -117,41 +121,64 @@ __device__ __forceinline__ float filter_range(const float ux[8], const float uy[
       t1 = fmaf_(uy[j], w1.y, t1);
       t0 = fmaf_(uz[j], w0.z, t0);
       t1 = fmaf_(uz[j], w1.z, t1);
-      t0 = fmaf_(ur[j], w0.w, t0);
-      t1 = fmaf_(ur[j], w1.w, t1);
       m0 = fminf(m0, t0);
       m1 = fminf(m1, t1);
     }
-    g = fminf(g, fminf(m0 + F0, m1 + F1));
+    g = fminf(g, fminf(m0 + G0, m1 + G1));
   }
   if (k < kend) {
     const float4 w = L.w[k];
-    const float Fk = L.F[k];
+    const float Gk = fmaf_(rmax, w.w, L.F[k]);
     float m = 3.0e38f;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       float t = fmaf_(ux[j], w.x, E[j]);
       t = fmaf_(uy[j], w.y, t);
       t = fmaf_(uz[j], w.z, t);
-      t = fmaf_(ur[j], w.w, t);
       m = fminf(m, t);
     }
-    g = fminf(g, m + Fk);
+    g = fminf(g, m + Gk);
   }
   return g;
 }
 
+// Own spheres of one body for filter_range_rmax: centres, E = |c|^2 - rmax^2
+// and the body's largest radius rmax (unused slots: zero centre, E parked).
+template <int LAY, int B_>
+__device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSets& L, float ux[8], float uy[8],
+                                                   float uz[8], float E[8]) {
+  constexpr int C = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
+  asm volatile("" ::: "memory");
+  float rmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < C; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
+  const float r2 = rmax * rmax;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const float4 p = L.slot[S0 + j];
+    float x, y, z;
+    frame_point(Fb, p.x, p.y, p.z, x, y, z);
+    const bool parked = p.w < 0.f;
+    ux[j] = parked ? 0.f : x;
+    uy[j] = parked ? 0.f : y;
+    uz[j] = parked ? 0.f : z;
+    E[j] = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -r2)));
+  }
+  return rmax;
+}
+
 // Filter pass over one staged set: body by body down the chain (one walking
-// frame), running minimum of the squared-gap expansion; bit b of `near` is
-// set when body b has a pair below the slack.
+// frame), running minimum of the squared-gap expansion with the body's
+// largest own radius; bit b of `near` is set when body b has a pair below the
+// slack.  The exact pass tests the flagged bodies' pairs with their own radii.
 template <int LAY, int B_>
 __device__ __forceinline__ void set_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
                                            const LdsSets& L, int k0, int K, unsigned& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
-  float ux[8], uy[8], uz[8], ur[8], E[8];
-  body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
-  const float gb = filter_range<Cb>(ux, uy, uz, ur, E, L, k0, K, 3.0e38f);
+  float ux[8], uy[8], uz[8], E[8];
+  const float rmax = body_spheres_rmax<LAY, B_>(W, L, ux, uy, uz, E);
+  const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, k0, K, 3.0e38f);
   near |= (gb < kSlack ? 1u : 0u) << B_;
   if constexpr (B_ + 1 < kBodies) set_filter<LAY, B_ + 1>(W, arm, C, L, k0, K, near);
 }
