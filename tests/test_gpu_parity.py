@@ -389,3 +389,62 @@ def test_end_to_end_within_conditioning_bound():
         bound = U * dC / lam + 1e-4
         assert np.abs(cap.mu - mu_o).max() <= bound
     ctl.close()
+
+
+@pytest.mark.parametrize("config", [1, 5])
+def test_obstacles_at_the_buffer_edge_of_small_spheres(config):
+    """The set filter gives every sphere of a body the body's largest radius;
+    the pairs it must still catch are those of a body's smaller spheres right
+    at the buffer edge.  Per body, one obstacle (r = 2 cm) sits at a gap of
+    exactly B from a sphere at least 1 cm smaller than the body's largest, in
+    a direction that leaves every other sphere of the arm at least 2 mm
+    beyond the buffer at the start pose, so the sampled rollouts fall on both
+    sides of the edge.  Stage costs match the oracle in every run, and the
+    obstacle term is on for some rollout steps and off for others."""
+    _say(f"case: an obstacle at the buffer edge of a small sphere of each body, arm of config {config}")
+    sc = small_scene(config, n=128, h=10, collision_mode=0)
+    sc.arms, sc.state, sc.goal = sc.arms[:1], sc.state[:1], sc.goal[:1]
+    arm = sc.arms[0]
+    sph = oracle.spheres(oracle.make_arm(arm), sc.state[0, :, 0].astype(np.float64))
+    links = np.asarray(arm.sphere_link)
+    B, r_obs = f32(sc.params["buf_env"]), 0.02
+
+    def run(obstacles):
+        ctl = native.Controller(sc.arms, sc.params)
+        ctl.debug_enable(True)
+        ctl.step(sc.state, sc.goal, obstacles)
+        ctl.sync()
+        cap = Capture(ctl, 0, want_spheres=obstacles is not None)
+        if obstacles is not None:
+            ref = oracle_stage(sc, 0, cap, obstacles, read_boards(ctl, sc))
+            assert rel_err(cap.stage, ref) < 1e-4
+        ctl.close()
+        return cap.stage
+
+    def placement(j):
+        for d in dirs:
+            p = sph[j, :3] + d * (sph[j, 3] + r_obs + B)
+            gaps = np.linalg.norm(sph[:, :3] - p, axis=1) - sph[:, 3] - r_obs
+            if np.all(np.delete(gaps, j) >= B + 0.002):
+                return p
+        return None
+
+    i = np.arange(1024) + 0.5
+    zs = 1.0 - 2.0 * i / 1024
+    ang = np.pi * (1 + 5 ** 0.5) * i
+    dirs = np.stack([np.sqrt(1 - zs * zs) * np.cos(ang), np.sqrt(1 - zs * zs) * np.sin(ang), zs], axis=1)
+    free = run(None)
+    on, off, placed = 0, 0, 0
+    for b in sorted(set(links.tolist())):
+        idx = np.nonzero(links == b)[0]
+        small = [j for j in idx[np.argsort(sph[idx, 3])] if sph[j, 3] <= sph[idx, 3].max() - 0.01]
+        p = next((x for x in map(placement, small) if x is not None), None)
+        if p is None:
+            continue
+        placed += 1
+        env = run(np.array([[*p, r_obs]], np.float32)) - free
+        on += int(np.sum(env > 0))
+        off += int(np.sum(env == 0))
+    _say(f"  bodies with an obstacle placed: {placed}; rollout steps with the obstacle term on / off: {on} / {off}")
+    assert placed >= 3
+    assert on > 0 and off > 0
