@@ -190,7 +190,8 @@ int mpc_sim_execute(mpc_ctx *c, float *state, const float *u);
  * horizon steps per work item, workgroups); valid after the first step. */
 int mpc_get_tuning(const mpc_ctx *c, int *rollouts_per_block, int *h_tile, int *grid);
 /* Force a launch shape (0 = let the tuner choose); takes effect at the next
- * mpc_step. */
+ * mpc_step.  Results do not depend on the launch shape: every rollout's
+ * stage costs are summed (Eq. 1) in step order whatever the tiling. */
 int mpc_set_tuning(mpc_ctx *c, int rollouts_per_block, int h_tile, int grid);
 
 /* Kernel timing for measurement: while on, mpc_step launches its kernels
