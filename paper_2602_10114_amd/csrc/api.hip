@@ -633,7 +633,10 @@ static int capture_graph(mpc_ctx* c) {
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   int rc = enqueue_body(c, false);
   hipError_t e = hipStreamEndCapture(c->stream, &g);
-  if (rc) return rc;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
   if (e != hipSuccess) return fail(c, MPC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
