@@ -123,6 +123,7 @@ struct mpc_ctx {
   float* sur_pred = nullptr;           // optional predictions (debug capture)
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
   float* sur_y = nullptr;              // predictions in descriptor order [items][32]
+  bool sur_bufs = false;               // every learned-distance step buffer allocated
   unsigned long long* sur_counts = nullptr;  // [A][5]
   SurItem* d_sur_items = nullptr;
   int n_sur_items = 0;
@@ -149,9 +150,9 @@ static int dalloc(mpc_ctx* c, T** p, size_t count) {
   if (count == 0) count = 1;
   hipError_t e = hipMalloc(&q, count * sizeof(T));
   if (e != hipSuccess) return fail(c, MPC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocations.push_back(q);  // freed by mpc_destroy, also when the fill below fails
   e = hipMemset(q, 0, count * sizeof(T));
   if (e != hipSuccess) return fail(c, MPC_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
-  c->allocations.push_back(q);
   *p = static_cast<T*>(q);
   return MPC_OK;
 }
@@ -596,7 +597,8 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
 // Per-step buffers of the learned distance and its work items: every
 // (arm, neighbour, step within both horizons, 32-rollout block).
 static int ensure_sur_buffers(mpc_ctx* c) {
-  if (c->sur_F) return MPC_OK;
+  if (c->sur_bufs) return MPC_OK;
+  // A call that failed part-way leaves its buffers to mpc_destroy and starts over.
   const size_t A = c->A, H = c->Hmax, N = c->Nmax;
   int rc;
   if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
@@ -620,6 +622,7 @@ static int ensure_sur_buffers(mpc_ctx* c) {
   HIPCHK(c, hipGetDevice(&dev));
   HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   c->sur_grid = std::max(1, std::min(c->n_sur_items, std::max(n_cu, 1)));
+  c->sur_bufs = true;
   return MPC_OK;
 }
 
@@ -753,7 +756,7 @@ extern "C" int mpc_get_plan(mpc_ctx* c, int arm, float* plan, float* plan_q, flo
 // ---------------------------------------------------------------------------
 extern "C" int mpc_debug_enable(mpc_ctx* c, int on) {
   if (!c) return MPC_EINVAL;
-  if (on && !c->dbg_q) {
+  if (on && !c->dbg_pairs) {  // allocated last: set only when every capture buffer is
     const size_t A = c->A, N = c->Nmax, H = c->Hmax, S = c->Smax;
     int rc;
     if ((rc = dalloc(c, &c->dbg_q, A * N * H * 7)) || (rc = dalloc(c, &c->dbg_qd, A * N * H * 7)) ||
@@ -773,7 +776,7 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
   float* out = static_cast<float*>(dev_out);
   const bool needs_dbg = what == MPC_DBG_Q || what == MPC_DBG_QD || what == MPC_DBG_SPHERES ||
                          what == MPC_DBG_STAGE_COST || what == MPC_DBG_PAIRS || what == MPC_DBG_PASSES;
-  if (needs_dbg && !c->dbg_q) return fail(c, MPC_ESTATE, "debug capture is off");
+  if (needs_dbg && !c->dbg_pairs) return fail(c, MPC_ESTATE, "debug capture is off");
   switch (what) {
     case MPC_DBG_NOISE:
       HIPCHK(c, launch_copy3d(c->eps + d.eps_off, d.Npad, 1, 0, out, d.N, 1, 0, d.H * 7, d.N, 1, c->stream));
