@@ -212,9 +212,19 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
   if (wave_any((near >> B_) & 1u)) {
   float ux[8], uy[8], uz[8], ur[8], E[8];
   body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
+  float rmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < Cb; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
   for (int k = k0; k < k0 + K; ++k) {
     const float4 w = L.w[k];
     const float Fk = L.F[k];
+    // Lower bound of the body's pair values for staged sphere k (each
+    // radius term r_s w_r is at least rmax w_r, w_r <= 0): k holds no
+    // candidate when the bound reaches the slack in every lane.
+    float mk = 3.0e38f;
+#pragma unroll
+    for (int j = 0; j < Cb; ++j) mk = fminf(mk, fmaf_(uz[j], w.z, fmaf_(uy[j], w.y, fmaf_(ux[j], w.x, E[j]))));
+    if (!wave_any(mk + fmaf_(rmax, w.w, Fk) < kSlack)) continue;
     unsigned cand = 0;
 #pragma unroll
     for (int j = 0; j < Cb; ++j) {
