@@ -28,6 +28,7 @@ namespace mrs {
 // terms do not depend on the set.  raw keeps (p_k, r_k) for the FP64 gap.
 constexpr int kLdsSpheres = kMaxObs + (kMaxArms - 1) * kMaxSpheres;
 constexpr int kMaxSets = kMaxArms;  // obstacles + up to 7 neighbours
+static_assert(kMaxSets * kBodies <= 64, "one near bit per (set, body) in a 64-bit mask");
 
 struct LdsSets {
   float4 w[kLdsSpheres];
@@ -167,20 +168,24 @@ __device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSet
   return rmax;
 }
 
-// Filter pass over one staged set: body by body down the chain (one walking
-// frame), running minimum of the squared-gap expansion with the body's
-// largest own radius; bit b of `near` is set when body b has a pair below the
-// slack.  The exact pass tests the flagged bodies' pairs with their own radii.
+// Filter pass over every staged set at once: body by body down the chain
+// (one walking frame, each body's spheres built once), the running minimum of
+// the squared-gap expansion with the body's largest own radius per set; bit
+// 8*si + b of `near` is set when body b has a pair below the slack in set si.
+// The exact pass tests the flagged bodies' pairs with their own radii.
 template <int LAY, int B_>
-__device__ __forceinline__ void set_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, int k0, int K, unsigned& near) {
+__device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
+                                            const LdsSets& L, int nsets, unsigned long long& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
   float ux[8], uy[8], uz[8], E[8];
   const float rmax = body_spheres_rmax<LAY, B_>(W, L, ux, uy, uz, E);
-  const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, k0, K, 3.0e38f);
-  near |= (gb < kSlack ? 1u : 0u) << B_;
-  if constexpr (B_ + 1 < kBodies) set_filter<LAY, B_ + 1>(W, arm, C, L, k0, K, near);
+#pragma nounroll
+  for (int si = 0; si < nsets; ++si) {
+    const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, L.set_k0[si], L.set_n[si], 3.0e38f);
+    near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
+  }
+  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, nsets, near);
 }
 
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
@@ -500,17 +505,19 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
       }
       // Self collision.
       c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_refines), c);
-      // Obstacles and neighbours' plans (Eqs. 6, 8, 9): a filter pass per set,
-      // then the exact pass if some lane of the wave may be within B.
+      // Obstacles and neighbours' plans (Eqs. 6, 8, 9): one filter pass over
+      // every set, then per set the exact pass if some lane of the wave may be
+      // within B.
+      unsigned long long near_all = 0ull;
+      if (nsets > 0) {
+        Frame W;
+        frame_base(W, arm);
+        sets_filter<LAY, 0>(W, arm, C, L, nsets, near_all);
+      }
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
         const int k0 = L.set_k0[si], K = L.set_n[si];
-        unsigned nearb = 0;
-        {
-          Frame W;
-          frame_base(W, arm);
-          set_filter<LAY, 0>(W, arm, C, L, k0, K, nearb);
-        }
+        const unsigned nearb = (unsigned)(near_all >> (8 * si)) & 0xFFu;
         const bool near = nearb != 0;
         ++set_passes;
         if (wave_any(near)) {
