@@ -143,17 +143,18 @@ __device__ __forceinline__ float filter_range_rmax(const float ux[8], const floa
   return g;
 }
 
-// Own spheres of one body for filter_range_rmax: centres, E = |c|^2 - rmax^2
-// and the body's largest radius rmax (unused slots: zero centre, E parked).
+// Own spheres of one body for the body-radius filters: centres,
+// E = |c|^2 - (rmax + buf)^2, and rmax + buf with rmax the body's largest
+// radius (unused slots: zero centre, E parked).
 template <int LAY, int B_>
-__device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSets& L, float ux[8], float uy[8],
-                                                   float uz[8], float E[8]) {
+__device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSets& L, float buf, float ux[8],
+                                                   float uy[8], float uz[8], float E[8]) {
   constexpr int C = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
   asm volatile("" ::: "memory");
   float rmax = 0.f;
 #pragma unroll
   for (int j = 0; j < C; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
-  const float r2 = rmax * rmax;
+  const float rb = rmax + buf, r2 = rb * rb;
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const float4 p = L.slot[S0 + j];
@@ -165,7 +166,7 @@ __device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSet
     uz[j] = parked ? 0.f : z;
     E[j] = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -r2)));
   }
-  return rmax;
+  return rb;
 }
 
 // Filter pass over every staged set at once: body by body down the chain
@@ -179,7 +180,7 @@ __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
   float ux[8], uy[8], uz[8], E[8];
-  const float rmax = body_spheres_rmax<LAY, B_>(W, L, ux, uy, uz, E);
+  const float rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
 #pragma nounroll
   for (int si = 0; si < nsets; ++si) {
     const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, L.set_k0[si], L.set_n[si], 3.0e38f);
@@ -250,13 +251,15 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
 // second walking frame runs from body B1 down the chain to every B2 > B1.
-// The filter pass sets bit 8*B1+B2 of `near` for a body pair with a pair
-// below the slack; the exact pass visits only pairs some lane flagged.
+// The filter pass gives body B1's spheres its largest radius (rmb = rmax +
+// buffer, three FMAs per pair) and sets bit 8*B1+B2 of `near` for a body
+// pair with a value below the slack; the exact pass tests the flagged body
+// pairs sphere by sphere and visits only pairs some lane flagged.
 template <int LAY, int B1, int B2>
 __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const DevArm* __restrict__ arm,
                                            const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
-                                           const float E[8], bool refine, unsigned long long& near,
+                                           const float E[8], float rmb, bool refine, unsigned long long& near,
                                            double& best) {
   constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
   constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
@@ -279,29 +282,27 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
         const float Fk = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
         float m = 3.0e38f;
         unsigned cand = 0;
-#pragma unroll
-        for (int j = 0; j < C1; ++j) {
-          float t = fmaf_(ux[j], wx, E[j]);
-          t = fmaf_(uy[j], wy, t);
-          t = fmaf_(uz[j], wz, t);
-          t = fmaf_(ur[j], wr, t);
-          if (refine) {
-            cand |= (t + Fk < kSlack ? 1u : 0u) << j;
-          } else {
-            m = fminf(m, t);
-          }
-        }
         if (refine) {
+#pragma unroll
+          for (int j = 0; j < C1; ++j) {
+            float t = fmaf_(ux[j], wx, E[j]);
+            t = fmaf_(uy[j], wy, t);
+            t = fmaf_(uz[j], wz, t);
+            t = fmaf_(ur[j], wr, t);
+            cand |= (t + Fk < kSlack ? 1u : 0u) << j;
+          }
           if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, best);
         } else {
-          gp = fminf(gp, m + Fk);
+#pragma unroll
+          for (int j = 0; j < C1; ++j) m = fminf(m, fmaf_(uz[j], wz, fmaf_(uy[j], wy, fmaf_(ux[j], wx, E[j]))));
+          gp = fminf(gp, m + fmaf_(rmb, wr, Fk));
         }
       }
       if (!refine) near |= gp < kSlack ? bit : 0ull;
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, refine, near, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, refine, near, best);
 }
 
 template <int LAY, int B1>
@@ -311,9 +312,16 @@ __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__
   if constexpr (B1 + 2 < kBodies) {
     walk(W1, arm, C, B1);
     float ux[8], uy[8], uz[8], ur[8], E[8];
-    body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
+    float rmb = 0.f;
+    if (refine) {
+      body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
+    } else {
+      rmb = body_spheres_rmax<LAY, B1>(W1, L, buf, ux, uy, uz, E);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ur[j] = 0.f;
+    }
     Frame W2 = W1;
-    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, refine, near, best);
+    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, refine, near, best);
     self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, near, best);
   }
 }
