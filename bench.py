@@ -40,7 +40,7 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # WRITE_SIZE passes, each scaled by the same counter's reading for a 256 MiB
 # device copy (fetch x2.000, write x1.000); valid only for the kernel sources
 # with this digest (see profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "da6988449d2a35f3", "bytes_per_launch": 47282176}
+TRAFFIC = {"sources_sha256": "570c86fbdbd43782", "bytes_per_launch": 47266176}
 
 
 def sources_digest():
