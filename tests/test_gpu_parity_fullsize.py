@@ -1,7 +1,9 @@
-"""GPU parity at the full size of the eight-arm workload (8 arms in two facing
-rows of 4, 4096 rollouts x 40 steps each, 64 spheres per arm, 20 obstacle
-spheres), in the launch configuration the tuner picks for it (the one the
-throughput benchmark times).
+"""GPU parity at the full sizes of the five benchmark workloads (1 arm x 64
+rollouts x 20 steps; 2 facing arms x 512 x 30; 4 arms with 256/512/768/1024
+rollouts and 20/30/30/40 steps; 4 arms x 1024 x 30; 8 arms in two facing rows
+of 4, 4096 rollouts x 40 steps each, 64 spheres per arm, 20 obstacle
+spheres), in the launch configuration the tuner picks (for the 8-arm one,
+the launch the throughput benchmark times).
 
 Exact mode: the production step (graph launch, no capture) and the
 capturing kernel must give bitwise-equal actions and plans; on the capture,
@@ -53,6 +55,10 @@ class _Rows:
         self.q, self.qd, self.sph, self.alpha = q, qd, sph, alpha
 
 
+def _obs(sc):
+    return sc.obstacles if sc.obstacles.shape[0] else None
+
+
 def _steps(sc, ctl, debug_last):
     boards, mu_before = None, None
     for t in range(STEPS):
@@ -62,19 +68,21 @@ def _steps(sc, ctl, debug_last):
             mu_before = [ctl.get_plan(a)[2].cpu().numpy().astype(np.float64) for a in range(sc.n_arms)]
             if debug_last:
                 ctl.debug_enable(True)
-        u = ctl.step(sc.state, sc.goal, sc.obstacles)
+        u = ctl.step(sc.state, sc.goal, _obs(sc))
         ctl.share_plans()
     ctl.sync()
     return u.cpu().numpy(), boards, mu_before
 
 
-def test_full_size_workload_sampled_against_oracle():
-    sc = scenes.make_scene(5, collision_mode=0)
+@pytest.mark.parametrize("config", [1, 2, 3, 4, 5])
+def test_full_size_workload_sampled_against_oracle(config):
+    sc = scenes.make_scene(config, collision_mode=0)
     A = sc.n_arms
-    assert A == 8 and all(a.n_rollouts == 4096 and a.horizon == 40 and a.n_spheres == 64 for a in sc.arms)
-    assert sc.obstacles.shape[0] == 20
+    if config == 5:
+        assert A == 8 and all(a.n_rollouts == 4096 and a.horizon == 40 and a.n_spheres == 64 for a in sc.arms)
+        assert sc.obstacles.shape[0] == 20
 
-    _say("case: full-size eight-arm workload, production step (tuned, graph launch)")
+    _say(f"case: full-size workload of config {config}, production step (tuned, graph launch)")
     c1 = native.Controller(sc.arms, sc.params)
     u1, _, _ = _steps(sc, c1, debug_last=False)
     tuning = c1.tuning()
@@ -83,7 +91,7 @@ def test_full_size_workload_sampled_against_oracle():
     c1.close()
     _say(f"  tuned launch (rollouts per block, horizon tile, grid) = {tuning}")
 
-    _say("case: full-size eight-arm workload, same launch with capture")
+    _say(f"case: full-size workload of config {config}, same launch with capture")
     c2 = native.Controller(sc.arms, sc.params)
     c2.set_tuning(*tuning)
     u2, boards, mu_before = _steps(sc, c2, debug_last=True)
@@ -127,7 +135,7 @@ def test_full_size_workload_sampled_against_oracle():
             for h in range(H):
                 assert np.abs(oracle.spheres(oa, q[r, h]) - sph[r, h]).max() < 1e-5, (a, n, h)
 
-        ref = oracle_stage(sc, a, _Rows(q, qd, sph, alpha), sc.obstacles, boards)
+        ref = oracle_stage(sc, a, _Rows(q, qd, sph, alpha), sc.obstacles, boards)  # empty set: no obstacle term
         assert rel_err(stage[:, rows], ref) < 1e-4, a
         tot = np.array([oracle.total_cost(stage[:, n], gamma) for n in rows])
         assert rel_err(cost[rows], tot) < 1e-5, a
@@ -169,24 +177,26 @@ def _normalised(q, lim):
     return (q - mid) / half
 
 
-def test_full_size_learned_step_sampled_against_oracle():
-    sc = scenes.make_scene(5, collision_mode=0)
+@pytest.mark.parametrize("config", [4, 5])
+def test_full_size_learned_step_sampled_against_oracle(config):
+    sc = scenes.make_scene(config, collision_mode=0)
     A = sc.n_arms
-    N, H = 4096, 40
+    N, H = sc.arms[0].n_rollouts, sc.arms[0].horizon
+    assert all(a.n_rollouts == N and a.horizon == H for a in sc.arms)
     params = _random_params(31)
-    _say("case: full-size eight-arm workload, learned distance (seeded random network), tuned launch")
+    _say(f"case: full-size workload of config {config}, learned distance (seeded random network), tuned launch")
     c = native.Controller(sc.arms, sc.params)
     c.set_surrogate_params(params)
     c.set_collision_mode(1)
     for _ in range(STEPS - 1):
-        c.step(sc.state, sc.goal, sc.obstacles)
+        c.step(sc.state, sc.goal, _obs(sc))
         c.share_plans()
     c.sync()
     boards = [c.get_board(i) for i in range(A)]
     assert all(b[3] == 1 for b in boards)
     c.surrogate_stats(reset=True)
     c.debug_enable(True)
-    c.step(sc.state, sc.goal, sc.obstacles)
+    c.step(sc.state, sc.goal, _obs(sc))
     c.sync()
     st = c.surrogate_stats()
     _say(f"  tuned launch {c.tuning()}, counts {st}")
