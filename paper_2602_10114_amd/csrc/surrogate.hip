@@ -437,21 +437,23 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
 }
 
 // Fused MLP inference, weight-stationary.  A block of 2 x kGroupWaves waves
-// (one block per CU) streams blocks of 32 queries (32 rollouts of one arm at
-// one step against one neighbour's plan) through a pipeline with one barrier
-// per stage:
+// (one block per CU) streams query blocks of 32 queries (32 rollouts of one
+// arm at one step against one neighbour's plan), kQB blocks per stage,
+// through a pipeline with one barrier per stage:
 //   group A (the lower kGroupWaves waves) holds kWaveRows rows each of the
 //   second layer's weights in registers; at stage s it runs the first layer
-//   of query block s (small weights in registers; its inputs, the own-
-//   feature rows and the neighbour record, were loaded a stage earlier) and
-//   then the second layer on block s-1;
+//   of stage s's blocks (small weights in registers; their inputs, the own-
+//   feature rows and the neighbour records, were loaded a stage earlier) and
+//   then the second layer on stage s-1's blocks, one chain per block;
 //   group B holds kWaveRows rows each of the third layer's weights; it runs
-//   that layer on block s-2 with the output layer folded into its epilogue
+//   that layer on stage s-2's blocks as one chain over both (kQB x kFB
+//   independent accumulators) with the output layer folded into its epilogue
 //   (each lane takes its ReLU'd third-layer features, rounded to bfloat16,
 //   times the matching output weights, and leaves one partial sum per query,
 //   wave and lane half in LDS); its first wave adds the partial sums of
-//   block s-3 and stores the predictions.  The skip decision is a separate
-//   element-wise kernel (k_sur_decide), off the pipeline's critical path.
+//   stage s-3 (one query per lane) and stores the predictions.  The skip
+//   decision is a separate element-wise kernel (k_sur_decide), off the
+//   pipeline's critical path.
 // Each SIMD holds one wave of each group, so one wave's MFMA chain runs
 // while the other does its latency-bound part (LDS round trips, VALU), and
 // the roles swap half-way through the stage.
@@ -474,10 +476,56 @@ static_assert(kParts % 4 == 0, "partial sums are read as float4");
 static_assert(kItemBatch <= kWave && kItemBatch >= 3, "one lane per staged descriptor; staged two stages early");
 static_assert(sizeof(SurItem) == 16, "descriptors are staged as 16-byte vectors");
 
+// Two query blocks through one 256-wide layer in one chain: kQB x kFB
+// independent accumulators, the bias chunks first, then per K chunk the
+// operand reads of both blocks (kInflight2 chunks ahead) and their MFMAs.
+constexpr int kInflight2 = 1;
+__device__ __forceinline__ void layer256x2(const bf16x8_t (&w)[kFB][16], const bf16x8_t (&wb)[kFB], bf16x8_t ones,
+                                           const uint16_t* row0, const uint16_t* row1, f32x16_t (&acc)[2][kFB]) {
+  __builtin_amdgcn_sched_barrier(0);
+  bf16x8_t b0[16], b1[16];
+#pragma unroll
+  for (int c = 0; c < kInflight2; ++c) {
+    b0[c] = load_bf16x8(row0 + c * 16);
+    b1[c] = load_bf16x8(row1 + c * 16);
+  }
+  const f32x16_t zero = {};
+#pragma unroll
+  for (int fb = 0; fb < kFB; ++fb) {
+    acc[0][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
+    acc[1][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c + kInflight2 < 16) {
+      b0[c + kInflight2] = load_bf16x8(row0 + (c + kInflight2) * 16);
+      b1[c + kInflight2] = load_bf16x8(row1 + (c + kInflight2) * 16);
+    }
+#pragma unroll
+    for (int fb = 0; fb < kFB; ++fb) {
+      acc[0][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b0[c], acc[0][fb], 0, 0, 0);
+      acc[1][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b1[c], acc[1][fb], 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, 2 * kInflight2, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, 2 * kFB, 0);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * kFB, 0);
+    if (c + kInflight2 < 16) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+constexpr int kQB = 2;                   // query blocks of 32 per pipeline stage
+constexpr int kStageQ = kQB * 32;        // queries per stage
+constexpr int kStagesPerBatch = kItemBatch / kQB;
+static_assert(kItemBatch % kQB == 0 && kStagesPerBatch >= 3, "a descriptor batch spans whole stages, staged two stages early");
+
 struct alignas(16) InferLds {
-  uint16_t act1[2][32][kActLd];  // first-layer outputs, two query blocks in flight
-  uint16_t act2[2][32][kActLd];  // second-layer outputs
-  float part[2][32][kPartLd];    // output-layer partial sums [block][query][wave * 2 + lane half]
+  uint16_t act1[2][kStageQ][kActLd];  // first-layer outputs, two stages in flight
+  uint16_t act2[2][kStageQ][kActLd];  // second-layer outputs
+  float part[2][kStageQ][kPartLd];    // output-layer partial sums [stage][query][wave * 2 + lane half]
   alignas(16) SurItem items[2][kItemBatch];  // this block's query-block descriptors, two batches
   float b4;
 };
@@ -629,6 +677,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 
   const int G = gridDim.x;
   const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+  const int n_st = (n_my + kQB - 1) / kQB;  // stages holding query blocks (the last may hold a stand-in)
   const int fcol = wq * kWaveRows + half * 4;  // this lane's first feature within an accumulator block
   // The pipeline body is straight-line code: edge stages (before the first
   // block reaches a layer, after the last one has left it) compute on
@@ -650,13 +699,14 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
     return L.items[(c / kItemBatch) & 1][c % kItemBatch];
   };
   uint4 batch_next = make_uint4(0u, 0u, 0u, 0u);  // a descriptor, kept as a vector in registers
-  // Group A's inputs of the next query block, loaded a stage ahead.
-  SurItem it_next{};
-  uint4 x0_next = make_uint4(0u, 0u, 0u, 0u), r1_next = make_uint4(0u, 0u, 0u, 0u);
+  // Group A's inputs of the next stage's query blocks, loaded a stage ahead.
+  uint4 x0_next[kQB], r1_next[kQB];
+#pragma unroll
+  for (int qb = 0; qb < kQB; ++qb) x0_next[qb] = r1_next[qb] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   if (grp == 0 && n_my > 0) {
-    it_next = item_at(0);
-    fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb) fetch_block(A, nA, Hmax, Nmax, item_at(qb), half, q, x0_next[qb], r1_next[qb]);
   }
   // Each SIMD holds one wave of each group, and the two alternate between
   // MFMA-bound and latency-bound work within a stage: group B starts its
@@ -685,20 +735,26 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
             bf16x8_t, make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
                                  v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16)));
       }
-    for (int s = 0; s < n_my + 3; ++s) {
-      // First layer of query block s (the last block again past the end),
-      // then the second layer of block s-1.  Block s's inputs arrived during
-      // the last stage; block s+1's are requested now.
-      const uint4 x0w = x0_next, r1 = r1_next;
-      it_next = item_at(s + 1);
-      fetch_block(A, nA, Hmax, Nmax, it_next, half, q, x0_next, r1_next);
+    for (int s = 0; s < n_st + 3; ++s) {
+      // First layer of stage s's query blocks (the last block again past the
+      // end), then the second layer of stage s-1's.  Stage s's inputs arrived
+      // during the last stage; stage s+1's are requested now.
+      uint4 x0s[kQB], r1s[kQB];
+#pragma unroll
+      for (int qb = 0; qb < kQB; ++qb) {
+        x0s[qb] = x0_next[qb];
+        r1s[qb] = r1_next[qb];
+        fetch_block(A, nA, Hmax, Nmax, item_at(kQB * (s + 1) + qb), half, q, x0_next[qb], r1_next[qb]);
+      }
       if (wq == 2 && lane < kItemBatch) {
-        const int k = s % kItemBatch, nb = s / kItemBatch + 1, e = nb * kItemBatch + lane;
+        const int k = s % kStagesPerBatch, nb = s / kStagesPerBatch + 1, e = nb * kItemBatch + lane;
         if (k == 0 && e < n_my)
           batch_next = *reinterpret_cast<const uint4*>(A.items + blockIdx.x + (long long)e * G);
-        if (k == kItemBatch - 2 && e < n_my) *reinterpret_cast<uint4*>(&L.items[nb & 1][lane]) = batch_next;
+        if (k == kStagesPerBatch - 2 && e < n_my) *reinterpret_cast<uint4*>(&L.items[nb & 1][lane]) = batch_next;
       }
-      {
+#pragma unroll
+      for (int qb = 0; qb < kQB; ++qb) {
+        const uint4 x0w = x0s[qb], r1 = r1s[qb];
         // B operands: chunk 0 as loaded; chunk 1 = [f15, f16, 1, 1, 1, 0..]
         // (the record's fifth word, then the bias ones) for lanes 0-31 and
         // zeros.
@@ -713,13 +769,14 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           acc1[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[fb][1], x1, acc1[fb], 0, 0, 0);
         }
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][q][fcol + fb * 32]);
+        for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][qb * 32 + q][fcol + fb * 32]);
       }
-      {
+#pragma nounroll
+      for (int qb = 0; qb < kQB; ++qb) {
         f32x16_t acc[kFB];
-        layer256(w, wb, ones, &L.act1[(s - 1) & 1][q][half * 8], acc);
+        layer256(w, wb, ones, &L.act1[(s - 1) & 1][qb * 32 + q][half * 8], acc);
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][q][fcol + fb * 32]);
+        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][qb * 32 + q][fcol + fb * 32]);
       }
       __syncthreads();
     }
@@ -731,14 +788,14 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4)
         w4v[fb][q4] = *reinterpret_cast<const uint2*>(A.W16 + mlp_w_off(3) + fcol + fb * 32 + q4 * 8);
-    for (int s = 0; s < n_my + 3; ++s) {
-      // First wave: the output of block s-3 (its partial sums are complete
-      // at the barrier), before its chain; then the third layer of block s-2
-      // with the output layer folded into its epilogue.
+    for (int s = 0; s < n_st + 3; ++s) {
+      // First wave: the outputs of stage s-3 (its partial sums are complete
+      // at the barrier), before the chains; then the third layer of stage
+      // s-2's query blocks with the output layer folded into the epilogue.
       if (wq == 0) {
-        // Lanes 0-31, one query each: the partial sums in a fixed order,
-        // then the bias; one 128-byte line of predictions per block.
-        const float* pr = &L.part[(s - 3) & 1][q][0];
+        // One query per lane (query block = lane half): the partial sums in
+        // a fixed order, then the bias; one 128-byte line per block.
+        const float* pr = &L.part[(s - 3) & 1][lane][0];
         float4 p[kParts / 4];
 #pragma unroll
         for (int i = 0; i < kParts / 4; ++i) p[i] = *reinterpret_cast<const float4*>(pr + 4 * i);
@@ -746,15 +803,19 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
         for (int i = 0; i < kParts / 4; ++i) y += (p[i].x + p[i].y) + (p[i].z + p[i].w);
         y += L.b4;
-        if (s >= 3 && half == 0) A.y[((long long)blockIdx.x + (long long)(s - 3) * G) * 32 + q] = y;
+        const int k = kQB * (s - 3) + half;
+        if (s >= 3 && k < n_my) A.y[((long long)blockIdx.x + (long long)k * G) * 32 + q] = y;
       }
       {
-        f32x16_t acc3[kFB];
-        layer256(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], acc3);
-        float t = 0.f;
+        f32x16_t acc3[2][kFB];
+        layer256x2(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], &L.act2[(s - 2) & 1][32 + q][half * 8], acc3);
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[fb], w4v[fb]);
-        L.part[(s - 2) & 1][q][wq * 2 + half] = t;
+        for (int qb = 0; qb < kQB; ++qb) {
+          float t = 0.f;
+#pragma unroll
+          for (int fb = 0; fb < kFB; ++fb) t += out_partial(acc3[qb][fb], w4v[fb]);
+          L.part[(s - 2) & 1][qb * 32 + q][wq * 2 + half] = t;
+        }
       }
       __syncthreads();
     }
