@@ -108,7 +108,8 @@ int mpc_share_plans(mpc_ctx *c, const unsigned char *publish_mask);
 /* One control step for every arm.
  *  state      [n_arms][dof][3] device: theta, theta_dot, theta_ddot per joint
  *  goal       [n_arms][7] device: goal position xyz, goal orientation quaternion w,x,y,z
- *  obstacles  [n_obstacles][4] device: world-frame sphere centre, radius;
+ *  obstacles  [n_obstacles][4] device: world-frame sphere centre, radius
+ *             (radius >= 0: the collision filter's bound assumes it);
  *             held fixed over the horizon (Sec. IV-A); may be NULL if 0
  *  u_out      [n_arms][dof] device: the executed command U* (first step of
  *             the minimum-cost rollout of the last iteration, Sec. III-A Act)
