@@ -142,7 +142,9 @@ void orc_fk(const orc_arm *arm, const double *q, double *frames) {
 }
 
 /* World-frame collision spheres S (Sec. IV-A): centre = T_body * p, radius
- * unchanged.  Pinned by: |c - t_body| = |p| per sphere. */
+ * unchanged.  Pinned by: |c - t_body| = |p| per sphere; hand-multiplied
+ * centres of offsets off the frame axes on non-symmetric frame rotations
+ * (a transposed rotation fails). */
 void orc_spheres(const orc_arm *arm, const double *q, double *out) {
   double frames[(ORC_MAX_DOF + 1) * 16];
   orc_fk(arm, q, frames);
@@ -155,6 +157,10 @@ void orc_spheres(const orc_arm *arm, const double *q, double *out) {
   }
 }
 
+/* End-effector frame: the last link frame translated by the tool point
+ * given in that frame (the pose term of Eq. 5).  Pinned by: the hand-derived
+ * Panda-scale zero pose with its 0.25 m tool, and the two-link tool offset
+ * off the frame axes. */
 void orc_ee_pose(const orc_arm *arm, const double *q, double *Tee) {
   double frames[(ORC_MAX_DOF + 1) * 16], M[16];
   orc_fk(arm, q, frames);
@@ -843,7 +849,10 @@ double orc_mlp_loss_grad(int L, const int *w, const double *params, int B, const
   return loss / B;
 }
 
-/* Adam (Kingma and Ba, ICLR 2015), bias-corrected, step counted from 1. */
+/* Adam (Kingma and Ba, ICLR 2015), bias-corrected, step counted from 1.
+ * Pinned by: the first step moves by lr against the gradient's sign; a
+ * constant gradient moves by lr at every step (bias correction exact, steps
+ * 1-3); two steps of +1, -1 worked by hand. */
 void orc_adam(long long n, double *p, double *m, double *v, const double *g, double lr,
               double b1, double b2, double eps, int step) {
   double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
@@ -894,7 +903,10 @@ void orc_mlp_forward_bf16(int L, const int *w, const double *params, int B, cons
 /* Reduced-precision dataflow of the training kernels (definition above):
  * Z_l = bf(A_{l-1}) bf(W_l)^T + b_l, A_l = relu(Z_l), y = Z_L;
  * dZ_L = dy; dW_l = bf(dZ_l)^T bf(A_{l-1}); db_l = sum dZ_l;
- * dA_{l-1} = bf(dZ_l) bf(W_l); dZ_{l-1} = dA_{l-1} * [Z_{l-1} > 0]. */
+ * dA_{l-1} = bf(dZ_l) bf(W_l); dZ_{l-1} = dA_{l-1} * [Z_{l-1} > 0].
+ * Pinned by: equality with the FP64 gradient when every operand is
+ * bfloat16-exact; closeness to it otherwise; every forward and backward
+ * rounding point on a 1-1-1 chain worked by hand. */
 double orc_mlp_loss_grad_bf16(int L, const int *w, const double *params, int B, const double *x,
                               const double *t, double over_w, double near_w, double near_band, double *grad) {
   long long np = orc_mlp_param_count(L, w);

@@ -108,6 +108,46 @@ def test_fk_franka_like_zero_pose(orc):
     np.testing.assert_allclose(flange, g["franka_like_q0_flange"], atol=1e-6)
 
 
+def test_ee_pose_franka_like_zero_pose_with_tool(orc):
+    """The end-effector point (Eq. 5's pose term) at the classic zero pose:
+    the tool's 0.25 m along the last frame's z axis, which points down, and
+    the last frame's orientation diag(1, -1, -1), both multiplied out by hand
+    (golden file)."""
+    g = _golden_fk()["franka_like_q0_ee"]
+    arm = _arm()
+    np.testing.assert_array_equal(arm.tool, np.array([0, 0, 0.25], np.float32))
+    T = orc.ee_pose(orc.make_arm(arm), np.zeros(7))
+    np.testing.assert_allclose(T[:3, 3], g[0:3], atol=1e-6)
+    np.testing.assert_allclose(T[:3, :3].ravel(), g[3:12], atol=1e-6)
+    np.testing.assert_allclose(T[3], [0, 0, 0, 1])
+
+
+def _two_link_offsets(p):
+    """The two-link arm with one sphere on each body and the tool, all at the
+    same offset p off the frames' axes."""
+    arm = _two_link()
+    sph = np.array([[p[0], p[1], p[2], 0.05], [p[0], p[1], p[2], 0.07]], np.float32)
+    return scenes.Arm(**{**arm.__dict__, "spheres": sph, "tool": np.array(p, np.float32)})
+
+
+def test_offsets_off_the_axes_rotate_with_their_frame(orc):
+    """A sphere centre and the tool point at an offset that is not along any
+    frame axis, on frames whose rotations are not symmetric (golden file, by
+    hand): catches a transposed rotation, which the norm-preservation pin
+    cannot see."""
+    g = _golden_fk()
+    arm = _two_link_offsets((0.1, 0.2, 0.3))
+    oa = orc.make_arm(arm)
+    q = np.array([math.pi / 2, 0.0])
+    sph = orc.spheres(oa, q)
+    np.testing.assert_allclose(sph[0, :3], g["two_link_q90_offset_on_frame1"], atol=1e-7)
+    np.testing.assert_allclose(sph[1, :3], g["two_link_q90_offset_on_frame2"], atol=1e-7)
+    assert sph[0, 3] == float(np.float32(0.05)) and sph[1, 3] == float(np.float32(0.07))
+    # the tool point rides on the last frame (frame 2 here)
+    T = orc.ee_pose(oa, q)
+    np.testing.assert_allclose(T[:3, 3], g["two_link_q90_offset_on_frame2"], atol=1e-7)
+
+
 def test_fk_orthonormal_and_spacing(orc):
     arm = _arm()
     oa = orc.make_arm(arm)
@@ -600,6 +640,32 @@ def test_adam_first_step_is_signed_lr(orc):
     np.testing.assert_allclose(p, [0.99, -1.99, 0.49], atol=1e-8)
 
 
+def test_adam_bias_correction_constant_gradient(orc):
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so with eps = 0
+    each step moves every parameter by exactly lr against the gradient's
+    sign: after 3 steps, 3 lr."""
+    p0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -4.0, 1e-3, -7.5])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    for t in (1, 2, 3):
+        orc.adam(p, m, v, g, 0.01, 0.9, 0.999, 0.0, t)
+        np.testing.assert_allclose(p, p0 - t * 0.01 * np.sign(g), rtol=0, atol=1e-14)
+
+
+def test_adam_two_steps_by_hand(orc):
+    """g = +1 then -1 with b1 = 1/2, b2 = 3/4, eps = 0, worked by hand:
+    step 1: m = 1/2, v = 1/4, m^ = 1, v^ = 1 -> p -= lr;
+    step 2: m = 1/4 - 1/2 = -1/4, v = 3/16 + 1/4 = 7/16, m^ = -1/4 / (3/4) = -1/3,
+    v^ = (7/16) / (7/16) = 1 -> p += lr/3; total -2 lr / 3."""
+    p, m, v = np.array([0.0]), np.zeros(1), np.zeros(1)
+    orc.adam(p, m, v, np.array([1.0]), 0.03, 0.5, 0.75, 0.0, 1)
+    assert abs(p[0] + 0.03) < 1e-15
+    orc.adam(p, m, v, np.array([-1.0]), 0.03, 0.5, 0.75, 0.0, 2)
+    assert abs(m[0] + 0.25) < 1e-15 and abs(v[0] - 7 / 16) < 1e-15
+    assert abs(p[0] + 0.02) < 1e-15
+
+
 def test_bf16_rounding_matches_torch(orc):
     """Round-to-nearest-even bfloat16 against torch's own conversion."""
     import torch
@@ -653,6 +719,34 @@ def test_bf16_forward_rounds_each_operand(orc):
     assert f([1, -2, 1, -0.25], 1.0) == -0.25
     # the plain forward keeps the digits the reduced one drops
     assert orc.mlp_forward([1, 1, 1], np.array([1 + e7, e9, 1, 0.0]), np.array([[1.0]]))[0, 0] == 1 + e7 + e9
+
+
+def test_bf16_backward_rounds_each_operand(orc):
+    """Each rounding point of the reduced-precision backward on a 1-1-1 chain,
+    worked by hand (bfloat16 keeps 8 significant bits: spacing 2^-7 at 1).
+    x = 1 + 2^-10, W0 = 1, b0 = 2^-10, W1 = 1 + 2^-7 + 2^-10, b1 = 0,
+    t = 1/2 + 3 2^-10, squared error only:
+      a0 = bf(x) = 1; z1 = 1 + 2^-10, a1 = bf(z1) = 1; y = bf(W1) a1 = 1 + 2^-7;
+      dy = 2 (y - t) = 1 + 2^-7 + 2^-9, bf(dy) = 1 + 2^-7;
+      db1 = dy (unrounded)                   = 1 + 2^-7 + 2^-9
+      dW1 = bf(dy) a1                        = 1 + 2^-7
+      dZ1 = bf(W1) bf(dy) = (1 + 2^-7)^2     = 1 + 2^-6 + 2^-14 (z1 > 0)
+      db0 = dZ1 (unrounded)                  = 1 + 2^-6 + 2^-14
+      dW0 = bf(dZ1) a0                       = 1 + 2^-6.
+    Dropping any one rounding (or rounding a bias gradient, or using the
+    unrounded input or activation) changes one of the four values."""
+    e = lambda k: 2.0 ** -k
+    params = np.array([1.0, e(10), 1 + e(7) + e(10), 0.0])
+    x = np.array([[1 + e(10)]])
+    t = np.array([0.5 + 3 * e(10)])
+    loss, g = orc.mlp_loss_grad_bf16([1, 1, 1], params, x, t, 0.0)
+    assert loss == (0.5 + 5 * e(10)) ** 2
+    np.testing.assert_array_equal(g, [1 + e(6), 1 + e(6) + e(14), 1 + e(7), 1 + e(7) + e(9)])
+    # a negative hidden pre-activation stops the gradient below the ReLU
+    params[1] = -2.0
+    loss, g = orc.mlp_loss_grad_bf16([1, 1, 1], params, x, t, 0.0)
+    assert loss == t[0] ** 2
+    np.testing.assert_array_equal(g, [0.0, 0.0, 0.0, -2 * t[0]])
 
 
 def test_bf16_forward_is_the_training_dataflow_forward(orc):
