@@ -43,6 +43,13 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 TRAFFIC = {"sources_sha256": "570c86fbdbd43782", "bytes_per_launch": 47266176}
 
 
+def traffic_bytes():
+    """HBM bytes per rollout launch from the recorded counters, or None when
+    the kernel sources changed since they were taken (stale counters are
+    never reported)."""
+    return TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_digest() else None
+
+
 def sources_digest():
     import hashlib
     h = hashlib.sha256()
@@ -458,7 +465,7 @@ def main():
                        "mean": float(lat.mean())},
         "roofline": {"kernel": "k_rollout", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_digest() else None,
+                     "traffic": traffic_bytes(),
                      "kernel_ms": roll_ms, "algorithmic_flop_per_launch": flops},
     }
     if not args.no_surrogate:

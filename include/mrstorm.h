@@ -49,9 +49,15 @@ extern "C" {
 typedef struct mpc_ctx mpc_ctx;
 
 /* One arm (Sec. III: joint state Theta in R^{d x 3}; Sec. IV-A: the sphere
- * matrix S in R^{N_S x 4} at constant transforms from the links). */
+ * matrix S in R^{N_S x 4} at constant transforms from the links).
+ * Geometry bounds (MPC_EINVAL otherwise): base within 3 m of the world
+ * origin; sum over joints of sqrt(a^2 + d^2), plus |tool|, plus the largest
+ * sphere-centre offset, at most 2.6 m; |a|, |d| and each centre coordinate at
+ * most 1.5 m; radii in [0, 1] m.  They keep every sphere within 6 m of the
+ * origin, the range the FP32 collision filter's slack is sized for. */
 typedef struct {
-  int dof;                 /* d: revolute joints, 1..MPC_MAX_DOF */
+  int dof;                 /* d: revolute joints; this build runs 7-DoF chains only (any other
+                              value: MPC_EUNSUPPORTED); MPC_MAX_DOF sizes the tables */
   int n_spheres;           /* N_S: 1..MPC_MAX_SPHERES, at most 8 per body */
   int n_rollouts;          /* N: 1..MPC_MAX_ROLLOUTS (any value; internally padded to 64) */
   int horizon;             /* H: 1..MPC_MAX_HORIZON */
@@ -82,7 +88,8 @@ typedef struct {
   unsigned long long seed; /* key of the counter-based noise */
   int max_obstacles;       /* capacity for obstacle spheres per step, <= MPC_MAX_OBSTACLES */
   int collision_mode;      /* 0: exact coordination distances; 1: learned distance with exact fallback */
-  float surrogate_margin;  /* mode 1: predictions below this (metres) are checked exactly */
+  float surrogate_margin;  /* mode 1: predictions below this (metres) are checked exactly;
+                              0 (= buf_dyn) or >= buf_dyn, else mpc_init fails with MPC_EINVAL */
   float alpha_sigma;       /* covariance step size (Eqs. 3-4), [0, 1]; 0 keeps Sigma = sigma^2 I */
   float sigma_floor;       /* floor of the Cholesky pivots of the adapted Sigma (std. dev. units), > 0 */
   int plan_mode;           /* 0: publish the predicted plan (Sec. IV-A); 1: publish the current
@@ -161,7 +168,11 @@ enum {
                               prediction against each neighbour (collision mode 1) */
   MPC_DBG_SIGMA = 14,      /* float [horizon][28]: sampling covariance Sigma_h (Eqs. 3-4), packed
                               lower triangle, row j holds (j, 0..j); always available */
-  MPC_DBG_CHOL = 15        /* float [horizon][28]: its Cholesky factor L_h (eps = L_h z); always available */
+  MPC_DBG_CHOL = 15,       /* float [horizon][28]: its Cholesky factor L_h (eps = L_h z); always available */
+  MPC_DBG_SKIP = 16        /* unsigned char [n_arms][horizon][n_rollouts]: learned-distance decision of the
+                              last step against each neighbour (1 = predicted far; collision mode 1).  A
+                              neighbour's check is dropped for rollouts 64b..64b+63 at a step when all 64
+                              are 1; steps beyond the shorter of the two horizons hold no decision */
 };
 /* Copy one captured quantity of one arm into dev_out (device). */
 int mpc_debug_get(mpc_ctx *c, int what, int arm, void *dev_out);
@@ -280,7 +291,19 @@ int mpc_surrogate_predict(mpc_ctx *c, const float *features, int m, float *y);
  * (device), loss (host). */
 int mpc_surrogate_grad(mpc_ctx *c, const float *features, const float *targets, int B, float over_weight,
                        float near_weight, float near_band, float *grad, float *loss);
-/* Switch between exact (0) and learned (1) coordination distances. */
+/* One Adam step (Kingma and Ba, bias-corrected, step counted from 1) on the
+ * network's FP32 parameters with a caller's gradient [136449] (device, e.g.
+ * from mpc_surrogate_grad), exactly as the training loop applies it:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps); the bfloat16
+ * copy the network runs on is refreshed.  step = 1 clears both moment
+ * estimates first.  Together with mpc_surrogate_grad it forms a training
+ * loop of the caller's own.  Errors: MPC_EINVAL for step < 1, lr <= 0, a
+ * beta outside [0, 1) or eps < 0. */
+int mpc_surrogate_adam(mpc_ctx *c, const float *grad, float lr, float beta1, float beta2, float eps, int step);
+/* Switch between exact (0) and learned (1) coordination distances.
+ * Errors: MPC_EINVAL for mode 1 when surrogate_margin is below buf_dyn;
+ * MPC_EUNSUPPORTED when the arms are not one model. */
 int mpc_set_collision_mode(mpc_ctx *c, int mode);
 /* Audit: in mode 1 also run the exact checks of the dropped blocks (the
  * costs stay those of mode 1) and count their queries whose exact distance

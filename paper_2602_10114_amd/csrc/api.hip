@@ -242,7 +242,20 @@ static int validate_arm(mpc_ctx* c, const mpc_arm_desc& d, int i, int counts[kBo
     if (!(d.q_lim[2 * k] <= d.q_lim[2 * k + 1])) return bad("joint limits reversed");
   }
   // The squared-gap filter is sized for world coordinates within 6 m of the
-  // origin: the base within 3 m, the chain within 2.6 m of its base.
+  // origin: the base within 3 m, every point of the chain within 2.6 m of its
+  // base.  Each joint origin lies sqrt(a^2 + d^2) past the previous one, and a
+  // sphere centre or the tool point lies at most its offset from its frame's
+  // origin, so the sum of the link spacings, the tool offset and the largest
+  // sphere offset bounds the reach.
+  double reach = 0.0, off = 0.0;
+  for (int k = 0; k < 7; ++k) reach += std::hypot((double)d.dh[4 * k], (double)d.dh[4 * k + 2]);
+  for (int s = 0; s < d.n_spheres; ++s)
+    off = std::max(off, std::sqrt((double)d.spheres[4 * s] * d.spheres[4 * s] +
+                                  (double)d.spheres[4 * s + 1] * d.spheres[4 * s + 1] +
+                                  (double)d.spheres[4 * s + 2] * d.spheres[4 * s + 2]));
+  reach += off + std::sqrt((double)d.tool[0] * d.tool[0] + (double)d.tool[1] * d.tool[1] +
+                           (double)d.tool[2] * d.tool[2]);
+  if (reach > 2.6) return bad("chain reach (link spacings + tool + largest sphere offset) above 2.6 m");
   if (std::sqrt(d.base[0] * d.base[0] + d.base[1] * d.base[1] + d.base[2] * d.base[2]) > 3.f)
     return bad("base more than 3 m from the world origin");
   return MPC_OK;
@@ -254,16 +267,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   *out = nullptr;
   if (!arms || !p) return fail(nullptr, MPC_EINVAL, "arms or params is NULL");
   if (n_arms < 1 || n_arms > MPC_MAX_ARMS) return fail(nullptr, MPC_EINVAL, "n_arms outside 1..8");
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
-    return fail(nullptr, MPC_EHIP, "no HIP device available");
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return fail(nullptr, MPC_EHIP, "hipGetDeviceProperties failed");
-  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(nullptr, MPC_EHIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  // Host-side validation first (no device needed), then the device.
   const float pf[] = {p->dt, p->sigma, p->lambda, p->gamma, p->alpha_mu, p->w_pose, p->w_rot,
                       p->w_stop, p->w_joint, p->w_coll, p->w_dyn, p->buf_env, p->buf_self,
                       p->buf_dyn, p->tau, p->prio_min, p->prio_max, p->dist_floor, p->joint_margin};
@@ -281,22 +285,34 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (p->plan_mode != 0 && p->plan_mode != 1) return fail(nullptr, MPC_EINVAL, "plan_mode must be 0 or 1");
   if (!(p->w_manip >= 0.f && p->w_manip < 1e30f) || !(p->manip_thresh > 0.f && p->manip_thresh < 1e30f))
     return fail(nullptr, MPC_EINVAL, "w_manip must be >= 0 and manip_thresh > 0");
-  if (p->collision_mode == 1 && !(p->surrogate_margin >= p->buf_dyn))
-    return fail(nullptr, MPC_EINVAL, "surrogate_margin must be at least buf_dyn");
+  // The learned distance may drop a check only when its prediction is at
+  // least the margin, so a margin below B would hide gaps the hinge sees.
+  // 0 means "B itself"; checked here whatever the mode, since the mode can be
+  // switched later.
+  if (!(p->surrogate_margin == 0.f || p->surrogate_margin >= p->buf_dyn))
+    return fail(nullptr, MPC_EINVAL, "surrogate_margin must be 0 (= buf_dyn) or at least buf_dyn");
+  bool all52 = true;
+  for (int i = 0; i < n_arms; ++i) {
+    int counts[kBodies];
+    const int rc = validate_arm(nullptr, arms[i], i, counts);
+    if (rc != MPC_OK) return rc;
+    for (int b = 0; b < kBodies; ++b) all52 = all52 && counts[b] == kLayoutCount[0][b];
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, MPC_EHIP, "no HIP device available");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, MPC_EHIP, "hipGetDeviceProperties failed");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MPC_EHIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
 
   mpc_ctx* c = new mpc_ctx();
   c->A = n_arms;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  bool all52 = true;
   for (int i = 0; i < n_arms; ++i) {
-    int counts[kBodies];
-    const int rc = validate_arm(c, arms[i], i, counts);
-    if (rc != MPC_OK) {
-      g_last_error = c->err;
-      delete c;
-      return rc;
-    }
-    for (int b = 0; b < kBodies; ++b) all52 = all52 && counts[b] == kLayoutCount[0][b];
     c->Hmax = std::max(c->Hmax, arms[i].horizon);
     c->Smax = std::max(c->Smax, arms[i].n_spheres);
     c->Nmax = std::max(c->Nmax, (arms[i].n_rollouts + kWave - 1) / kWave * kWave);
@@ -826,6 +842,13 @@ extern "C" int mpc_debug_get(mpc_ctx* c, int what, int arm, void* dev_out) {
     case MPC_DBG_ARGMIN:
       HIPCHK(c, hipMemcpyAsync(out, c->argmin + arm, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
       break;
+    case MPC_DBG_SKIP:
+      if (!c->sur_skip) return fail(c, MPC_ESTATE, "no learned-distance step has run");
+      for (int i = 0; i < c->A; ++i)
+        HIPCHK(c, hipMemcpy2DAsync(static_cast<uint8_t*>(dev_out) + (size_t)i * d.H * d.N, d.N,
+                                   c->sur_skip + ((size_t)arm * c->A + i) * H * N, N, d.N, d.H,
+                                   hipMemcpyDeviceToDevice, c->stream));
+      break;
     case MPC_DBG_SIGMA:
     case MPC_DBG_CHOL:
       HIPCHK(c, hipMemcpyAsync(out, (what == MPC_DBG_SIGMA ? c->sig : c->chol) + (size_t)arm * H * kTri,
@@ -1311,12 +1334,27 @@ extern "C" int mpc_surrogate_samples(mpc_ctx* c, unsigned long long seed, long l
   return MPC_OK;
 }
 
+extern "C" int mpc_surrogate_adam(mpc_ctx* c, const float* grad, float lr, float b1, float b2, float eps, int step) {
+  if (!c) return MPC_EINVAL;
+  if (!grad || step < 1 || !(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps >= 0.f))
+    return fail(c, MPC_EINVAL, "bad Adam arguments");
+  if (step == 1) {
+    HIPCHK(c, hipMemsetAsync(c->sur_m, 0, sizeof(float) * kMlpParams, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->sur_v, 0, sizeof(float) * kMlpParams, c->stream));
+  }
+  HIPCHK(c, launch_adam(c->sur_p, c->sur_m, c->sur_v, grad, kMlpParams, lr, b1, b2, eps, step, c->stream));
+  HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  return MPC_OK;
+}
+
 extern "C" int mpc_set_collision_mode(mpc_ctx* c, int mode) {
   if (!c) return MPC_EINVAL;
   if (mode != 0 && mode != 1) return fail(c, MPC_EINVAL, "mode must be 0 or 1");
   if (mode == 1) {
     int rc = check_shared_model(c);
     if (rc) return rc;
+    if (!(c->hmodel.margin >= c->P.buf_dyn))
+      return fail(c, MPC_EINVAL, "surrogate_margin must be at least buf_dyn");
   }
   if (mode != c->collision_mode) {
     c->collision_mode = mode;

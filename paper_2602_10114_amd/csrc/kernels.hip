@@ -612,13 +612,17 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
     const int H = A.arms[a].H;
     if (h + 1 < H) A.mu[i] = s_mu[i + 7];
   }
-  // The adapted covariances and their factors shift with the means (one
-  // thread per (arm, entry), steps in increasing order).
-  if (P.cov && tid < nA * 2 * kTri) {
-    const int a = tid / (2 * kTri), e = tid % (2 * kTri);
-    float* m = (e < kTri ? A.sig : A.chol) + (size_t)a * P.Hmax * kTri + e % kTri;
-    const int H = A.arms[a].H;
-    for (int h = 0; h + 1 < H; ++h) m[(size_t)h * kTri] = m[(size_t)(h + 1) * kTri];
+  // The adapted covariances and their factors shift with the means: each
+  // (arm, entry) column belongs to one thread of a block-stride loop (8 arms
+  // hold 448 columns, more than the block's threads) and moves its steps in
+  // increasing order.
+  if (P.cov) {
+    for (int col = tid; col < nA * 2 * kTri; col += blockDim.x) {
+      const int a = col / (2 * kTri), e = col % (2 * kTri);
+      float* m = (e < kTri ? A.sig : A.chol) + (size_t)a * P.Hmax * kTri + e % kTri;
+      const int H = A.arms[a].H;
+      for (int h = 0; h + 1 < H; ++h) m[(size_t)h * kTri] = m[(size_t)(h + 1) * kTri];
+    }
   }
   if (tid < nA) {
     const int a = tid;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrstorm.so")
 
 MPC_OK, MPC_EINVAL, MPC_ENOMEM, MPC_EHIP, MPC_ESTATE, MPC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DBG = dict(NOISE=0, Q=1, QD=2, SPHERES=3, STAGE_COST=4, COST=5, WEIGHTS=6, MEAN=7, ALPHA=8,
-           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12, PRED=13, SIGMA=14, CHOL=15)
+           DIST=9, PAIRS=10, ARGMIN=11, PASSES=12, PRED=13, SIGMA=14, CHOL=15, SKIP=16)
 EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destroy",
            "mpc_last_error", "mpc_sync", "mpc_debug_enable", "mpc_debug_get", "mpc_get_board",
            "mpc_set_board", "mpc_set_mean", "mpc_get_step", "mpc_set_step", "mpc_sim_execute",
@@ -25,7 +25,8 @@ EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destr
            "mpc_profile_read", "mpc_pair_distance", "mpc_pair_features", "mpc_surrogate_samples",
            "mpc_surrogate_train", "mpc_surrogate_get_params", "mpc_surrogate_set_params",
            "mpc_surrogate_predict", "mpc_surrogate_grad", "mpc_set_collision_mode",
-           "mpc_surrogate_audit", "mpc_surrogate_stats", "mpc_profile_read_surrogate"]
+           "mpc_surrogate_audit", "mpc_surrogate_stats", "mpc_profile_read_surrogate",
+           "mpc_surrogate_adam"]
 MLP_WIDTHS = [17, 256, 256, 256, 1]
 MLP_PARAMS = 136449
 # Default training recipe of the learned distance: 2M exact-kernel samples,
@@ -115,6 +116,7 @@ def lib():
         L.mpc_surrogate_set_params.argtypes = [vp, vp]
         L.mpc_surrogate_predict.argtypes = [vp, vp, ip, vp]
         L.mpc_surrogate_grad.argtypes = [vp, vp, vp, ip, fp, fp, fp, vp, C.POINTER(fp)]
+        L.mpc_surrogate_adam.argtypes = [vp, vp, fp, fp, fp, fp, ip]
         L.mpc_set_collision_mode.argtypes = [vp, ip]
         L.mpc_surrogate_audit.argtypes = [vp, ip]
         L.mpc_surrogate_stats.argtypes = [vp, vp, ip]
@@ -147,6 +149,30 @@ def params_struct(p: dict) -> MpcParams:
     return s
 
 
+def arm_descs(arms):
+    """C descriptors of scenes.Arm records, and the host tables they point at
+    (keep them alive until mpc_init returns)."""
+    keep = []
+    descs = (MpcArmDesc * len(arms))()
+    for i, a in enumerate(arms):
+        tabs = [np.ascontiguousarray(a.dh, np.float32), np.ascontiguousarray(a.q_lim, np.float32),
+                np.ascontiguousarray(a.qd_max, np.float32), np.ascontiguousarray(a.spheres, np.float32),
+                np.ascontiguousarray(a.sphere_link, np.int32)]
+        keep.append(tabs)
+        d = descs[i]
+        d.dof, d.n_spheres, d.n_rollouts, d.horizon = a.dof, a.n_spheres, a.n_rollouts, a.horizon
+        d.dh = tabs[0].ctypes.data_as(C.POINTER(C.c_float))
+        d.q_lim = tabs[1].ctypes.data_as(C.POINTER(C.c_float))
+        d.qd_max = tabs[2].ctypes.data_as(C.POINTER(C.c_float))
+        d.spheres = tabs[3].ctypes.data_as(C.POINTER(C.c_float))
+        d.sphere_link = tabs[4].ctypes.data_as(C.POINTER(C.c_int))
+        for k in range(4):
+            d.base[k] = float(a.base[k])
+        for k in range(3):
+            d.tool[k] = float(a.tool[k])
+    return descs, keep
+
+
 class Controller:
     """One context for every arm of a scene.  `arms` are scenes.Arm records;
     `stream` a torch.cuda.Stream (default: the current stream)."""
@@ -157,24 +183,7 @@ class Controller:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.A = len(arms)
         self.arms = arms
-        self._keep = []
-        descs = (MpcArmDesc * self.A)()
-        for i, a in enumerate(arms):
-            tabs = [np.ascontiguousarray(a.dh, np.float32), np.ascontiguousarray(a.q_lim, np.float32),
-                    np.ascontiguousarray(a.qd_max, np.float32), np.ascontiguousarray(a.spheres, np.float32),
-                    np.ascontiguousarray(a.sphere_link, np.int32)]
-            self._keep.append(tabs)
-            d = descs[i]
-            d.dof, d.n_spheres, d.n_rollouts, d.horizon = a.dof, a.n_spheres, a.n_rollouts, a.horizon
-            d.dh = tabs[0].ctypes.data_as(C.POINTER(C.c_float))
-            d.q_lim = tabs[1].ctypes.data_as(C.POINTER(C.c_float))
-            d.qd_max = tabs[2].ctypes.data_as(C.POINTER(C.c_float))
-            d.spheres = tabs[3].ctypes.data_as(C.POINTER(C.c_float))
-            d.sphere_link = tabs[4].ctypes.data_as(C.POINTER(C.c_int))
-            for k in range(4):
-                d.base[k] = float(a.base[k])
-            for k in range(3):
-                d.tool[k] = float(a.tool[k])
+        descs, self._keep = arm_descs(arms)
         self.params = params_struct(params)
         h = C.c_void_p()
         _check(lib().mpc_init(descs, self.A, C.byref(self.params), C.c_void_p(self.stream.cuda_stream),
@@ -240,8 +249,8 @@ class Controller:
         shapes = dict(NOISE=(H, 7, N), Q=(N, H, 7), QD=(N, H, 7), SPHERES=(N, H, S, 4),
                       STAGE_COST=(H, N), COST=(N,), WEIGHTS=(N,), MEAN=(H, 7), ALPHA=(self.A,),
                       DIST=(1,), PAIRS=(1,), ARGMIN=(1,), PASSES=(3,), PRED=(self.A, H, N),
-                      SIGMA=(H, 28), CHOL=(H, 28))
-        dtype = dict(PAIRS=t.int64, ARGMIN=t.int32, PASSES=t.int64).get(what, t.float32)
+                      SIGMA=(H, 28), CHOL=(H, 28), SKIP=(self.A, H, N))
+        dtype = dict(PAIRS=t.int64, ARGMIN=t.int32, PASSES=t.int64, SKIP=t.uint8).get(what, t.float32)
         out = t.empty(shapes[what], dtype=dtype, device=self.dev)
         _check(lib().mpc_debug_get(self.h, DBG[what], arm, _ptr(out)), self.h)
         return out
@@ -360,6 +369,11 @@ class Controller:
                                         float(over_weight), float(near_weight), float(near_band), _ptr(g),
                                         C.byref(loss)), self.h)
         return g, loss.value
+
+    def surrogate_adam(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+        grad = self._f32(grad)
+        _check(lib().mpc_surrogate_adam(self.h, _ptr(grad), float(lr), float(beta1), float(beta2), float(eps),
+                                        int(step)), self.h)
 
     def set_collision_mode(self, mode):
         _check(lib().mpc_set_collision_mode(self.h, int(mode)), self.h)

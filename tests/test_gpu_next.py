@@ -9,7 +9,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
-from paper_2602_10114_amd import native
+from paper_2602_10114_amd import native, scenes
 from helpers import small_scene
 
 pytestmark = pytest.mark.gpu
@@ -144,3 +144,54 @@ def test_manipulability_term_stage_isolated():
                             for n in range(0, 96, 7) for h in range(6))
     _say(f"  sampled rollout steps with an active manipulability term: {manip_active}")
     assert manip_active > 0
+
+
+def test_covariance_shift_covers_every_arm_of_eight():
+    """Eight arms (the 64-sphere workload's arms, 64 rollouts x 4 steps),
+    alpha_sigma 0.5, two steps.  After the first step every arm's Sigma and
+    factor match the oracle stage-isolated; at the second step every arm,
+    arm index 7 included, draws eps = L_{h+1} z from its shifted factor, and
+    its Sigma is the EMA of the shifted Sigma and the step's weighted
+    covariance (1e-6)."""
+    _say("case: covariance adaptation, 8 arms, 64 rollouts x 4 steps, alpha_sigma 0.5")
+    sc = scenes.make_scene(5, collision_mode=0)
+    for a in sc.arms:
+        a.n_rollouts, a.horizon = 64, 4
+    p = {**sc.params, "alpha_sigma": 0.5}
+    ctl = native.Controller(sc.arms, p)
+    ctl.debug_enable(True)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    ctl.sync()
+    s2 = float(np.float32(0.3)) ** 2
+    fl = float(np.float32(1e-3)) ** 2
+    sig1, chol1 = [], []
+    for a in range(8):
+        eps = ctl.debug_get("NOISE", a).cpu().numpy().astype(np.float64)
+        w = ctl.debug_get("WEIGHTS", a).cpu().numpy().astype(np.float64)
+        sig = _unpack(ctl.debug_get("SIGMA", a).cpu().numpy().astype(np.float64))
+        L = _lower(ctl.debug_get("CHOL", a).cpu().numpy().astype(np.float64))
+        U = eps.transpose(2, 0, 1)
+        ref = 0.5 * s2 * np.eye(7) + 0.5 * oracle.weighted_cov(w, U, oracle.weighted_mean(w, U))
+        assert np.abs(sig - ref).max() < 1e-6, a
+        for h in range(4):
+            Lr = oracle.cholesky_floor(sig[h], fl)
+            assert np.abs(L[h] - Lr).max() < 1e-5 * np.abs(Lr).max(), a
+        sig1.append(sig)
+        chol1.append(L)
+    ctl.step(sc.state, sc.goal, sc.obstacles)
+    ctl.sync()
+    seed = int(p["seed"])
+    for a in range(8):
+        eps2 = ctl.debug_get("NOISE", a).cpu().numpy().astype(np.float64)
+        w2 = ctl.debug_get("WEIGHTS", a).cpu().numpy().astype(np.float64)
+        sig2 = _unpack(ctl.debug_get("SIGMA", a).cpu().numpy().astype(np.float64))
+        Lu = np.concatenate([chol1[a][1:], chol1[a][-1:]])
+        Su = np.concatenate([sig1[a][1:], sig1[a][-1:]])
+        for n in (0, 17, 63):
+            for h in range(4):
+                z = oracle.normals(seed, a, 1, 0, n, h, 7)
+                assert np.abs(eps2[h, :, n] - Lu[h] @ z).max() < 2e-6, (a, n, h)
+        U2 = eps2.transpose(2, 0, 1)
+        ref2 = 0.5 * Su + 0.5 * oracle.weighted_cov(w2, U2, oracle.weighted_mean(w2, U2))
+        assert np.abs(sig2 - ref2).max() < 1e-6, a
+    ctl.close()

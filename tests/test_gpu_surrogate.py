@@ -356,3 +356,127 @@ def test_trained_network_skips_exact_work_without_missed_collisions(trained4):
     assert skipped > 0.3
     assert aud["queries"] > 0 and aud["predicted_far"] > 0.3 * aud["queries"]
     assert aud["missed_collisions"] == 0
+
+
+def _joint_threshold_params(j, c, gain=64.0):
+    """A network whose output is gain * (f_j - c), f_j the j-th own-joint
+    feature: first-layer units 0 and 1 carry relu(+-gain (f_j - c)), the next
+    two layers pass them on, the output takes their difference.  Every
+    weight is a small power of two (bfloat16-exact)."""
+    Wd = native.MLP_WIDTHS
+    p = np.zeros(native.MLP_PARAMS, np.float32)
+    offs, o = [], 0
+    for l in range(len(Wd) - 1):
+        offs.append((o, o + Wd[l + 1] * Wd[l]))
+        o += Wd[l + 1] * Wd[l] + Wd[l + 1]
+    (w0, b0), (w1, _), (w2, _), (w3, _) = offs
+    p[w0 + j], p[b0] = gain, -gain * c
+    p[w0 + Wd[0] + j], p[b0 + 1] = -gain, gain * c
+    p[w1], p[w1 + Wd[1] + 1] = 1.0, 1.0
+    p[w2], p[w2 + Wd[2] + 1] = 1.0, 1.0
+    p[w3], p[w3 + 1] = 1.0, -1.0
+    return p
+
+
+def test_learned_mixed_drops_stage_costs_against_oracle():
+    """Collision mode 1 with a mix of dropped and kept 64-rollout blocks (a
+    network thresholding one own joint near the low end of its spread, so
+    that some blocks are far in every rollout and others are not): the GPU's
+    stage costs equal the oracle's with the neighbour inactive exactly where
+    the GPU's own skip decisions drop it (all 64 rollouts of a block far) and
+    active elsewhere, 1e-4 relative; the exact pass evaluates exactly the
+    sphere pairs of the kept blocks.  The audited run keeps the same costs
+    and decisions, and counts dropped queries whose exact gap is below B:
+    the drops do hide live coordination terms, so the comparison bites."""
+    _say("case: collision mode 1, mixed drops, config 2 shape, 160 rollouts (ragged block) x 20 steps")
+    sc = small_scene(2, n=160, h=20)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    # the rollouts' joints at the second step, from an exact-mode run
+    ref = native.Controller(sc.arms, sc.params)
+    ref.step(sc.state, sc.goal, obst)
+    ref.share_plans()
+    ref.debug_enable(True)
+    ref.step(sc.state, sc.goal, obst)
+    ref.sync()
+    q0 = ref.debug_get("Q", 0).cpu().numpy().astype(np.float64)
+    ref.close()
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
+    f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
+    runs = {}
+    for audit in (False, True):
+        ctl = native.Controller(sc.arms, sc.params)
+        ctl.set_surrogate_params(params)
+        ctl.set_collision_mode(1)
+        ctl.surrogate_audit(audit)
+        ctl.step(sc.state, sc.goal, obst)
+        ctl.share_plans()
+        ctl.sync()
+        boards = read_boards(ctl, sc)
+        ctl.debug_enable(True)
+        ctl.surrogate_stats(reset=True)
+        ctl.step(sc.state, sc.goal, obst)
+        ctl.sync()
+        runs[audit] = ([Capture(ctl, a) for a in range(2)], [ctl.debug_get("SKIP", a).cpu().numpy() for a in range(2)],
+                       ctl.surrogate_stats(), boards)
+        ctl.close()
+    caps, skips, st, boards = runs[False]
+    n_drop = n_keep = 0
+    for a in range(2):
+        i = 1 - a
+        arm, nb = sc.arms[a], sc.arms[i]
+        N, H, Hc = arm.n_rollouts, arm.horizon, min(arm.horizon, nb.horizon)
+        assert boards[i][1] == 1
+        drop = np.zeros((H, N), bool)
+        for h in range(Hc):
+            for b in range(N // 64):        # a ragged last block is never dropped
+                if skips[a][i, h, 64 * b:64 * b + 64].all():
+                    drop[h, 64 * b:64 * b + 64] = True
+                    n_drop += 1
+                else:
+                    n_keep += 1
+            n_keep += N % 64 > 0
+        on = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+        off_boards = list(boards)
+        off_boards[i] = (boards[i][0], 0, boards[i][2])
+        off = oracle_stage(sc, a, caps[a], sc.obstacles, off_boards)
+        assert rel_err(caps[a].stage, np.where(drop, off, on)) < 1e-4, a
+        assert caps[a].pairs == int(np.sum(~drop[:Hc])) * arm.n_spheres * nb.n_spheres
+        _say(f"  arm {a}: dropped rollout-steps {int(drop.sum())} of {N * Hc}")
+    _say(f"  blocks dropped {n_drop}, kept {n_keep}; counters {st}")
+    assert n_drop > 0 and n_keep > 0
+    assert st["waves_skipped"] == n_drop
+    caps2, skips2, st2, _ = runs[True]
+    for a in range(2):
+        np.testing.assert_array_equal(skips2[a], skips[a])
+        np.testing.assert_array_equal(caps2[a].stage, caps[a].stage)
+    _say(f"  audited: {st2}")
+    assert st2["misses"] > 0
+
+
+def test_adam_matches_oracle_over_three_steps():
+    """The training loop's Adam kernel (bias-corrected, FP32) against the
+    oracle's FP64 Adam on the same FP32 parameters and gradients, over three
+    steps (so the bias correction of steps 2 and 3 is exercised): parameters
+    within 1e-7 absolute after every step."""
+    _say("case: Adam, 136449 parameters, 3 steps")
+    sc = small_scene(2, n=64, h=4)
+    ctl = native.Controller(sc.arms, sc.params)
+    rng = np.random.default_rng(41)
+    n = native.MLP_PARAMS
+    p0 = (rng.uniform(-1, 1, n) * 0.1).astype(np.float32)
+    ctl.set_surrogate_params(p0)
+    p, m, v = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t in (1, 2, 3):
+        g = (rng.normal(size=n) * 10.0 ** rng.uniform(-4, 0, size=n)).astype(np.float32)
+        ctl.surrogate_adam(torch.from_numpy(g).cuda(), lr, b1, b2, eps, t)
+        oracle.adam(p, m, v, g.astype(np.float64), f32(lr), f32(b1), f32(b2), f32(eps), t)
+        got = ctl.surrogate_params().cpu().numpy().astype(np.float64)
+        err = np.abs(got - p).max()
+        _say(f"  step {t}: max |p_gpu - p_oracle| {err:.2e}")
+        assert err < 1e-7
+    with pytest.raises(native.MpcError):
+        ctl.surrogate_adam(torch.from_numpy(g).cuda(), lr, b1, b2, eps, 0)
+    ctl.close()
