@@ -198,12 +198,20 @@ int mpc_set_step(mpc_ctx *c, unsigned int t);
  * (device, in place) by one step of the rollout dynamics under u [n_arms][dof]. */
 int mpc_sim_execute(mpc_ctx *c, float *state, const float *u);
 
-/* Rollout-kernel launch shape picked by the tuner (rollouts per block,
- * horizon steps per work item, workgroups); valid after the first step. */
+/* Rollout-kernel launch shape picked by the tuner: rollouts per workgroup
+ * (64, 128 or 256: 1, 2 or 4 waves sharing one LDS copy of each step's
+ * obstacle and neighbour-plan spheres), horizon steps per work item, and
+ * workgroups; valid after the first step.  The tuner times the candidates on
+ * the first step at which every arm's plan is published (or the fourth step)
+ * and keeps its choice per problem shape and device for the process, so a
+ * later context of the same shape reuses it without timing. */
 int mpc_get_tuning(const mpc_ctx *c, int *rollouts_per_block, int *h_tile, int *grid);
 /* Force a launch shape (0 = let the tuner choose); takes effect at the next
- * mpc_step.  Results do not depend on the launch shape: every rollout's
- * stage costs are summed (Eq. 1) in step order whatever the tiling. */
+ * mpc_step.  rollouts_per_block must be 0, 64, 128 or 256 (else
+ * MPC_EUNSUPPORTED) and divide every arm's rollout count padded to a
+ * multiple of 64 (else MPC_EINVAL).  Results do not depend on the launch
+ * shape: every rollout's stage costs are summed (Eq. 1) in step order
+ * whatever the tiling, and each wave scores its own 64 rollouts. */
 int mpc_set_tuning(mpc_ctx *c, int rollouts_per_block, int h_tile, int grid);
 
 /* Kernel timing for measurement: while on, mpc_step launches its kernels

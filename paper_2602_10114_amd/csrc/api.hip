@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +22,7 @@ using namespace mrs;
 // neighbours' planned joints in the inference kernel) are sized for the
 // largest valid problem.
 static_assert(kMaxH >= MPC_MAX_HORIZON && kMaxArms >= MPC_MAX_ARMS, "device tables cover every valid problem");
+static_assert(kWmeanMaxChunks * kWmeanChunk >= MPC_MAX_ROLLOUTS, "weighted-mean partials cover every rollout count");
 
 static thread_local std::string g_last_error;
 
@@ -75,6 +78,8 @@ struct mpc_ctx {
   float* manip = nullptr;              // [A][Hmax][Nmax] C_manip of the iteration (w_manip > 0)
   float* sig = nullptr;                // [A][Hmax][28] adapted covariances (packed lower triangles)
   float* chol = nullptr;               // their Cholesky factors
+  float* wpart = nullptr;              // weighted-mean chunk partials [A][Hmax][kWmeanMaxChunks][35]
+  unsigned* wcnt = nullptr;            // chunks finished per (arm, step) [A][Hmax]
   float* partial = nullptr;
   float* cost = nullptr;
   float* w = nullptr;
@@ -89,8 +94,9 @@ struct mpc_ctx {
   Item* d_items = nullptr;
   size_t items_cap = 0;
   int n_items = 0;
-  int h_tile = 0, grid = 0;
-  int force_tile = 0, force_grid = 0;
+  int h_tile = 0, grid = 0, waves = 1;  // launch shape: horizon tile, workgroups, 64-rollout waves per workgroup
+  int force_tile = 0, force_grid = 0, force_waves = 0;
+  unsigned long long* tune_counts = nullptr;  // learned-distance counters of tuner replays [A][5]
   bool tuned = false;
   int n_published = 0;                 // arms whose plan has been published at least once
   std::vector<char> published;
@@ -352,6 +358,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
       (rc = dalloc(c, &c->planq[0], A * H * 7)) || (rc = dalloc(c, &c->planq[1], A * H * 7)) ||
       (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A)) ||
       (rc = dalloc(c, &c->sig, A * H * kTri)) || (rc = dalloc(c, &c->chol, A * H * kTri)) ||
+      (rc = dalloc(c, &c->wpart, A * H * kWmeanMaxChunks * kWmeanSums)) || (rc = dalloc(c, &c->wcnt, A * H)) ||
       (p->w_manip > 0.f && (rc = dalloc(c, &c->manip, A * H * N)))) {
     g_last_error = c->err;
     mpc_destroy(c);
@@ -420,18 +427,50 @@ extern "C" int mpc_sync(mpc_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Work items of the rollout launch for a horizon tile T: every arm's 64-rollout
-// blocks times its ceil(H/T) tiles, heaviest (longest tile) first.
-static void build_items(const mpc_ctx* c, int T, std::vector<Item>& items) {
+// Work items of the rollout launch for a horizon tile T and W waves per
+// workgroup: every arm's blocks of 64 W rollouts times its ceil(H/T) tiles,
+// heaviest (longest tile) first.
+static void build_items(const mpc_ctx* c, int T, int W, std::vector<Item>& items) {
   items.clear();
   for (int a = 0; a < c->A; ++a) {
     const DevArm& arm = c->harms[a];
-    const int blocks = arm.Npad / kWave;
+    const int blocks = arm.Npad / (kWave * W);
     for (int h0 = 0; h0 < arm.H; h0 += T)
       for (int b = 0; b < blocks; ++b) items.push_back(Item{a, b, h0, std::min(arm.H, h0 + T)});
   }
   std::stable_sort(items.begin(), items.end(),
                    [](const Item& x, const Item& y) { return (x.h1 - x.h0) > (y.h1 - y.h0); });
+}
+
+// W waves per workgroup fit when every arm's padded rollout count is a
+// multiple of 64 W (no wave of an item past an arm's rollouts).
+static bool waves_fit(const mpc_ctx* c, int W) {
+  if (W != 1 && W != 2 && W != 4) return false;
+  for (const DevArm& arm : c->harms)
+    if (arm.Npad % (kWave * W) != 0) return false;
+  return true;
+}
+
+// Launch shapes the tuner chose, per problem shape and device, for the
+// lifetime of the process: a context with the same shape on the same device
+// starts from the cached choice instead of timing candidates again.
+struct TuneChoice {
+  int T, grid, waves;
+};
+static std::mutex g_tune_mu;
+static std::map<std::vector<long long>, TuneChoice> g_tune_cache;
+
+static std::vector<long long> tune_key(const mpc_ctx* c) {
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  std::vector<long long> k = {dev, c->layout, c->collision_mode, c->sur_audit ? 1 : 0, c->P.cov,
+                              c->manip ? 1 : 0, c->P.max_obs, c->A};
+  for (const DevArm& arm : c->harms) {
+    k.push_back(arm.N);
+    k.push_back(arm.H);
+    k.push_back(arm.S);
+  }
+  return k;
 }
 
 static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
@@ -481,12 +520,14 @@ static ReduceArgs reduce_args(const mpc_ctx* c) {
   R.meta = c->d_meta;
   R.sig = c->sig;
   R.chol = c->chol;
+  R.wpart = c->wpart;
+  R.wcnt = c->wcnt;
   return R;
 }
 
-static int set_items(mpc_ctx* c, int T) {
+static int set_items(mpc_ctx* c, int T, int W) {
   std::vector<Item> items;
-  build_items(c, T, items);
+  build_items(c, T, W, items);
   if (items.size() > c->items_cap) {
     Item* p = nullptr;
     HIPCHK(c, hipMalloc(&p, items.size() * sizeof(Item)));
@@ -498,12 +539,40 @@ static int set_items(mpc_ctx* c, int T) {
   HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
   c->n_items = (int)items.size();
   c->h_tile = T;
+  c->waves = W;
   return MPC_OK;
 }
 
-// Launch-shape tuner: times the rollout launch for every candidate horizon
-// tile and grid size on the live inputs of the first step, keeps the fastest.
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts);
+
+// Launch-shape tuner: times the rollout launch for every candidate number of
+// waves per workgroup, horizon tile and grid size on the live inputs of the
+// first representative step and keeps the fastest; the choice is cached per
+// problem shape and device.  In collision mode 1 the candidates run on this
+// step's skip decisions, and their counts go to a scratch row, not to the
+// context's counters.
 static int tune(mpc_ctx* c) {
+  const std::vector<long long> key = tune_key(c);
+  const bool forced = c->force_tile > 0 || c->force_grid > 0 || c->force_waves > 0;
+  if (!forced) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto hit = g_tune_cache.find(key);
+    if (hit != g_tune_cache.end()) {
+      const TuneChoice ch = hit->second;
+      int rc = set_items(c, ch.T, ch.waves);
+      if (rc) return rc;
+      c->grid = std::min(ch.grid, c->n_items);
+      c->tuned = true;
+      return MPC_OK;
+    }
+  }
+  std::vector<int> waves;
+  if (c->force_waves > 0) {
+    waves.push_back(c->force_waves);
+  } else {
+    for (int W : {1, 2, 4})
+      if (waves_fit(c, W)) waves.push_back(W);
+  }
   std::vector<int> tiles;
   if (c->force_tile > 0) {
     tiles.push_back(std::min(c->force_tile, c->Hmax));
@@ -512,45 +581,99 @@ static int tune(mpc_ctx* c) {
       if (T <= c->Hmax) tiles.push_back(T);
     if (std::find(tiles.begin(), tiles.end(), c->Hmax) == tiles.end()) tiles.push_back(c->Hmax);
   }
+  if (c->collision_mode == 1 && !c->tune_counts) {
+    int rc = dalloc(c, &c->tune_counts, (size_t)5 * c->A);
+    if (rc) return rc;
+  }
+  if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
+  if (c->collision_mode == 1) {
+    int rc = enqueue_learned_prelude(c, 0, false, c->tune_counts);
+    if (rc) return rc;
+  }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   float best_ms = 1e30f;
-  int best_T = tiles[0], best_grid = 0;
-  for (int T : tiles) {
-    int rc = set_items(c, T);
-    if (rc) return rc;
-    std::vector<int> grids;
-    if (c->force_grid > 0) {
-      grids.push_back(std::min(c->force_grid, c->n_items));
-    } else {
-      grids.push_back(c->n_items);
-      for (int g : {1024, 2048, 4096})
-        if (g < c->n_items) grids.push_back(g);
-    }
-    if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
-    for (int g : grids) {
-      RolloutArgs R = rollout_args(c, 0);
-      HIPCHK(c, launch_rollout(R, c->layout, false, g, c->stream));
-      HIPCHK(c, hipEventRecord(e0, c->stream));
-      for (int r = 0; r < 3; ++r) HIPCHK(c, launch_rollout(R, c->layout, false, g, c->stream));
-      HIPCHK(c, hipEventRecord(e1, c->stream));
-      HIPCHK(c, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_T = T;
-        best_grid = g;
+  int best_T = tiles[0], best_grid = 0, best_W = waves[0];
+  for (int W : waves) {
+    for (int T : tiles) {
+      int rc = set_items(c, T, W);
+      if (rc) return rc;
+      std::vector<int> grids;
+      if (c->force_grid > 0) {
+        grids.push_back(std::min(c->force_grid, c->n_items));
+      } else {
+        grids.push_back(c->n_items);
+        for (int g : {1024, 2048, 4096})
+          if (g / W < c->n_items) grids.push_back(g / W);
+      }
+      for (int g : grids) {
+        RolloutArgs R = rollout_args(c, 0);
+        if (R.sur_counts) R.sur_counts = c->tune_counts;
+        HIPCHK(c, launch_rollout(R, c->layout, false, W, g, c->stream));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 3; ++r) HIPCHK(c, launch_rollout(R, c->layout, false, W, g, c->stream));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_T = T;
+          best_grid = g;
+          best_W = W;
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  int rc = set_items(c, best_T);
+  int rc = set_items(c, best_T, best_W);
   if (rc) return rc;
   c->grid = best_grid;
   c->tuned = true;
+  if (!forced) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = TuneChoice{best_T, best_grid, best_W};
+  }
+  return MPC_OK;
+}
+
+// Learned distance before each rollout launch of iteration k: own-joint
+// features of every rollout step, the neighbour records, the network's
+// predictions and the skip decision per (rollout, step, neighbour), counted
+// into `counts`.
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts) {
+  const float* eps_in = c->P.cov ? c->eps : nullptr;
+  HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, eps_in, k, c->A, c->Nmax,
+                              c->sur_F, c->stream));
+  HIPCHK(c, launch_sur_pairs(c->d_arms, c->d_model, c->d_meta, c->planq[0], c->A, c->Hmax, c->sur_nbrec, c->stream));
+  SurInferArgs I{};
+  I.P = c->d_P;
+  I.model = c->d_model;
+  I.W16 = c->sur_p16;
+  I.P32 = c->sur_p;
+  I.F = c->sur_F;
+  I.nbrec = c->sur_nbrec;
+  I.items = c->d_sur_items;
+  I.n_items = c->n_sur_items;
+  I.y = c->sur_y;
+  hipEvent_t ei = nullptr;
+  if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
+  HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
+  if (ei) HIPCHK(c, hipEventRecord(ei, c->stream));
+  SurDecideArgs D{};
+  D.P = c->d_P;
+  D.model = c->d_model;
+  D.F = c->sur_F;
+  D.nbrec = c->sur_nbrec;
+  D.items = c->d_sur_items;
+  D.y = c->sur_y;
+  D.n_items = c->n_sur_items;
+  D.skip = c->sur_skip;
+  D.pred = debug ? c->sur_pred : nullptr;
+  D.counts = counts;
+  HIPCHK(c, launch_sur_decide(D, c->stream));
   return MPC_OK;
 }
 
@@ -566,45 +689,15 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A, c->Nmax, c->manip,
                              c->stream));
     if (c->collision_mode == 1) {
-      // Learned distance: own-joint features of every rollout step, then the MLP's
-      // skip decision per (rollout, step, neighbour).
-      HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A,
-                                  c->Nmax, c->sur_F, c->stream));
-      HIPCHK(c, launch_sur_pairs(c->d_arms, c->d_model, c->d_meta, c->planq[0], c->A, c->Hmax, c->sur_nbrec,
-                                 c->stream));
-      SurInferArgs I{};
-      I.P = c->d_P;
-      I.model = c->d_model;
-      I.W16 = c->sur_p16;
-      I.P32 = c->sur_p;
-      I.F = c->sur_F;
-      I.nbrec = c->sur_nbrec;
-      I.items = c->d_sur_items;
-      I.n_items = c->n_sur_items;
-      I.y = c->sur_y;
-      hipEvent_t ei = nullptr;
-      if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
-      HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
-      if (ei) HIPCHK(c, hipEventRecord(ei, c->stream));
-      SurDecideArgs D{};
-      D.P = c->d_P;
-      D.model = c->d_model;
-      D.F = c->sur_F;
-      D.nbrec = c->sur_nbrec;
-      D.items = c->d_sur_items;
-      D.y = c->sur_y;
-      D.n_items = c->n_sur_items;
-      D.skip = c->sur_skip;
-      D.pred = debug ? c->sur_pred : nullptr;
-      D.counts = c->sur_counts;
-      HIPCHK(c, launch_sur_decide(D, c->stream));
+      int rc = enqueue_learned_prelude(c, k, debug, c->sur_counts);
+      if (rc) return rc;
     }
     hipEvent_t e1 = nullptr;
     if (c->profile) HIPCHK(c, c->prof_roll.begin(c->stream, &e1));
-    HIPCHK(c, launch_rollout(R, c->layout, debug, c->grid, c->stream));
+    HIPCHK(c, launch_rollout(R, c->layout, debug, c->waves, c->grid, c->stream));
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, launch_softmax(Rr, c->A, c->Nmax, c->stream));
-    HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->stream));
+    HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->Nmax, c->stream));
   }
   HIPCHK(c, launch_toplan(Rr, c->A, c->stream));
   return MPC_OK;
@@ -704,7 +797,7 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
     } else {
       if (c->n_items == 0) {
         const int T = c->force_tile > 0 ? std::min(c->force_tile, c->Hmax) : std::min(4, c->Hmax);
-        if ((rc = set_items(c, T))) return rc;
+        if ((rc = set_items(c, T, c->force_waves > 0 ? c->force_waves : 1))) return rc;
       }
       c->grid = c->force_grid > 0 ? std::min(c->force_grid, c->n_items) : c->n_items;
       ++c->untuned_steps;
@@ -926,7 +1019,7 @@ extern "C" int mpc_sim_execute(mpc_ctx* c, float* state, const float* u) {
 
 extern "C" int mpc_get_tuning(const mpc_ctx* c, int* rollouts_per_block, int* h_tile, int* grid) {
   if (!c) return MPC_EINVAL;
-  if (rollouts_per_block) *rollouts_per_block = kWave;
+  if (rollouts_per_block) *rollouts_per_block = kWave * c->waves;
   if (h_tile) *h_tile = c->h_tile;
   if (grid) *grid = c->grid;
   return c->n_items > 0 ? MPC_OK : MPC_ESTATE;
@@ -934,11 +1027,15 @@ extern "C" int mpc_get_tuning(const mpc_ctx* c, int* rollouts_per_block, int* h_
 
 extern "C" int mpc_set_tuning(mpc_ctx* c, int rollouts_per_block, int h_tile, int grid) {
   if (!c) return MPC_EINVAL;
-  if (rollouts_per_block != 0 && rollouts_per_block != kWave)
-    return fail(c, MPC_EUNSUPPORTED, "this build runs 64 rollouts per block");
+  if (rollouts_per_block != 0 && rollouts_per_block != kWave && rollouts_per_block != 2 * kWave &&
+      rollouts_per_block != 4 * kWave)
+    return fail(c, MPC_EUNSUPPORTED, "rollouts per block must be 64, 128 or 256 (0 = tuned)");
+  if (rollouts_per_block != 0 && !waves_fit(c, rollouts_per_block / kWave))
+    return fail(c, MPC_EINVAL, "every arm's rollout count, padded to 64, must be a multiple of rollouts_per_block");
   if (h_tile < 0 || grid < 0) return fail(c, MPC_EINVAL, "negative tuning value");
   c->force_tile = h_tile;
   c->force_grid = grid;
+  c->force_waves = rollouts_per_block / kWave;
   c->tuned = false;
   c->n_items = 0;
   return MPC_OK;

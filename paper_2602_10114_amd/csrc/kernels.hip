@@ -35,12 +35,12 @@ struct LdsSets {
   float4 raw[kLdsSpheres];
   float F[kLdsSpheres];
   float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
-  int set_k0[kMaxSets], set_n[kMaxSets], set_drop[kMaxSets];
+  int set_k0[kMaxSets], set_n[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
-  // learned-distance counters of the current item (lane 0 only), in the
-  // layout of the per-arm counter rows (slots 0 and 1, queries and predicted
-  // far, are the inference kernel's): waves skipped, audited misses (exact
-  // gap < B), audited missed collisions (gap < 0)
+  // learned-distance counters of the current item (added by each wave's
+  // lane 0), in the layout of the per-arm counter rows (slots 0 and 1,
+  // queries and predicted far, are the inference kernel's): waves skipped,
+  // audited misses (exact gap < B), audited missed collisions (gap < 0)
   unsigned sur[5];
 };
 
@@ -176,17 +176,19 @@ __device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSet
 // The exact pass tests the flagged bodies' pairs with their own radii.
 template <int LAY, int B_>
 __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, int nsets, unsigned long long& near) {
+                                            const LdsSets& L, int nsets, unsigned scored,
+                                            unsigned long long& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
   float ux[8], uy[8], uz[8], E[8];
   const float rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
 #pragma nounroll
   for (int si = 0; si < nsets; ++si) {
+    if (!((scored >> si) & 1u)) continue;  // a set this wave dropped (learned distance)
     const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, L.set_k0[si], L.set_n[si], 3.0e38f);
     near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
   }
-  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, nsets, near);
+  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, nsets, scored, near);
 }
 
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
@@ -343,26 +345,36 @@ __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, cons
 }
 
 // ---------------------------------------------------------------------------
-template <int LAY, bool DBG, int SURM>
-__global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__ arms,
-                                                   const Params* __restrict__ Pp,
-                                                   const StepState* __restrict__ ssp,
-                                                   const Item* __restrict__ items,
-                                                   const float* __restrict__ mu_all,
-                                                   const float* __restrict__ state,
-                                                   const float* __restrict__ goal,
-                                                   const float* __restrict__ goalR,
-                                                   const float* __restrict__ obs,
-                                                   const float* __restrict__ plan_read,
-                                                   RolloutArgs A) {
+// Work item = (arm, block of WPB x 64 rollouts, horizon tile); one workgroup
+// of WPB waves per item, lane = rollout.  The WPB waves share one LDS copy of
+// the sets staged at each rollout step (obstacles and neighbour plans), so a
+// step's staging is done once per WPB waves; every arm's padded rollout
+// count is a multiple of 64 x WPB (the host only picks such WPB), so no wave
+// of an item lies past the arm's padded rollouts.
+template <int LAY, bool DBG, int SURM, int WPB>
+__global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __restrict__ arms,
+                                                         const Params* __restrict__ Pp,
+                                                         const StepState* __restrict__ ssp,
+                                                         const Item* __restrict__ items,
+                                                         const float* __restrict__ mu_all,
+                                                         const float* __restrict__ state,
+                                                         const float* __restrict__ goal,
+                                                         const float* __restrict__ goalR,
+                                                         const float* __restrict__ obs,
+                                                         const float* __restrict__ plan_read,
+                                                         RolloutArgs A) {
   __shared__ LdsSets L;
-  const int lane = threadIdx.x;
+  // learned distance: the waves' drop masks over the neighbour table at the
+  // current step (bit i: every rollout of the wave predicted far from i)
+  __shared__ unsigned s_wdrop[WPB];
+  constexpr int kThreads = kWave * WPB;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *Pp;
   const StepState& SS = *ssp;
   const uint32_t t = SS.t;
   const int n_obs = SS.n_obs;
   // Obstacles are the same for every item of this launch.
-  for (int o = lane; o < n_obs; o += kWave)
+  for (int o = tid; o < n_obs; o += kThreads)
     stage_sphere(L, o, reinterpret_cast<const float4*>(obs)[o], P.buf_env);
 
   for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) {
@@ -370,13 +382,15 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
     const int a = item.arm;
     const DevArm* __restrict__ arm = arms + a;
     const int N = arm->N, H = arm->H;
-    const int n = item.block * kWave + lane;
+    const int n = item.block * kThreads + tid;
     const bool live = n < N;
     const float* __restrict__ mu = mu_all + (size_t)a * P.Hmax * 7;
     float* __restrict__ eps = A.eps + arm->eps_off;
     const int Npad = arm->Npad;
     __syncthreads();
-    L.slot[lane] = reinterpret_cast<const float4*>(arm->slot)[lane];
+    if (tid < kWave) L.slot[tid] = reinterpret_cast<const float4*>(arm->slot)[tid];
+    if (SURM && tid == 0)
+      for (int c2 = 0; c2 < 5; ++c2) L.sur[c2] = 0u;
     float q[8], qd[8];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
@@ -407,8 +421,6 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
     const int nnb = SS.nb_count[a];
     unsigned long long pairs = 0;
     unsigned set_passes = 0, set_refines = 0, self_refines = 0;
-    if (SURM && lane == 0)
-      for (int c2 = 0; c2 < 5; ++c2) L.sur[c2] = 0u;
     for (int h = item.h0; h < item.h1; ++h) {
       float z[8];
       if (A.eps_in) {
@@ -431,52 +443,73 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
       }
       Chain C;
       chain_angles(C, arm, q);
+      // Learned distance: a neighbour is dropped for this wave at step h
+      // when every rollout of the wave is predicted beyond the margin.  The
+      // masks go to LDS before the barrier below (the previous step's
+      // staging, their last reader, finished at the barrier after it).
+      unsigned wdrop = 0u;
+      if (SURM) {
+        for (int i = 0; i < nnb; ++i) {
+          const Nb nb = SS.nb[a][i];
+          if (h >= nb.H) continue;
+          const bool sk = A.skip[(((size_t)a * P.A + nb.arm) * P.Hmax + h) * P.Nmax + n] != 0;
+          if (__ballot(sk) == ~0ull) wdrop |= 1u << i;
+        }
+        if (lane == 0) s_wdrop[wv] = wdrop;
+      }
 
       // Stage the sets scored at step h: obstacles (set 0) and every
       // published neighbour plan that reaches this step (Sec. IV-C: the
-      // shorter of the two horizons applies).
+      // shorter of the two horizons applies).  A neighbour dropped by every
+      // wave of the item is not staged in learned mode (SURM 1); the audit
+      // (SURM 2) stages it and marks it for the waves that dropped it.
       __syncthreads();
       int nsets = 0;
       if (n_obs > 0) {
-        if (lane == 0) {
+        if (tid == 0) {
           L.set_k0[0] = 0;
           L.set_n[0] = n_obs;
-          L.set_drop[0] = 0;
           L.set_buf[0] = P.buf_env;
           L.set_wt[0] = P.w_coll;
         }
         nsets = 1;
       }
+      unsigned wskip = 0u;  // bit si: set si dropped for this wave
       {
         int off = kMaxObs;
         for (int i = 0; i < nnb; ++i) {
           const Nb nb = SS.nb[a][i];
           if (h >= nb.H) continue;
-          // Learned distance: the neighbour is dropped from this step's sets
-          // when every rollout of the wave is predicted beyond the margin
-          // (SURM 1); the audit (SURM 2) keeps it and marks it.
-          bool dropped = false;
+          bool wd = false;
           if (SURM) {
-            const bool sk = A.skip[(((size_t)a * P.A + nb.arm) * P.Hmax + h) * P.Nmax + n] != 0;
-            dropped = __ballot(sk) == ~0ull;
-            if (dropped && lane == 0) L.sur[2] += 1u;
-            if (SURM == 1 && dropped) continue;
+            wd = ((wdrop >> i) & 1u) != 0u;
+            bool all = true;
+#pragma unroll
+            for (int w = 0; w < WPB; ++w) all = all && ((s_wdrop[w] >> i) & 1u) != 0u;
+            if (wd && lane == 0) {
+              if (WPB == 1) L.sur[2] += 1u;
+              else atomicAdd(&L.sur[2], 1u);
+            }
+            if (SURM == 1 && all) continue;
           }
           const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
-          for (int s = lane; s < nb.S; s += kWave) stage_sphere(L, off + s, src[s], P.buf_dyn);
-          if (lane == 0) {
+          for (int s2 = tid; s2 < nb.S; s2 += kThreads) stage_sphere(L, off + s2, src[s2], P.buf_dyn);
+          if (tid == 0) {
             L.set_k0[nsets] = off;
             L.set_n[nsets] = nb.S;
-            L.set_drop[nsets] = dropped ? 1 : 0;
             L.set_buf[nsets] = P.buf_dyn;
             L.set_wt[nsets] = P.w_dyn * nb.alpha;
           }
-          if (DBG) pairs += (unsigned long long)arm->S * (unsigned long long)nb.S;
+          if (wd) wskip |= 1u << nsets;
+          if (DBG && !(SURM == 1 && wd)) pairs += (unsigned long long)arm->S * (unsigned long long)nb.S;
           ++nsets;
           off += nb.S;
         }
       }
       __syncthreads();
+      // Sets the wave scores: in learned mode the ones it did not drop; the
+      // audit scores every set and zeroes the dropped ones' hinge.
+      const unsigned wscored = SURM == 1 ? ~wskip : ~0u;
 
       // Goal pose (Eq. 5, C_pose) at the end-effector point of the last link.
       float c;
@@ -520,10 +553,11 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
       if (nsets > 0) {
         Frame W;
         frame_base(W, arm);
-        sets_filter<LAY, 0>(W, arm, C, L, nsets, near_all);
+        sets_filter<LAY, 0>(W, arm, C, L, nsets, wscored, near_all);
       }
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
+        if (!((wscored >> si) & 1u)) continue;
         const int k0 = L.set_k0[si], K = L.set_n[si];
         const unsigned nearb = (unsigned)(near_all >> (8 * si)) & 0xFFu;
         const bool near = nearb != 0;
@@ -535,13 +569,18 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
           frame_base(W, arm);
           set_refine<LAY, 0>(W, arm, C, L, k0, K, nearb, best);
           float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
-          if (SURM == 2 && L.set_drop[si]) {
+          if (SURM == 2 && ((wskip >> si) & 1u)) {
             const bool hit = live && near;
             const unsigned m1 = (unsigned)__popcll(__ballot(hit && best < (double)L.set_buf[si]));
             const unsigned m2 = (unsigned)__popcll(__ballot(hit && best < 0.0));
             if (lane == 0) {
-              L.sur[3] += m1;
-              L.sur[4] += m2;
+              if (WPB == 1) {
+                L.sur[3] += m1;
+                L.sur[4] += m2;
+              } else {
+                atomicAdd(&L.sur[3], m1);
+                atomicAdd(&L.sur[4], m2);
+              }
             }
             hv = 0.f;
           }
@@ -549,7 +588,7 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
         }
       }
       // The stage cost goes out per step; Eq. 1's discounted sum is formed in
-      // k_softmax over h in a fixed order, so it does not depend on the tiling.
+      // k_total over h in a fixed order, so it does not depend on the tiling.
       if (live) A.partial[((size_t)a * kMaxH + h) * P.Nmax + n] = c;
 
       if (DBG && live) {
@@ -578,11 +617,14 @@ __global__ __launch_bounds__(kWave, 2) void k_rollout(const DevArm* __restrict__
       }
     }
     if (DBG && live) atomicAdd(A.dbg_pairs + 4 * a, pairs);
-    if (SURM && lane == 0) {
-      // one atomic per counter and item
+    if (SURM) {
+      // one atomic per counter and item, after every wave's last count
+      __syncthreads();
+      if (tid == 0) {
 #pragma unroll
-      for (int c2 = 0; c2 < 5; ++c2)
-        if (L.sur[c2]) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)L.sur[c2]);
+        for (int c2 = 0; c2 < 5; ++c2)
+          if (L.sur[c2]) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)L.sur[c2]);
+      }
     }
     if (DBG && lane == 0) {
       atomicAdd(A.dbg_pairs + 4 * a + 1, (unsigned long long)set_passes);
@@ -765,7 +807,6 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   if (tid == 0) A.argmin[a] = nstar;
 }
 
-// Eq. 3 (weighted mean) and Eq. 4 (mean update), one block per (arm, step).
 // Manipulability term of Eq. 5 for every rollout step: the rollout's joints
 // (the same noise and integration as the rollout kernel), the end-effector
 // point by the same walking frame, the geometric Jacobian (column k = (z_k x
@@ -873,56 +914,116 @@ __global__ __launch_bounds__(kWave) void k_noise(const DevArm* __restrict__ arms
   }
 }
 
+// Eq. 3 (weighted mean, and with covariance adaptation the weighted second
+// moments) and Eq. 4 (updates), split over (chunk of 1024 rollouts, step,
+// arm) so that the noise stream is read by enough workgroups to keep HBM
+// busy.  Each thread reads four consecutive rollouts of the 7 noise rows
+// (16-byte loads), the block reduces its sums with wave shuffles and then
+// across its 4 waves in a fixed order and stores them as the chunk's
+// partial; the block that finishes last for its (arm, step) adds the
+// partials in chunk order, so the result does not depend on which block
+// came last, applies the updates and resets the counter.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
-  // 7 weighted noise sums (Eq. 3, first half) and, with covariance
-  // adaptation, the 28 weighted second moments of the noise.
-  __shared__ float s_r[7 + kTri][256];
-  const int a = blockIdx.y, h = blockIdx.x, tid = threadIdx.x;
+  __shared__ float s_w[4][kWmeanSums];
+  __shared__ float s_tot[kWmeanSums];
+  __shared__ int s_last;
+  const int chunk = blockIdx.x, h = blockIdx.y, a = blockIdx.z, tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
-  if (h >= arm->H) return;
   const int N = arm->N, Npad = arm->Npad;
+  const int nchunks = (N + kWmeanChunk - 1) / kWmeanChunk;
+  if (h >= arm->H || chunk >= nchunks) return;
   const bool cov = P.cov != 0;
-  const float* w = A.w + (size_t)a * P.Nmax;
-  const float* eps = A.eps + arm->eps_off + (size_t)h * 7 * Npad;
+  const int nsum = cov ? kWmeanSums : 7;
+  const int n0 = chunk * kWmeanChunk + 4 * tid;
   float s[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float s2[kTri];
 #pragma unroll
   for (int e = 0; e < kTri; ++e) s2[e] = 0.f;
-  for (int n = tid; n < N; n += blockDim.x) {
-    const float wn = w[n];
-    float en[7];
+  if (n0 < N) {
+    // Npad is a multiple of 64 and the arm's block starts 64-float aligned,
+    // so the four rollouts n0..n0+3 (< Npad) form one aligned 16-byte load;
+    // rollouts from N on carry no weight.
+    float4 w4 = *reinterpret_cast<const float4*>(A.w + (size_t)a * P.Nmax + n0);
+    float wn[4] = {w4.x, w4.y, w4.z, w4.w};
+    float en[4][7];
+    const float* eps = A.eps + arm->eps_off + (size_t)h * 7 * Npad + n0;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-      en[j] = eps[(size_t)j * Npad + n];
-      s[j] = fmaf_(wn, en[j], s[j]);
+      const float4 e4 = *reinterpret_cast<const float4*>(eps + (size_t)j * Npad);
+      en[0][j] = e4.x;
+      en[1][j] = e4.y;
+      en[2][j] = e4.z;
+      en[3][j] = e4.w;
     }
-    if (cov) {
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        const float we = wn * en[j];
+    for (int r = 0; r < 4; ++r) {
+      if (n0 + r >= N) {
+        wn[r] = 0.f;
 #pragma unroll
-        for (int m = 0; m <= j; ++m) s2[tri7(j, m)] = fmaf_(we, en[m], s2[tri7(j, m)]);
+        for (int j = 0; j < 7; ++j) en[r][j] = 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 7; ++j) s[j] = fmaf_(wn[r], en[r][j], s[j]);
+      if (cov) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const float we = wn[r] * en[r][j];
+#pragma unroll
+          for (int m = 0; m <= j; ++m) s2[tri7(j, m)] = fmaf_(we, en[r][m], s2[tri7(j, m)]);
+        }
       }
     }
   }
-  const int nsum = cov ? 7 + kTri : 7;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) s_r[j][tid] = s[j];
+  for (int j = 0; j < 7; ++j) {
+    const float v = wave_sum(s[j]);
+    if (lane == 0) s_w[wv][j] = v;
+  }
   if (cov) {
 #pragma unroll
-    for (int e = 0; e < kTri; ++e) s_r[7 + e][tid] = s2[e];
+    for (int e = 0; e < kTri; ++e) {
+      const float v = wave_sum(s2[e]);
+      if (lane == 0) s_w[wv][7 + e] = v;
+    }
   }
   __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (tid < st)
-      for (int j = 0; j < nsum; ++j) s_r[j][tid] += s_r[j][tid + st];
-    __syncthreads();
+  float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums;
+  // Partials cross workgroups (and XCDs, whose L2s are not coherent with
+  // each other): device-scope atomic stores and loads, ordered by a release
+  // fence before the count and an acquire fence after it.
+  if (tid < nsum) {
+    const float v = ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
+    __hip_atomic_store(part + (size_t)chunk * kWmeanSums + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned done = atomicAdd(A.wcnt + a * P.Hmax + h, 1u);
+    s_last = done == (unsigned)(nchunks - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (tid < nsum) {
+    float t = __hip_atomic_load(part + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int c2 = 1; c2 < nchunks; ++c2)
+      t += __hip_atomic_load(part + (size_t)c2 * kWmeanSums + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_tot[tid] = t;
+  }
+  if (tid == 0) A.wcnt[a * P.Hmax + h] = 0u;  // every chunk of this pass has counted
+  __syncthreads();
   if (tid < 7) {
     float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + tid;
     const float m0 = *mu;
-    const float mt = m0 + s_r[tid][0];
+    const float mt = m0 + s_tot[tid];
     *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
   }
   if (cov && tid == 64) {
@@ -932,10 +1033,10 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
     float* sg = A.sig + ((size_t)a * P.Hmax + h) * kTri;
     float* L = A.chol + ((size_t)a * P.Hmax + h) * kTri;
     float eb[7], S[kTri], Lc[kTri];
-    for (int j = 0; j < 7; ++j) eb[j] = s_r[j][0];
+    for (int j = 0; j < 7; ++j) eb[j] = s_tot[j];
     for (int j = 0; j < 7; ++j)
       for (int m = 0; m <= j; ++m) {
-        const float st = s_r[7 + tri7(j, m)][0] - eb[j] * eb[m];
+        const float st = s_tot[7 + tri7(j, m)] - eb[j] * eb[m];
         S[tri7(j, m)] = fmaf_(P.alpha_sigma, st, (1.0f - P.alpha_sigma) * sg[tri7(j, m)]);
       }
     const float f2 = P.sigma_floor * P.sigma_floor;
@@ -1065,24 +1166,35 @@ __global__ void k_set_meta(BoardMeta* meta, int arm, float dist, int valid) {
 
 // ---------------------------------------------------------------------------
 // Launchers.
-template <int LAY, bool DBG, int SURM>
+template <int LAY, bool DBG, int SURM, int WPB>
 static hipError_t launch_rollout_t(const RolloutArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_rollout<LAY, DBG, SURM>), dim3(grid), dim3(kWave), 0, s, A.arms, A.P, A.ss, A.items,
-                     A.mu, A.state, A.goal, A.goalR, A.obs, A.plan_read, A);
+  hipLaunchKernelGGL((k_rollout<LAY, DBG, SURM, WPB>), dim3(grid), dim3(kWave * WPB), 0, s, A.arms, A.P, A.ss,
+                     A.items, A.mu, A.state, A.goal, A.goalR, A.obs, A.plan_read, A);
   return hipGetLastError();
 }
 
+template <int LAY, bool DBG, int SURM>
+static hipError_t launch_rollout_w(const RolloutArgs& A, int waves, int grid, hipStream_t s) {
+  switch (waves) {
+    case 1: return launch_rollout_t<LAY, DBG, SURM, 1>(A, grid, s);
+    case 2: return launch_rollout_t<LAY, DBG, SURM, 2>(A, grid, s);
+    case 4: return launch_rollout_t<LAY, DBG, SURM, 4>(A, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int LAY, bool DBG>
-static hipError_t launch_rollout_s(const RolloutArgs& A, int grid, hipStream_t s) {
-  if (!A.skip) return launch_rollout_t<LAY, DBG, 0>(A, grid, s);
-  return A.audit ? launch_rollout_t<LAY, DBG, 2>(A, grid, s) : launch_rollout_t<LAY, DBG, 1>(A, grid, s);
+static hipError_t launch_rollout_s(const RolloutArgs& A, int waves, int grid, hipStream_t s) {
+  if (!A.skip) return launch_rollout_w<LAY, DBG, 0>(A, waves, grid, s);
+  return A.audit ? launch_rollout_w<LAY, DBG, 2>(A, waves, grid, s) : launch_rollout_w<LAY, DBG, 1>(A, waves, grid, s);
 }
 
 // The learned-distance variants (A.skip set; audited or not) are separate
 // instantiations so that the exact kernel carries none of their bookkeeping.
-hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s) {
-  if (layout == 0) return debug ? launch_rollout_s<0, true>(A, grid, s) : launch_rollout_s<0, false>(A, grid, s);
-  return debug ? launch_rollout_s<1, true>(A, grid, s) : launch_rollout_s<1, false>(A, grid, s);
+hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s) {
+  if (layout == 0)
+    return debug ? launch_rollout_s<0, true>(A, waves, grid, s) : launch_rollout_s<0, false>(A, waves, grid, s);
+  return debug ? launch_rollout_s<1, true>(A, waves, grid, s) : launch_rollout_s<1, false>(A, waves, grid, s);
 }
 
 hipError_t launch_sense(const SenseArgs& A, hipStream_t s) {
@@ -1098,8 +1210,9 @@ hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_wmean, dim3(hmax, n_arms), dim3(256), 0, s, A);
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s) {
+  const int chunks = (nmax + kWmeanChunk - 1) / kWmeanChunk;
+  hipLaunchKernelGGL(k_wmean, dim3(chunks, hmax, n_arms), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 

@@ -78,7 +78,15 @@ struct ReduceArgs {
   BoardMeta* meta;
   float* sig;                  // [A][Hmax][28] packed lower triangles (covariance adaptation)
   float* chol;                 // their Cholesky factors
+  float* wpart;                // weighted-mean partial sums [A][Hmax][kWmeanMaxChunks][7 + 28]
+  unsigned* wcnt;              // chunks finished per (arm, step) [A][Hmax]; back to 0 after each pass
 };
+
+// The weighted mean (Eq. 3) splits every (arm, step) over chunks of
+// kWmeanChunk rollouts (256 threads x 4 consecutive rollouts).
+constexpr int kWmeanChunk = 1024;
+constexpr int kWmeanMaxChunks = 16;   // 16384 rollouts
+constexpr int kWmeanSums = 7 + 28;
 
 struct PublishArgs {
   const float* plan_write;
@@ -91,9 +99,11 @@ struct PublishArgs {
 };
 
 hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
-hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int grid, hipStream_t s);
+// waves: 64-rollout waves per workgroup (1, 2 or 4); every arm's padded
+// rollout count must be a multiple of 64 * waves.
+hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s);
 hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s);  // k_total, then k_softmax
-hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, hipStream_t s);
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s);
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
 // C_manip (Eq. 5) of every rollout step of iteration k: out [A][Hmax][Nmax].

@@ -273,24 +273,60 @@ def test_deterministic_repeat():
 
 
 def test_tiles_do_not_change_results():
-    _say("case: forced horizon tiles 1, 3, H give identical costs, weights, means and actions")
-    sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
+    """Every launch shape gives bitwise the same stage costs, totals,
+    weights, means and actions: horizon tiles 1, 3 and H, and 1, 2 or 4
+    waves (64, 128 or 256 rollouts) per workgroup sharing one staged copy of
+    the step's sets (rollout counts 256, 200, 512, 460: ragged last waves),
+    two steps with plan sharing so the neighbour sets are live."""
+    _say("case: forced launch shapes (waves per workgroup x horizon tile) give identical results")
+    sc = small_scene(3, n=[256, 200, 512, 460], h=[8, 12, 12, 16])
     res = []
-    for T in (1, 3, 16):
+    for W, T in ((1, 1), (1, 3), (1, 16), (2, 3), (2, 16), (4, 1), (4, 5), (4, 16)):
         ctl = native.Controller(sc.arms, sc.params)
-        ctl.set_tuning(0, T, 0)
+        ctl.set_tuning(64 * W, T, 0)
+        ctl.step(sc.state, sc.goal, sc.obstacles)
+        ctl.share_plans()
         ctl.debug_enable(True)
         u = ctl.step(sc.state, sc.goal, sc.obstacles).cpu().numpy()
         ctl.sync()
-        res.append((u, [[ctl.debug_get(k, a).cpu().numpy() for k in ("STAGE_COST", "COST", "WEIGHTS", "MEAN")]
+        res.append((u, [[ctl.debug_get(k, a).cpu().numpy() for k in ("STAGE_COST", "COST", "WEIGHTS", "MEAN", "PAIRS")]
                         for a in range(4)]))
-        assert ctl.tuning()[1] == T
+        assert ctl.tuning()[:2] == (64 * W, T)
         ctl.close()
     for u, r in res[1:]:
         np.testing.assert_array_equal(u, res[0][0])
         for a in range(4):
             for x, x0 in zip(r[a], res[0][1][a]):
                 np.testing.assert_array_equal(x, x0)
+    # a workgroup may not reach past an arm's padded rollouts
+    bad = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
+    ctl = native.Controller(bad.arms, bad.params)
+    with pytest.raises(native.MpcError) as e:
+        ctl.set_tuning(128, 0, 0)
+    assert e.value.code == native.MPC_EINVAL
+    with pytest.raises(native.MpcError) as e:
+        ctl.set_tuning(96, 0, 0)
+    assert e.value.code == native.MPC_EUNSUPPORTED
+    ctl.close()
+
+
+def test_tuner_choice_is_cached_per_shape():
+    """The tuner's launch shape is kept per problem shape and device: a second
+    context with the same shape starts from the same choice."""
+    _say("case: tuner cache, config 3 shape")
+    sc = small_scene(3, n=[256, 200, 512, 460], h=[8, 12, 12, 16])
+    shapes = []
+    for _ in range(2):
+        ctl = native.Controller(sc.arms, sc.params)
+        for _ in range(2):
+            ctl.step(sc.state, sc.goal, sc.obstacles)
+            ctl.share_plans()
+        ctl.sync()
+        shapes.append(ctl.tuning())
+        ctl.close()
+    _say(f"  tuned launch shapes {shapes}")
+    assert shapes[0] == shapes[1]
+    assert shapes[0][0] in (64, 128, 256)
 
 
 # ------------------------------------------------------------- edge cases

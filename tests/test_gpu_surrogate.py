@@ -480,3 +480,50 @@ def test_adam_matches_oracle_over_three_steps():
     with pytest.raises(native.MpcError):
         ctl.surrogate_adam(torch.from_numpy(g).cuda(), lr, b1, b2, eps, 0)
     ctl.close()
+
+
+def test_learned_drops_do_not_depend_on_waves_per_workgroup():
+    """With 2 or 4 waves per workgroup the waves of one workgroup share the
+    staged sets but drop neighbours each on their own 64 rollouts: learned
+    and audited stage costs, skip decisions and counters are bitwise those of
+    one wave per workgroup (a network thresholding one joint, so that waves
+    of one workgroup decide differently)."""
+    _say("case: collision mode 1, config 2 shape, 256 rollouts x 20 steps, 1 / 2 / 4 waves per workgroup")
+    sc = small_scene(2, n=256, h=20)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    ref = native.Controller(sc.arms, sc.params)
+    ref.step(sc.state, sc.goal, obst)
+    ref.share_plans()
+    ref.debug_enable(True)
+    ref.step(sc.state, sc.goal, obst)
+    ref.sync()
+    q0 = ref.debug_get("Q", 0).cpu().numpy().astype(np.float64)
+    ref.close()
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
+    f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
+    for audit in (False, True):
+        out = []
+        for W in (1, 2, 4):
+            ctl = native.Controller(sc.arms, sc.params)
+            ctl.set_surrogate_params(params)
+            ctl.set_collision_mode(1)
+            ctl.surrogate_audit(audit)
+            ctl.set_tuning(64 * W, 0, 0)
+            ctl.step(sc.state, sc.goal, obst)
+            ctl.share_plans()
+            ctl.debug_enable(True)
+            ctl.surrogate_stats(reset=True)
+            ctl.step(sc.state, sc.goal, obst)
+            ctl.sync()
+            out.append(([ctl.debug_get("STAGE_COST", a).cpu().numpy() for a in range(2)],
+                        [ctl.debug_get("SKIP", a).cpu().numpy() for a in range(2)], ctl.surrogate_stats()))
+            ctl.close()
+        _say(f"  audit={audit}: counters {[o[2] for o in out]}")
+        assert out[0][2]["waves_skipped"] > 0
+        for st, sk, cnt in out[1:]:
+            for a in range(2):
+                np.testing.assert_array_equal(st[a], out[0][0][a])
+                np.testing.assert_array_equal(sk[a], out[0][1][a])
+            assert cnt == out[0][2]
