@@ -196,12 +196,28 @@ def _oracle_window_step(args):
     return t0, time.time()
 
 
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs the OS reports, the
+    CPUs this process may use, and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
 def cpu_baseline(scene):
     """The FP64 oracle, as it stands, on the host cores, on bounded samples of
     one control step: (1) one thread on the first 320 rollouts of every arm;
     (2) the first 640 rollouts of every arm split over worker processes, one
-    per available core (at most 16), each running the unmodified oracle on a
-    disjoint rollout window; value = rollout-steps / wall time of (2)."""
+    per core this process may use, at most 16 (a one-GPU machine's CPU share),
+    each running the unmodified oracle on a disjoint rollout window; value =
+    rollout-steps / wall time of (2).  The host's CPU count and model are
+    recorded with it."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     window = 320
@@ -221,7 +237,7 @@ def cpu_baseline(scene):
             "sample": f"one control step of all 8 arms restricted to their first {N} of 4096 rollouts "
                       f"({rs} rollout-steps, FP64), split into {cores} rollout windows run by {cores} "
                       f"processes in {wall:.1f} s",
-            "single_thread": single}
+            "host": host_info(), "single_thread": single}
 
 
 def obstacle_track(scene, n):
@@ -231,6 +247,73 @@ def obstacle_track(scene, n):
         out.append(scene.obstacles.copy())
         scenes.move_obstacles(scene, float(scene.params["dt"]))
     return np.stack(out)
+
+
+# Closed-loop steps of each workload (BASELINE configs): config 1 is a
+# single control step, timed here over 200 independent repetitions.
+CONFIG_STEPS = {1: 200, 2: 200, 3: 500, 4: 1000, 5: 1000}
+
+
+def goal_schedule(scene, steps, goal_age=50):
+    """Goals of `steps` consecutive control steps, [steps][A][7]: each arm's
+    goal re-drawn every goal_age steps (one second at dt = 0.02 s, the
+    reaching task's time-out of Sec. V-A), staggered over the arms."""
+    A = scene.n_arms
+    rng = np.random.default_rng(scene.seed + 99)
+    age = np.arange(A) * (goal_age // A)
+    out = []
+    for _ in range(steps):
+        m = scenes.reset_goals(scene, rng, np.full(A, np.inf), age, max_age=goal_age)
+        age = np.where(m, 0, age + 1)
+        out.append(scene.goal.copy())
+    return np.stack(out)
+
+
+def latency_leg(config, steps, dev, stream, params=None, warmup=10):
+    """The workload's own closed loop (Publish + mpc_step + plant) for
+    `steps` control steps after `warmup`, goals re-drawn every second and
+    obstacles moving, every input resident in HBM (goal and obstacle
+    sequences uploaded beforehand): per-step HIP-event latency p50 / p99 and
+    the rollout-steps/s of the mean step.  params: learned distance on."""
+    import torch
+    from paper_2602_10114_amd import native
+    sc = scenes.make_scene(config, collision_mode=0)
+    goals = torch.as_tensor(goal_schedule(scenes.make_scene(config, collision_mode=0), warmup + steps), device=dev)
+    obs = None
+    if sc.obstacles.shape[0]:
+        obs = torch.as_tensor(obstacle_track(scenes.make_scene(config, collision_mode=0), warmup + steps), device=dev)
+    ctl = native.Controller(sc.arms, sc.params, stream=stream)
+    if params is not None:
+        ctl.set_surrogate_params(params)
+        ctl.set_collision_mode(1)
+    with torch.cuda.stream(stream):
+        state = torch.as_tensor(sc.state, device=dev).contiguous()
+        u = torch.zeros((sc.n_arms, 7), dtype=torch.float32, device=dev)
+
+        def one(k):
+            ctl.share_plans()
+            ctl.step(state, goals[k], obs[k] if obs is not None else None, u_out=u)
+            ctl.sim_execute(state, u)
+
+        for k in range(warmup):
+            one(k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for i in range(steps):
+            ev[i][0].record(stream)
+            one(warmup + i)
+            ev[i][1].record(stream)
+        stream.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    tuning = list(ctl.tuning())
+    stats = ctl.surrogate_stats() if params is not None else None
+    ctl.close()
+    out = {"config": config, "mode": "learned" if params is not None else "exact", "steps": steps,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+           "rollout_steps_per_s": sc.rollout_steps() / (lat.mean() * 1e-3), "tuning": tuning}
+    if stats is not None:
+        out["exact_checks_skipped"] = stats["waves_skipped"] * 64 / max(stats["queries"], 1)
+    return out
 
 
 def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
@@ -320,12 +403,18 @@ def audit_run(scene, params, steps, dev, goal_age=50):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctl.surrogate_stats()
-    gap = min(float(ctl.pair_distance(i, j, qs[:, i].contiguous(), qs[:, j].contiguous()).min())
-              for i in range(A) for j in range(i + 1, A))
+    gap, first = np.inf, None
+    for i in range(A):
+        for j in range(i + 1, A):
+            gij = ctl.pair_distance(i, j, qs[:, i].contiguous(), qs[:, j].contiguous()).cpu().numpy()
+            gap = min(gap, float(gij.min()))
+            neg = np.nonzero(gij < 0)[0]
+            if neg.size and (first is None or neg[0] < first["step"]):
+                first = {"step": int(neg[0]), "arms": [i, j], "gap_m": float(gij[neg[0]])}
     ctl.close()
     return {"steps": steps, "queries": st["queries"], "predicted_far": st["predicted_far"],
             "misses_below_buffer": st["misses"], "missed_collisions": st["missed_collisions"],
-            "executed_min_arm_gap_m": gap, "seconds": wall}
+            "executed_min_arm_gap_m": gap, "first_executed_contact": first, "seconds": wall}
 
 
 def ablation_run(variant, steps, dev, seed=None):
@@ -389,6 +478,87 @@ def ablation(steps, seeds, dev):
     return out
 
 
+def fig1_run(variant, steps, dev, seed, goal=(0.0, 0.0, 0.35)):
+    """The livelock scenario of Fig. 1 (Sec. IV-B): two arms facing each
+    other 0.8 m apart reach for the same goal point between them, tool
+    pointing down.  An arm that arrives (5 cm) then leaves for a waiting
+    point beside its own base, which frees the goal for the other.  Per
+    step: each arm's distance to its goal; "withdrawals" are steps at which
+    both arms, both more than 10 cm from the shared goal, move away from it
+    by more than 1 mm (the retreat of Fig. 1 D.1), counted as episodes of
+    consecutive such steps; "stalled" steps have both arms slow (joint speed
+    below 0.05 rad/s) and away from their goals."""
+    import torch
+    from paper_2602_10114_amd import native
+    over = {"M": {}, "M_tau": {"tau": 0.0}, "S_d": {"plan_mode": 1}}[variant]
+    sc = scenes.make_scene(2, seed=seed, collision_mode=0, **over)
+    down = np.array([0.0, 1.0, 0.0, 0.0], np.float32)          # w, x, y, z: tool along -z
+    shared = np.concatenate([np.array(goal, np.float32), down])
+    wait = [np.concatenate([np.array([-0.35, 0.35, 0.5], np.float32), down]),
+            np.concatenate([np.array([0.35, -0.35, 0.5], np.float32), down])]
+    goals = np.stack([shared, shared]).astype(np.float32)
+    ctl = native.Controller(sc.arms, sc.params)
+    state = torch.as_tensor(sc.state, device=dev).contiguous()
+    g = torch.as_tensor(goals, device=dev).contiguous()
+    u = torch.zeros((2, 7), dtype=torch.float32, device=dev)
+    reached = [None, None]
+    prev = None
+    withdraw_steps = withdraw_episodes = stalled = 0
+    in_episode = False
+    qs = torch.empty((steps, 2, 7), dtype=torch.float32, device=dev)
+    for k in range(steps):
+        ctl.share_plans()
+        ctl.step(state, g, None, u_out=u)
+        ctl.sim_execute(state, u)
+        qs[k].copy_(state[:, :, 0])
+        dist = np.array([float(ctl.debug_get("DIST", a)[0]) for a in range(2)])
+        speed = state[:, :, 1].abs().max(dim=1).values.cpu().numpy()
+        to_shared = [dist[a] if reached[a] is None else np.inf for a in range(2)]
+        if prev is not None and reached[0] is None and reached[1] is None:
+            back = all(to_shared[a] > 0.10 and dist[a] > prev[a] + 1e-3 for a in range(2))
+            withdraw_steps += back
+            withdraw_episodes += back and not in_episode
+            in_episode = back
+        if np.all((speed < 0.05) & (dist > 0.10)):
+            stalled += 1
+        for a in range(2):
+            if reached[a] is None and dist[a] < 0.05:
+                reached[a] = k + 1
+                goals[a] = wait[a]
+                g.copy_(torch.as_tensor(goals))
+        prev = dist
+        if reached[0] is not None and reached[1] is not None:
+            break
+    gaps = ctl.pair_distance(0, 1, qs[:k + 1, 0].contiguous(), qs[:k + 1, 1].contiguous())
+    ctl.close()
+    order = sorted(r for r in reached if r is not None)
+    return {"first_arrival": order[0] if order else None, "both_arrived": order[1] if len(order) == 2 else None,
+            "withdraw_steps": withdraw_steps, "withdraw_episodes": withdraw_episodes, "stalled_steps": stalled,
+            "executed_min_arm_gap_m": float(gaps[1:].min()), "steps_run": k + 1}
+
+
+def fig1(steps, seeds, dev):
+    """Fig. 1's shared-goal scenario over several scene seeds (start poses,
+    noise) for MR-STORM (tau = 3), M_tau (tau = 0) and S_d (no plans)."""
+    base = scenes.make_scene(2).seed
+    seed_list = [base + 100 * i for i in range(seeds)]
+    out = {"seeds": seed_list, "max_steps": steps}
+    for v in ("M", "M_tau", "S_d"):
+        runs = [fig1_run(v, steps, dev, sd) for sd in seed_list]
+        out[v] = {"runs": runs,
+                  "both_arrived": sum(r["both_arrived"] is not None for r in runs),
+                  "mean_first_arrival": float(np.mean([r["first_arrival"] for r in runs if r["first_arrival"]]))
+                  if any(r["first_arrival"] for r in runs) else None,
+                  "withdraw_episodes": int(sum(r["withdraw_episodes"] for r in runs)),
+                  "withdraw_steps": int(sum(r["withdraw_steps"] for r in runs)),
+                  "stalled_steps": int(sum(r["stalled_steps"] for r in runs)),
+                  "executed_min_arm_gap_m": min(r["executed_min_arm_gap_m"] for r in runs)}
+    m, mt = out["M"], out["M_tau"]
+    out["priority_resolves_livelock"] = bool(m["withdraw_episodes"] < mt["withdraw_episodes"] and
+                                             m["both_arrived"] >= mt["both_arrived"])
+    return out
+
+
 def train_surrogate(scene):
     from paper_2602_10114_amd import native
     ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
@@ -406,7 +576,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-distance legs")
     ap.add_argument("--audit-steps", type=int, default=10000,
-                    help="closed-loop steps of the audited learned-distance run on the 4-arm scene (0: skip)")
+                    help="closed-loop steps of the audited learned-distance runs on the 8-arm and 4-arm scenes "
+                         "(0: skip)")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the per-workload latency legs (each workload's own closed-loop step count)")
+    ap.add_argument("--fig1-steps", type=int, default=600,
+                    help="step limit of each run of the Fig. 1 shared-goal scenario (0: skip)")
+    ap.add_argument("--fig1-seeds", type=int, default=5)
     ap.add_argument("--ablation-steps", type=int, default=1500,
                     help="closed-loop steps of each variant of the two-arm ablation (0: skip)")
     ap.add_argument("--ablation-seeds", type=int, default=5,
@@ -498,6 +674,18 @@ def main():
             "recipe": native.TRAINING_RECIPE,
         }
         if args.audit_steps > 0:
+            # The same 8-arm workload, audited: goals re-drawn every second so
+            # the arms keep crossing, every dropped check also computed exactly.
+            aud5 = audit_run(scenes.make_scene(5, collision_mode=0), params, args.audit_steps, dev)
+            aud5_exact = audit_run(scenes.make_scene(5, collision_mode=0), None, args.audit_steps, dev)
+            out["surrogate"]["audit"] = aud5
+            out["surrogate"]["audited_dynamics"] = {
+                "learned_s": aud5["seconds"], "exact_s": aud5_exact["seconds"],
+                "exact_executed_min_arm_gap_m": aud5_exact["executed_min_arm_gap_m"],
+                "exact_first_executed_contact": aud5_exact["first_executed_contact"]}
+        if not args.no_latency:
+            out["surrogate"]["latency_1000"] = latency_leg(5, CONFIG_STEPS[5], dev, stream, params=params)
+        if args.audit_steps > 0:
             sc4 = scenes.make_scene(4, collision_mode=0)
             p4, rep4 = train_surrogate(scenes.make_scene(4, collision_mode=0))
             ctl4 = native.Controller(sc4.arms, {**sc4.params, "collision_mode": 0}, stream=stream)
@@ -516,9 +704,18 @@ def main():
                 "exact_checks_skipped": st4["waves_skipped"] * 64 / max(st4["queries"], 1),
                 "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep4.items()},
                 "audit": aud,
+                "audited_dynamics": {"learned_s": aud["seconds"], "exact_s": aud_exact["seconds"]},
                 "exact_same_goals": {"executed_min_arm_gap_m": aud_exact["executed_min_arm_gap_m"],
+                                     "first_executed_contact": aud_exact["first_executed_contact"],
                                      "seconds": aud_exact["seconds"]},
             }
+            if not args.no_latency:
+                out["surrogate_4arm"]["latency_1000"] = latency_leg(4, CONFIG_STEPS[4], dev, stream, params=p4)
+    if not args.no_latency:
+        # Every workload's own closed loop (exact distances): configs 1-5.
+        out["latency"] = {f"config{c}": latency_leg(c, CONFIG_STEPS[c], dev, stream) for c in (1, 2, 3, 4, 5)}
+    if args.fig1_steps > 0:
+        out["fig1_shared_goal"] = fig1(args.fig1_steps, args.fig1_seeds, dev)
     if args.ablation_steps > 0:
         out["ablation_2arm"] = ablation(args.ablation_steps, args.ablation_seeds, dev)
     if args.calibrate_copy:

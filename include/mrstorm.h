@@ -165,7 +165,8 @@ enum {
                               passes over obstacle/neighbour sets, of exact (FP64) passes
                               over such sets, and of exact self-collision passes */
   MPC_DBG_PRED = 13,       /* float [n_arms][horizon][n_rollouts]: learned-distance
-                              prediction against each neighbour (collision mode 1) */
+                              prediction against each neighbour (collision mode 1) for the
+                              live queries of the last iteration; 0 elsewhere */
   MPC_DBG_SIGMA = 14,      /* float [horizon][28]: sampling covariance Sigma_h (Eqs. 3-4), packed
                               lower triangle, row j holds (j, 0..j); always available */
   MPC_DBG_CHOL = 15,       /* float [horizon][28]: its Cholesky factor L_h (eps = L_h z); always available */

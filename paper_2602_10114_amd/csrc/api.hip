@@ -79,7 +79,6 @@ struct mpc_ctx {
   float* sig = nullptr;                // [A][Hmax][28] adapted covariances (packed lower triangles)
   float* chol = nullptr;               // their Cholesky factors
   float* wpart = nullptr;              // weighted-mean chunk partials [A][Hmax][kWmeanMaxChunks][35]
-  unsigned* wcnt = nullptr;            // chunks finished per (arm, step) [A][Hmax]
   float* partial = nullptr;
   float* cost = nullptr;
   float* w = nullptr;
@@ -125,8 +124,9 @@ struct mpc_ctx {
   float* sur_g = nullptr;              // gradient
   uint16_t* sur_p16 = nullptr;         // bfloat16 copy
   uint16_t* sur_F = nullptr;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16)
-  uint8_t* sur_skip = nullptr;         // [A][A][Hmax][Nmax]
-  float* sur_pred = nullptr;           // optional predictions (debug capture)
+  uint8_t* sur_skip = nullptr;         // decisions of live queries [A][A][Hmax][Nmax] (debug capture)
+  float* sur_pred = nullptr;           // their predictions (debug capture)
+  int* sur_base = nullptr;             // first inference descriptor of each (arm, neighbour) [A][A]
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
   float* sur_y = nullptr;              // predictions in descriptor order [items][32]
   bool sur_bufs = false;               // every learned-distance step buffer allocated
@@ -358,7 +358,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
       (rc = dalloc(c, &c->planq[0], A * H * 7)) || (rc = dalloc(c, &c->planq[1], A * H * 7)) ||
       (rc = dalloc(c, &c->u_stage, A * 7)) || (rc = dalloc(c, &c->argmin, A)) ||
       (rc = dalloc(c, &c->sig, A * H * kTri)) || (rc = dalloc(c, &c->chol, A * H * kTri)) ||
-      (rc = dalloc(c, &c->wpart, A * H * kWmeanMaxChunks * kWmeanSums)) || (rc = dalloc(c, &c->wcnt, A * H)) ||
+      (rc = dalloc(c, &c->wpart, A * H * kWmeanMaxChunks * kWmeanSums)) ||
       (p->w_manip > 0.f && (rc = dalloc(c, &c->manip, A * H * N)))) {
     g_last_error = c->err;
     mpc_destroy(c);
@@ -494,9 +494,16 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.dbg_sph = c->dbg_sph;
   R.dbg_stage = c->dbg_stage;
   R.dbg_pairs = c->dbg_pairs;
-  R.skip = c->collision_mode == 1 ? c->sur_skip : nullptr;
+  R.learned = c->collision_mode == 1 ? 1 : 0;
   R.audit = c->sur_audit ? 1 : 0;
+  R.sur_y = c->sur_y;
+  R.sur_base = c->sur_base;
+  R.sur_F = c->sur_F;
+  R.sur_rec = c->sur_nbrec;
+  R.sur_margin = c->hmodel.margin;
   R.sur_counts = c->sur_counts;
+  R.dbg_pred = c->sur_pred;
+  R.dbg_skip = c->sur_skip;
   R.eps_in = c->P.cov ? c->eps : nullptr;
   R.manip = c->manip;
   return R;
@@ -521,7 +528,6 @@ static ReduceArgs reduce_args(const mpc_ctx* c) {
   R.sig = c->sig;
   R.chol = c->chol;
   R.wpart = c->wpart;
-  R.wcnt = c->wcnt;
   return R;
 }
 
@@ -543,7 +549,7 @@ static int set_items(mpc_ctx* c, int T, int W) {
   return MPC_OK;
 }
 
-static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts);
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug);
 
 // Launch-shape tuner: times the rollout launch for every candidate number of
 // waves per workgroup, horizon tile and grid size on the live inputs of the
@@ -587,7 +593,7 @@ static int tune(mpc_ctx* c) {
   }
   if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
   if (c->collision_mode == 1) {
-    int rc = enqueue_learned_prelude(c, 0, false, c->tune_counts);
+    int rc = enqueue_learned_prelude(c, 0, false);
     if (rc) return rc;
   }
   hipEvent_t e0, e1;
@@ -640,14 +646,19 @@ static int tune(mpc_ctx* c) {
 }
 
 // Learned distance before each rollout launch of iteration k: own-joint
-// features of every rollout step, the neighbour records, the network's
-// predictions and the skip decision per (rollout, step, neighbour), counted
-// into `counts`.
-static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts) {
+// features of every rollout step and the neighbour records (one launch),
+// then the network's prediction of every (rollout, step, neighbour) query;
+// the rollout kernel takes the skip decisions from the predictions and
+// counts the queries.  In a debug step the capture buffers start cleared.
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug) {
   const float* eps_in = c->P.cov ? c->eps : nullptr;
+  if (debug) {
+    const size_t n = (size_t)c->A * c->A * c->Hmax * c->Nmax;
+    HIPCHK(c, hipMemsetAsync(c->sur_skip, 0, n, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->sur_pred, 0, n * sizeof(float), c->stream));
+  }
   HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, eps_in, k, c->A, c->Nmax,
-                              c->sur_F, c->stream));
-  HIPCHK(c, launch_sur_pairs(c->d_arms, c->d_model, c->d_meta, c->planq[0], c->A, c->Hmax, c->sur_nbrec, c->stream));
+                              c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->stream));
   SurInferArgs I{};
   I.P = c->d_P;
   I.model = c->d_model;
@@ -662,18 +673,6 @@ static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long 
   if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
   HIPCHK(c, launch_sur_infer(I, c->sur_grid, c->stream));
   if (ei) HIPCHK(c, hipEventRecord(ei, c->stream));
-  SurDecideArgs D{};
-  D.P = c->d_P;
-  D.model = c->d_model;
-  D.F = c->sur_F;
-  D.nbrec = c->sur_nbrec;
-  D.items = c->d_sur_items;
-  D.y = c->sur_y;
-  D.n_items = c->n_sur_items;
-  D.skip = c->sur_skip;
-  D.pred = debug ? c->sur_pred : nullptr;
-  D.counts = counts;
-  HIPCHK(c, launch_sur_decide(D, c->stream));
   return MPC_OK;
 }
 
@@ -689,7 +688,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A, c->Nmax, c->manip,
                              c->stream));
     if (c->collision_mode == 1) {
-      int rc = enqueue_learned_prelude(c, k, debug, c->sur_counts);
+      int rc = enqueue_learned_prelude(c, k, debug);
       if (rc) return rc;
     }
     hipEvent_t e1 = nullptr;
@@ -711,17 +710,24 @@ static int ensure_sur_buffers(mpc_ctx* c) {
   const size_t A = c->A, H = c->Hmax, N = c->Nmax;
   int rc;
   if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
-      (rc = dalloc(c, &c->sur_pred, A * A * H * N)) || (rc = dalloc(c, &c->sur_nbrec, A * A * H * kNbrRec)))
+      (rc = dalloc(c, &c->sur_pred, A * A * H * N)) || (rc = dalloc(c, &c->sur_nbrec, A * A * H * kNbrRec)) ||
+      (rc = dalloc(c, &c->sur_base, A * A)))
     return rc;
+  // Descriptors in (arm, neighbour, step, 32-rollout block) order: the
+  // queries of pair (a, i) start at item base[a][i], so the prediction of
+  // rollout n at step h is y[base[a][i] * 32 + h * Npad_a + n].
   std::vector<SurItem> items;
+  std::vector<int> base(A * A, 0);
   for (int a = 0; a < c->A; ++a)
     for (int i = 0; i < c->A; ++i) {
+      base[a * c->A + i] = (int)items.size();
       if (i == a) continue;
       const int H2 = std::min(c->harms[a].H, c->harms[i].H);
       for (int h = 0; h < H2; ++h)
         for (int n0 = 0; n0 < c->harms[a].Npad; n0 += 32) items.push_back(SurItem{a, i, h, n0});
     }
   c->n_sur_items = (int)items.size();
+  HIPCHK(c, hipMemcpy(c->sur_base, base.data(), base.size() * sizeof(int), hipMemcpyHostToDevice));
   if (!items.empty()) {
     if ((rc = dalloc(c, &c->d_sur_items, items.size())) || (rc = dalloc(c, &c->sur_y, items.size() * 32))) return rc;
     HIPCHK(c, hipMemcpy(c->d_sur_items, items.data(), items.size() * sizeof(SurItem), hipMemcpyHostToDevice));

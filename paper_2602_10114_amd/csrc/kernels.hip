@@ -7,7 +7,8 @@
 //                written per rollout step.
 //   k_total      Eq. 1 totals from the per-step stage costs.
 //   k_softmax    Eq. 2 weights, PickBest (Act).
-//   k_wmean      Eq. 3 weighted mean and Eq. 4 update of the means.
+//   k_wmean      Eq. 3 weighted sums per chunk of rollouts; k_wmean_fin adds
+//                them in order, Eq. 4 update of the means.
 //   k_toplan     ToPlan: integrate the means, forward kinematics, plan spheres.
 //   k_publish    Publish: board write side -> read side.
 #include <hip/hip_runtime.h>
@@ -15,6 +16,7 @@
 #include "common.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
+#include "surrogate.hpp"
 
 namespace mrs {
 
@@ -38,9 +40,9 @@ struct LdsSets {
   int set_k0[kMaxSets], set_n[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
   // learned-distance counters of the current item (added by each wave's
-  // lane 0), in the layout of the per-arm counter rows (slots 0 and 1,
-  // queries and predicted far, are the inference kernel's): waves skipped,
-  // audited misses (exact gap < B), audited missed collisions (gap < 0)
+  // lane 0), in the layout of the per-arm counter rows: live queries,
+  // predicted far, waves skipped, audited misses (exact gap < B), audited
+  // missed collisions (gap < 0)
   unsigned sur[5];
 };
 
@@ -367,6 +369,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
   // learned distance: the waves' drop masks over the neighbour table at the
   // current step (bit i: every rollout of the wave predicted far from i)
   __shared__ unsigned s_wdrop[WPB];
+  static_assert(kNbrRec == 8, "neighbour record layout of the learned distance");
   constexpr int kThreads = kWave * WPB;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *Pp;
@@ -422,6 +425,48 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
     unsigned long long pairs = 0;
     unsigned set_passes = 0, set_refines = 0, self_refines = 0;
     for (int h = item.h0; h < item.h1; ++h) {
+      // Learned distance: a neighbour is dropped for this wave at step h
+      // when every rollout of the wave is far: live, both arms' joints
+      // inside the training box, prediction at least the margin.  Taken
+      // first, while few values are live.  The masks go to LDS before the
+      // staging barrier below (the previous step's staging, their last
+      // reader, finished at the barrier after it).
+      unsigned wdrop = 0u;
+      if (SURM) {
+        // Uniform row bases plus the lane's rollout index (32-bit offsets).
+        const uint16_t* Frow = A.sur_F + (((size_t)a * P.Hmax + h) * P.Nmax) * 8;
+        const bool own_in = Frow[(uint32_t)n * 8u + 7u] != 0;
+        unsigned nq = 0u, nf = 0u;
+        for (int i = 0; i < nnb; ++i) {
+          const Nb nb = SS.nb[a][i];
+          if (h >= nb.H) continue;
+          const size_t pi = (size_t)a * P.A + nb.arm;
+          const float* yrow = A.sur_y + (size_t)A.sur_base[pi] * 32 + (size_t)h * Npad;
+          const float y = yrow[(uint32_t)n];
+          const bool nb_in = (A.sur_rec[(pi * P.Hmax + h) * kNbrRec + 5] & 1u) != 0u;
+          const bool far = live && own_in && nb_in && y >= A.sur_margin;
+          const unsigned long long mf = __ballot(far);
+          nq += (unsigned)__popcll(__ballot(live));
+          nf += (unsigned)__popcll(mf);
+          if (mf == ~0ull) wdrop |= 1u << i;
+          if (DBG && live) {
+            const size_t o = (pi * P.Hmax + h) * P.Nmax + n;
+            A.dbg_pred[o] = y;
+            A.dbg_skip[o] = far ? 1 : 0;
+          }
+        }
+        if (lane == 0) {
+          s_wdrop[wv] = wdrop;
+          if (WPB == 1) {
+            L.sur[0] += nq;
+            L.sur[1] += nf;
+          } else {
+            atomicAdd(&L.sur[0], nq);
+            atomicAdd(&L.sur[1], nf);
+          }
+        }
+      }
+
       float z[8];
       if (A.eps_in) {
 #pragma unroll
@@ -443,21 +488,6 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       }
       Chain C;
       chain_angles(C, arm, q);
-      // Learned distance: a neighbour is dropped for this wave at step h
-      // when every rollout of the wave is predicted beyond the margin.  The
-      // masks go to LDS before the barrier below (the previous step's
-      // staging, their last reader, finished at the barrier after it).
-      unsigned wdrop = 0u;
-      if (SURM) {
-        for (int i = 0; i < nnb; ++i) {
-          const Nb nb = SS.nb[a][i];
-          if (h >= nb.H) continue;
-          const bool sk = A.skip[(((size_t)a * P.A + nb.arm) * P.Hmax + h) * P.Nmax + n] != 0;
-          if (__ballot(sk) == ~0ull) wdrop |= 1u << i;
-        }
-        if (lane == 0) s_wdrop[wv] = wdrop;
-      }
-
       // Stage the sets scored at step h: obstacles (set 0) and every
       // published neighbour plan that reaches this step (Sec. IV-C: the
       // shorter of the two horizons applies).  A neighbour dropped by every
@@ -915,14 +945,13 @@ __global__ __launch_bounds__(kWave) void k_noise(const DevArm* __restrict__ arms
 }
 
 // Eq. 3 (weighted mean, and with covariance adaptation the weighted second
-// moments) and Eq. 4 (updates), split over (chunk of 1024 rollouts, step,
-// arm) so that the noise stream is read by enough workgroups to keep HBM
-// busy.  Each thread reads four consecutive rollouts of the 7 noise rows
-// (16-byte loads), the block reduces its sums with wave shuffles and then
-// across its 4 waves in a fixed order and stores them as the chunk's
-// partial; the block that finishes last for its (arm, step) adds the
-// partials in chunk order, so the result does not depend on which block
-// came last, applies the updates and resets the counter.
+// moments), split over (chunk of 1024 rollouts, step, arm) so that the noise
+// stream is read by enough workgroups to keep HBM busy.  Each thread reads
+// four consecutive rollouts of the 7 noise rows (16-byte loads); the block
+// reduces its sums with wave shuffles and then across its 4 waves in a fixed
+// order and stores them as the chunk's partial.  k_wmean_fin adds the
+// partials in chunk order (the result does not depend on the launch) and
+// applies Eq. 4.
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -931,8 +960,6 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
   __shared__ float s_w[4][kWmeanSums];
-  __shared__ float s_tot[kWmeanSums];
-  __shared__ int s_last;
   const int chunk = blockIdx.x, h = blockIdx.y, a = blockIdx.z, tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *A.P;
@@ -995,30 +1022,29 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
     }
   }
   __syncthreads();
-  float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums;
-  // Partials cross workgroups (and XCDs, whose L2s are not coherent with
-  // each other): device-scope atomic stores and loads, ordered by a release
-  // fence before the count and an acquire fence after it.
+  if (tid < nsum)
+    A.wpart[((((size_t)a * P.Hmax + h) * kWmeanMaxChunks) + chunk) * kWmeanSums + tid] =
+        ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
+}
+
+// The chunk partials of one (arm, step) added in chunk order, then Eq. 4:
+// the mean update and, with covariance adaptation, Eq. 3's weighted
+// covariance, its EMA and the floored Cholesky factor.
+__global__ __launch_bounds__(64) void k_wmean_fin(ReduceArgs A) {
+  __shared__ float s_tot[kWmeanSums];
+  const int h = blockIdx.x, a = blockIdx.y, tid = threadIdx.x;
+  const Params& P = *A.P;
+  const DevArm* arm = A.arms + a;
+  if (h >= arm->H) return;
+  const int nchunks = (arm->N + kWmeanChunk - 1) / kWmeanChunk;
+  const bool cov = P.cov != 0;
+  const int nsum = cov ? kWmeanSums : 7;
+  const float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums;
   if (tid < nsum) {
-    const float v = ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
-    __hip_atomic_store(part + (size_t)chunk * kWmeanSums + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned done = atomicAdd(A.wcnt + a * P.Hmax + h, 1u);
-    s_last = done == (unsigned)(nchunks - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (tid < nsum) {
-    float t = __hip_atomic_load(part + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int c2 = 1; c2 < nchunks; ++c2)
-      t += __hip_atomic_load(part + (size_t)c2 * kWmeanSums + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float t = part[tid];
+    for (int c2 = 1; c2 < nchunks; ++c2) t += part[(size_t)c2 * kWmeanSums + tid];
     s_tot[tid] = t;
   }
-  if (tid == 0) A.wcnt[a * P.Hmax + h] = 0u;  // every chunk of this pass has counted
   __syncthreads();
   if (tid < 7) {
     float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + tid;
@@ -1026,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
     const float mt = m0 + s_tot[tid];
     *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
   }
-  if (cov && tid == 64) {
+  if (cov && tid == 32) {
     // Eq. 3: Sigma~ = sum_n w_n (U_n - mu~)(U_n - mu~)^T = sum_n w_n eps eps^T - ebar ebar^T
     // (U_n - mu~ = eps_n - ebar, ebar = sum_n w_n eps_n); Eq. 4: EMA; then the
     // Cholesky factor, pivots floored at sigma_floor^2.
@@ -1185,11 +1211,11 @@ static hipError_t launch_rollout_w(const RolloutArgs& A, int waves, int grid, hi
 
 template <int LAY, bool DBG>
 static hipError_t launch_rollout_s(const RolloutArgs& A, int waves, int grid, hipStream_t s) {
-  if (!A.skip) return launch_rollout_w<LAY, DBG, 0>(A, waves, grid, s);
+  if (!A.learned) return launch_rollout_w<LAY, DBG, 0>(A, waves, grid, s);
   return A.audit ? launch_rollout_w<LAY, DBG, 2>(A, waves, grid, s) : launch_rollout_w<LAY, DBG, 1>(A, waves, grid, s);
 }
 
-// The learned-distance variants (A.skip set; audited or not) are separate
+// The learned-distance variants (A.learned set; audited or not) are separate
 // instantiations so that the exact kernel carries none of their bookkeeping.
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s) {
   if (layout == 0)
@@ -1213,6 +1239,9 @@ hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t
 hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s) {
   const int chunks = (nmax + kWmeanChunk - 1) / kWmeanChunk;
   hipLaunchKernelGGL(k_wmean, dim3(chunks, hmax, n_arms), dim3(256), 0, s, A);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wmean_fin, dim3(hmax, n_arms), dim3(64), 0, s, A);
   return hipGetLastError();
 }
 

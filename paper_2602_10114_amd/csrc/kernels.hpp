@@ -29,11 +29,23 @@ struct RolloutArgs {
   float* dbg_sph;              // [A][Nmax][Hmax][Smax][4]
   float* dbg_stage;            // [A][Hmax][Nmax]
   unsigned long long* dbg_pairs;  // [A][4]: queries, set filter passes, set exact passes, self exact passes (per wave)
-  // learned distance (collision mode 1): skip mask [A][A][Hmax][Nmax] and counters [A][5]
-  const uint8_t* skip;
+  // learned distance (collision mode 1, `learned` set): the network's
+  // predictions in inference-descriptor order, the first descriptor of each
+  // (arm, neighbour) pair [A][A], the own-feature rows (slot 7 = in-box
+  // flag) and neighbour records (word 5 bit 0 = neighbour in box), the
+  // margin, and the counters [A][5]; the debug instantiation also stores
+  // each live query's prediction and decision [A][A][Hmax][Nmax]
+  int learned;
   int audit;
+  const float* sur_y;
+  const int* sur_base;
+  const uint16_t* sur_F;
+  const uint32_t* sur_rec;
+  float sur_margin;
   int pad2;
   unsigned long long* sur_counts;
+  float* dbg_pred;
+  uint8_t* dbg_skip;
   // adapted covariance: the iteration's noise, precomputed (same layout as
   // eps); NULL = draw sigma z in the kernel
   const float* eps_in;
@@ -79,7 +91,6 @@ struct ReduceArgs {
   float* sig;                  // [A][Hmax][28] packed lower triangles (covariance adaptation)
   float* chol;                 // their Cholesky factors
   float* wpart;                // weighted-mean partial sums [A][Hmax][kWmeanMaxChunks][7 + 28]
-  unsigned* wcnt;              // chunks finished per (arm, step) [A][Hmax]; back to 0 after each pass
 };
 
 // The weighted mean (Eq. 3) splits every (arm, step) over chunks of
@@ -103,7 +114,7 @@ hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
 // rollout count must be a multiple of 64 * waves.
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s);
 hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s);  // k_total, then k_softmax
-hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s);
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s);  // k_wmean, k_wmean_fin
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
 // C_manip (Eq. 5) of every rollout step of iteration k: out [A][Hmax][Nmax].

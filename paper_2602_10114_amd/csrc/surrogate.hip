@@ -143,17 +143,12 @@ __global__ void k_features(const DevArm* __restrict__ arms, const SurModel* __re
   for (int k = 0; k < kFeat; ++k) F[(size_t)m * kFeat + k] = f[k];
 }
 
-// Neighbour records of the fused inference, one per (arm a, neighbour i,
-// step h) of the read-side plans: the neighbour half of the features
-// (identical for every rollout of a at step h) and what the decision needs.
-__global__ __launch_bounds__(kWave) void k_sur_pairs(const DevArm* __restrict__ arms,
-                                                     const SurModel* __restrict__ sm,
-                                                     const BoardMeta* __restrict__ meta,
-                                                     const float* __restrict__ planq, int n_arms, int Hmax,
-                                                     uint32_t* __restrict__ rec) {
-  const int h = blockIdx.x * kWave + threadIdx.x;
-  const int a = blockIdx.y / n_arms, i = blockIdx.y % n_arms;
-  if (h >= Hmax) return;
+// Neighbour record of the fused inference for (arm a, neighbour i, step h)
+// of the read-side plans: the neighbour half of the features (identical for
+// every rollout of a at step h) and what the decision needs.
+__device__ __forceinline__ void nb_record(const DevArm* __restrict__ arms, const SurModel* __restrict__ sm,
+                                          const BoardMeta* __restrict__ meta, const float* __restrict__ planq,
+                                          int n_arms, int Hmax, int a, int i, int h, uint32_t* __restrict__ rec) {
   uint32_t* r = rec + (((size_t)a * n_arms + i) * Hmax + h) * kNbrRec;
   const DevArm* A = arms + a;
   const DevArm* I = arms + i;
@@ -393,6 +388,8 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 // rollout: lane j < 7 integrates joint j (the joints are independent) and
 // writes its feature; lane 7 writes the flag, the AND of the group's box
 // tests taken with a ballot.  The eight 2-byte writes form the row.
+// The launch's last row of blocks (blockIdx.y = number of arms) writes the
+// neighbour records, one thread per (arm, neighbour, step).
 constexpr int kStatesThreads = 256;
 __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __restrict__ arms,
                                                                const Params* __restrict__ Pp,
@@ -401,9 +398,19 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
                                                                const float* __restrict__ mu_all,
                                                                const float* __restrict__ state,
                                                                const float* __restrict__ eps_in, int k_iter,
-                                                               uint16_t* __restrict__ F) {
+                                                               uint16_t* __restrict__ F,
+                                                               const BoardMeta* __restrict__ meta,
+                                                               const float* __restrict__ planq,
+                                                               uint32_t* __restrict__ rec) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
+  if (a == P.A) {
+    const int g = blockIdx.x * kStatesThreads + threadIdx.x;
+    if (g >= P.A * P.A * P.Hmax) return;
+    const int h = g % P.Hmax, ai = g / P.Hmax;
+    nb_record(arms, sm, meta, planq, P.A, P.Hmax, ai / P.A, ai % P.A, h, rec);
+    return;
+  }
   const DevArm* arm = arms + a;
   const int j = threadIdx.x & 7, lane = threadIdx.x & 63;
   const int n = blockIdx.x * (kStatesThreads / 8) + (threadIdx.x >> 3);
@@ -452,8 +459,8 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
 //   times the matching output weights, and leaves one partial sum per query,
 //   wave and lane half in LDS); its first wave adds the partial sums of
 //   stage s-3 (one query per lane) and stores the predictions.  The skip
-//   decision is a separate element-wise kernel (k_sur_decide), off the
-//   pipeline's critical path.
+//   decision is taken by the rollout kernel from the stored predictions,
+//   off the pipeline's critical path.
 // Each SIMD holds one wave of each group, so one wave's MFMA chain runs
 // while the other does its latency-bound part (LDS round trips, VALU), and
 // the roles swap half-way through the stage.
@@ -822,62 +829,6 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   }
 }
 
-// The skip decision of every query (one thread each, query blocks in
-// descriptor order): far when the query is live (the neighbour's plan is
-// readable and covers the step, the rollout exists), both arms' joints lie
-// inside the training box and the prediction reaches the margin.  Writes the
-// skip byte (and the prediction when asked) at the query's (arm, neighbour,
-// step, rollout) slot and adds per-arm counts of live and far queries.
-constexpr int kDecideThreads = 256;
-constexpr int kDecideBlocks = 1024;
-__global__ __launch_bounds__(kDecideThreads) void k_sur_decide(const SurDecideArgs D) {
-  // Per-block counts in LDS (return-less atomics), one global add per arm
-  // and block at the end.
-  __shared__ unsigned cnt[kMaxArms][2];
-  if (threadIdx.x < 2 * kMaxArms) cnt[threadIdx.x >> 1][threadIdx.x & 1] = 0u;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, q = lane & 31;
-  const int nA = D.P->A, Hmax = D.P->Hmax, Nmax = D.P->Nmax;
-  const float margin = D.model->margin;
-  const long long total = (long long)D.n_items * 32;
-  // Every thread runs the same number of iterations (the ballots below are
-  // wave-wide); threads past the end take no part.
-  const long long stride = (long long)gridDim.x * kDecideThreads;
-  for (long long base = (long long)blockIdx.x * kDecideThreads; base < total; base += stride) {
-    const long long gid = base + threadIdx.x;
-    const long long item = gid >> 5;
-    bool live = false, far = false;
-    int arm = 0;
-    if (gid < total) {
-      const SurItem it = D.items[item];
-      arm = it.arm;
-      const uint32_t* rec = D.nbrec + (((size_t)it.arm * nA + it.nbr) * Hmax + it.h) * kNbrRec;
-      const uint32_t flags = rec[5];
-      const int n = it.n0 + q;
-      const float y = D.y[gid];
-      const uint16_t own_flag = D.F[(((size_t)it.arm * Hmax + it.h) * Nmax + n) * 8 + 7];
-      live = (flags & 2u) != 0u && n < (int)rec[6];
-      far = live && (flags & 1u) != 0u && own_flag != 0 && y >= margin;
-      const size_t o = (((size_t)it.arm * nA + it.nbr) * Hmax + it.h) * Nmax + n;
-      D.skip[o] = far ? 1 : 0;
-      if (D.pred) D.pred[o] = y;
-    }
-    // Each half-wave is one query block (one arm).
-    const unsigned long long mq = __ballot(live), mf = __ballot(far);
-    const unsigned long long half_mask = lane < 32 ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull;
-    const unsigned nq = (unsigned)__popcll(mq & half_mask), nf = (unsigned)__popcll(mf & half_mask);
-    if (q == 0 && (nq | nf)) {
-      atomicAdd(&cnt[arm][0], nq);
-      atomicAdd(&cnt[arm][1], nf);
-    }
-  }
-  __syncthreads();
-  if (D.counts && threadIdx.x < 2 * nA) {
-    const unsigned v = cnt[threadIdx.x >> 1][threadIdx.x & 1];
-    if (v) atomicAdd(D.counts + 5 * (threadIdx.x >> 1) + (threadIdx.x & 1), (unsigned long long)v);
-  }
-}
-
 // ---------------------------------------------------------------------------
 template <int LAY>
 static hipError_t pair_distance_t(const DevArm* arms, int ai, int aj, const float* qi, const float* qj, int M,
@@ -954,25 +905,13 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
 
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
-                             int npad_max, uint16_t* F, hipStream_t s) {
-  const int per_block = kStatesThreads / 8;
-  hipLaunchKernelGGL(k_sur_states, dim3((npad_max + per_block - 1) / per_block, n_arms), dim3(kStatesThreads), 0, s,
-                     arms, P, model, ss, mu, state, eps_in, k_iter, F);
-  return hipGetLastError();
-}
-
-hipError_t launch_sur_pairs(const DevArm* arms, const SurModel* model, const BoardMeta* meta, const float* planq,
-                            int n_arms, int Hmax, uint32_t* rec, hipStream_t s) {
-  hipLaunchKernelGGL(k_sur_pairs, dim3((Hmax + kWave - 1) / kWave, n_arms * n_arms), dim3(kWave), 0, s, arms, model,
-                     meta, planq, n_arms, Hmax, rec);
-  return hipGetLastError();
-}
-
-hipError_t launch_sur_decide(const SurDecideArgs& D, hipStream_t s) {
-  if (D.n_items <= 0) return hipSuccess;
-  const long long blocks = ((long long)D.n_items * 32 + kDecideThreads - 1) / kDecideThreads;
-  hipLaunchKernelGGL(k_sur_decide, dim3((unsigned)(blocks < kDecideBlocks ? blocks : kDecideBlocks)),
-                     dim3(kDecideThreads), 0, s, D);
+                             int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
+                             uint32_t* rec, hipStream_t s) {
+  constexpr int per_block = kStatesThreads / 8;
+  const int rows = (npad_max + per_block - 1) / per_block;
+  const int recs = (n_arms * n_arms * hmax + kStatesThreads - 1) / kStatesThreads;
+  hipLaunchKernelGGL(k_sur_states, dim3(rows > recs ? rows : recs, n_arms + 1), dim3(kStatesThreads), 0, s, arms, P,
+                     model, ss, mu, state, eps_in, k_iter, F, meta, planq, rec);
   return hipGetLastError();
 }
 

@@ -77,33 +77,17 @@ struct SurInferArgs {
   float* y;                    // predictions in descriptor order [n_items][32]
 };
 
-// The skip decision from the predictions (see k_sur_decide).
-struct SurDecideArgs {
-  const Params* P;
-  const SurModel* model;
-  const uint16_t* F;           // own-joint feature rows (slot 7 = in-box flag)
-  const uint32_t* nbrec;       // neighbour records
-  const SurItem* items;
-  const float* y;              // predictions [n_items][32]
-  int n_items;
-  int pad;
-  uint8_t* skip;               // [A][A][Hmax][Nmax]: 1 = predicted beyond the margin
-  float* pred;                 // optional predictions, same layout
-  unsigned long long* counts;  // per-arm counter rows [A][5]: adds live queries (slot 0) and predicted far (slot 1)
-};
-
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, const float* qi, const float* qj,
                                 int M, float* out, hipStream_t s);
+// Own-feature rows of every (arm, step, rollout) and the neighbour records
+// of every (a, i, h < Hmax) from the read-side plans, in one launch.
 // eps_in: the iteration's precomputed noise (adapted covariance), or NULL to draw sigma z.
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
-                             int npad_max, uint16_t* F, hipStream_t s);
-// Neighbour records for every (a, i, h < Hmax) from the read-side plans.
-hipError_t launch_sur_pairs(const DevArm* arms, const SurModel* model, const BoardMeta* meta, const float* planq,
-                            int n_arms, int Hmax, uint32_t* rec, hipStream_t s);
+                             int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
+                             uint32_t* rec, hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
-hipError_t launch_sur_decide(const SurDecideArgs& D, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);
 // features (bfloat16 [M][17]), FP32 targets max(min(rho, clip), floor), and
