@@ -294,6 +294,18 @@ int mpc_surrogate_get_params(mpc_ctx *c, float *params);
 int mpc_surrogate_set_params(mpc_ctx *c, const float *params);
 /* Network output for features [m][17]; y [m].  Device; waits for the GPU. */
 int mpc_surrogate_predict(mpc_ctx *c, const float *features, int m, float *y);
+/* mpc_surrogate_predict for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same network output, bitwise, for features [m][17] into y [m] (device),
+ * enqueued on the context's stream and not waited for; no hipMalloc, hipFree
+ * or allocating library call.  Its working memory (the inputs and two
+ * activation buffers of up to MPC_PREDICT_NOALLOC_MAX queries, 4.3 MB) is
+ * one fixed array per GPU, held until the process ends and shared by every
+ * call on that GPU: calls that overlap on one GPU (two streams or threads)
+ * race on it.  Nothing in it needs to start at zero.  Errors: MPC_EINVAL for
+ * m < 0, m > MPC_PREDICT_NOALLOC_MAX or a NULL array with m > 0. */
+#define MPC_PREDICT_NOALLOC_MAX 4096
+int mpc_surrogate_predict_noalloc(mpc_ctx *c, const float *features, int m, float *y);
 /* One forward + backward pass of the training dataflow on a batch
  * (features [B][17], targets [B]) with the training loss (over_weight,
  * near_weight, near_band as in mpc_train_params): gradient [136449]

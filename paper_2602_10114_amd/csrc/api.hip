@@ -26,6 +26,35 @@ static_assert(kWmeanMaxChunks * kWmeanChunk >= MPC_MAX_ROLLOUTS, "weighted-mean 
 
 static thread_local std::string g_last_error;
 
+// Working memory of mpc_surrogate_predict_noalloc: the bfloat16 input rows
+// and two ping-pong bfloat16 activation buffers of MPC_PREDICT_NOALLOC_MAX
+// queries.  One copy per GPU for the life of the process; host code reaches
+// it only through the address hipGetSymbolAddress gives on that device.
+constexpr size_t kNaQueries = MPC_PREDICT_NOALLOC_MAX;
+constexpr size_t kNaX16Bytes = (kNaQueries * 17 * sizeof(uint16_t) + 255) / 256 * 256;
+constexpr size_t kNaActBytes = kNaQueries * 256 * sizeof(uint16_t);
+constexpr size_t kNaBytes = kNaX16Bytes + 2 * kNaActBytes;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Per-device address of `scratch`, taken once per device with that device
+// current (each GPU holds its own copy at its own address).
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNaMaxDevices] = {};
+
+static hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 // (start, end) HIP event pairs recorded around launches while profiling.
 struct EventLog {
   std::vector<hipEvent_t> ev;
@@ -67,6 +96,7 @@ struct EventLog {
 struct mpc_ctx {
   int A = 0, Hmax = 0, Smax = 0, Nmax = 0, layout = 0;
   hipStream_t stream = nullptr;
+  void* na_scratch = nullptr;          // this device's copy of `scratch` (allocation-free prediction)
   Params P{};
   std::vector<DevArm> harms;
   DevArm* d_arms = nullptr;
@@ -315,9 +345,17 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, MPC_EHIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
 
+  void* na_scratch = nullptr;
+  {
+    const hipError_t e = scratch_address(dev, &na_scratch);
+    if (e != hipSuccess)
+      return fail(nullptr, MPC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+
   mpc_ctx* c = new mpc_ctx();
   c->A = n_arms;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->na_scratch = na_scratch;
   for (int i = 0; i < n_arms; ++i) {
     c->Hmax = std::max(c->Hmax, arms[i].horizon);
     c->Smax = std::max(c->Smax, arms[i].n_spheres);
@@ -1243,6 +1281,39 @@ extern "C" int mpc_surrogate_predict(mpc_ctx* c, const float* features, int m, f
     HIPCHK(c, hipMemcpyAsync(y + m0, S.y, sizeof(float) * b, hipMemcpyDeviceToDevice, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MPC_OK;
+}
+
+extern "C" int mpc_surrogate_predict_noalloc(mpc_ctx* c, const float* features, int m, float* y) {
+  if (!c) return MPC_EINVAL;
+  if (m < 0 || (m > 0 && (!features || !y))) return fail(c, MPC_EINVAL, "bad prediction arguments");
+  if (m > MPC_PREDICT_NOALLOC_MAX)
+    return fail(c, MPC_EINVAL, "m above MPC_PREDICT_NOALLOC_MAX (" + std::to_string(MPC_PREDICT_NOALLOC_MAX) +
+                                   "): the fixed working memory holds that many queries");
+  if (m == 0) return MPC_OK;
+  if (!c->na_scratch) return fail(c, MPC_ESTATE, "no working memory on this device");
+  unsigned char* base = static_cast<unsigned char*>(c->na_scratch);
+  uint16_t* X16 = reinterpret_cast<uint16_t*>(base);
+  uint16_t* act[2] = {reinterpret_cast<uint16_t*>(base + kNaX16Bytes),
+                      reinterpret_cast<uint16_t*>(base + kNaX16Bytes + kNaActBytes)};
+  // The forward pass of mpc_surrogate_predict (same kernels, same bfloat16
+  // dataflow) with the hidden activations ping-ponging through the fixed
+  // buffers and the output written straight to y.
+  HIPCHK(c, launch_f32_to_bf16(features, X16, (long long)m * kFeat, c->stream));
+  const uint16_t* in = X16;
+  int K = kFeat;
+  for (int l = 0; l < 3; ++l) {
+    GemmArgs g = gemm(m, kHid, K, in, K, 0, c->sur_p16 + mlp_w_off(l), K, 1);
+    g.bias = c->sur_p + mlp_b_off(l);
+    g.C16 = act[l & 1]; g.ldc16 = kHid; g.relu = 1;
+    HIPCHK(c, launch_gemm_bf16(g, c->stream));
+    in = act[l & 1];
+    K = kHid;
+  }
+  GemmArgs g = gemm(m, 1, kHid, in, kHid, 0, c->sur_p16 + mlp_w_off(3), kHid, 1);
+  g.bias = c->sur_p + mlp_b_off(3);
+  g.C32 = y; g.ldc = 1;
+  HIPCHK(c, launch_gemm_bf16(g, c->stream));
   return MPC_OK;
 }
 

@@ -26,8 +26,9 @@ EXPORTS = ["mpc_init", "mpc_share_plans", "mpc_step", "mpc_get_plan", "mpc_destr
            "mpc_surrogate_train", "mpc_surrogate_get_params", "mpc_surrogate_set_params",
            "mpc_surrogate_predict", "mpc_surrogate_grad", "mpc_set_collision_mode",
            "mpc_surrogate_audit", "mpc_surrogate_stats", "mpc_profile_read_surrogate",
-           "mpc_surrogate_adam"]
+           "mpc_surrogate_adam", "mpc_surrogate_predict_noalloc"]
 MLP_WIDTHS = [17, 256, 256, 256, 1]
+PREDICT_NOALLOC_MAX = 4096   # MPC_PREDICT_NOALLOC_MAX
 MLP_PARAMS = 136449
 # Default training recipe of the learned distance: 2M exact-kernel samples,
 # Adam; the loss weighs over-prediction (the unsafe direction) 256x and
@@ -117,6 +118,7 @@ def lib():
         L.mpc_surrogate_predict.argtypes = [vp, vp, ip, vp]
         L.mpc_surrogate_grad.argtypes = [vp, vp, vp, ip, fp, fp, fp, vp, C.POINTER(fp)]
         L.mpc_surrogate_adam.argtypes = [vp, vp, fp, fp, fp, fp, ip]
+        L.mpc_surrogate_predict_noalloc.argtypes = [vp, vp, ip, vp]
         L.mpc_set_collision_mode.argtypes = [vp, ip]
         L.mpc_surrogate_audit.argtypes = [vp, ip]
         L.mpc_surrogate_stats.argtypes = [vp, vp, ip]
