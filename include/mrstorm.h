@@ -96,6 +96,11 @@ typedef struct {
                               spheres at every step, a static obstacle (the paper's S_d ablation) */
   float w_manip;           /* weight of C_manip (Eq. 5), >= 0; 0 leaves the term out */
   float manip_thresh;      /* C_manip = max(0, 1 - sqrt(det(J J^T)) / manip_thresh), > 0 */
+  float surrogate_screen;  /* mode 1: an (arm, neighbour, step) whose mean rollout (the means
+                              integrated from the sensed state) lies closer than this (metres)
+                              to the neighbour's plan at that step is checked exactly for every
+                              rollout without running the network (it would keep nearly all of
+                              them); >= 0, 0 = off.  Only ever adds exact checks. */
 } mpc_params;
 
 /* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).

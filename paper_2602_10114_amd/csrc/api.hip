@@ -156,7 +156,9 @@ struct mpc_ctx {
   uint16_t* sur_F = nullptr;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16)
   uint8_t* sur_skip = nullptr;         // decisions of live queries [A][A][Hmax][Nmax] (debug capture)
   float* sur_pred = nullptr;           // their predictions (debug capture)
-  int* sur_base = nullptr;             // first inference descriptor of each (arm, neighbour) [A][A]
+  uint8_t* sur_screen = nullptr;       // groups that need no prediction [A][A][Hmax]
+  int* sur_grp = nullptr;              // first inference descriptor of each group [A][A][Hmax] (-1: none)
+  int* sur_count = nullptr;            // descriptors of the step
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
   float* sur_y = nullptr;              // predictions in descriptor order [items][32]
   bool sur_bufs = false;               // every learned-distance step buffer allocated
@@ -327,6 +329,8 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   // switched later.
   if (!(p->surrogate_margin == 0.f || p->surrogate_margin >= p->buf_dyn))
     return fail(nullptr, MPC_EINVAL, "surrogate_margin must be 0 (= buf_dyn) or at least buf_dyn");
+  if (!(p->surrogate_screen >= 0.f && p->surrogate_screen < 10.f))
+    return fail(nullptr, MPC_EINVAL, "surrogate_screen outside [0, 10) m");
   bool all52 = true;
   for (int i = 0; i < n_arms; ++i) {
     int counts[kBodies];
@@ -427,6 +431,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
     c->hmodel.inv_half[j] = (float)(hi > lo ? 2.0 / (hi - lo) : 1.0);
   }
   c->hmodel.margin = p->surrogate_margin > 0.f ? p->surrogate_margin : p->buf_dyn;
+  c->hmodel.screen = p->surrogate_screen;
   if ((rc = dalloc(c, &c->d_model, 1)) || (rc = dalloc(c, &c->sur_p, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_m, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_v, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_g, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_p16, (size_t)kMlpParams)) ||
@@ -535,7 +540,7 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.learned = c->collision_mode == 1 ? 1 : 0;
   R.audit = c->sur_audit ? 1 : 0;
   R.sur_y = c->sur_y;
-  R.sur_base = c->sur_base;
+  R.sur_grp = c->sur_grp;
   R.sur_F = c->sur_F;
   R.sur_rec = c->sur_nbrec;
   R.sur_margin = c->hmodel.margin;
@@ -696,7 +701,10 @@ static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug) {
     HIPCHK(c, hipMemsetAsync(c->sur_pred, 0, n * sizeof(float), c->stream));
   }
   HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, eps_in, k, c->A, c->Nmax,
-                              c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->stream));
+                              c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->plan[0], c->sur_screen,
+                              c->stream));
+  HIPCHK(c, launch_sur_items(c->d_arms, c->d_P, c->sur_screen, c->A, c->Hmax, c->d_sur_items, c->sur_grp, c->sur_count,
+                             c->stream));
   SurInferArgs I{};
   I.P = c->d_P;
   I.model = c->d_model;
@@ -705,7 +713,7 @@ static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug) {
   I.F = c->sur_F;
   I.nbrec = c->sur_nbrec;
   I.items = c->d_sur_items;
-  I.n_items = c->n_sur_items;
+  I.count = c->sur_count;
   I.y = c->sur_y;
   hipEvent_t ei = nullptr;
   if (c->profile) HIPCHK(c, c->prof_infer.begin(c->stream, &ei));
@@ -734,9 +742,11 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
     HIPCHK(c, launch_rollout(R, c->layout, debug, c->waves, c->grid, c->stream));
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, launch_softmax(Rr, c->A, c->Nmax, c->stream));
-    HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->Nmax, c->stream));
+    // Between iterations the totals and Eq. 4 run on their own; after the
+    // last one ToPlan applies them first.
+    HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->Nmax, k + 1 < c->P.iters, c->stream));
   }
-  HIPCHK(c, launch_toplan(Rr, c->A, c->stream));
+  HIPCHK(c, launch_toplan(Rr, c->A, true, c->stream));
   return MPC_OK;
 }
 
@@ -749,27 +759,19 @@ static int ensure_sur_buffers(mpc_ctx* c) {
   int rc;
   if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
       (rc = dalloc(c, &c->sur_pred, A * A * H * N)) || (rc = dalloc(c, &c->sur_nbrec, A * A * H * kNbrRec)) ||
-      (rc = dalloc(c, &c->sur_base, A * A)))
+      (rc = dalloc(c, &c->sur_screen, A * A * H)) || (rc = dalloc(c, &c->sur_grp, A * A * H)) ||
+      (rc = dalloc(c, &c->sur_count, 1)))
     return rc;
-  // Descriptors in (arm, neighbour, step, 32-rollout block) order: the
-  // queries of pair (a, i) start at item base[a][i], so the prediction of
-  // rollout n at step h is y[base[a][i] * 32 + h * Npad_a + n].
-  std::vector<SurItem> items;
-  std::vector<int> base(A * A, 0);
+  // Room for the descriptors of every (arm, neighbour, step within both
+  // horizons, 32-rollout block), the step's are written by k_sur_items.
+  long long n_items = 0;
   for (int a = 0; a < c->A; ++a)
-    for (int i = 0; i < c->A; ++i) {
-      base[a * c->A + i] = (int)items.size();
-      if (i == a) continue;
-      const int H2 = std::min(c->harms[a].H, c->harms[i].H);
-      for (int h = 0; h < H2; ++h)
-        for (int n0 = 0; n0 < c->harms[a].Npad; n0 += 32) items.push_back(SurItem{a, i, h, n0});
-    }
-  c->n_sur_items = (int)items.size();
-  HIPCHK(c, hipMemcpy(c->sur_base, base.data(), base.size() * sizeof(int), hipMemcpyHostToDevice));
-  if (!items.empty()) {
-    if ((rc = dalloc(c, &c->d_sur_items, items.size())) || (rc = dalloc(c, &c->sur_y, items.size() * 32))) return rc;
-    HIPCHK(c, hipMemcpy(c->d_sur_items, items.data(), items.size() * sizeof(SurItem), hipMemcpyHostToDevice));
-  }
+    for (int i = 0; i < c->A; ++i)
+      if (i != a) n_items += (long long)std::min(c->harms[a].H, c->harms[i].H) * (c->harms[a].Npad / 32);
+  c->n_sur_items = (int)n_items;
+  if (n_items > 0 &&
+      ((rc = dalloc(c, &c->d_sur_items, (size_t)n_items)) || (rc = dalloc(c, &c->sur_y, (size_t)n_items * 32))))
+    return rc;
   // One inference block per compute unit (its LDS and registers fill one).
   int dev = 0, n_cu = 0;
   HIPCHK(c, hipGetDevice(&dev));

@@ -7,8 +7,9 @@
 //                written per rollout step.
 //   k_total      Eq. 1 totals from the per-step stage costs.
 //   k_softmax    Eq. 2 weights, PickBest (Act).
-//   k_wmean      Eq. 3 weighted sums per chunk of rollouts; k_wmean_fin adds
-//                them in order, Eq. 4 update of the means.
+//   k_wmean      Eq. 3 weighted sums per chunk of rollouts; k_wmean_fin (or
+//                k_toplan after the last iteration) adds them in order and
+//                applies Eq. 4.
 //   k_toplan     ToPlan: integrate the means, forward kinematics, plan spheres.
 //   k_publish    Publish: board write side -> read side.
 #include <hip/hip_runtime.h>
@@ -441,10 +442,11 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           const Nb nb = SS.nb[a][i];
           if (h >= nb.H) continue;
           const size_t pi = (size_t)a * P.A + nb.arm;
-          const float* yrow = A.sur_y + (size_t)A.sur_base[pi] * 32 + (size_t)h * Npad;
-          const float y = yrow[(uint32_t)n];
+          const int first = A.sur_grp[pi * P.Hmax + h];  // uniform; -1: no prediction
+          float y = __builtin_nanf("");
+          if (first >= 0) y = (A.sur_y + (size_t)first * 32)[(uint32_t)n];
           const bool nb_in = (A.sur_rec[(pi * P.Hmax + h) * kNbrRec + 5] & 1u) != 0u;
-          const bool far = live && own_in && nb_in && y >= A.sur_margin;
+          const bool far = first >= 0 && live && own_in && nb_in && y >= A.sur_margin;
           const unsigned long long mf = __ballot(far);
           nq += (unsigned)__popcll(__ballot(live));
           nf += (unsigned)__popcll(mf);
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           if (DBG && live) {
             const size_t o = (pi * P.Hmax + h) * P.Nmax + n;
             A.dbg_pred[o] = y;
-            A.dbg_skip[o] = far ? 1 : 0;
+            A.dbg_skip[o] = first < 0 ? 2 : (far ? 1 : 0);
           }
         }
         if (lane == 0) {
@@ -1027,9 +1029,58 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
         ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
 }
 
-// The chunk partials of one (arm, step) added in chunk order, then Eq. 4:
-// the mean update and, with covariance adaptation, Eq. 3's weighted
-// covariance, its EMA and the floored Cholesky factor.
+// Eq. 4 for one (arm a, step h) from the chunk totals t[0..6] (the weighted
+// noise sums) and, with covariance adaptation, t[7..34] (the weighted second
+// moments): the mean update for joint j (one thread per joint), and Eq. 3's
+// weighted covariance, its EMA and the floored Cholesky factor (one thread).
+__device__ __forceinline__ void mean_update(const ReduceArgs& A, const Params& P, int a, int h, int j,
+                                            const float* t) {
+  float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + j;
+  const float m0 = *mu;
+  const float mt = m0 + t[j];
+  *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
+}
+
+__device__ __forceinline__ void cov_update(const ReduceArgs& A, const Params& P, int a, int h, const float* t) {
+  // Eq. 3: Sigma~ = sum_n w_n (U_n - mu~)(U_n - mu~)^T = sum_n w_n eps eps^T - ebar ebar^T
+  // (U_n - mu~ = eps_n - ebar, ebar = sum_n w_n eps_n); Eq. 4: EMA; then the
+  // Cholesky factor, pivots floored at sigma_floor^2.
+  float* sg = A.sig + ((size_t)a * P.Hmax + h) * kTri;
+  float* L = A.chol + ((size_t)a * P.Hmax + h) * kTri;
+  float S[kTri], Lc[kTri];
+  for (int j = 0; j < 7; ++j)
+    for (int m = 0; m <= j; ++m) {
+      const float st = t[7 + tri7(j, m)] - t[j] * t[m];
+      S[tri7(j, m)] = fmaf_(P.alpha_sigma, st, (1.0f - P.alpha_sigma) * sg[tri7(j, m)]);
+    }
+  const float f2 = P.sigma_floor * P.sigma_floor;
+  for (int j = 0; j < 7; ++j) {
+    float d = S[tri7(j, j)];
+    for (int m = 0; m < j; ++m) d -= Lc[tri7(j, m)] * Lc[tri7(j, m)];
+    const float ljj = sqrtf(fmaxf(d, f2));
+    Lc[tri7(j, j)] = ljj;
+    for (int i = j + 1; i < 7; ++i) {
+      float v = S[tri7(i, j)];
+      for (int m = 0; m < j; ++m) v -= Lc[tri7(i, m)] * Lc[tri7(j, m)];
+      Lc[tri7(i, j)] = v / ljj;
+    }
+  }
+  for (int e = 0; e < kTri; ++e) {
+    sg[e] = S[e];
+    L[e] = Lc[e];
+  }
+}
+
+// The chunk partials of one (arm, step) added in chunk order.
+__device__ __forceinline__ float chunk_total(const ReduceArgs& A, const Params& P, int a, int h, int nchunks, int e) {
+  const float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums + e;
+  float t = part[0];
+  for (int c2 = 1; c2 < nchunks; ++c2) t += part[(size_t)c2 * kWmeanSums];
+  return t;
+}
+
+// Between optimisation iterations (K > 1): the totals of every (arm, step)
+// and Eq. 4; after the last iteration k_toplan does the same.
 __global__ __launch_bounds__(64) void k_wmean_fin(ReduceArgs A) {
   __shared__ float s_tot[kWmeanSums];
   const int h = blockIdx.x, a = blockIdx.y, tid = threadIdx.x;
@@ -1039,59 +1090,38 @@ __global__ __launch_bounds__(64) void k_wmean_fin(ReduceArgs A) {
   const int nchunks = (arm->N + kWmeanChunk - 1) / kWmeanChunk;
   const bool cov = P.cov != 0;
   const int nsum = cov ? kWmeanSums : 7;
-  const float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums;
-  if (tid < nsum) {
-    float t = part[tid];
-    for (int c2 = 1; c2 < nchunks; ++c2) t += part[(size_t)c2 * kWmeanSums + tid];
-    s_tot[tid] = t;
-  }
+  if (tid < nsum) s_tot[tid] = chunk_total(A, P, a, h, nchunks, tid);
   __syncthreads();
-  if (tid < 7) {
-    float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + tid;
-    const float m0 = *mu;
-    const float mt = m0 + s_tot[tid];
-    *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
-  }
-  if (cov && tid == 32) {
-    // Eq. 3: Sigma~ = sum_n w_n (U_n - mu~)(U_n - mu~)^T = sum_n w_n eps eps^T - ebar ebar^T
-    // (U_n - mu~ = eps_n - ebar, ebar = sum_n w_n eps_n); Eq. 4: EMA; then the
-    // Cholesky factor, pivots floored at sigma_floor^2.
-    float* sg = A.sig + ((size_t)a * P.Hmax + h) * kTri;
-    float* L = A.chol + ((size_t)a * P.Hmax + h) * kTri;
-    float eb[7], S[kTri], Lc[kTri];
-    for (int j = 0; j < 7; ++j) eb[j] = s_tot[j];
-    for (int j = 0; j < 7; ++j)
-      for (int m = 0; m <= j; ++m) {
-        const float st = s_tot[7 + tri7(j, m)] - eb[j] * eb[m];
-        S[tri7(j, m)] = fmaf_(P.alpha_sigma, st, (1.0f - P.alpha_sigma) * sg[tri7(j, m)]);
-      }
-    const float f2 = P.sigma_floor * P.sigma_floor;
-    for (int j = 0; j < 7; ++j) {
-      float d = S[tri7(j, j)];
-      for (int m = 0; m < j; ++m) d -= Lc[tri7(j, m)] * Lc[tri7(j, m)];
-      const float ljj = sqrtf(fmaxf(d, f2));
-      Lc[tri7(j, j)] = ljj;
-      for (int i = j + 1; i < 7; ++i) {
-        float v = S[tri7(i, j)];
-        for (int m = 0; m < j; ++m) v -= Lc[tri7(i, m)] * Lc[tri7(j, m)];
-        Lc[tri7(i, j)] = v / ljj;
-      }
-    }
-    for (int e = 0; e < kTri; ++e) {
-      sg[e] = S[e];
-      L[e] = Lc[e];
-    }
-  }
+  if (tid < 7) mean_update(A, P, a, h, tid, s_tot);
+  if (cov && tid == 32) cov_update(A, P, a, h, s_tot);
 }
 
-// ToPlan: integrate the updated means from the current state, forward
-// kinematics per step, plan spheres into the board's write side.
-__global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
+// ToPlan (one 256-thread block per arm): first the last iteration's
+// weighted-mean totals and Eq. 4 (when `fin`), then the updated means
+// integrated from the current state (one thread per joint), the link frames
+// of every step (one thread per step, into LDS), and the plan spheres and
+// planned joints of every (step, sphere) in parallel, into the board's write
+// side.
+constexpr int kToplanThreads = 256;
+__global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin) {
+  __shared__ float s_tot[kMaxH][kWmeanSums];
   __shared__ float s_q[kMaxH][8];
+  __shared__ Frame s_F[kMaxH][7];
   const int a = blockIdx.x, tid = threadIdx.x;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int H = arm->H;
+  if (fin) {
+    const int nchunks = (arm->N + kWmeanChunk - 1) / kWmeanChunk;
+    const bool cov = P.cov != 0;
+    const int nsum = cov ? kWmeanSums : 7;
+    for (int e = tid; e < H * nsum; e += kToplanThreads) s_tot[e / nsum][e % nsum] = chunk_total(A, P, a, e / nsum, nchunks, e % nsum);
+    __syncthreads();
+    for (int e = tid; e < H * 7; e += kToplanThreads) mean_update(A, P, a, e / 7, e % 7, s_tot[e / 7]);
+    if (cov)
+      for (int h = tid; h < H; h += kToplanThreads) cov_update(A, P, a, h, s_tot[h]);
+    __syncthreads();
+  }
   if (tid < 7) {
     // One thread per joint (the joints integrate independently).
     const int j = tid;
@@ -1107,46 +1137,52 @@ __global__ __launch_bounds__(64) void k_toplan(ReduceArgs A) {
     }
   }
   __syncthreads();
-  const int lay = arm->layout;
-  for (int h = tid; h < H; h += blockDim.x) {
+  for (int h = tid; h < H; h += kToplanThreads) {
     float q[8];
     for (int j = 0; j < 7; ++j) q[j] = s_q[h][j];
     q[7] = 0.f;
     Frame F[7];
     forward_kinematics(F, arm, q);
-    float4* out = reinterpret_cast<float4*>(A.plan_write) + ((size_t)a * P.Hmax + h) * P.Smax;
-    // Body by body (a static frame index keeps the frames in registers):
-    // each body's slots, written to their spheres' user positions; the
-    // hand is rigid with the last link.
-#pragma unroll
-    for (int b = 0; b < kBodies; ++b) {
-      const Frame& Fb = F[b < 7 ? b : 6];
-      for (int jslot = kLayoutStart[lay][b]; jslot < kLayoutStart[lay][b + 1]; ++jslot) {
-        const int src = arm->slot_src[jslot];
-        if (src < 0) continue;
-        const float* p = arm->slot[jslot];
-        float x, y, z;
-        frame_point(Fb, p[0], p[1], p[2], x, y, z);
-        out[src] = make_float4(x, y, z, p[3]);
-      }
-    }
-    for (int j = 0; j < 7; ++j) A.planq_write[((size_t)a * P.Hmax + h) * 7 + j] = q[j];
+    for (int k = 0; k < 7; ++k) s_F[h][k] = F[k];
   }
+  __syncthreads();
+  // Spheres in the arm's slot order (the hand is rigid with the last link),
+  // written to their user positions.
+  float4* out = reinterpret_cast<float4*>(A.plan_write) + (size_t)a * P.Hmax * P.Smax;
+  const int slots = kLayoutSlots[arm->layout];
+  for (int e = tid; e < H * slots; e += kToplanThreads) {
+    const int h = e / slots, jslot = e % slots;
+    const int src = arm->slot_src[jslot];
+    if (src < 0) continue;
+    int b = 0;
+    while (jslot >= kLayoutStart[arm->layout][b + 1]) ++b;
+    const float* p = arm->slot[jslot];
+    float x, y, z;
+    frame_point(s_F[h][b < 7 ? b : 6], p[0], p[1], p[2], x, y, z);
+    out[(size_t)h * P.Smax + src] = make_float4(x, y, z, p[3]);
+  }
+  for (int e = tid; e < H * 7; e += kToplanThreads)
+    A.planq_write[((size_t)a * P.Hmax + e / 7) * 7 + e % 7] = s_q[e / 7][e % 7];
   if (tid == 0) {
     A.meta->dist[1][a] = A.ss->dist_now[a];
     A.meta->valid[1][a] = 1;
   }
 }
 
-// Publish: copy the masked arms' written plans to the read side.
+// Publish: copy the masked arms' written plans to the read side, each arm's
+// plan split over kPublishSplit blocks.
+constexpr int kPublishSplit = 8;
 __global__ __launch_bounds__(256) void k_publish(PublishArgs A) {
-  const int a = blockIdx.x;
+  const int a = blockIdx.x, part = blockIdx.y;
   if (!((A.mask >> a) & 1u)) return;
   if (!A.meta->valid[1][a]) return;
-  const size_t n = (size_t)A.Hmax * A.Smax * 4, nq = (size_t)A.Hmax * 7;
-  for (size_t i = threadIdx.x; i < n; i += blockDim.x) A.plan_read[a * n + i] = A.plan_write[a * n + i];
-  for (size_t i = threadIdx.x; i < nq; i += blockDim.x) A.planq_read[a * nq + i] = A.planq_write[a * nq + i];
-  if (threadIdx.x == 0) {
+  const size_t n = (size_t)A.Hmax * A.Smax, nq = (size_t)A.Hmax * 7;
+  const float4* src = reinterpret_cast<const float4*>(A.plan_write) + a * n;
+  float4* dst = reinterpret_cast<float4*>(A.plan_read) + a * n;
+  for (size_t i = part * 256 + threadIdx.x; i < n; i += 256 * kPublishSplit) dst[i] = src[i];
+  for (size_t i = part * 256 + threadIdx.x; i < nq; i += 256 * kPublishSplit)
+    A.planq_read[a * nq + i] = A.planq_write[a * nq + i];
+  if (part == 0 && threadIdx.x == 0) {
     A.meta->dist[0][a] = A.meta->dist[1][a];
     A.meta->valid[0][a] = 1;
   }
@@ -1236,22 +1272,22 @@ hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s) {
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, bool fin, hipStream_t s) {
   const int chunks = (nmax + kWmeanChunk - 1) / kWmeanChunk;
   hipLaunchKernelGGL(k_wmean, dim3(chunks, hmax, n_arms), dim3(256), 0, s, A);
   const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !fin) return e;
   hipLaunchKernelGGL(k_wmean_fin, dim3(hmax, n_arms), dim3(64), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s) {
-  hipLaunchKernelGGL(k_toplan, dim3(n_arms), dim3(64), 0, s, A);
+hipError_t launch_toplan(const ReduceArgs& A, int n_arms, bool fin, hipStream_t s) {
+  hipLaunchKernelGGL(k_toplan, dim3(n_arms), dim3(kToplanThreads), 0, s, A, fin ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s) {
-  hipLaunchKernelGGL(k_publish, dim3(n_arms), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_publish, dim3(n_arms, kPublishSplit), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 

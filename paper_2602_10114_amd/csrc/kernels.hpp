@@ -31,14 +31,16 @@ struct RolloutArgs {
   unsigned long long* dbg_pairs;  // [A][4]: queries, set filter passes, set exact passes, self exact passes (per wave)
   // learned distance (collision mode 1, `learned` set): the network's
   // predictions in inference-descriptor order, the first descriptor of each
-  // (arm, neighbour) pair [A][A], the own-feature rows (slot 7 = in-box
-  // flag) and neighbour records (word 5 bit 0 = neighbour in box), the
-  // margin, and the counters [A][5]; the debug instantiation also stores
-  // each live query's prediction and decision [A][A][Hmax][Nmax]
+  // (arm, neighbour, step) group [A][A][Hmax] (-1: no prediction, the group's
+  // queries are checked exactly), the own-feature rows (slot 7 = in-box flag)
+  // and neighbour records (word 5 bit 0 = neighbour in box), the margin, and
+  // the counters [A][5]; the debug instantiation also stores each live
+  // query's prediction (NaN without one) and decision (1 far, 0 near, 2 no
+  // prediction) [A][A][Hmax][Nmax]
   int learned;
   int audit;
   const float* sur_y;
-  const int* sur_base;
+  const int* sur_grp;
   const uint16_t* sur_F;
   const uint32_t* sur_rec;
   float sur_margin;
@@ -114,8 +116,10 @@ hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
 // rollout count must be a multiple of 64 * waves.
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s);
 hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s);  // k_total, then k_softmax
-hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, hipStream_t s);  // k_wmean, k_wmean_fin
-hipError_t launch_toplan(const ReduceArgs& A, int n_arms, hipStream_t s);
+// k_wmean (chunk partials), then with `fin` k_wmean_fin (totals and Eq. 4).
+hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, bool fin, hipStream_t s);
+// ToPlan; with `fin` it first applies the last iteration's totals and Eq. 4.
+hipError_t launch_toplan(const ReduceArgs& A, int n_arms, bool fin, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
 // C_manip (Eq. 5) of every rollout step of iteration k: out [A][Hmax][Nmax].
 hipError_t launch_manip(const DevArm* arms, const Params* P, const StepState* ss, const float* mu, const float* state,

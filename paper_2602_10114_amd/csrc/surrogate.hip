@@ -6,6 +6,8 @@
 //   skipped.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "device.hpp"
 #include "surrogate.hpp"
@@ -388,8 +390,66 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 // rollout: lane j < 7 integrates joint j (the joints are independent) and
 // writes its feature; lane 7 writes the flag, the AND of the group's box
 // tests taken with a ballot.  The eight 2-byte writes form the row.
-// The launch's last row of blocks (blockIdx.y = number of arms) writes the
-// neighbour records, one thread per (arm, neighbour, step).
+// Screen of one (arm a, neighbour i, step h) group, one wave: 1 when no query
+// of the group needs the network -- the neighbour's plan is not published
+// (its queries are not live), or the arm's mean rollout (the means
+// integrated from the sensed state) lies closer than the screen distance to
+// the neighbour's plan at step h, so that nearly every rollout would be
+// predicted near anyway (its queries are checked exactly).  Lane = own
+// sphere slot: each lane integrates the means, walks the chain and places its
+// sphere; the wave takes the minimum gap to the plan's spheres.
+__device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, const Params& P,
+                                             const SurModel* __restrict__ sm, const BoardMeta* __restrict__ meta,
+                                             const float* __restrict__ mu_all, const float* __restrict__ state,
+                                             const float* __restrict__ plan_read, int g, int lane,
+                                             uint8_t* __restrict__ flag) {
+  const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
+  const DevArm* arm = arms + a;
+  const DevArm* nb = arms + i;
+  uint8_t f = 0;
+  if (i != a && h < arm->H && h < nb->H) {
+    if (!meta->valid[0][i]) {
+      f = 1;
+    } else if (sm->screen > 0.f) {
+      const float* mu = mu_all + (size_t)a * P.Hmax * 7;
+      float q[8];
+      for (int j = 0; j < 7; ++j) {
+        float qq = state[(a * 7 + j) * 3 + 0], qd = state[(a * 7 + j) * 3 + 1];
+        for (int hh = 0; hh <= h; ++hh) {
+          qd = fmaf_(P.dt, mu[hh * 7 + j], qd);
+          qq = fmaf_(P.dt, qd, qq);
+        }
+        q[j] = qq;
+      }
+      q[7] = 0.f;
+      Frame F[7];
+      forward_kinematics(F, arm, q);
+      float gmin = 3.0e38f;
+      const int slots = kLayoutSlots[arm->layout];
+      if (lane < slots && arm->slot_src[lane] >= 0) {
+        int b = 0;
+        while (lane >= kLayoutStart[arm->layout][b + 1]) ++b;
+        const float* p = arm->slot[lane];
+        float x, y, z;
+        frame_point(F[b < 7 ? b : 6], p[0], p[1], p[2], x, y, z);
+        const float4* pl = reinterpret_cast<const float4*>(plan_read) + ((size_t)i * P.Hmax + h) * P.Smax;
+        for (int k = 0; k < nb->S; ++k) {
+          const float4 o = pl[k];
+          const float dx = x - o.x, dy = y - o.y, dz = z - o.z;
+          gmin = fminf(gmin, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - p[3] - o.w);
+        }
+      }
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) gmin = fminf(gmin, __shfl_xor(gmin, off));
+      f = gmin < sm->screen ? 1 : 0;
+    }
+  }
+  if (lane == 0) flag[g] = f;
+}
+
+// The launch's row of blocks blockIdx.y = number of arms writes the
+// neighbour records, one thread per (arm, neighbour, step); the next row
+// screens the (arm, neighbour, step) groups, one wave each.
 constexpr int kStatesThreads = 256;
 __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __restrict__ arms,
                                                                const Params* __restrict__ Pp,
@@ -401,7 +461,9 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
                                                                uint16_t* __restrict__ F,
                                                                const BoardMeta* __restrict__ meta,
                                                                const float* __restrict__ planq,
-                                                               uint32_t* __restrict__ rec) {
+                                                               uint32_t* __restrict__ rec,
+                                                               const float* __restrict__ plan_read,
+                                                               uint8_t* __restrict__ screened) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
   if (a == P.A) {
@@ -409,6 +471,12 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
     if (g >= P.A * P.A * P.Hmax) return;
     const int h = g % P.Hmax, ai = g / P.Hmax;
     nb_record(arms, sm, meta, planq, P.A, P.Hmax, ai / P.A, ai % P.A, h, rec);
+    return;
+  }
+  if (a == P.A + 1) {
+    const int g = blockIdx.x * (kStatesThreads / kWave) + (int)(threadIdx.x / kWave);
+    if (g >= P.A * P.A * P.Hmax) return;  // whole waves
+    screen_group(arms, P, sm, meta, mu_all, state, plan_read, g, threadIdx.x & (kWave - 1), screened);
     return;
   }
   const DevArm* arm = arms + a;
@@ -683,7 +751,12 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   const bf16x8_t ones = ones_operand(half);
 
   const int G = gridDim.x;
-  const int n_my = A.n_items > (int)blockIdx.x ? (A.n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+  const int n_items = *A.count;  // descriptors written for this step (uniform)
+  const int n_my = n_items > (int)blockIdx.x ? (n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+  // A block without descriptors leaves before its first barrier (the whole
+  // block agrees); the pipeline below needs at least one (its stand-in
+  // stages reuse the last descriptor).
+  if (n_my == 0) return;
   const int n_st = (n_my + kQB - 1) / kQB;  // stages holding query blocks (the last may hold a stand-in)
   const int fcol = wq * kWaveRows + half * 4;  // this lane's first feature within an accumulator block
   // The pipeline body is straight-line code: edge stages (before the first
@@ -906,17 +979,84 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
                              int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
-                             uint32_t* rec, hipStream_t s) {
+                             uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s) {
   constexpr int per_block = kStatesThreads / 8;
-  const int rows = (npad_max + per_block - 1) / per_block;
-  const int recs = (n_arms * n_arms * hmax + kStatesThreads - 1) / kStatesThreads;
-  hipLaunchKernelGGL(k_sur_states, dim3(rows > recs ? rows : recs, n_arms + 1), dim3(kStatesThreads), 0, s, arms, P,
-                     model, ss, mu, state, eps_in, k_iter, F, meta, planq, rec);
+  const int groups = n_arms * n_arms * hmax;
+  int gx = (npad_max + per_block - 1) / per_block;
+  gx = std::max(gx, (groups + kStatesThreads - 1) / kStatesThreads);
+  gx = std::max(gx, (groups + kStatesThreads / kWave - 1) / (kStatesThreads / kWave));
+  hipLaunchKernelGGL(k_sur_states, dim3(gx, n_arms + 2), dim3(kStatesThreads), 0, s, arms, P, model, ss, mu, state,
+                     eps_in, k_iter, F, meta, planq, rec, plan_read, screened);
+  return hipGetLastError();
+}
+
+// Inference descriptors of every group that needs the network, in (arm,
+// neighbour, step, 32-rollout block) order: every block scans the groups'
+// descriptor counts (Npad/32 for a live, unscreened group of arm a with
+// i != a and h below both horizons, else 0) in LDS and writes the
+// descriptors of its kItemsGroups groups at their offsets, the group's first
+// descriptor index (-1 when it has none) and, from the block holding the
+// last group, the total.
+constexpr int kItemsGroups = 8;
+constexpr int kItemsThreads = 256;
+constexpr int kMaxGroups = kMaxArms * kMaxArms * kMaxH;
+__global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __restrict__ arms,
+                                                            const Params* __restrict__ Pp,
+                                                            const uint8_t* __restrict__ screened,
+                                                            SurItem* __restrict__ items, int* __restrict__ grp_first,
+                                                            int* __restrict__ count) {
+  __shared__ int s_off[kMaxGroups + 1];
+  __shared__ int s_part[kItemsThreads];
+  const Params& P = *Pp;
+  const int tid = threadIdx.x, ng = P.A * P.A * P.Hmax;
+  auto cnt = [&](int g) -> int {
+    const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
+    if (i == a || h >= arms[a].H || h >= arms[i].H || screened[g]) return 0;
+    return arms[a].Npad / 32;
+  };
+  // Exclusive scan: each thread a contiguous run of groups, then the runs.
+  const int per = (ng + kItemsThreads - 1) / kItemsThreads;
+  const int g0 = tid * per, g1 = min(ng, g0 + per);
+  int run = 0;
+  for (int g = g0; g < g1; ++g) {
+    s_off[g] = run;
+    run += cnt(g);
+  }
+  s_part[tid] = run;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < kItemsThreads; ++k) {
+      const int v = s_part[k];
+      s_part[k] = acc;
+      acc += v;
+    }
+    s_off[ng] = acc;
+  }
+  __syncthreads();
+  for (int g = g0; g < g1; ++g) s_off[g] += s_part[tid];
+  __syncthreads();
+  const int gb = blockIdx.x * kItemsGroups;
+  for (int k = 0; k < kItemsGroups && gb + k < ng; ++k) {
+    const int g = gb + k, n = s_off[g + 1] - s_off[g];
+    if (tid == 0) grp_first[g] = n > 0 ? s_off[g] : -1;
+    if (n == 0) continue;
+    const int h = g % P.Hmax, ai = g / P.Hmax;
+    for (int e = tid; e < n; e += kItemsThreads) items[s_off[g] + e] = SurItem{ai / P.A, ai % P.A, h, 32 * e};
+  }
+  if (tid == 0 && gb <= ng - 1 && ng - 1 < gb + kItemsGroups) *count = s_off[ng];
+}
+
+hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
+                            SurItem* items, int* grp_first, int* count, hipStream_t s) {
+  const int ng = n_arms * n_arms * hmax;
+  hipLaunchKernelGGL(k_sur_items, dim3((ng + kItemsGroups - 1) / kItemsGroups), dim3(kItemsThreads), 0, s, arms, P,
+                     screened, items, grp_first, count);
   return hipGetLastError();
 }
 
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s) {
-  if (A.n_items <= 0) return hipSuccess;
+  if (!A.items || grid <= 0) return hipSuccess;  // no arm pair: nothing to predict
   hipLaunchKernelGGL(k_sur_infer, dim3(grid), dim3(kInferThreads), 0, s, A);
   return hipGetLastError();
 }

@@ -28,7 +28,7 @@ __host__ __device__ constexpr long long mlp_b_off(int l) {
 struct SurModel {
   float mid[7], inv_half[7];
   float margin;                // predictions below this are checked exactly
-  float pad;
+  float screen;                // mean-rollout distance below which a group skips the network (0 = off)
 };
 
 // GEMM: C[m][n] = sum_k A(m,k) B(k,n) over bfloat16 operands, FP32 sum.
@@ -71,22 +71,28 @@ struct SurInferArgs {
   const float* P32;            // FP32 parameters (biases are taken in FP32)
   const uint16_t* F;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16, slot 7 = in-box flag)
   const uint32_t* nbrec;       // neighbour records [A][A][Hmax][kNbrRec]
-  const SurItem* items;
-  int n_items;
-  int pad;
-  float* y;                    // predictions in descriptor order [n_items][32]
+  const SurItem* items;        // this step's descriptors (k_sur_items)
+  const int* count;            // their number (device)
+  float* y;                    // predictions in descriptor order [descriptors][32]
 };
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, const float* qi, const float* qj,
                                 int M, float* out, hipStream_t s);
-// Own-feature rows of every (arm, step, rollout) and the neighbour records
-// of every (a, i, h < Hmax) from the read-side plans, in one launch.
+// Own-feature rows of every (arm, step, rollout), the neighbour records of
+// every (a, i, h < Hmax) from the read-side plans and the screen flag of
+// every such group ([A][A][Hmax], 1: the group needs no prediction), in one
+// launch.
 // eps_in: the iteration's precomputed noise (adapted covariance), or NULL to draw sigma z.
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
                              const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
                              int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
-                             uint32_t* rec, hipStream_t s);
+                             uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s);
+// This step's inference descriptors from the screen (groups in (arm,
+// neighbour, step) order), each group's first descriptor [A][A][Hmax] (-1:
+// none) and their number.
+hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
+                            SurItem* items, int* grp_first, int* count, hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);

@@ -75,7 +75,8 @@ class MpcParams(C.Structure):
                 ("dist_floor", C.c_float), ("joint_margin", C.c_float), ("seed", C.c_ulonglong),
                 ("max_obstacles", C.c_int), ("collision_mode", C.c_int),
                 ("surrogate_margin", C.c_float), ("alpha_sigma", C.c_float), ("sigma_floor", C.c_float),
-                ("plan_mode", C.c_int), ("w_manip", C.c_float), ("manip_thresh", C.c_float)]
+                ("plan_mode", C.c_int), ("w_manip", C.c_float), ("manip_thresh", C.c_float),
+                ("surrogate_screen", C.c_float)]
 
 
 _lib = None

@@ -38,8 +38,9 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(mpc_arm_desc), offsetof(mpc_arm_desc, sphere_link),
          offsetof(mpc_arm_desc, base), offsetof(mpc_arm_desc, tool), sizeof(mpc_params));
-  printf("%zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
-         offsetof(mpc_params, collision_mode), offsetof(mpc_params, surrogate_margin));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
+         offsetof(mpc_params, collision_mode), offsetof(mpc_params, surrogate_margin),
+         offsetof(mpc_params, surrogate_screen));
   printf("%zu %zu %zu %zu\\n", sizeof(mpc_train_params), offsetof(mpc_train_params, seed),
          offsetof(mpc_train_params, lr_final), offsetof(mpc_train_params, target_floor));
   printf("%zu %zu %zu\\n", sizeof(mpc_train_report), offsetof(mpc_train_report, steps),
@@ -54,6 +55,7 @@ int main(void) {
     T, R = native.MpcTrainParams, native.MpcTrainReport
     expect = [C.sizeof(A), A.sphere_link.offset, A.base.offset, A.tool.offset, C.sizeof(P),
               P.iters.offset, P.seed.offset, P.collision_mode.offset, P.surrogate_margin.offset,
+              P.surrogate_screen.offset,
               C.sizeof(T), T.seed.offset, T.lr_final.offset, T.target_floor.offset,
               C.sizeof(R), R.steps.offset, R.val_max_over_near.offset]
     assert [int(x) for x in out] == expect

@@ -527,3 +527,93 @@ def test_learned_drops_do_not_depend_on_waves_per_workgroup():
                 np.testing.assert_array_equal(st[a], out[0][0][a])
                 np.testing.assert_array_equal(sk[a], out[0][1][a])
             assert cnt == out[0][2]
+
+
+def test_screened_groups_skip_the_network_and_stay_exact():
+    """surrogate_screen: an (arm, neighbour, step) group whose mean rollout
+    (the shifted means integrated from the sensed state) comes within the
+    screen distance of the neighbour's plan gets no prediction and all its
+    queries are checked exactly.  The GPU's screened groups equal the host's
+    rule on the oracle's kinematics (groups within 1e-5 m of the edge
+    excepted), screened groups are never dropped, and the stage costs match
+    the oracle with the neighbour inactive exactly where the GPU dropped it
+    (1e-4 relative).  With a screen wider than the scene every group is
+    screened: no descriptor at all, and the costs equal exact mode bitwise."""
+    _say("case: collision mode 1 with the screen, config 2 shape, 160 rollouts x 20 steps")
+    sc = small_scene(2, n=160, h=20)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    ref = native.Controller(sc.arms, sc.params)
+    ref.step(sc.state, sc.goal, obst)
+    ref.share_plans()
+    ref.debug_enable(True)
+    ref.step(sc.state, sc.goal, obst)
+    ref.sync()
+    q0 = ref.debug_get("Q", 0).cpu().numpy().astype(np.float64)
+    exact = [ref.debug_get("STAGE_COST", a).cpu().numpy() for a in range(2)]
+    ref.close()
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
+    f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
+    screen = 0.12
+    ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": screen})
+    ctl.set_surrogate_params(params)
+    ctl.set_collision_mode(1)
+    ctl.step(sc.state, sc.goal, obst)
+    ctl.share_plans()
+    ctl.sync()
+    boards = read_boards(ctl, sc)
+    mu1 = [ctl.get_plan(a)[2].cpu().numpy().astype(np.float64) for a in range(2)]
+    ctl.debug_enable(True)
+    ctl.surrogate_stats(reset=True)
+    ctl.step(sc.state, sc.goal, obst)
+    ctl.sync()
+    caps = [Capture(ctl, a) for a in range(2)]
+    skips = [ctl.debug_get("SKIP", a).cpu().numpy() for a in range(2)]
+    st = ctl.surrogate_stats()
+    ctl.close()
+    n_screened = n_drop = 0
+    for a in range(2):
+        i = 1 - a
+        arm, nb = sc.arms[a], sc.arms[i]
+        N, H = arm.n_rollouts, arm.horizon
+        oa = oracle.make_arm(arm)
+        st_a = sc.state[a].astype(np.float64)
+        qm, _ = oracle.integrate(st_a[:, 0], st_a[:, 1], oracle.shift(mu1[a]), f32(sc.params["dt"]))
+        drop = np.zeros((H, N), bool)
+        for h in range(min(H, nb.horizon)):
+            gap = oracle.rho_sets(oracle.spheres(oa, qm[h]), boards[i][0][h])
+            row = skips[a][i, h]
+            screened = bool(np.all(row == 2))
+            assert screened or not np.any(row == 2), (a, h)          # a whole group or nothing
+            if abs(gap - screen) > 1e-5:
+                assert screened == (gap < screen), (a, h, gap)
+            n_screened += screened
+            for b in range(N // 64):
+                if np.all(row[64 * b:64 * b + 64] == 1):
+                    drop[h, 64 * b:64 * b + 64] = True
+                    n_drop += 1
+        on = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+        off_b = list(boards)
+        off_b[i] = (boards[i][0], 0, boards[i][2])
+        off = oracle_stage(sc, a, caps[a], sc.obstacles, off_b)
+        assert rel_err(caps[a].stage, np.where(drop, off, on)) < 1e-4, a
+    _say(f"  screened groups {n_screened}, dropped blocks {n_drop}, counters {st}")
+    assert n_screened > 0 and n_drop > 0
+    assert st["waves_skipped"] == n_drop
+    # a screen wider than the scene: nothing goes through the network
+    ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": 5.0})
+    ctl.set_surrogate_params(params)
+    ctl.set_collision_mode(1)
+    ctl.step(sc.state, sc.goal, obst)
+    ctl.share_plans()
+    ctl.debug_enable(True)
+    ctl.surrogate_stats(reset=True)
+    ctl.step(sc.state, sc.goal, obst)
+    ctl.sync()
+    for a in range(2):
+        np.testing.assert_array_equal(ctl.debug_get("STAGE_COST", a).cpu().numpy(), exact[a])
+        assert torch.isnan(ctl.debug_get("PRED", a)[1 - a]).all()
+    st = ctl.surrogate_stats()
+    assert st["predicted_far"] == 0 and st["waves_skipped"] == 0 and st["queries"] > 0
+    ctl.close()
