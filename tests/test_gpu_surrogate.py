@@ -545,6 +545,9 @@ def test_screened_groups_skip_the_network_and_stay_exact():
     ref = native.Controller(sc.arms, sc.params)
     ref.step(sc.state, sc.goal, obst)
     ref.share_plans()
+    ref.sync()
+    mu_ref = [ref.get_plan(a)[2].cpu().numpy().astype(np.float64) for a in range(2)]
+    board_ref = read_boards(ref, sc)
     ref.debug_enable(True)
     ref.step(sc.state, sc.goal, obst)
     ref.sync()
@@ -555,7 +558,19 @@ def test_screened_groups_skip_the_network_and_stay_exact():
     f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
     f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
     params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
-    screen = 0.12
+
+    def mean_rollout_gaps(a, mu1, boards):
+        i = 1 - a
+        st_a = sc.state[a].astype(np.float64)
+        qm, _ = oracle.integrate(st_a[:, 0], st_a[:, 1], oracle.shift(mu1), f32(sc.params["dt"]))
+        oa = oracle.make_arm(sc.arms[a])
+        return [oracle.rho_sets(oracle.spheres(oa, qm[h]), boards[i][0][h])
+                for h in range(min(sc.arms[a].horizon, sc.arms[i].horizon))]
+
+    # the screen distance at the median gap: about half the groups screened
+    gaps = np.concatenate([mean_rollout_gaps(a, mu_ref[a], board_ref) for a in range(2)])
+    screen = float(np.float32(np.median(gaps)))
+    _say(f"  mean-rollout gaps {gaps.min():.4f} .. {gaps.max():.4f} m, screen {screen:.4f} m")
     ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": screen})
     ctl.set_surrogate_params(params)
     ctl.set_collision_mode(1)
@@ -577,12 +592,10 @@ def test_screened_groups_skip_the_network_and_stay_exact():
         i = 1 - a
         arm, nb = sc.arms[a], sc.arms[i]
         N, H = arm.n_rollouts, arm.horizon
-        oa = oracle.make_arm(arm)
-        st_a = sc.state[a].astype(np.float64)
-        qm, _ = oracle.integrate(st_a[:, 0], st_a[:, 1], oracle.shift(mu1[a]), f32(sc.params["dt"]))
+        g_a = mean_rollout_gaps(a, mu1[a], boards)
         drop = np.zeros((H, N), bool)
         for h in range(min(H, nb.horizon)):
-            gap = oracle.rho_sets(oracle.spheres(oa, qm[h]), boards[i][0][h])
+            gap = g_a[h]
             row = skips[a][i, h]
             screened = bool(np.all(row == 2))
             assert screened or not np.any(row == 2), (a, h)          # a whole group or nothing
