@@ -559,7 +559,7 @@ def fig1(steps, seeds, dev):
     return out
 
 
-SCREEN_SWEEP = (0.0, 0.05, 0.1, 0.15, 0.2)
+SCREEN_SWEEP = (0.0, 0.1, 0.2, 0.3, 0.4, 0.6)
 
 
 def screen_sweep(config, params, stream, dev, steps, warmup):
@@ -677,17 +677,18 @@ def main():
         w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev)
         ctl2.close()
         q = max(st["queries"], 1)
-        # Inference roofline: every (rollout, step, neighbour) query costs the
-        # network's multiply-adds (17*256 + 2*256*256 + 256) x 2 FLOP.
-        n_queries = sum(a.n_rollouts * min(a.horizon, b.horizon) for i, a in enumerate(scene.arms)
-                        for j, b in enumerate(scene.arms) if i != j)
-        mlp_flops = n_queries * 2 * (17 * 256 + 2 * 256 * 256 + 256)
+        # Inference roofline: every query row the network runs (the screened
+        # groups' queries run none) costs its multiply-adds
+        # (17*256 + 2*256*256 + 256) x 2 FLOP.
+        rows_per_launch = st["network_rows"] / args.steps
+        mlp_flops = rows_per_launch * 2 * (17 * 256 + 2 * 256 * 256 + 256)
         inf_ach = mlp_flops / (st["infer_ms"] * 1e-3) / 1e12
         out["surrogate"] = {
             "value": rs_per_step / (w2 / args.steps), "unit": "rollout-steps/s",
             "ms_per_step": 1e3 * w2 / args.steps, "speedup_vs_exact": wall / w2,
             "latency_ms": {"p50": float(np.percentile(lat2, 50)), "p99": float(np.percentile(lat2, 99))},
             "rollout_kernel_ms": roll2, "queries_predicted_far": st["predicted_far"] / q,
+            "queries_through_network": st["network_rows"] / q,
             "roofline": {"kernel": "k_sur_infer", "bound": "mfma", "achieved": inf_ach, "peak": BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": inf_ach / BF16_PEAK_TFLOPS, "traffic": None,
                          "kernel_ms": st["infer_ms"], "algorithmic_flop_per_launch": mlp_flops},

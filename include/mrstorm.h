@@ -335,9 +335,11 @@ int mpc_set_collision_mode(mpc_ctx *c, int mode);
  * costs stay those of mode 1) and count their queries whose exact distance
  * is below buf_dyn (misses) or below zero (missed collisions). */
 int mpc_surrogate_audit(mpc_ctx *c, int on);
-/* Counters summed over arms since the last reset: out[5] = queries, far
+/* Counters summed over arms since the last reset: out[6] = queries, far
  * queries, dropped (block, neighbour, step) checks of 64 rollouts, misses,
- * missed collisions (the last two only while auditing).  Waits for the GPU. */
+ * missed collisions (the last two only while auditing), query rows run
+ * through the network (32 per descriptor, padded rollouts included; the
+ * screen lowers it).  Waits for the GPU. */
 int mpc_surrogate_stats(mpc_ctx *c, unsigned long long *out, int reset);
 
 /* Device Philox4x32-10 (the noise generator) on n counters: ctr [n][4],

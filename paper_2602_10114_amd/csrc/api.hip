@@ -125,7 +125,7 @@ struct mpc_ctx {
   int n_items = 0;
   int h_tile = 0, grid = 0, waves = 1;  // launch shape: horizon tile, workgroups, 64-rollout waves per workgroup
   int force_tile = 0, force_grid = 0, force_waves = 0;
-  unsigned long long* tune_counts = nullptr;  // learned-distance counters of tuner replays [A][5]
+  unsigned long long* tune_counts = nullptr;  // learned-distance counters of tuner replays [A][kSurCounters]
   bool tuned = false;
   int n_published = 0;                 // arms whose plan has been published at least once
   std::vector<char> published;
@@ -162,7 +162,7 @@ struct mpc_ctx {
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
   float* sur_y = nullptr;              // predictions in descriptor order [items][32]
   bool sur_bufs = false;               // every learned-distance step buffer allocated
-  unsigned long long* sur_counts = nullptr;  // [A][5]
+  unsigned long long* sur_counts = nullptr;  // [A][kSurCounters]
   SurItem* d_sur_items = nullptr;
   int n_sur_items = 0;
   int sur_grid = 0;
@@ -435,7 +435,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   if ((rc = dalloc(c, &c->d_model, 1)) || (rc = dalloc(c, &c->sur_p, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_m, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_v, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_g, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_p16, (size_t)kMlpParams)) ||
-      (rc = dalloc(c, &c->sur_counts, 5 * A))) {
+      (rc = dalloc(c, &c->sur_counts, kSurCounters * A))) {
     g_last_error = c->err;
     mpc_destroy(c);
     return rc;
@@ -592,7 +592,7 @@ static int set_items(mpc_ctx* c, int T, int W) {
   return MPC_OK;
 }
 
-static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug);
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts);
 
 // Launch-shape tuner: times the rollout launch for every candidate number of
 // waves per workgroup, horizon tile and grid size on the live inputs of the
@@ -631,12 +631,12 @@ static int tune(mpc_ctx* c) {
     if (std::find(tiles.begin(), tiles.end(), c->Hmax) == tiles.end()) tiles.push_back(c->Hmax);
   }
   if (c->collision_mode == 1 && !c->tune_counts) {
-    int rc = dalloc(c, &c->tune_counts, (size_t)5 * c->A);
+    int rc = dalloc(c, &c->tune_counts, (size_t)kSurCounters * c->A);
     if (rc) return rc;
   }
   if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
   if (c->collision_mode == 1) {
-    int rc = enqueue_learned_prelude(c, 0, false);
+    int rc = enqueue_learned_prelude(c, 0, false, c->tune_counts);
     if (rc) return rc;
   }
   hipEvent_t e0, e1;
@@ -693,7 +693,7 @@ static int tune(mpc_ctx* c) {
 // then the network's prediction of every (rollout, step, neighbour) query;
 // the rollout kernel takes the skip decisions from the predictions and
 // counts the queries.  In a debug step the capture buffers start cleared.
-static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug) {
+static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts) {
   const float* eps_in = c->P.cov ? c->eps : nullptr;
   if (debug) {
     const size_t n = (size_t)c->A * c->A * c->Hmax * c->Nmax;
@@ -704,7 +704,7 @@ static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug) {
                               c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->plan[0], c->sur_screen,
                               c->stream));
   HIPCHK(c, launch_sur_items(c->d_arms, c->d_P, c->sur_screen, c->A, c->Hmax, c->d_sur_items, c->sur_grp, c->sur_count,
-                             c->stream));
+                             counts, c->stream));
   SurInferArgs I{};
   I.P = c->d_P;
   I.model = c->d_model;
@@ -734,7 +734,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
       HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A, c->Nmax, c->manip,
                              c->stream));
     if (c->collision_mode == 1) {
-      int rc = enqueue_learned_prelude(c, k, debug);
+      int rc = enqueue_learned_prelude(c, k, debug, c->sur_counts);
       if (rc) return rc;
     }
     hipEvent_t e1 = nullptr;
@@ -1552,12 +1552,12 @@ extern "C" int mpc_surrogate_audit(mpc_ctx* c, int on) {
 
 extern "C" int mpc_surrogate_stats(mpc_ctx* c, unsigned long long* out, int reset) {
   if (!c || !out) return MPC_EINVAL;
-  std::vector<unsigned long long> h(5 * c->A);
+  std::vector<unsigned long long> h(kSurCounters * c->A);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(h.data(), c->sur_counts, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kSurCounters; ++k) {
     out[k] = 0;
-    for (int a = 0; a < c->A; ++a) out[k] += h[5 * a + k];
+    for (int a = 0; a < c->A; ++a) out[k] += h[kSurCounters * a + k];
   }
   if (reset) HIPCHK(c, hipMemset(c->sur_counts, 0, h.size() * sizeof(unsigned long long)));
   return MPC_OK;

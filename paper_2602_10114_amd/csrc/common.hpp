@@ -13,6 +13,10 @@ constexpr int kMaxPerBody = 8;
 constexpr int kMaxH = 64;
 constexpr int kMaxObs = 64;
 constexpr int kWave = 64;
+// Learned-distance counters per arm: live queries, predicted far, dropped
+// 64-rollout checks, audited misses (< B), audited missed collisions (< 0),
+// query rows run through the network.
+constexpr int kSurCounters = 6;
 
 // Sphere layouts compiled into the rollout kernel: spheres sorted by body,
 // `count[b]` slots per body.  Layout 0 = the 52-sphere tiling (4,6,6,6,8,6,8,8),

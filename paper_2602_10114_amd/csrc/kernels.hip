@@ -655,7 +655,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       if (tid == 0) {
 #pragma unroll
         for (int c2 = 0; c2 < 5; ++c2)
-          if (L.sur[c2]) atomicAdd(A.sur_counts + 5 * a + c2, (unsigned long long)L.sur[c2]);
+          if (L.sur[c2]) atomicAdd(A.sur_counts + kSurCounters * a + c2, (unsigned long long)L.sur[c2]);
       }
     }
     if (DBG && lane == 0) {

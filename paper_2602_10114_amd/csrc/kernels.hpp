@@ -34,7 +34,7 @@ struct RolloutArgs {
   // (arm, neighbour, step) group [A][A][Hmax] (-1: no prediction, the group's
   // queries are checked exactly), the own-feature rows (slot 7 = in-box flag)
   // and neighbour records (word 5 bit 0 = neighbour in box), the margin, and
-  // the counters [A][5]; the debug instantiation also stores each live
+  // the counters [A][kSurCounters]; the debug instantiation also stores each live
   // query's prediction (NaN without one) and decision (1 far, 0 near, 2 no
   // prediction) [A][A][Hmax][Nmax]
   int learned;

@@ -1004,7 +1004,8 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
                                                             const Params* __restrict__ Pp,
                                                             const uint8_t* __restrict__ screened,
                                                             SurItem* __restrict__ items, int* __restrict__ grp_first,
-                                                            int* __restrict__ count) {
+                                                            int* __restrict__ count,
+                                                            unsigned long long* __restrict__ counts) {
   __shared__ int s_off[kMaxGroups + 1];
   __shared__ int s_part[kItemsThreads];
   const Params& P = *Pp;
@@ -1041,6 +1042,8 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
     const int g = gb + k, n = s_off[g + 1] - s_off[g];
     if (tid == 0) grp_first[g] = n > 0 ? s_off[g] : -1;
     if (n == 0) continue;
+    // query rows the network will run for this group (counter slot 5)
+    if (tid == 0 && counts) atomicAdd(counts + kSurCounters * (g / P.Hmax / P.A) + 5, (unsigned long long)n * 32ull);
     const int h = g % P.Hmax, ai = g / P.Hmax;
     for (int e = tid; e < n; e += kItemsThreads) items[s_off[g] + e] = SurItem{ai / P.A, ai % P.A, h, 32 * e};
   }
@@ -1048,10 +1051,10 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
 }
 
 hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
-                            SurItem* items, int* grp_first, int* count, hipStream_t s) {
+                            SurItem* items, int* grp_first, int* count, unsigned long long* counts, hipStream_t s) {
   const int ng = n_arms * n_arms * hmax;
   hipLaunchKernelGGL(k_sur_items, dim3((ng + kItemsGroups - 1) / kItemsGroups), dim3(kItemsThreads), 0, s, arms, P,
-                     screened, items, grp_first, count);
+                     screened, items, grp_first, count, counts);
   return hipGetLastError();
 }
 

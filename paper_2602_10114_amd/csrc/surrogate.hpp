@@ -92,7 +92,7 @@ hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel
 // neighbour, step) order), each group's first descriptor [A][A][Hmax] (-1:
 // none) and their number.
 hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
-                            SurItem* items, int* grp_first, int* count, hipStream_t s);
+                            SurItem* items, int* grp_first, int* count, unsigned long long* counts, hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);

@@ -385,10 +385,10 @@ class Controller:
         _check(lib().mpc_surrogate_audit(self.h, 1 if on else 0), self.h)
 
     def surrogate_stats(self, reset=False):
-        out = (C.c_ulonglong * 5)()
+        out = (C.c_ulonglong * 6)()
         _check(lib().mpc_surrogate_stats(self.h, C.cast(out, C.c_void_p), 1 if reset else 0), self.h)
-        return dict(zip(["queries", "predicted_far", "waves_skipped", "misses", "missed_collisions"],
-                        [int(x) for x in out]))
+        return dict(zip(["queries", "predicted_far", "waves_skipped", "misses", "missed_collisions",
+                         "network_rows"], [int(x) for x in out]))
 
 
 def philox(ctr, key, stream=None):
