@@ -547,7 +547,6 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.sur_counts = c->sur_counts;
   R.dbg_pred = c->sur_pred;
   R.dbg_skip = c->sur_skip;
-  R.eps_in = c->P.cov ? c->eps : nullptr;
   R.manip = c->manip;
   return R;
 }
@@ -594,6 +593,12 @@ static int set_items(mpc_ctx* c, int T, int W) {
 
 static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts);
 
+// Noise of iteration k: sigma z, or L_h z with the adapted covariance.
+static hipError_t enqueue_noise(mpc_ctx* c, int k) {
+  return launch_noise(c->d_arms, c->d_P, c->d_ss, c->P.cov ? c->chol : nullptr, c->eps, k, c->A, c->Hmax, c->Nmax,
+                      c->stream);
+}
+
 // Launch-shape tuner: times the rollout launch for every candidate number of
 // waves per workgroup, horizon tile and grid size on the live inputs of the
 // first representative step and keeps the fastest; the choice is cached per
@@ -634,7 +639,7 @@ static int tune(mpc_ctx* c) {
     int rc = dalloc(c, &c->tune_counts, (size_t)kSurCounters * c->A);
     if (rc) return rc;
   }
-  if (c->P.cov) HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, 0, c->A, c->Nmax, c->stream));
+  HIPCHK(c, enqueue_noise(c, 0));
   if (c->collision_mode == 1) {
     int rc = enqueue_learned_prelude(c, 0, false, c->tune_counts);
     if (rc) return rc;
@@ -694,13 +699,13 @@ static int tune(mpc_ctx* c) {
 // the rollout kernel takes the skip decisions from the predictions and
 // counts the queries.  In a debug step the capture buffers start cleared.
 static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts) {
-  const float* eps_in = c->P.cov ? c->eps : nullptr;
+  (void)k;
   if (debug) {
     const size_t n = (size_t)c->A * c->A * c->Hmax * c->Nmax;
     HIPCHK(c, hipMemsetAsync(c->sur_skip, 0, n, c->stream));
     HIPCHK(c, hipMemsetAsync(c->sur_pred, 0, n * sizeof(float), c->stream));
   }
-  HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, eps_in, k, c->A, c->Nmax,
+  HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, c->eps, c->A, c->Nmax,
                               c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->plan[0], c->sur_screen,
                               c->stream));
   HIPCHK(c, launch_sur_items(c->d_arms, c->d_P, c->sur_screen, c->A, c->Hmax, c->d_sur_items, c->sur_grp, c->sur_count,
@@ -728,10 +733,9 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
   ReduceArgs Rr = reduce_args(c);
   for (int k = 0; k < c->P.iters; ++k) {
     RolloutArgs R = rollout_args(c, k);
-    if (c->P.cov)
-      HIPCHK(c, launch_noise(c->d_arms, c->d_P, c->d_ss, c->chol, c->eps, k, c->A, c->Nmax, c->stream));
+    HIPCHK(c, enqueue_noise(c, k));
     if (c->manip)
-      HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, R.eps_in, k, c->A, c->Nmax, c->manip,
+      HIPCHK(c, launch_manip(c->d_arms, c->d_P, c->d_ss, c->mu, c->st_state, c->eps, c->A, c->Nmax, c->manip,
                              c->stream));
     if (c->collision_mode == 1) {
       int rc = enqueue_learned_prelude(c, k, debug, c->sur_counts);

@@ -38,38 +38,28 @@ __device__ __forceinline__ float unit_open(uint32_t x) {
 }
 
 // Standard normals of rollout n, step h, iteration k, control step t of arm
-// `arm` for joints 0..dof-1 (dof <= 8): counter (n, 2h+c, t, arm<<8|k),
+// `arm`: counter (n, 2h+c, t, arm<<8|k) gives joints 4c..4c+3 by
 // Box-Muller on word pairs (0,1) and (2,3), lanes cos, sin, cos, sin.
-__device__ __forceinline__ void normals8(uint32_t slo, uint32_t shi, int arm, uint32_t t, int k,
-                                         int n, int h, float z[8]) {
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    uint32_t c0 = (uint32_t)n, c1 = (uint32_t)(2 * h + c), c2 = t, c3 = ((uint32_t)arm << 8) | (uint32_t)k;
-    philox4x32_10(c0, c1, c2, c3, slo, shi);
-    const float r01 = sqrtf(-2.0f * logf(unit_open(c0)));
-    const float r23 = sqrtf(-2.0f * logf(unit_open(c2)));
-    float s1, co1, s3, co3;
-    sincospif(2.0f * unit_open(c1), &s1, &co1);
-    sincospif(2.0f * unit_open(c3), &s3, &co3);
-    z[4 * c + 0] = r01 * co1;
-    z[4 * c + 1] = r01 * s1;
-    z[4 * c + 2] = r23 * co3;
-    z[4 * c + 3] = r23 * s3;
-  }
+__device__ __forceinline__ void normals4(uint32_t slo, uint32_t shi, int arm, uint32_t t, int k, int n, int h,
+                                         int c, float z[4]) {
+  uint32_t c0 = (uint32_t)n, c1 = (uint32_t)(2 * h + c), c2 = t, c3 = ((uint32_t)arm << 8) | (uint32_t)k;
+  philox4x32_10(c0, c1, c2, c3, slo, shi);
+  const float r01 = sqrtf(-2.0f * logf(unit_open(c0)));
+  const float r23 = sqrtf(-2.0f * logf(unit_open(c2)));
+  float s1, co1, s3, co3;
+  sincospif(2.0f * unit_open(c1), &s1, &co1);
+  sincospif(2.0f * unit_open(c3), &s3, &co3);
+  z[0] = r01 * co1;
+  z[1] = r01 * s1;
+  z[2] = r23 * co3;
+  z[3] = r23 * s3;
 }
 
-// Joint j's value of normals8 computed alone: the same counter, the same
-// Box-Muller word pair and the same cos / sin lane, so the result is
-// bit-identical.
-__device__ __forceinline__ float normal1(uint32_t slo, uint32_t shi, int arm, uint32_t t, int k, int n, int h,
-                                        int j) {
-  uint32_t c0 = (uint32_t)n, c1 = (uint32_t)(2 * h + (j >> 2)), c2 = t, c3 = ((uint32_t)arm << 8) | (uint32_t)k;
-  philox4x32_10(c0, c1, c2, c3, slo, shi);
-  const bool second = ((j >> 1) & 1) != 0;
-  const float r = sqrtf(-2.0f * logf(unit_open(second ? c2 : c0)));
-  float sn, cs;
-  sincospif(2.0f * unit_open(second ? c3 : c1), &sn, &cs);
-  return r * ((j & 1) ? sn : cs);
+// All joints 0..dof-1 (dof <= 8) of one rollout step.
+__device__ __forceinline__ void normals8(uint32_t slo, uint32_t shi, int arm, uint32_t t, int k, int n, int h,
+                                         float z[8]) {
+  normals4(slo, shi, arm, t, k, n, h, 0, z);
+  normals4(slo, shi, arm, t, k, n, h, 1, z + 4);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,10 +1,12 @@
 // gfx950 kernels of one MR-STORM control step (arXiv 2602.10114, Alg. 1):
 //   k_sense      Sense + Shift: stage inputs, own distance to goal, priority
 //                factors (Eq. 10), neighbour table, left shift of the means.
-//   k_rollout    SampleControls + Rollout for every arm in one launch: noise,
-//                dynamics, forward kinematics over the collision spheres, the
-//                stage cost of Eq. 5 with the coordination term of Eqs. 6-9,
-//                written per rollout step.
+//   k_noise      SampleControls: the iteration's Gaussian noise of every
+//                (arm, step, rollout), isotropic or from the adapted covariance.
+//   k_rollout    Rollout for every arm in one launch: dynamics, forward
+//                kinematics over the collision spheres, the stage cost of
+//                Eq. 5 with the coordination term of Eqs. 6-9, written per
+//                rollout step.
 //   k_total      Eq. 1 totals from the per-step stage costs.
 //   k_softmax    Eq. 2 weights, PickBest (Act).
 //   k_wmean      Eq. 3 weighted sums per chunk of rollouts; k_wmean_fin (or
@@ -375,7 +377,6 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const Params& P = *Pp;
   const StepState& SS = *ssp;
-  const uint32_t t = SS.t;
   const int n_obs = SS.n_obs;
   // Obstacles are the same for every item of this launch.
   for (int o = tid; o < n_obs; o += kThreads)
@@ -389,7 +390,8 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
     const int n = item.block * kThreads + tid;
     const bool live = n < N;
     const float* __restrict__ mu = mu_all + (size_t)a * P.Hmax * 7;
-    float* __restrict__ eps = A.eps + arm->eps_off;
+    // The iteration's noise (drawn by k_noise before the launch), column n.
+    const float* __restrict__ eps = A.eps + arm->eps_off + n;
     const int Npad = arm->Npad;
     __syncthreads();
     if (tid < kWave) L.slot[tid] = reinterpret_cast<const float4*>(arm->slot)[tid];
@@ -402,17 +404,11 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       qd[j] = state[(a * 7 + j) * 3 + 1];
     }
     q[7] = qd[7] = 0.f;
-    // Integration prefix of this horizon tile (noise regenerated, not stored).
+    // Integration prefix of this horizon tile.
     for (int h = 0; h < item.h0; ++h) {
-      float z[8];
-      if (A.eps_in) {
+      float z[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) z[j] = A.eps_in[arm->eps_off + ((size_t)h * 7 + j) * Npad + n];
-      } else {
-        normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
-      }
+      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(h * 7 + j) * Npad];
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         const float u = z[j] + mu[h * 7 + j];
@@ -469,18 +465,9 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
         }
       }
 
-      float z[8];
-      if (A.eps_in) {
+      float z[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) z[j] = A.eps_in[arm->eps_off + ((size_t)h * 7 + j) * Npad + n];
-      } else {
-        normals8(P.seed_lo, P.seed_hi, a, t, A.k, n, h, z);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-          z[j] *= P.sigma;
-          if (live) eps[((size_t)h * 7 + j) * Npad + n] = z[j];
-        }
-      }
+      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(h * 7 + j) * Npad];
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         const float e = z[j];
@@ -840,20 +827,19 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
 }
 
 // Manipulability term of Eq. 5 for every rollout step: the rollout's joints
-// (the same noise and integration as the rollout kernel), the end-effector
+// (the iteration's noise, integrated as in the rollout kernel), the end-effector
 // point by the same walking frame, the geometric Jacobian (column k = (z_k x
 // (p_ee - o_k), z_k) from frame k), J J^T and its Cholesky factor, whose
 // pivot product is sqrt(det(J J^T)); C_manip = max(0, 1 - that / thresh).
 __global__ __launch_bounds__(kWave) void k_manip(const DevArm* __restrict__ arms, const Params* __restrict__ Pp,
                                                  const StepState* __restrict__ ssp, const float* __restrict__ mu_all,
-                                                 const float* __restrict__ state, const float* __restrict__ eps_in,
-                                                 int k_iter, float* __restrict__ out) {
+                                                 const float* __restrict__ state, const float* __restrict__ eps,
+                                                 float* __restrict__ out) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
   const DevArm* arm = arms + a;
   const int n = blockIdx.x * kWave + threadIdx.x;
   if (n >= arm->Npad) return;
-  const uint32_t t = ssp->t;
   const float* mu = mu_all + (size_t)a * P.Hmax * 7;
   float q[8], qd[8];
   for (int j = 0; j < 7; ++j) {
@@ -862,13 +848,8 @@ __global__ __launch_bounds__(kWave) void k_manip(const DevArm* __restrict__ arms
   }
   q[7] = qd[7] = 0.f;
   for (int h = 0; h < arm->H; ++h) {
-    float z[8];
-    if (eps_in) {
-      for (int j = 0; j < 7; ++j) z[j] = eps_in[arm->eps_off + ((size_t)h * 7 + j) * arm->Npad + n];
-    } else {
-      normals8(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, z);
-      for (int j = 0; j < 7; ++j) z[j] *= P.sigma;
-    }
+    float z[7];
+    for (int j = 0; j < 7; ++j) z[j] = eps[arm->eps_off + ((size_t)h * 7 + j) * arm->Npad + n];
     for (int j = 0; j < 7; ++j) {
       const float u = z[j] + mu[h * 7 + j];
       qd[j] = fmaf_(P.dt, u, qd[j]);
@@ -918,31 +899,39 @@ __global__ __launch_bounds__(kWave) void k_manip(const DevArm* __restrict__ arms
   }
 }
 
-// Noise with the adapted covariance (Eqs. 3-4): eps_{n,h} = L_h z_{n,h}, L_h
-// the Cholesky factor of Sigma_h, z the same standard normals as the rollout
-// kernel draws; written in its [H][7][Npad] per-arm layout.
-__global__ __launch_bounds__(kWave) void k_noise(const DevArm* __restrict__ arms, const Params* __restrict__ Pp,
-                                                 const StepState* __restrict__ ssp, const float* __restrict__ chol,
-                                                 float* __restrict__ eps, int k) {
+// The iteration's exploration noise of every (arm, step, rollout), padded
+// rollouts included, in the [H][7][Npad] per-arm layout that the rollout,
+// manipulability, learned-distance and weighted-mean kernels read: sigma z
+// (Sec. III-A's Gaussian sampling), or with the adapted covariance (Eqs. 3-4)
+// L_h z, L_h the Cholesky factor of Sigma_h (`chol` non-null).  One thread per
+// (arm, step, rollout), so the launch is wide whatever the horizon.
+constexpr int kNoiseThreads = 256;
+__global__ __launch_bounds__(kNoiseThreads) void k_noise(const DevArm* __restrict__ arms,
+                                                         const Params* __restrict__ Pp,
+                                                         const StepState* __restrict__ ssp,
+                                                         const float* __restrict__ chol, float* __restrict__ eps,
+                                                         int k) {
   const Params& P = *Pp;
-  const int a = blockIdx.y;
+  const int a = blockIdx.z, h = blockIdx.y;
   const DevArm* arm = arms + a;
-  const int n = blockIdx.x * kWave + threadIdx.x;
-  if (n >= arm->Npad) return;
-  const uint32_t t = ssp->t;
+  const int n = blockIdx.x * kNoiseThreads + threadIdx.x;
+  if (h >= arm->H || n >= arm->Npad) return;
   const int Npad = arm->Npad;
-  float* out = eps + arm->eps_off;
-  for (int h = 0; h < arm->H; ++h) {
-    float z[8];
-    normals8(P.seed_lo, P.seed_hi, a, t, k, n, h, z);
+  float z[8];
+  normals8(P.seed_lo, P.seed_hi, a, ssp->t, k, n, h, z);
+  float* out = eps + arm->eps_off + (size_t)h * 7 * Npad + n;
+  if (chol) {
     const float* L = chol + ((size_t)a * P.Hmax + h) * kTri;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
       float e = 0.f;
 #pragma unroll
       for (int m = 0; m <= j; ++m) e = fmaf_(L[tri7(j, m)], z[m], e);
-      out[((size_t)h * 7 + j) * Npad + n] = e;
+      out[(size_t)j * Npad] = e;
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) out[(size_t)j * Npad] = z[j] * P.sigma;
   }
 }
 
@@ -1292,16 +1281,16 @@ hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s) {
 }
 
 hipError_t launch_manip(const DevArm* arms, const Params* P, const StepState* ss, const float* mu, const float* state,
-                        const float* eps_in, int k, int n_arms, int npad_max, float* out, hipStream_t s) {
+                        const float* eps, int n_arms, int npad_max, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_manip, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, ss, mu, state,
-                     eps_in, k, out);
+                     eps, out);
   return hipGetLastError();
 }
 
 hipError_t launch_noise(const DevArm* arms, const Params* P, const StepState* ss, const float* chol, float* eps, int k,
-                        int n_arms, int npad_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_noise, dim3((npad_max + kWave - 1) / kWave, n_arms), dim3(kWave), 0, s, arms, P, ss, chol, eps,
-                     k);
+                        int n_arms, int hmax, int npad_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_noise, dim3((npad_max + kNoiseThreads - 1) / kNoiseThreads, hmax, n_arms), dim3(kNoiseThreads),
+                     0, s, arms, P, ss, chol, eps, k);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ struct RolloutArgs {
   int k;                       // optimisation iteration
   int pad;
   const float* mu;             // [A][Hmax][7]
-  float* eps;                  // per-arm [H][7][Npad] blocks
+  const float* eps;            // the iteration's noise, per-arm [H][7][Npad] blocks (k_noise)
   float* partial;              // stage costs [A][kMaxH][Nmax] (step-major)
   const float* state;          // staged [A][7][3]
   const float* goal;           // staged [A][7]
@@ -48,9 +48,6 @@ struct RolloutArgs {
   unsigned long long* sur_counts;
   float* dbg_pred;
   uint8_t* dbg_skip;
-  // adapted covariance: the iteration's noise, precomputed (same layout as
-  // eps); NULL = draw sigma z in the kernel
-  const float* eps_in;
   // C_manip of every (arm, step, rollout) [A][Hmax][Nmax], or NULL (w_manip = 0)
   const float* manip;
 };
@@ -121,12 +118,13 @@ hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, boo
 // ToPlan; with `fin` it first applies the last iteration's totals and Eq. 4.
 hipError_t launch_toplan(const ReduceArgs& A, int n_arms, bool fin, hipStream_t s);
 hipError_t launch_publish(const PublishArgs& A, int n_arms, hipStream_t s);
-// C_manip (Eq. 5) of every rollout step of iteration k: out [A][Hmax][Nmax].
+// C_manip (Eq. 5) of every rollout step from the iteration's noise: out [A][Hmax][Nmax].
 hipError_t launch_manip(const DevArm* arms, const Params* P, const StepState* ss, const float* mu, const float* state,
-                        const float* eps_in, int k, int n_arms, int npad_max, float* out, hipStream_t s);
-// Noise of iteration k from the adapted covariances: eps = L_h z.
+                        const float* eps, int n_arms, int npad_max, float* out, hipStream_t s);
+// Noise of iteration k for every arm, step and padded rollout: sigma z, or
+// L_h z from the adapted covariances' factors when `chol` is non-null.
 hipError_t launch_noise(const DevArm* arms, const Params* P, const StepState* ss, const float* chol, float* eps, int k,
-                        int n_arms, int npad_max, hipStream_t s);
+                        int n_arms, int hmax, int npad_max, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n, hipStream_t s);
 hipError_t launch_sim_execute(float* state, const float* u, int n, float dt, hipStream_t s);
 hipError_t launch_copy3d(const float* src, long long s0, long long s1, long long s2, float* dst,

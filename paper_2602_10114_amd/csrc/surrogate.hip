@@ -383,13 +383,6 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 }
 
 // ---------------------------------------------------------------------------
-// Own-joint features of every (arm, step, rollout) for the learned distance:
-// the same noise and integration as the rollout kernel, then the normalised
-// joints as one 16-byte row of bfloat16 [f0..f6, in-box flag] (flag 1.0 when
-// all seven lie within the training box, else 0.0).  Eight lanes per
-// rollout: lane j < 7 integrates joint j (the joints are independent) and
-// writes its feature; lane 7 writes the flag, the AND of the group's box
-// tests taken with a ballot.  The eight 2-byte writes form the row.
 // Screen of one (arm a, neighbour i, step h) group, one wave: 1 when no query
 // of the group needs the network -- the neighbour's plan is not published
 // (its queries are not live), or the arm's mean rollout (the means
@@ -430,8 +423,14 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
         int b = 0;
         while (lane >= kLayoutStart[arm->layout][b + 1]) ++b;
         const float* p = arm->slot[lane];
+        // the body's frame picked by selects (no indexed register array)
+        const int fb = b < 7 ? b : 6;
+        Frame Fb = F[0];
+#pragma unroll
+        for (int k = 1; k < 7; ++k)
+          if (k == fb) Fb = F[k];
         float x, y, z;
-        frame_point(F[b < 7 ? b : 6], p[0], p[1], p[2], x, y, z);
+        frame_point(Fb, p[0], p[1], p[2], x, y, z);
         const float4* pl = reinterpret_cast<const float4*>(plan_read) + ((size_t)i * P.Hmax + h) * P.Smax;
         for (int k = 0; k < nb->S; ++k) {
           const float4 o = pl[k];
@@ -447,9 +446,17 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
   if (lane == 0) flag[g] = f;
 }
 
-// The launch's row of blocks blockIdx.y = number of arms writes the
-// neighbour records, one thread per (arm, neighbour, step); the next row
-// screens the (arm, neighbour, step) groups, one wave each.
+// Rows of blocks blockIdx.y < number of arms: own-joint features of every
+// (arm, step, rollout) for the learned distance -- the iteration's noise
+// integrated as in the rollout kernel, then the normalised joints as one
+// 16-byte row of bfloat16 [f0..f6, in-box flag] (flag 1.0 when all seven lie
+// within the training box, else 0.0).  Eight lanes per rollout: lane j < 7
+// integrates joint j (the joints are independent) and writes its feature;
+// lane 7 writes the flag, the AND of the group's box tests taken with a
+// ballot.  The eight 2-byte writes form the row.
+// The row blockIdx.y = number of arms writes the neighbour records, one
+// thread per (arm, neighbour, step); the next row screens the (arm,
+// neighbour, step) groups, one wave each.
 constexpr int kStatesThreads = 256;
 __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __restrict__ arms,
                                                                const Params* __restrict__ Pp,
@@ -457,7 +464,7 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
                                                                const StepState* __restrict__ ssp,
                                                                const float* __restrict__ mu_all,
                                                                const float* __restrict__ state,
-                                                               const float* __restrict__ eps_in, int k_iter,
+                                                               const float* __restrict__ eps,
                                                                uint16_t* __restrict__ F,
                                                                const BoardMeta* __restrict__ meta,
                                                                const float* __restrict__ planq,
@@ -486,28 +493,33 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
   // arm's padded count (Npad is a multiple of 64, so a wave is all in or all
   // out and every lane takes part in the ballots below).
   if (n >= arm->Npad) return;
-  const uint32_t t = ssp->t;
   const float* mu = mu_all + (size_t)a * P.Hmax * 7;
   const int jj = j < 7 ? j : 0;
   float q = state[(a * 7 + jj) * 3 + 0], qd = state[(a * 7 + jj) * 3 + 1];
   const float mid = sm->mid[jj], ih = sm->inv_half[jj];
   const int group_shift = lane & ~7;
-  for (int h = 0; h < arm->H; ++h) {
-    float z;
-    if (eps_in) {
-      z = eps_in[arm->eps_off + ((size_t)h * 7 + jj) * arm->Npad + n];
-    } else {
-      z = normal1(P.seed_lo, P.seed_hi, a, t, k_iter, n, h, jj) * P.sigma;
+  const int H = arm->H, Npad = arm->Npad;
+  const float* zc = eps + arm->eps_off + (size_t)jj * Npad + n;  // the lane's noise column
+  // Steps in groups of kStatesAhead: the group's noise loads go out together.
+  constexpr int kStatesAhead = 8;
+  for (int h0 = 0; h0 < H; h0 += kStatesAhead) {
+    float z[kStatesAhead];
+#pragma unroll
+    for (int u = 0; u < kStatesAhead; ++u) z[u] = h0 + u < H ? zc[(size_t)(h0 + u) * 7 * Npad] : 0.f;
+#pragma unroll
+    for (int u = 0; u < kStatesAhead; ++u) {
+      const int h = h0 + u;
+      if (h >= H) break;  // uniform
+      const float uu = z[u] + mu[h * 7 + jj];
+      qd = fmaf_(P.dt, uu, qd);
+      q = fmaf_(P.dt, qd, q);
+      const float x = (q - mid) * ih;
+      const bool out_of_box = j < 7 && !(fabsf(x) <= 1.0f + 1e-3f);
+      const unsigned long long bad = __ballot(out_of_box);
+      const bool inbox = ((bad >> group_shift) & 0x7Full) == 0ull;
+      const uint16_t v = j < 7 ? f2bf(x) : (inbox ? (uint16_t)0x3F80u : (uint16_t)0u);
+      F[(((size_t)a * P.Hmax + h) * P.Nmax + n) * 8 + j] = v;
     }
-    const float u = z + mu[h * 7 + jj];
-    qd = fmaf_(P.dt, u, qd);
-    q = fmaf_(P.dt, qd, q);
-    const float x = (q - mid) * ih;
-    const bool out_of_box = j < 7 && !(fabsf(x) <= 1.0f + 1e-3f);
-    const unsigned long long bad = __ballot(out_of_box);
-    const bool inbox = ((bad >> group_shift) & 0x7Full) == 0ull;
-    const uint16_t v = j < 7 ? f2bf(x) : (inbox ? (uint16_t)0x3F80u : (uint16_t)0u);
-    F[(((size_t)a * P.Hmax + h) * P.Nmax + n) * 8 + j] = v;
   }
 }
 
@@ -977,7 +989,7 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
 }
 
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
+                             const float* mu, const float* state, const float* eps, int n_arms,
                              int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
                              uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s) {
   constexpr int per_block = kStatesThreads / 8;
@@ -986,7 +998,7 @@ hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel
   gx = std::max(gx, (groups + kStatesThreads - 1) / kStatesThreads);
   gx = std::max(gx, (groups + kStatesThreads / kWave - 1) / (kStatesThreads / kWave));
   hipLaunchKernelGGL(k_sur_states, dim3(gx, n_arms + 2), dim3(kStatesThreads), 0, s, arms, P, model, ss, mu, state,
-                     eps_in, k_iter, F, meta, planq, rec, plan_read, screened);
+                     eps, F, meta, planq, rec, plan_read, screened);
   return hipGetLastError();
 }
 
@@ -1007,7 +1019,7 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
                                                             int* __restrict__ count,
                                                             unsigned long long* __restrict__ counts) {
   __shared__ int s_off[kMaxGroups + 1];
-  __shared__ int s_part[kItemsThreads];
+  __shared__ int s_wave[kItemsThreads / kWave];
   const Params& P = *Pp;
   const int tid = threadIdx.x, ng = P.A * P.A * P.Hmax;
   auto cnt = [&](int g) -> int {
@@ -1015,7 +1027,9 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
     if (i == a || h >= arms[a].H || h >= arms[i].H || screened[g]) return 0;
     return arms[a].Npad / 32;
   };
-  // Exclusive scan: each thread a contiguous run of groups, then the runs.
+  // Exclusive scan: each thread a contiguous run of groups, then the runs'
+  // totals by wave prefix sums (shuffles) and the waves' totals in order.
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int per = (ng + kItemsThreads - 1) / kItemsThreads;
   const int g0 = tid * per, g1 = min(ng, g0 + per);
   int run = 0;
@@ -1023,19 +1037,23 @@ __global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __res
     s_off[g] = run;
     run += cnt(g);
   }
-  s_part[tid] = run;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int k = 0; k < kItemsThreads; ++k) {
-      const int v = s_part[k];
-      s_part[k] = acc;
-      acc += v;
-    }
-    s_off[ng] = acc;
+  int incl = run;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(incl, off);
+    if (lane >= off) incl += u;
   }
+  if (lane == kWave - 1) s_wave[wv] = incl;
   __syncthreads();
-  for (int g = g0; g < g1; ++g) s_off[g] += s_part[tid];
+  int base = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kItemsThreads / kWave; ++w) {
+    base += w < wv ? s_wave[w] : 0;
+    total += s_wave[w];
+  }
+  const int excl = base + incl - run;
+  for (int g = g0; g < g1; ++g) s_off[g] += excl;
+  if (tid == 0) s_off[ng] = total;
   __syncthreads();
   const int gb = blockIdx.x * kItemsGroups;
   for (int k = 0; k < kItemsGroups && gb + k < ng; ++k) {

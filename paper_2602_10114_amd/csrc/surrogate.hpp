@@ -83,9 +83,9 @@ hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, 
 // every (a, i, h < Hmax) from the read-side plans and the screen flag of
 // every such group ([A][A][Hmax], 1: the group needs no prediction), in one
 // launch.
-// eps_in: the iteration's precomputed noise (adapted covariance), or NULL to draw sigma z.
+// eps: the iteration's noise (k_noise).
 hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, const float* eps_in, int k_iter, int n_arms,
+                             const float* mu, const float* state, const float* eps, int n_arms,
                              int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
                              uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s);
 // This step's inference descriptors from the screen (groups in (arm,
