@@ -593,10 +593,14 @@ static int set_items(mpc_ctx* c, int T, int W) {
 
 static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts);
 
-// Noise of iteration k: sigma z, or L_h z with the adapted covariance.
+// Noise of iteration k: sigma z, or L_h z with the adapted covariance; in
+// collision mode 1 the same launch screens the learned distance's groups.
 static hipError_t enqueue_noise(mpc_ctx* c, int k) {
-  return launch_noise(c->d_arms, c->d_P, c->d_ss, c->P.cov ? c->chol : nullptr, c->eps, k, c->A, c->Hmax, c->Nmax,
-                      c->stream);
+  const float* chol = c->P.cov ? c->chol : nullptr;
+  if (c->collision_mode == 1)
+    return launch_noise_screen(c->d_arms, c->d_P, c->d_ss, chol, c->eps, k, c->A, c->Hmax, c->Nmax, c->d_model,
+                               c->d_meta, c->mu, c->st_state, c->plan[0], c->sur_screen, c->stream);
+  return launch_noise(c->d_arms, c->d_P, c->d_ss, chol, c->eps, k, c->A, c->Hmax, c->Nmax, c->stream);
 }
 
 // Launch-shape tuner: times the rollout launch for every candidate number of
@@ -693,9 +697,10 @@ static int tune(mpc_ctx* c) {
   return MPC_OK;
 }
 
-// Learned distance before each rollout launch of iteration k: own-joint
-// features of every rollout step and the neighbour records (one launch),
-// then the network's prediction of every (rollout, step, neighbour) query;
+// Learned distance before each rollout launch of iteration k (after the
+// noise launch, which also screened the groups): own-joint features of every
+// rollout step, the neighbour records and the inference descriptors (one
+// launch), then the network's prediction of every query that needs one;
 // the rollout kernel takes the skip decisions from the predictions and
 // counts the queries.  In a debug step the capture buffers start cleared.
 static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long long* counts) {
@@ -705,11 +710,9 @@ static int enqueue_learned_prelude(mpc_ctx* c, int k, bool debug, unsigned long 
     HIPCHK(c, hipMemsetAsync(c->sur_skip, 0, n, c->stream));
     HIPCHK(c, hipMemsetAsync(c->sur_pred, 0, n * sizeof(float), c->stream));
   }
-  HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->d_ss, c->mu, c->st_state, c->eps, c->A, c->Nmax,
-                              c->Hmax, c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->plan[0], c->sur_screen,
-                              c->stream));
-  HIPCHK(c, launch_sur_items(c->d_arms, c->d_P, c->sur_screen, c->A, c->Hmax, c->d_sur_items, c->sur_grp, c->sur_count,
-                             counts, c->stream));
+  HIPCHK(c, launch_sur_states(c->d_arms, c->d_P, c->d_model, c->mu, c->st_state, c->eps, c->A, c->Nmax, c->Hmax,
+                              c->sur_F, c->d_meta, c->planq[0], c->sur_nbrec, c->sur_screen, c->d_sur_items,
+                              c->sur_grp, c->sur_count, counts, c->stream));
   SurInferArgs I{};
   I.P = c->d_P;
   I.model = c->d_model;
@@ -767,7 +770,7 @@ static int ensure_sur_buffers(mpc_ctx* c) {
       (rc = dalloc(c, &c->sur_count, 1)))
     return rc;
   // Room for the descriptors of every (arm, neighbour, step within both
-  // horizons, 32-rollout block), the step's are written by k_sur_items.
+  // horizons, 32-rollout block), the step's are written by k_sur_states.
   long long n_items = 0;
   for (int a = 0; a < c->A; ++a)
     for (int i = 0; i < c->A; ++i)

@@ -62,6 +62,36 @@ __device__ __forceinline__ void normals8(uint32_t slo, uint32_t shi, int arm, ui
   normals4(slo, shi, arm, t, k, n, h, 1, z + 4);
 }
 
+// The iteration's exploration noise of rollout n at step h of arm a, padded
+// rollouts included, in the [H][7][Npad] per-arm layout that the rollout,
+// manipulability, learned-feature and weighted-mean kernels read: sigma z
+// (Sec. III-A's Gaussian sampling), or with the adapted covariance (Eqs. 3-4)
+// L_h z, L_h the Cholesky factor of Sigma_h (`chol` non-null).
+constexpr int kNoiseThreads = 256;
+__device__ __forceinline__ void noise_at(const DevArm* __restrict__ arms, const Params& P, uint32_t t,
+                                         const float* __restrict__ chol, float* __restrict__ eps, int k, int a,
+                                         int h, int n) {
+  const DevArm* arm = arms + a;
+  if (h >= arm->H || n >= arm->Npad) return;
+  const int Npad = arm->Npad;
+  float z[8];
+  normals8(P.seed_lo, P.seed_hi, a, t, k, n, h, z);
+  float* out = eps + arm->eps_off + (size_t)h * 7 * Npad + n;
+  if (chol) {
+    const float* L = chol + ((size_t)a * P.Hmax + h) * kTri;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      float e = 0.f;
+#pragma unroll
+      for (int m = 0; m <= j; ++m) e = fmaf_(L[tri7(j, m)], z[m], e);
+      out[(size_t)j * Npad] = e;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) out[(size_t)j * Npad] = z[j] * P.sigma;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Rigid frame: rotation columns x, y, z and origin t.
 struct Frame {

@@ -899,40 +899,15 @@ __global__ __launch_bounds__(kWave) void k_manip(const DevArm* __restrict__ arms
   }
 }
 
-// The iteration's exploration noise of every (arm, step, rollout), padded
-// rollouts included, in the [H][7][Npad] per-arm layout that the rollout,
-// manipulability, learned-distance and weighted-mean kernels read: sigma z
-// (Sec. III-A's Gaussian sampling), or with the adapted covariance (Eqs. 3-4)
-// L_h z, L_h the Cholesky factor of Sigma_h (`chol` non-null).  One thread per
-// (arm, step, rollout), so the launch is wide whatever the horizon.
-constexpr int kNoiseThreads = 256;
+// SampleControls: the iteration's noise of every (arm, step, rollout) (see
+// noise_at).  One thread per (arm, step, rollout), so the launch is wide
+// whatever the horizon.
 __global__ __launch_bounds__(kNoiseThreads) void k_noise(const DevArm* __restrict__ arms,
                                                          const Params* __restrict__ Pp,
                                                          const StepState* __restrict__ ssp,
                                                          const float* __restrict__ chol, float* __restrict__ eps,
                                                          int k) {
-  const Params& P = *Pp;
-  const int a = blockIdx.z, h = blockIdx.y;
-  const DevArm* arm = arms + a;
-  const int n = blockIdx.x * kNoiseThreads + threadIdx.x;
-  if (h >= arm->H || n >= arm->Npad) return;
-  const int Npad = arm->Npad;
-  float z[8];
-  normals8(P.seed_lo, P.seed_hi, a, ssp->t, k, n, h, z);
-  float* out = eps + arm->eps_off + (size_t)h * 7 * Npad + n;
-  if (chol) {
-    const float* L = chol + ((size_t)a * P.Hmax + h) * kTri;
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      float e = 0.f;
-#pragma unroll
-      for (int m = 0; m <= j; ++m) e = fmaf_(L[tri7(j, m)], z[m], e);
-      out[(size_t)j * Npad] = e;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 7; ++j) out[(size_t)j * Npad] = z[j] * P.sigma;
-  }
+  noise_at(arms, *Pp, ssp->t, chol, eps, k, blockIdx.z, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
 }
 
 // Eq. 3 (weighted mean, and with covariance adaptation the weighted second

@@ -383,6 +383,69 @@ __global__ void k_init_params(float* __restrict__ p, uint32_t slo, uint32_t shi)
 }
 
 // ---------------------------------------------------------------------------
+// Inference descriptors of every group that needs the network, in (arm,
+// neighbour, step, 32-rollout block) order: every block of the descriptor
+// row scans the groups' descriptor counts (Npad/32 for a live, unscreened
+// group of arm a with i != a and h below both horizons, else 0) in LDS and
+// writes the descriptors of its kItemsGroups groups at their offsets, the
+// group's first descriptor index (-1 when it has none) and, from the block
+// holding the last group, the total.
+constexpr int kItemsGroups = 8;
+constexpr int kMaxGroups = kMaxArms * kMaxArms * kMaxH;
+template <int kThreads>
+__device__ __forceinline__ void items_block(const DevArm* __restrict__ arms, const Params& P,
+                                            const uint8_t* __restrict__ screened, SurItem* __restrict__ items,
+                                            int* __restrict__ grp_first, int* __restrict__ count,
+                                            unsigned long long* __restrict__ counts, int block) {
+  __shared__ int s_off[kMaxGroups + 1];
+  __shared__ int s_wave[kThreads / kWave];
+  const int tid = threadIdx.x, ng = P.A * P.A * P.Hmax;
+  auto cnt = [&](int g) -> int {
+    const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
+    if (i == a || h >= arms[a].H || h >= arms[i].H || screened[g]) return 0;
+    return arms[a].Npad / 32;
+  };
+  // Exclusive scan: each thread a contiguous run of groups, then the runs'
+  // totals by wave prefix sums (shuffles) and the waves' totals in order.
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int per = (ng + kThreads - 1) / kThreads;
+  const int g0 = tid * per, g1 = min(ng, g0 + per);
+  int run = 0;
+  for (int g = g0; g < g1; ++g) {
+    s_off[g] = run;
+    run += cnt(g);
+  }
+  int incl = run;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(incl, off);
+    if (lane >= off) incl += u;
+  }
+  if (lane == kWave - 1) s_wave[wv] = incl;
+  __syncthreads();
+  int base = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / kWave; ++w) {
+    base += w < wv ? s_wave[w] : 0;
+    total += s_wave[w];
+  }
+  const int excl = base + incl - run;
+  for (int g = g0; g < g1; ++g) s_off[g] += excl;
+  if (tid == 0) s_off[ng] = total;
+  __syncthreads();
+  const int gb = block * kItemsGroups;
+  for (int k = 0; k < kItemsGroups && gb + k < ng; ++k) {
+    const int g = gb + k, n = s_off[g + 1] - s_off[g];
+    if (tid == 0) grp_first[g] = n > 0 ? s_off[g] : -1;
+    if (n == 0) continue;
+    // query rows the network will run for this group (counter slot 5)
+    if (tid == 0 && counts) atomicAdd(counts + kSurCounters * (g / P.Hmax / P.A) + 5, (unsigned long long)n * 32ull);
+    const int h = g % P.Hmax, ai = g / P.Hmax;
+    for (int e = tid; e < n; e += kThreads) items[s_off[g] + e] = SurItem{ai / P.A, ai % P.A, h, 32 * e};
+  }
+  if (tid == 0 && gb <= ng - 1 && ng - 1 < gb + kItemsGroups) *count = s_off[ng];
+}
+
 // Screen of one (arm a, neighbour i, step h) group, one wave: 1 when no query
 // of the group needs the network -- the neighbour's plan is not published
 // (its queries are not live), or the arm's mean rollout (the means
@@ -455,13 +518,13 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
 // lane 7 writes the flag, the AND of the group's box tests taken with a
 // ballot.  The eight 2-byte writes form the row.
 // The row blockIdx.y = number of arms writes the neighbour records, one
-// thread per (arm, neighbour, step); the next row screens the (arm,
-// neighbour, step) groups, one wave each.
+// thread per (arm, neighbour, step); the next row writes the inference
+// descriptors from the screen flags (k_noise_screen), kItemsGroups groups
+// per block.
 constexpr int kStatesThreads = 256;
 __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __restrict__ arms,
                                                                const Params* __restrict__ Pp,
                                                                const SurModel* __restrict__ sm,
-                                                               const StepState* __restrict__ ssp,
                                                                const float* __restrict__ mu_all,
                                                                const float* __restrict__ state,
                                                                const float* __restrict__ eps,
@@ -469,8 +532,11 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
                                                                const BoardMeta* __restrict__ meta,
                                                                const float* __restrict__ planq,
                                                                uint32_t* __restrict__ rec,
-                                                               const float* __restrict__ plan_read,
-                                                               uint8_t* __restrict__ screened) {
+                                                               const uint8_t* __restrict__ screened,
+                                                               SurItem* __restrict__ items,
+                                                               int* __restrict__ grp_first,
+                                                               int* __restrict__ count,
+                                                               unsigned long long* __restrict__ counts) {
   const Params& P = *Pp;
   const int a = blockIdx.y;
   if (a == P.A) {
@@ -481,9 +547,8 @@ __global__ __launch_bounds__(kStatesThreads) void k_sur_states(const DevArm* __r
     return;
   }
   if (a == P.A + 1) {
-    const int g = blockIdx.x * (kStatesThreads / kWave) + (int)(threadIdx.x / kWave);
-    if (g >= P.A * P.A * P.Hmax) return;  // whole waves
-    screen_group(arms, P, sm, meta, mu_all, state, plan_read, g, threadIdx.x & (kWave - 1), screened);
+    if ((int)blockIdx.x * kItemsGroups >= P.A * P.A * P.Hmax) return;  // whole block
+    items_block<kStatesThreads>(arms, P, screened, items, grp_first, count, counts, blockIdx.x);
     return;
   }
   const DevArm* arm = arms + a;
@@ -988,93 +1053,59 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, long long n, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, const float* eps, int n_arms,
-                             int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
-                             uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s) {
+hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const float* mu,
+                             const float* state, const float* eps, int n_arms, int npad_max, int hmax, uint16_t* F,
+                             const BoardMeta* meta, const float* planq, uint32_t* rec, const uint8_t* screened,
+                             SurItem* items, int* grp_first, int* count, unsigned long long* counts,
+                             hipStream_t s) {
   constexpr int per_block = kStatesThreads / 8;
   const int groups = n_arms * n_arms * hmax;
   int gx = (npad_max + per_block - 1) / per_block;
   gx = std::max(gx, (groups + kStatesThreads - 1) / kStatesThreads);
-  gx = std::max(gx, (groups + kStatesThreads / kWave - 1) / (kStatesThreads / kWave));
-  hipLaunchKernelGGL(k_sur_states, dim3(gx, n_arms + 2), dim3(kStatesThreads), 0, s, arms, P, model, ss, mu, state,
-                     eps, F, meta, planq, rec, plan_read, screened);
+  gx = std::max(gx, (groups + kItemsGroups - 1) / kItemsGroups);
+  hipLaunchKernelGGL(k_sur_states, dim3(gx, n_arms + 2), dim3(kStatesThreads), 0, s, arms, P, model, mu, state, eps,
+                     F, meta, planq, rec, screened, items, grp_first, count, counts);
   return hipGetLastError();
 }
 
-// Inference descriptors of every group that needs the network, in (arm,
-// neighbour, step, 32-rollout block) order: every block scans the groups'
-// descriptor counts (Npad/32 for a live, unscreened group of arm a with
-// i != a and h below both horizons, else 0) in LDS and writes the
-// descriptors of its kItemsGroups groups at their offsets, the group's first
-// descriptor index (-1 when it has none) and, from the block holding the
-// last group, the total.
-constexpr int kItemsGroups = 8;
-constexpr int kItemsThreads = 256;
-constexpr int kMaxGroups = kMaxArms * kMaxArms * kMaxH;
-__global__ __launch_bounds__(kItemsThreads) void k_sur_items(const DevArm* __restrict__ arms,
-                                                            const Params* __restrict__ Pp,
-                                                            const uint8_t* __restrict__ screened,
-                                                            SurItem* __restrict__ items, int* __restrict__ grp_first,
-                                                            int* __restrict__ count,
-                                                            unsigned long long* __restrict__ counts) {
-  __shared__ int s_off[kMaxGroups + 1];
-  __shared__ int s_wave[kItemsThreads / kWave];
+// The iteration's noise (planes blockIdx.z < number of arms, as k_noise) and
+// in the plane blockIdx.z = number of arms the screen flag of every (arm,
+// neighbour, step) group, one wave each, ahead of the feature launch whose
+// descriptor row reads the flags.
+__global__ __launch_bounds__(kNoiseThreads) void k_noise_screen(const DevArm* __restrict__ arms,
+                                                                const Params* __restrict__ Pp,
+                                                                const StepState* __restrict__ ssp,
+                                                                const float* __restrict__ chol,
+                                                                float* __restrict__ eps, int k,
+                                                                const SurModel* __restrict__ sm,
+                                                                const BoardMeta* __restrict__ meta,
+                                                                const float* __restrict__ mu_all,
+                                                                const float* __restrict__ state,
+                                                                const float* __restrict__ plan_read,
+                                                                uint8_t* __restrict__ screened) {
   const Params& P = *Pp;
-  const int tid = threadIdx.x, ng = P.A * P.A * P.Hmax;
-  auto cnt = [&](int g) -> int {
-    const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
-    if (i == a || h >= arms[a].H || h >= arms[i].H || screened[g]) return 0;
-    return arms[a].Npad / 32;
-  };
-  // Exclusive scan: each thread a contiguous run of groups, then the runs'
-  // totals by wave prefix sums (shuffles) and the waves' totals in order.
-  const int lane = tid & (kWave - 1), wv = tid / kWave;
-  const int per = (ng + kItemsThreads - 1) / kItemsThreads;
-  const int g0 = tid * per, g1 = min(ng, g0 + per);
-  int run = 0;
-  for (int g = g0; g < g1; ++g) {
-    s_off[g] = run;
-    run += cnt(g);
+  const int a = blockIdx.z;
+  if (a < P.A) {
+    noise_at(arms, P, ssp->t, chol, eps, k, a, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
+    return;
   }
-  int incl = run;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int u = __shfl_up(incl, off);
-    if (lane >= off) incl += u;
-  }
-  if (lane == kWave - 1) s_wave[wv] = incl;
-  __syncthreads();
-  int base = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < kItemsThreads / kWave; ++w) {
-    base += w < wv ? s_wave[w] : 0;
-    total += s_wave[w];
-  }
-  const int excl = base + incl - run;
-  for (int g = g0; g < g1; ++g) s_off[g] += excl;
-  if (tid == 0) s_off[ng] = total;
-  __syncthreads();
-  const int gb = blockIdx.x * kItemsGroups;
-  for (int k = 0; k < kItemsGroups && gb + k < ng; ++k) {
-    const int g = gb + k, n = s_off[g + 1] - s_off[g];
-    if (tid == 0) grp_first[g] = n > 0 ? s_off[g] : -1;
-    if (n == 0) continue;
-    // query rows the network will run for this group (counter slot 5)
-    if (tid == 0 && counts) atomicAdd(counts + kSurCounters * (g / P.Hmax / P.A) + 5, (unsigned long long)n * 32ull);
-    const int h = g % P.Hmax, ai = g / P.Hmax;
-    for (int e = tid; e < n; e += kItemsThreads) items[s_off[g] + e] = SurItem{ai / P.A, ai % P.A, h, 32 * e};
-  }
-  if (tid == 0 && gb <= ng - 1 && ng - 1 < gb + kItemsGroups) *count = s_off[ng];
+  const int g = ((int)(blockIdx.y * gridDim.x + blockIdx.x)) * (kNoiseThreads / kWave) + (int)(threadIdx.x / kWave);
+  if (g >= P.A * P.A * P.Hmax) return;  // whole waves
+  screen_group(arms, P, sm, meta, mu_all, state, plan_read, g, threadIdx.x & (kWave - 1), screened);
 }
 
-hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
-                            SurItem* items, int* grp_first, int* count, unsigned long long* counts, hipStream_t s) {
-  const int ng = n_arms * n_arms * hmax;
-  hipLaunchKernelGGL(k_sur_items, dim3((ng + kItemsGroups - 1) / kItemsGroups), dim3(kItemsThreads), 0, s, arms, P,
-                     screened, items, grp_first, count, counts);
+hipError_t launch_noise_screen(const DevArm* arms, const Params* P, const StepState* ss, const float* chol,
+                               float* eps, int k, int n_arms, int hmax, int npad_max, const SurModel* model,
+                               const BoardMeta* meta, const float* mu, const float* state, const float* plan_read,
+                               uint8_t* screened, hipStream_t s) {
+  // the screen plane holds gx * hmax blocks of kNoiseThreads / 64 waves, one per group
+  constexpr int waves = kNoiseThreads / kWave;
+  const int gx = std::max((npad_max + kNoiseThreads - 1) / kNoiseThreads, (n_arms * n_arms + waves - 1) / waves);
+  hipLaunchKernelGGL(k_noise_screen, dim3(gx, hmax, n_arms + 1), dim3(kNoiseThreads), 0, s, arms, P, ss, chol, eps,
+                     k, model, meta, mu, state, plan_read, screened);
   return hipGetLastError();
 }
+
 
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s) {
   if (!A.items || grid <= 0) return hipSuccess;  // no arm pair: nothing to predict

@@ -71,7 +71,7 @@ struct SurInferArgs {
   const float* P32;            // FP32 parameters (biases are taken in FP32)
   const uint16_t* F;           // own-joint feature rows [A][Hmax][Nmax][8] (bfloat16, slot 7 = in-box flag)
   const uint32_t* nbrec;       // neighbour records [A][A][Hmax][kNbrRec]
-  const SurItem* items;        // this step's descriptors (k_sur_items)
+  const SurItem* items;        // this step's descriptors (k_sur_states)
   const int* count;            // their number (device)
   float* y;                    // predictions in descriptor order [descriptors][32]
 };
@@ -79,20 +79,23 @@ struct SurInferArgs {
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, const float* qi, const float* qj,
                                 int M, float* out, hipStream_t s);
-// Own-feature rows of every (arm, step, rollout), the neighbour records of
-// every (a, i, h < Hmax) from the read-side plans and the screen flag of
-// every such group ([A][A][Hmax], 1: the group needs no prediction), in one
-// launch.
-// eps: the iteration's noise (k_noise).
-hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const StepState* ss,
-                             const float* mu, const float* state, const float* eps, int n_arms,
-                             int npad_max, int hmax, uint16_t* F, const BoardMeta* meta, const float* planq,
-                             uint32_t* rec, const float* plan_read, uint8_t* screened, hipStream_t s);
-// This step's inference descriptors from the screen (groups in (arm,
-// neighbour, step) order), each group's first descriptor [A][A][Hmax] (-1:
-// none) and their number.
-hipError_t launch_sur_items(const DevArm* arms, const Params* P, const uint8_t* screened, int n_arms, int hmax,
-                            SurItem* items, int* grp_first, int* count, unsigned long long* counts, hipStream_t s);
+// The iteration's noise (as launch_noise) and the screen flag of every
+// (arm, neighbour, step) group ([A][A][Hmax], 1: the group needs no
+// prediction) in one launch.
+hipError_t launch_noise_screen(const DevArm* arms, const Params* P, const StepState* ss, const float* chol,
+                               float* eps, int k, int n_arms, int hmax, int npad_max, const SurModel* model,
+                               const BoardMeta* meta, const float* mu, const float* state, const float* plan_read,
+                               uint8_t* screened, hipStream_t s);
+// Own-feature rows of every (arm, step, rollout) from the iteration's noise
+// `eps`, the neighbour records of every (a, i, h < Hmax) from the read-side
+// plans, and this step's inference descriptors from the screen flags (groups
+// in (arm, neighbour, step) order) with each group's first descriptor
+// [A][A][Hmax] (-1: none) and their number, in one launch.
+hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel* model, const float* mu,
+                             const float* state, const float* eps, int n_arms, int npad_max, int hmax, uint16_t* F,
+                             const BoardMeta* meta, const float* planq, uint32_t* rec, const uint8_t* screened,
+                             SurItem* items, int* grp_first, int* count, unsigned long long* counts,
+                             hipStream_t s);
 hipError_t launch_sur_infer(const SurInferArgs& A, int grid, hipStream_t s);
 // Training samples: arm pairs drawn from `pairs` ([n_pairs][2] arm indices),
 // joints uniform within the limits (counter-based draws keyed by seed);

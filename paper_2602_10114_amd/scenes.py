@@ -213,8 +213,10 @@ def make_scene(config: int, seed: int | None = None, **param_over) -> Scene:
         if config == 4:
             params["collision_mode"] = param_over.get("collision_mode", 1)
     elif config == 5:
+        # Rows 1.0 m apart, so that the perturbed ready poses of facing arms
+        # start clear of each other (0.18 m at the closest pair).
         xs = (-0.75, -0.25, 0.25, 0.75)
-        bases = [(x, -0.4, 0.0, math.pi / 2) for x in xs] + [(x, 0.4, 0.0, -math.pi / 2) for x in xs]
+        bases = [(x, -0.5, 0.0, math.pi / 2) for x in xs] + [(x, 0.5, 0.0, -math.pi / 2) for x in xs]
         nh = [(4096, 40)] * 8
         steps = 1000
         params["collision_mode"] = param_over.get("collision_mode", 1)
