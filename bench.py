@@ -269,7 +269,7 @@ def goal_schedule(scene, steps, goal_age=50):
     return np.stack(out)
 
 
-def latency_leg(config, steps, dev, stream, params=None, warmup=10, screen=0.0):
+def latency_leg(config, steps, dev, stream, params=None, warmup=10, screen=0.0, probe=0, min_drop=0.0):
     """The workload's own closed loop (Publish + mpc_step + plant) for
     `steps` control steps after `warmup`, goals re-drawn every second and
     obstacles moving, every input resident in HBM (goal and obstacle
@@ -282,7 +282,8 @@ def latency_leg(config, steps, dev, stream, params=None, warmup=10, screen=0.0):
     obs = None
     if sc.obstacles.shape[0]:
         obs = torch.as_tensor(obstacle_track(scenes.make_scene(config, collision_mode=0), warmup + steps), device=dev)
-    ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": screen}, stream=stream)
+    ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": screen, "surrogate_probe": probe,
+                                      "surrogate_min_drop": min_drop}, stream=stream)
     if params is not None:
         ctl.set_surrogate_params(params)
         ctl.set_collision_mode(1)
@@ -312,7 +313,10 @@ def latency_leg(config, steps, dev, stream, params=None, warmup=10, screen=0.0):
            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
            "rollout_steps_per_s": sc.rollout_steps() / (lat.mean() * 1e-3), "tuning": tuning}
     if stats is not None:
-        out["exact_checks_skipped"] = stats["waves_skipped"] * 64 / max(stats["queries"], 1)
+        q = max(stats["queries"], 1)
+        out.update({"screen_m": screen, "probe": probe, "min_drop": min_drop,
+                    "exact_checks_skipped": stats["waves_skipped"] * 64 / q,
+                    "queries_through_network": stats["network_rows"] / q})
     return out
 
 
@@ -365,7 +369,7 @@ def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
     return wall, lat, ms_roll / max(n_roll, 1), stats
 
 
-def audit_run(scene, params, steps, dev, goal_age=50, screen=0.0):
+def audit_run(scene, params, steps, dev, goal_age=50, screen=0.0, probe=0, min_drop=0.0):
     """Closed loop with goals reset every goal_age steps (staggered per arm)
     so that the arms keep crossing the shared workspace.  With params: the
     learned distance, audited (the dropped checks are also computed exactly):
@@ -377,7 +381,8 @@ def audit_run(scene, params, steps, dev, goal_age=50, screen=0.0):
     from paper_2602_10114_amd import native
     A = scene.n_arms
     rng = np.random.default_rng(scene.seed + 99)
-    ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": screen})
+    ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": screen,
+                                         "surrogate_probe": probe, "surrogate_min_drop": min_drop})
     if params is not None:
         ctl.set_surrogate_params(params)
         ctl.set_collision_mode(1)
@@ -560,9 +565,23 @@ def fig1(steps, seeds, dev):
 
 
 SCREEN_SWEEP = (0.0, 0.1, 0.2, 0.3, 0.4, 0.6)
+# Drop-history screen of the learned legs: a group that dropped at most a
+# share min_drop of its checks in the last control step skips the network,
+# re-probed every 8th step; min_drop is picked from MIN_DROP_SWEEP on the
+# first 300 steps of the workload's closed loop (goals re-drawn).
+SURROGATE_PROBE = 8
+MIN_DROP_SWEEP = (0.0, 0.25, 0.5, 0.75)
 
 
-def screen_sweep(config, params, stream, dev, steps, warmup):
+def min_drop_sweep(config, params, screen, dev, stream, steps=300):
+    """Mean learned step time (ms) of the closed loop with goals re-drawn
+    for each min_drop of MIN_DROP_SWEEP; returns the sweep and the fastest."""
+    out = {m: latency_leg(config, steps, dev, stream, params=params, screen=screen, probe=SURROGATE_PROBE,
+                          min_drop=m)["mean_ms"] for m in MIN_DROP_SWEEP}
+    return out, min(out, key=out.get)
+
+
+def screen_sweep(config, params, stream, dev, steps, warmup, probe=SURROGATE_PROBE):
     """Learned step time (ms) for each screen distance of SCREEN_SWEEP (the
     mean-rollout distance below which an arm-neighbour-step group skips the
     network and is checked exactly); returns the sweep and the fastest."""
@@ -570,7 +589,8 @@ def screen_sweep(config, params, stream, dev, steps, warmup):
     out = {}
     for tau in SCREEN_SWEEP:
         sc = scenes.make_scene(config, collision_mode=0)
-        ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": tau}, stream=stream)
+        ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": tau, "surrogate_probe": probe},
+                                stream=stream)
         ctl.set_surrogate_params(params)
         w, _, _, _ = timed_loop(ctl, sc, stream, steps, warmup, 1, dev)
         ctl.close()
@@ -670,8 +690,11 @@ def main():
         print(f"bench: surrogate trained in {rep['seconds']:.1f} s", file=sys.stderr, flush=True)
         sweep5, tau5 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup)
         print(f"bench: screen sweep {sweep5} -> {tau5}", file=sys.stderr, flush=True)
+        drops5, md5 = min_drop_sweep(5, params, tau5, dev, stream)
+        print(f"bench: min_drop sweep {drops5} -> {md5}", file=sys.stderr, flush=True)
         scene = scenes.make_scene(5, collision_mode=0)
-        ctl2 = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": tau5},
+        ctl2 = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": tau5,
+                                              "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5},
                                  stream=stream)
         ctl2.set_surrogate_params(params)
         w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev)
@@ -693,14 +716,17 @@ def main():
                          "unit": "TFLOP/s", "frac": inf_ach / BF16_PEAK_TFLOPS, "traffic": None,
                          "kernel_ms": st["infer_ms"], "algorithmic_flop_per_launch": mlp_flops},
             "exact_checks_skipped": st["waves_skipped"] * 64 / q,
-            "screen_m": tau5, "screen_sweep_ms": {str(k): v for k, v in sweep5.items()},
+            "screen_m": tau5, "probe": SURROGATE_PROBE, "min_drop": md5,
+            "screen_sweep_ms": {str(k): v for k, v in sweep5.items()},
+            "min_drop_sweep_mean_ms": {str(k): v for k, v in drops5.items()},
             "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()},
             "recipe": native.TRAINING_RECIPE,
         }
         if args.audit_steps > 0:
             # The same 8-arm workload, audited: goals re-drawn every second so
             # the arms keep crossing, every dropped check also computed exactly.
-            aud5 = audit_run(scenes.make_scene(5, collision_mode=0), params, args.audit_steps, dev, screen=tau5)
+            aud5 = audit_run(scenes.make_scene(5, collision_mode=0), params, args.audit_steps, dev, screen=tau5,
+                             probe=SURROGATE_PROBE, min_drop=md5)
             aud5_exact = audit_run(scenes.make_scene(5, collision_mode=0), None, args.audit_steps, dev)
             out["surrogate"]["audit"] = aud5
             out["surrogate"]["audited_dynamics"] = {
@@ -709,13 +735,17 @@ def main():
                 "exact_first_executed_contact": aud5_exact["first_executed_contact"]}
         if not args.no_latency:
             out["surrogate"]["latency_1000"] = latency_leg(5, CONFIG_STEPS[5], dev, stream, params=params,
-                                                           screen=tau5)
+                                                           screen=tau5, probe=SURROGATE_PROBE, min_drop=md5)
+            out["surrogate"]["latency_1000_no_history"] = latency_leg(5, CONFIG_STEPS[5], dev, stream,
+                                                                      params=params, screen=tau5)
         # The 4-arm workload with its own network: exact vs learned step,
         # then the audit.
         sc4 = scenes.make_scene(4, collision_mode=0)
         p4, rep4 = train_surrogate(scenes.make_scene(4, collision_mode=0))
         sweep4, tau4 = screen_sweep(4, p4, stream, dev, max(5, args.steps // 2), args.warmup)
-        ctl4 = native.Controller(sc4.arms, {**sc4.params, "collision_mode": 0, "surrogate_screen": tau4},
+        drops4, md4 = min_drop_sweep(4, p4, tau4, dev, stream)
+        ctl4 = native.Controller(sc4.arms, {**sc4.params, "collision_mode": 0, "surrogate_screen": tau4,
+                                            "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md4},
                                  stream=stream)
         ctl4.set_surrogate_params(p4)
         w4e, _, _, _ = timed_loop(ctl4, scenes.make_scene(4, collision_mode=0), stream, args.steps,
@@ -725,14 +755,16 @@ def main():
         ctl4.close()
         aud = aud_exact = None
         if args.audit_steps > 0:
-            aud = audit_run(sc4, p4, args.audit_steps, dev, screen=tau4)
+            aud = audit_run(sc4, p4, args.audit_steps, dev, screen=tau4, probe=SURROGATE_PROBE, min_drop=md4)
             aud_exact = audit_run(scenes.make_scene(4, collision_mode=0), None, args.audit_steps, dev)
         out["surrogate_4arm"] = {
             "workload": "4 arms on a 1.2 m square, 1024 rollouts x 30 steps each, 8 moving obstacles",
             "exact_ms_per_step": 1e3 * w4e / args.steps, "surrogate_ms_per_step": 1e3 * w4l / args.steps,
             "speedup_vs_exact": w4e / w4l,
             "exact_checks_skipped": st4["waves_skipped"] * 64 / max(st4["queries"], 1),
-            "screen_m": tau4, "screen_sweep_ms": {str(k): v for k, v in sweep4.items()},
+            "screen_m": tau4, "probe": SURROGATE_PROBE, "min_drop": md4,
+            "screen_sweep_ms": {str(k): v for k, v in sweep4.items()},
+            "min_drop_sweep_mean_ms": {str(k): v for k, v in drops4.items()},
             "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep4.items()},
         }
         if aud is not None:
@@ -744,7 +776,9 @@ def main():
                                      "seconds": aud_exact["seconds"]}})
         if not args.no_latency:
             out["surrogate_4arm"]["latency_1000"] = latency_leg(4, CONFIG_STEPS[4], dev, stream, params=p4,
-                                                                screen=tau4)
+                                                                screen=tau4, probe=SURROGATE_PROBE, min_drop=md4)
+            out["surrogate_4arm"]["latency_1000_no_history"] = latency_leg(4, CONFIG_STEPS[4], dev, stream,
+                                                                           params=p4, screen=tau4)
     if not args.no_latency:
         # Every workload's own closed loop (exact distances): configs 1-5.
         out["latency"] = {f"config{c}": latency_leg(c, CONFIG_STEPS[c], dev, stream) for c in (1, 2, 3, 4, 5)}

@@ -101,6 +101,16 @@ typedef struct {
                               to the neighbour's plan at that step is checked exactly for every
                               rollout without running the network (it would keep nearly all of
                               them); >= 0, 0 = off.  Only ever adds exact checks. */
+  int surrogate_probe;     /* mode 1: 0 = off, else 2..1000.  An (arm, neighbour, step) group that
+                              dropped at most surrogate_min_drop of its 64-rollout checks in the
+                              previous control step (at the step one later, which the shift brings
+                              to this one) is checked exactly for every rollout without running
+                              the network, except on every surrogate_probe-th control step
+                              (staggered over the groups), when it runs the network again.
+                              History is forgotten when the mode or the network changes.  Only
+                              ever adds exact checks. */
+  float surrogate_min_drop;  /* share of a group's checks, [0, 1), see surrogate_probe; 0: a group
+                              keeps running the network if it dropped any check */
 } mpc_params;
 
 /* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).

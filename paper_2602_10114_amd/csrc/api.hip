@@ -157,6 +157,10 @@ struct mpc_ctx {
   uint8_t* sur_skip = nullptr;         // decisions of live queries [A][A][Hmax][Nmax] (debug capture)
   float* sur_pred = nullptr;           // their predictions (debug capture)
   uint8_t* sur_screen = nullptr;       // groups that need no prediction [A][A][Hmax]
+  // dropped 64-rollout checks per group, two control steps [2][A][A][Hmax]
+  // (parity of the step counter); kHistNone = no history
+  unsigned* sur_hist = nullptr;
+  bool hist_stale = true;
   int* sur_grp = nullptr;              // first inference descriptor of each group [A][A][Hmax] (-1: none)
   int* sur_count = nullptr;            // descriptors of the step
   uint32_t* sur_nbrec = nullptr;       // neighbour records of the inference [A][A][Hmax][kNbrRec]
@@ -331,6 +335,10 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
     return fail(nullptr, MPC_EINVAL, "surrogate_margin must be 0 (= buf_dyn) or at least buf_dyn");
   if (!(p->surrogate_screen >= 0.f && p->surrogate_screen < 10.f))
     return fail(nullptr, MPC_EINVAL, "surrogate_screen outside [0, 10) m");
+  if (!(p->surrogate_probe == 0 || (p->surrogate_probe >= 2 && p->surrogate_probe <= 1000)))
+    return fail(nullptr, MPC_EINVAL, "surrogate_probe must be 0 or in [2, 1000]");
+  if (!(p->surrogate_min_drop >= 0.f && p->surrogate_min_drop < 1.f))
+    return fail(nullptr, MPC_EINVAL, "surrogate_min_drop outside [0, 1)");
   bool all52 = true;
   for (int i = 0; i < n_arms; ++i) {
     int counts[kBodies];
@@ -432,6 +440,8 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   }
   c->hmodel.margin = p->surrogate_margin > 0.f ? p->surrogate_margin : p->buf_dyn;
   c->hmodel.screen = p->surrogate_screen;
+  c->hmodel.probe = p->surrogate_probe;
+  c->hmodel.min_drop = p->surrogate_min_drop;
   if ((rc = dalloc(c, &c->d_model, 1)) || (rc = dalloc(c, &c->sur_p, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_m, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_v, (size_t)kMlpParams)) ||
       (rc = dalloc(c, &c->sur_g, (size_t)kMlpParams)) || (rc = dalloc(c, &c->sur_p16, (size_t)kMlpParams)) ||
@@ -545,6 +555,7 @@ static RolloutArgs rollout_args(const mpc_ctx* c, int k) {
   R.sur_rec = c->sur_nbrec;
   R.sur_margin = c->hmodel.margin;
   R.sur_counts = c->sur_counts;
+  R.sur_hist = c->sur_hist;
   R.dbg_pred = c->sur_pred;
   R.dbg_skip = c->sur_skip;
   R.manip = c->manip;
@@ -599,7 +610,7 @@ static hipError_t enqueue_noise(mpc_ctx* c, int k) {
   const float* chol = c->P.cov ? c->chol : nullptr;
   if (c->collision_mode == 1)
     return launch_noise_screen(c->d_arms, c->d_P, c->d_ss, chol, c->eps, k, c->A, c->Hmax, c->Nmax, c->d_model,
-                               c->d_meta, c->mu, c->st_state, c->plan[0], c->sur_screen, c->stream);
+                               c->d_meta, c->mu, c->st_state, c->plan[0], c->sur_screen, c->sur_hist, c->stream);
   return launch_noise(c->d_arms, c->d_P, c->d_ss, chol, c->eps, k, c->A, c->Hmax, c->Nmax, c->stream);
 }
 
@@ -668,6 +679,7 @@ static int tune(mpc_ctx* c) {
       for (int g : grids) {
         RolloutArgs R = rollout_args(c, 0);
         if (R.sur_counts) R.sur_counts = c->tune_counts;
+        R.sur_hist = nullptr;  // replays leave the drop history alone
         HIPCHK(c, launch_rollout(R, c->layout, false, W, g, c->stream));
         HIPCHK(c, hipEventRecord(e0, c->stream));
         for (int r = 0; r < 3; ++r) HIPCHK(c, launch_rollout(R, c->layout, false, W, g, c->stream));
@@ -767,8 +779,9 @@ static int ensure_sur_buffers(mpc_ctx* c) {
   if ((rc = dalloc(c, &c->sur_F, A * H * N * 8)) || (rc = dalloc(c, &c->sur_skip, A * A * H * N)) ||
       (rc = dalloc(c, &c->sur_pred, A * A * H * N)) || (rc = dalloc(c, &c->sur_nbrec, A * A * H * kNbrRec)) ||
       (rc = dalloc(c, &c->sur_screen, A * A * H)) || (rc = dalloc(c, &c->sur_grp, A * A * H)) ||
-      (rc = dalloc(c, &c->sur_count, 1)))
+      (rc = dalloc(c, &c->sur_count, 1)) || (rc = dalloc(c, &c->sur_hist, 2 * A * A * H)))
     return rc;
+  c->hist_stale = true;
   // Room for the descriptors of every (arm, neighbour, step within both
   // horizons, 32-rollout block), the step's are written by k_sur_states.
   long long n_items = 0;
@@ -820,6 +833,15 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
     if (!c->sur_ready) return fail(c, MPC_ESTATE, "collision mode 1 needs trained or set distance-model parameters");
     const int rc0 = ensure_sur_buffers(c);
     if (rc0) return rc0;
+    if (c->hist_stale) {
+      // No drop history yet: every group runs the network on its next step
+      // (outside the captured step body).
+      const std::vector<unsigned> none((size_t)2 * c->A * c->A * c->Hmax, kHistNone);
+      HIPCHK(c, hipMemcpyAsync(c->sur_hist, none.data(), none.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->hist_stale = false;
+    }
   }
   SenseArgs S{};
   S.arms = c->d_arms;
@@ -1339,6 +1361,7 @@ extern "C" int mpc_surrogate_set_params(mpc_ctx* c, const float* params) {
   HIPCHK(c, hipMemcpyAsync(c->sur_p, params, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
   c->sur_ready = true;
+  c->hist_stale = true;
   return MPC_OK;
 }
 
@@ -1465,6 +1488,7 @@ extern "C" int mpc_surrogate_train(mpc_ctx* c, const mpc_train_params* tp, mpc_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->sur_ready = true;
+  c->hist_stale = true;
   if (rep) {
     rep->final_loss = last_loss;
     rep->val_mae = mae;
@@ -1543,6 +1567,7 @@ extern "C" int mpc_set_collision_mode(mpc_ctx* c, int mode) {
     c->collision_mode = mode;
     c->tuned = false;  // re-tune and re-capture for the new step body
     c->n_items = 0;
+    c->hist_stale = true;
   }
   return MPC_OK;
 }

@@ -446,7 +446,12 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           const unsigned long long mf = __ballot(far);
           nq += (unsigned)__popcll(__ballot(live));
           nf += (unsigned)__popcll(mf);
-          if (mf == ~0ull) wdrop |= 1u << i;
+          if (mf == ~0ull) {
+            wdrop |= 1u << i;
+            // drop history of the group for the next control step's screen
+            if (A.sur_hist && lane == 0)
+              atomicAdd(A.sur_hist + ((size_t)(SS.t & 1u) * P.A * P.A + pi) * P.Hmax + h, 1u);
+          }
           if (DBG && live) {
             const size_t o = (pi * P.Hmax + h) * P.Nmax + n;
             A.dbg_pred[o] = y;

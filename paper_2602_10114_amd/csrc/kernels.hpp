@@ -46,6 +46,7 @@ struct RolloutArgs {
   float sur_margin;
   int pad2;
   unsigned long long* sur_counts;
+  unsigned* sur_hist;          // dropped checks per group, [2][A][A][Hmax] by step parity (NULL: not counted)
   float* dbg_pred;
   uint8_t* dbg_skip;
   // C_manip of every (arm, step, rollout) [A][Hmax][Nmax], or NULL (w_manip = 0)

@@ -448,7 +448,9 @@ __device__ __forceinline__ void items_block(const DevArm* __restrict__ arms, con
 
 // Screen of one (arm a, neighbour i, step h) group, one wave: 1 when no query
 // of the group needs the network -- the neighbour's plan is not published
-// (its queries are not live), or the arm's mean rollout (the means
+// (its queries are not live), or the group dropped no check in the previous
+// control step and is not being probed (drop history), or the arm's mean
+// rollout (the means
 // integrated from the sensed state) lies closer than the screen distance to
 // the neighbour's plan at step h, so that nearly every rollout would be
 // predicted near anyway (its queries are checked exactly).  Lane = own
@@ -457,14 +459,24 @@ __device__ __forceinline__ void items_block(const DevArm* __restrict__ arms, con
 __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, const Params& P,
                                              const SurModel* __restrict__ sm, const BoardMeta* __restrict__ meta,
                                              const float* __restrict__ mu_all, const float* __restrict__ state,
-                                             const float* __restrict__ plan_read, int g, int lane,
-                                             uint8_t* __restrict__ flag) {
+                                             const float* __restrict__ plan_read, uint32_t t,
+                                             const unsigned* __restrict__ hist_prev, unsigned* __restrict__ hist_cur,
+                                             int g, int lane, uint8_t* __restrict__ flag) {
   const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
   const DevArm* arm = arms + a;
   const DevArm* nb = arms + i;
   uint8_t f = 0;
-  if (i != a && h < arm->H && h < nb->H) {
-    if (!meta->valid[0][i]) {
+  bool quiet = false;
+  const bool inside = i != a && h < arm->H && h < nb->H;
+  if (inside) {
+    // Drop history: the group at step h + 1 of the previous control step
+    // (the shift brings it here) ran the network or was quiet and dropped at
+    // most min_drop of its checks, and this is not the group's probe step.
+    if (sm->probe > 0 && (t + (uint32_t)g) % (uint32_t)sm->probe != 0u && h + 1 < arm->H && h + 1 < nb->H) {
+      const unsigned v = hist_prev[g + 1];
+      quiet = v < kHistNone && (float)v <= sm->min_drop * (float)(arm->Npad / kWave);
+    }
+    if (!meta->valid[0][i] || quiet) {
       f = 1;
     } else if (sm->screen > 0.f) {
       const float* mu = mu_all + (size_t)a * P.Hmax * 7;
@@ -506,7 +518,14 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
       f = gmin < sm->screen ? 1 : 0;
     }
   }
-  if (lane == 0) flag[g] = f;
+  if (lane == 0) {
+    flag[g] = f;
+    // This step's history (first iteration): 0 for a group that runs the
+    // network (the rollout kernel counts its dropped checks) or stays
+    // quiet; none for one screened for another reason or outside both
+    // horizons.
+    if (hist_cur) hist_cur[g] = inside && (f == 0 || quiet) ? 0u : kHistNone;
+  }
 }
 
 // Rows of blocks blockIdx.y < number of arms: own-joint features of every
@@ -1082,27 +1101,33 @@ __global__ __launch_bounds__(kNoiseThreads) void k_noise_screen(const DevArm* __
                                                                 const float* __restrict__ mu_all,
                                                                 const float* __restrict__ state,
                                                                 const float* __restrict__ plan_read,
-                                                                uint8_t* __restrict__ screened) {
+                                                                uint8_t* __restrict__ screened,
+                                                                unsigned* __restrict__ hist) {
   const Params& P = *Pp;
   const int a = blockIdx.z;
+  const uint32_t t = ssp->t;
   if (a < P.A) {
-    noise_at(arms, P, ssp->t, chol, eps, k, a, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
+    noise_at(arms, P, t, chol, eps, k, a, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
     return;
   }
+  const int ng = P.A * P.A * P.Hmax;
   const int g = ((int)(blockIdx.y * gridDim.x + blockIdx.x)) * (kNoiseThreads / kWave) + (int)(threadIdx.x / kWave);
-  if (g >= P.A * P.A * P.Hmax) return;  // whole waves
-  screen_group(arms, P, sm, meta, mu_all, state, plan_read, g, threadIdx.x & (kWave - 1), screened);
+  if (g >= ng) return;  // whole waves
+  // The previous step's drop history is read; this step's is started in
+  // the first iteration.
+  screen_group(arms, P, sm, meta, mu_all, state, plan_read, t, hist + (size_t)((t + 1u) & 1u) * ng,
+               k == 0 ? hist + (size_t)(t & 1u) * ng : nullptr, g, threadIdx.x & (kWave - 1), screened);
 }
 
 hipError_t launch_noise_screen(const DevArm* arms, const Params* P, const StepState* ss, const float* chol,
                                float* eps, int k, int n_arms, int hmax, int npad_max, const SurModel* model,
                                const BoardMeta* meta, const float* mu, const float* state, const float* plan_read,
-                               uint8_t* screened, hipStream_t s) {
+                               uint8_t* screened, unsigned* hist, hipStream_t s) {
   // the screen plane holds gx * hmax blocks of kNoiseThreads / 64 waves, one per group
   constexpr int waves = kNoiseThreads / kWave;
   const int gx = std::max((npad_max + kNoiseThreads - 1) / kNoiseThreads, (n_arms * n_arms + waves - 1) / waves);
   hipLaunchKernelGGL(k_noise_screen, dim3(gx, hmax, n_arms + 1), dim3(kNoiseThreads), 0, s, arms, P, ss, chol, eps,
-                     k, model, meta, mu, state, plan_read, screened);
+                     k, model, meta, mu, state, plan_read, screened, hist);
   return hipGetLastError();
 }
 

@@ -29,7 +29,12 @@ struct SurModel {
   float mid[7], inv_half[7];
   float margin;                // predictions below this are checked exactly
   float screen;                // mean-rollout distance below which a group skips the network (0 = off)
+  int probe;                   // drop-history screen: re-probe period in control steps (0 = off)
+  float min_drop;              // share of a group's checks dropped at or below which it goes quiet
 };
+// Drop history of a group with no history yet (never ran the network, or
+// screened for another reason); otherwise the count of dropped checks.
+constexpr unsigned kHistNone = 0x80000000u;
 
 // GEMM: C[m][n] = sum_k A(m,k) B(k,n) over bfloat16 operands, FP32 sum.
 // A(m,k) = transA ? A[k*lda + m] : A[m*lda + k]; B(k,n) = transB ? B[n*ldb + k] : B[k*ldb + n].
@@ -81,11 +86,14 @@ hipError_t launch_pair_distance(int layout, const DevArm* arms, int ai, int aj, 
                                 int M, float* out, hipStream_t s);
 // The iteration's noise (as launch_noise) and the screen flag of every
 // (arm, neighbour, step) group ([A][A][Hmax], 1: the group needs no
-// prediction) in one launch.
+// prediction) in one launch.  hist: the groups' drop history of the last two
+// control steps [2][A][A][Hmax] (step parity; 0 = ran the network or stayed
+// quiet and dropped nothing); the previous step's is read, the current
+// step's started in iteration 0.
 hipError_t launch_noise_screen(const DevArm* arms, const Params* P, const StepState* ss, const float* chol,
                                float* eps, int k, int n_arms, int hmax, int npad_max, const SurModel* model,
                                const BoardMeta* meta, const float* mu, const float* state, const float* plan_read,
-                               uint8_t* screened, hipStream_t s);
+                               uint8_t* screened, unsigned* hist, hipStream_t s);
 // Own-feature rows of every (arm, step, rollout) from the iteration's noise
 // `eps`, the neighbour records of every (a, i, h < Hmax) from the read-side
 // plans, and this step's inference descriptors from the screen flags (groups

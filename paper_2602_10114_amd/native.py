@@ -76,7 +76,8 @@ class MpcParams(C.Structure):
                 ("max_obstacles", C.c_int), ("collision_mode", C.c_int),
                 ("surrogate_margin", C.c_float), ("alpha_sigma", C.c_float), ("sigma_floor", C.c_float),
                 ("plan_mode", C.c_int), ("w_manip", C.c_float), ("manip_thresh", C.c_float),
-                ("surrogate_screen", C.c_float)]
+                ("surrogate_screen", C.c_float), ("surrogate_probe", C.c_int),
+                ("surrogate_min_drop", C.c_float)]
 
 
 _lib = None
@@ -145,6 +146,10 @@ def params_struct(p: dict) -> MpcParams:
     for name, _ in MpcParams._fields_:
         if name in ("iters", "max_obstacles", "collision_mode", "plan_mode"):
             setattr(s, name, int(p[name]))
+        elif name == "surrogate_probe":
+            s.surrogate_probe = int(p.get("surrogate_probe", 0))
+        elif name == "surrogate_min_drop":
+            s.surrogate_min_drop = float(p.get("surrogate_min_drop", 0.0))
         elif name == "seed":
             s.seed = int(p["seed"])
         else:

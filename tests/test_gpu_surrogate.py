@@ -630,3 +630,86 @@ def test_screened_groups_skip_the_network_and_stay_exact():
     st = ctl.surrogate_stats()
     assert st["predicted_far"] == 0 and st["waves_skipped"] == 0 and st["queries"] > 0
     ctl.close()
+
+
+@pytest.mark.parametrize("min_drop", [0.0, 0.5])
+def test_drop_history_screens_quiet_groups(min_drop):
+    """surrogate_probe / surrogate_min_drop: a group (arm, neighbour, step)
+    that dropped at most min_drop of its 64-rollout checks at step h + 1 in
+    the previous control step (the shift brings that step to h) runs no
+    network on this step unless (t + g) mod P = 0, g the group's index; all
+    its queries are then checked exactly.  Step 0 has no published plan,
+    step 1 no history (every group runs the network); on step 2 the GPU's
+    screened groups equal that rule applied to step 1's dropped blocks, and
+    the stage costs match the oracle with the neighbour inactive exactly
+    where the GPU dropped it (1e-4 relative)."""
+    _say(f"case: collision mode 1 with the drop-history screen (min_drop {min_drop}), config 2 shape, "
+         "160 rollouts x 20 steps")
+    sc = small_scene(2, n=160, h=20)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    ref = native.Controller(sc.arms, sc.params)
+    ref.debug_enable(True)
+    ref.step(sc.state, sc.goal, obst)
+    ref.sync()
+    q0 = ref.debug_get("Q", 0).cpu().numpy().astype(np.float64)
+    ref.close()
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
+    f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
+    P = 3
+    ctl = native.Controller(sc.arms, {**sc.params, "surrogate_probe": P, "surrogate_min_drop": min_drop})
+    ctl.set_surrogate_params(params)
+    ctl.set_collision_mode(1)
+    ctl.step(sc.state, sc.goal, obst)          # t = 0: nothing published
+    ctl.share_plans()
+    ctl.debug_enable(True)
+    ctl.step(sc.state, sc.goal, obst)          # t = 1: every group runs the network
+    ctl.share_plans()
+    ctl.sync()
+    skips1 = [ctl.debug_get("SKIP", a).cpu().numpy() for a in range(2)]
+    boards = read_boards(ctl, sc)
+    ctl.surrogate_stats(reset=True)
+    ctl.step(sc.state, sc.goal, obst)          # t = 2: the rule under test
+    ctl.sync()
+    caps = [Capture(ctl, a) for a in range(2)]
+    skips2 = [ctl.debug_get("SKIP", a).cpu().numpy() for a in range(2)]
+    st = ctl.surrogate_stats()
+    ctl.close()
+    Hmax = max(a.horizon for a in sc.arms)
+    n_quiet = n_net = n_drop = 0
+    for a in range(2):
+        i = 1 - a
+        arm, nb = sc.arms[a], sc.arms[i]
+        N, H = arm.n_rollouts, arm.horizon
+        Hmin = min(H, nb.horizon)
+
+        def dropped(row):
+            return [bool(np.all(row[64 * b:64 * b + 64] == 1)) for b in range(N // 64)]
+
+        waves = -(-N // 64)   # the padded rollouts' waves (a partial wave never drops)
+
+        drop = np.zeros((H, N), bool)
+        for h in range(Hmin):
+            assert not np.any(skips1[a][i, h] == 2), (a, h)   # step 1: no history, nothing screened
+            g = (a * 2 + i) * Hmax + h
+            quiet = (h + 1 < Hmin and (2 + g) % P != 0
+                     and sum(dropped(skips1[a][i, h + 1])) <= min_drop * waves)
+            row = skips2[a][i, h]
+            screened = bool(np.all(row == 2))
+            assert screened or not np.any(row == 2), (a, h)
+            assert screened == quiet, (a, h, g)
+            n_quiet += screened
+            n_net += not screened
+            for b, d in enumerate(dropped(row)):
+                if d:
+                    drop[h, 64 * b:64 * b + 64] = True
+                    n_drop += 1
+        on = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+        off_b = list(boards)
+        off_b[i] = (boards[i][0], 0, boards[i][2])
+        off = oracle_stage(sc, a, caps[a], sc.obstacles, off_b)
+        assert rel_err(caps[a].stage, np.where(drop, off, on)) < 1e-4, a
+    _say(f"  quiet groups {n_quiet}, through the network {n_net}, dropped blocks {n_drop}, counters {st}")
+    assert n_quiet > 0 and n_net > 0 and n_drop > 0
+    assert st["waves_skipped"] == n_drop
