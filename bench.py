@@ -631,7 +631,13 @@ def main():
     ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
                     help="print a summary of a rocprofv3 --pmc pass (per-kernel counters, MFMA busy share) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters)")
+                    help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters) and "
+                         "a plain sum over the weighted mean's bytes (read-only reference rate)")
+    ap.add_argument("--screen", type=float, default=None,
+                    help="learned legs: this screen distance instead of the sweep")
+    ap.add_argument("--min-drop", type=float, default=None,
+                    help="learned legs: this drop-history share instead of the sweep")
+    ap.add_argument("--no-4arm", action="store_true", help="skip the 4-arm learned-distance legs")
     args = ap.parse_args()
     if args.summarize:
         print(summarize(*args.summarize, steps=args.steps))
@@ -688,10 +694,16 @@ def main():
         # below the margin, same inputs and step count.
         params, rep = train_surrogate(scenes.make_scene(5, collision_mode=0))
         print(f"bench: surrogate trained in {rep['seconds']:.1f} s", file=sys.stderr, flush=True)
-        sweep5, tau5 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup)
-        print(f"bench: screen sweep {sweep5} -> {tau5}", file=sys.stderr, flush=True)
-        drops5, md5 = min_drop_sweep(5, params, tau5, dev, stream)
-        print(f"bench: min_drop sweep {drops5} -> {md5}", file=sys.stderr, flush=True)
+        if args.screen is None:
+            sweep5, tau5 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup)
+            print(f"bench: screen sweep {sweep5} -> {tau5}", file=sys.stderr, flush=True)
+        else:
+            sweep5, tau5 = {}, args.screen
+        if args.min_drop is None:
+            drops5, md5 = min_drop_sweep(5, params, tau5, dev, stream)
+            print(f"bench: min_drop sweep {drops5} -> {md5}", file=sys.stderr, flush=True)
+        else:
+            drops5, md5 = {}, args.min_drop
         scene = scenes.make_scene(5, collision_mode=0)
         ctl2 = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": tau5,
                                               "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5},
@@ -738,12 +750,19 @@ def main():
                                                            screen=tau5, probe=SURROGATE_PROBE, min_drop=md5)
             out["surrogate"]["latency_1000_no_history"] = latency_leg(5, CONFIG_STEPS[5], dev, stream,
                                                                       params=params, screen=tau5)
+    if not args.no_surrogate and not args.no_4arm:
         # The 4-arm workload with its own network: exact vs learned step,
         # then the audit.
         sc4 = scenes.make_scene(4, collision_mode=0)
         p4, rep4 = train_surrogate(scenes.make_scene(4, collision_mode=0))
-        sweep4, tau4 = screen_sweep(4, p4, stream, dev, max(5, args.steps // 2), args.warmup)
-        drops4, md4 = min_drop_sweep(4, p4, tau4, dev, stream)
+        if args.screen is None:
+            sweep4, tau4 = screen_sweep(4, p4, stream, dev, max(5, args.steps // 2), args.warmup)
+        else:
+            sweep4, tau4 = {}, args.screen
+        if args.min_drop is None:
+            drops4, md4 = min_drop_sweep(4, p4, tau4, dev, stream)
+        else:
+            drops4, md4 = {}, args.min_drop
         ctl4 = native.Controller(sc4.arms, {**sc4.params, "collision_mode": 0, "surrogate_screen": tau4,
                                             "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md4},
                                  stream=stream)
@@ -791,8 +810,15 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        # a plain read-only reduction over as many bytes as the weighted
+        # mean reads on this workload (the noise of every arm, step, joint)
+        n_eps = sum(a.n_rollouts * a.horizon for a in scenes.make_scene(5, collision_mode=0).arms) * 7
+        for _ in range(3):
+            red = src[:n_eps].sum()
         torch.cuda.synchronize()
+        del red
         out["copy_calibration_bytes"] = src.numel() * 4
+        out["reduction_reference_bytes"] = n_eps * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scenes.make_scene(5, collision_mode=0))
     ctl.close()
