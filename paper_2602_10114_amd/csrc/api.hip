@@ -853,6 +853,7 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
   S.obstacles = obstacles;
   S.n_obs = n_obstacles;
   S.t = c->t;
+  S.u_out = u_out;
   S.st_state = c->st_state;
   S.st_goal = c->st_goal;
   S.st_obs = c->st_obs;
@@ -886,7 +887,6 @@ extern "C" int mpc_step(mpc_ctx* c, const float* state, const float* goal, const
   } else {
     if ((rc = enqueue_body(c, false))) return rc;
   }
-  HIPCHK(c, hipMemcpyAsync(u_out, c->u_stage, sizeof(float) * 7 * c->A, hipMemcpyDeviceToDevice, c->stream));
   c->t += 1;
   c->stepped = true;
   return MPC_OK;

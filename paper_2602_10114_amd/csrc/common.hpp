@@ -72,7 +72,7 @@ constexpr int kTri = 28;
 struct StepState {
   uint32_t t;                  // control step counter (noise stream)
   int n_obs;
-  int pad0, pad1;
+  float* u_out;                // the caller's U* array [A][7] of this step (device)
   float dist_now[kMaxArms];
   int nb_count[kMaxArms];
   Nb nb[kMaxArms][kMaxArms];

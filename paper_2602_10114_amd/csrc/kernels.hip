@@ -715,6 +715,7 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
   if (tid == 0) {
     SS.t = A.t;
     SS.n_obs = A.n_obs;
+    SS.u_out = A.u_out;
   }
   __syncthreads();
   // Priority factors against every published neighbour (Eq. 10) and the
@@ -825,8 +826,13 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   float* w = A.w + (size_t)a * P.Nmax;
   for (int n = tid; n < N; n += blockDim.x) w[n] = expf(-(cost[n] - m) * inv_lambda) * zinv;
   if (tid < 7) {
+    // U* into the staged copy and straight into the caller's array of this
+    // step (its address came with Sense, outside the captured graph)
     const float* eps = A.eps + arm->eps_off;
-    A.u_out[a * 7 + tid] = A.mu[(size_t)a * P.Hmax * 7 + tid] + eps[(size_t)tid * arm->Npad + nstar];
+    const float u = A.mu[(size_t)a * P.Hmax * 7 + tid] + eps[(size_t)tid * arm->Npad + nstar];
+    A.u_out[a * 7 + tid] = u;
+    float* uo = A.ss->u_out;
+    if (uo) uo[a * 7 + tid] = u;
   }
   if (tid == 0) A.argmin[a] = nstar;
 }

@@ -63,6 +63,7 @@ struct SenseArgs {
   const float* obstacles;      // caller [O][4]
   int n_obs;
   uint32_t t;
+  float* u_out;                // caller [A][7], written by k_softmax (PickBest / Act)
   float* st_state;
   float* st_goal;
   float* st_obs;
@@ -82,7 +83,7 @@ struct ReduceArgs {
   float* w;                    // [A][Nmax]
   const float* eps;
   float* mu;
-  float* u_out;                // [A][7]
+  float* u_out;                // [A][7] staged copy (debug capture); the caller's array is ss->u_out
   int* argmin;                 // [A]
   const float* st_state;
   float* plan_write;

@@ -399,11 +399,17 @@ __device__ __forceinline__ void items_block(const DevArm* __restrict__ arms, con
                                             unsigned long long* __restrict__ counts, int block) {
   __shared__ int s_off[kMaxGroups + 1];
   __shared__ int s_wave[kThreads / kWave];
+  __shared__ int s_H[kMaxArms], s_blk[kMaxArms];
   const int tid = threadIdx.x, ng = P.A * P.A * P.Hmax;
+  if (tid < P.A) {
+    s_H[tid] = arms[tid].H;
+    s_blk[tid] = arms[tid].Npad / 32;
+  }
+  __syncthreads();
   auto cnt = [&](int g) -> int {
     const int h = g % P.Hmax, ai = g / P.Hmax, a = ai / P.A, i = ai % P.A;
-    if (i == a || h >= arms[a].H || h >= arms[i].H || screened[g]) return 0;
-    return arms[a].Npad / 32;
+    if (i == a || h >= s_H[a] || h >= s_H[i] || screened[g]) return 0;
+    return s_blk[a];
   };
   // Exclusive scan: each thread a contiguous run of groups, then the runs'
   // totals by wave prefix sums (shuffles) and the waves' totals in order.
@@ -480,15 +486,25 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
       f = 1;
     } else if (sm->screen > 0.f) {
       const float* mu = mu_all + (size_t)a * P.Hmax * 7;
-      float q[8];
-      for (int j = 0; j < 7; ++j) {
-        float qq = state[(a * 7 + j) * 3 + 0], qd = state[(a * 7 + j) * 3 + 1];
-        for (int hh = 0; hh <= h; ++hh) {
-          qd = fmaf_(P.dt, mu[hh * 7 + j], qd);
+      // The mean rollout's joints at step h: lane j < 7 integrates joint j
+      // (the loads of eight steps go out together), then every lane takes
+      // the seven values.
+      const int jj = lane < 7 ? lane : 0;
+      float qq = state[(a * 7 + jj) * 3 + 0], qd = state[(a * 7 + jj) * 3 + 1];
+      for (int h0 = 0; h0 <= h; h0 += 8) {
+        float m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = h0 + u <= h ? mu[(h0 + u) * 7 + jj] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (h0 + u > h) break;  // uniform
+          qd = fmaf_(P.dt, m[u], qd);
           qq = fmaf_(P.dt, qd, qq);
         }
-        q[j] = qq;
       }
+      float q[8];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) q[j] = __shfl(qq, j);
       q[7] = 0.f;
       Frame F[7];
       forward_kinematics(F, arm, q);
@@ -507,10 +523,18 @@ __device__ __forceinline__ void screen_group(const DevArm* __restrict__ arms, co
         float x, y, z;
         frame_point(Fb, p[0], p[1], p[2], x, y, z);
         const float4* pl = reinterpret_cast<const float4*>(plan_read) + ((size_t)i * P.Hmax + h) * P.Smax;
-        for (int k = 0; k < nb->S; ++k) {
-          const float4 o = pl[k];
-          const float dx = x - o.x, dy = y - o.y, dz = z - o.z;
-          gmin = fminf(gmin, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - p[3] - o.w);
+        // eight plan spheres per batch, loads first (past the end the last
+        // sphere repeats, which leaves the minimum unchanged)
+        const int S = nb->S;
+        for (int k0 = 0; k0 < S; k0 += 8) {
+          float4 o[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) o[u] = pl[min(k0 + u, S - 1)];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float dx = x - o[u].x, dy = y - o[u].y, dz = z - o[u].z;
+            gmin = fminf(gmin, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - p[3] - o[u].w);
+          }
         }
       }
 #pragma unroll
@@ -1087,10 +1111,11 @@ hipError_t launch_sur_states(const DevArm* arms, const Params* P, const SurModel
   return hipGetLastError();
 }
 
-// The iteration's noise (planes blockIdx.z < number of arms, as k_noise) and
-// in the plane blockIdx.z = number of arms the screen flag of every (arm,
-// neighbour, step) group, one wave each, ahead of the feature launch whose
-// descriptor row reads the flags.
+// The screen flag of every (arm, neighbour, step) group, one wave each, in
+// the plane blockIdx.z = 0 (dispatched first, so its latency-bound waves
+// overlap the noise), and the iteration's noise in the planes blockIdx.z =
+// 1 + arm (as k_noise), ahead of the feature launch whose descriptor row
+// reads the flags.
 __global__ __launch_bounds__(kNoiseThreads) void k_noise_screen(const DevArm* __restrict__ arms,
                                                                 const Params* __restrict__ Pp,
                                                                 const StepState* __restrict__ ssp,
@@ -1104,10 +1129,9 @@ __global__ __launch_bounds__(kNoiseThreads) void k_noise_screen(const DevArm* __
                                                                 uint8_t* __restrict__ screened,
                                                                 unsigned* __restrict__ hist) {
   const Params& P = *Pp;
-  const int a = blockIdx.z;
   const uint32_t t = ssp->t;
-  if (a < P.A) {
-    noise_at(arms, P, t, chol, eps, k, a, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
+  if (blockIdx.z > 0) {
+    noise_at(arms, P, t, chol, eps, k, blockIdx.z - 1, blockIdx.y, blockIdx.x * kNoiseThreads + threadIdx.x);
     return;
   }
   const int ng = P.A * P.A * P.Hmax;
