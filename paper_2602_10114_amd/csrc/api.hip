@@ -760,7 +760,7 @@ static int enqueue_body(mpc_ctx* c, bool debug) {
     if (c->profile) HIPCHK(c, c->prof_roll.begin(c->stream, &e1));
     HIPCHK(c, launch_rollout(R, c->layout, debug, c->waves, c->grid, c->stream));
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, launch_softmax(Rr, c->A, c->Nmax, c->stream));
+    HIPCHK(c, launch_softmax(Rr, c->A, c->Nmax, c->Hmax, c->stream));
     // Between iterations the totals and Eq. 4 run on their own; after the
     // last one ToPlan applies them first.
     HIPCHK(c, launch_wmean(Rr, c->A, c->Hmax, c->Nmax, k + 1 < c->P.iters, c->stream));

@@ -757,21 +757,27 @@ __device__ __forceinline__ void argmin_merge(float& v, int& i, float v2, int i2)
 // Eq. 1 totals, one thread per rollout of every arm: C_n = sum_h gamma^h
 // C_{n,h} as one FMA chain in step order, so the value does not depend on the
 // rollout kernel's horizon tiling.
+// Eq. 1 total of rollout n of arm a: the stage costs weighted by gamma^h,
+// one FMA chain in step order.
+__device__ __forceinline__ float rollout_total(const ReduceArgs& A, const Params& P, int a, int H, int n) {
+  const float* stage = A.partial + (size_t)a * kMaxH * P.Nmax + n;
+  float c = 0.f;
+#pragma unroll 8
+  for (int h = 0; h < H; ++h) c = fmaf_(P.gpow[h], stage[(size_t)h * P.Nmax], c);
+  return c;
+}
+
 __global__ __launch_bounds__(256) void k_total(ReduceArgs A) {
   const int a = blockIdx.y;
   const int n = blockIdx.x * 256 + threadIdx.x;
   const DevArm* arm = A.arms + a;
   if (n >= arm->N) return;
-  const Params& P = *A.P;
-  const int H = arm->H;
-  const float* stage = A.partial + (size_t)a * kMaxH * P.Nmax + n;
-  float c = 0.f;
-#pragma unroll 8
-  for (int h = 0; h < H; ++h) c = fmaf_(P.gpow[h], stage[(size_t)h * P.Nmax], c);
-  A.cost[(size_t)a * P.Nmax + n] = c;
+  A.cost[(size_t)a * A.P->Nmax + n] = rollout_total(A, *A.P, a, arm->H, n);
 }
 
-__global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
+// with_total: the block first forms its arm's Eq. 1 totals itself (small
+// problems, where a separate k_total launch costs more than the work).
+__global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A, int with_total) {
   // Reductions: shuffles inside each wave, then the 16 wave results in a
   // fixed order (4 barriers in all).
   constexpr int kWaves = 1024 / kWave;
@@ -783,11 +789,17 @@ __global__ __launch_bounds__(1024) void k_softmax(ReduceArgs A) {
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int N = arm->N;
-  const float* cost = A.cost + (size_t)a * P.Nmax;
+  float* cost = A.cost + (size_t)a * P.Nmax;
   float best = 3.4e38f;
   int bi = 0x7fffffff;
   for (int n = tid; n < N; n += blockDim.x) {
-    const float c = cost[n];
+    float c;
+    if (with_total) {
+      c = rollout_total(A, P, a, arm->H, n);
+      cost[n] = c;  // read back below by the same thread only
+    } else {
+      c = cost[n];
+    }
     if (c < best) { best = c; bi = n; }
   }
 #pragma unroll
@@ -1008,12 +1020,14 @@ __global__ __launch_bounds__(256) void k_wmean(ReduceArgs A) {
 // noise sums) and, with covariance adaptation, t[7..34] (the weighted second
 // moments): the mean update for joint j (one thread per joint), and Eq. 3's
 // weighted covariance, its EMA and the floored Cholesky factor (one thread).
-__device__ __forceinline__ void mean_update(const ReduceArgs& A, const Params& P, int a, int h, int j,
-                                            const float* t) {
+__device__ __forceinline__ float mean_update(const ReduceArgs& A, const Params& P, int a, int h, int j,
+                                             const float* t) {
   float* mu = A.mu + ((size_t)a * P.Hmax + h) * 7 + j;
   const float m0 = *mu;
   const float mt = m0 + t[j];
-  *mu = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
+  const float m1 = fmaf_(P.alpha_mu, mt, (1.0f - P.alpha_mu) * m0);
+  *mu = m1;
+  return m1;
 }
 
 __device__ __forceinline__ void cov_update(const ReduceArgs& A, const Params& P, int a, int h, const float* t) {
@@ -1067,7 +1081,7 @@ __global__ __launch_bounds__(64) void k_wmean_fin(ReduceArgs A) {
   const int nsum = cov ? kWmeanSums : 7;
   if (tid < nsum) s_tot[tid] = chunk_total(A, P, a, h, nchunks, tid);
   __syncthreads();
-  if (tid < 7) mean_update(A, P, a, h, tid, s_tot);
+  if (tid < 7) (void)mean_update(A, P, a, h, tid, s_tot);
   if (cov && tid == 32) cov_update(A, P, a, h, s_tot);
 }
 
@@ -1080,31 +1094,35 @@ __global__ __launch_bounds__(64) void k_wmean_fin(ReduceArgs A) {
 constexpr int kToplanThreads = 256;
 __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin) {
   __shared__ float s_tot[kMaxH][kWmeanSums];
+  __shared__ float s_mu[kMaxH * 7];
   __shared__ float s_q[kMaxH][8];
   __shared__ Frame s_F[kMaxH][7];
   const int a = blockIdx.x, tid = threadIdx.x;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int H = arm->H;
+  // The arm's means (updated here after the last iteration) in LDS for the
+  // integration below.
   if (fin) {
     const int nchunks = (arm->N + kWmeanChunk - 1) / kWmeanChunk;
     const bool cov = P.cov != 0;
     const int nsum = cov ? kWmeanSums : 7;
     for (int e = tid; e < H * nsum; e += kToplanThreads) s_tot[e / nsum][e % nsum] = chunk_total(A, P, a, e / nsum, nchunks, e % nsum);
     __syncthreads();
-    for (int e = tid; e < H * 7; e += kToplanThreads) mean_update(A, P, a, e / 7, e % 7, s_tot[e / 7]);
+    for (int e = tid; e < H * 7; e += kToplanThreads) s_mu[e] = mean_update(A, P, a, e / 7, e % 7, s_tot[e / 7]);
     if (cov)
       for (int h = tid; h < H; h += kToplanThreads) cov_update(A, P, a, h, s_tot[h]);
-    __syncthreads();
+  } else {
+    for (int e = tid; e < H * 7; e += kToplanThreads) s_mu[e] = A.mu[(size_t)a * P.Hmax * 7 + e];
   }
+  __syncthreads();
   if (tid < 7) {
     // One thread per joint (the joints integrate independently).
     const int j = tid;
     float q = A.st_state[(a * 7 + j) * 3 + 0], qd = A.st_state[(a * 7 + j) * 3 + 1];
-    const float* mu = A.mu + (size_t)a * P.Hmax * 7;
     for (int h = 0; h < H; ++h) {
       if (P.plan_mode == 0) {
-        qd = fmaf_(P.dt, mu[h * 7 + j], qd);
+        qd = fmaf_(P.dt, s_mu[h * 7 + j], qd);
         q = fmaf_(P.dt, qd, q);
       }
       // plan_mode 1 (the S_d ablation): the current configuration at every step
@@ -1239,11 +1257,17 @@ hipError_t launch_sense(const SenseArgs& A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_total, dim3((nmax + 255) / 256, n_arms), dim3(256), 0, s, A);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_softmax, dim3(n_arms), dim3(1024), 0, s, A);
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, int hmax, hipStream_t s) {
+  // Up to 64 stage costs per thread of the 1024-thread block the totals go
+  // into the softmax launch; beyond that a launch of their own, one thread
+  // per rollout, reads them at full width.
+  const int with_total = (long long)nmax * hmax <= 64 * 1024 ? 1 : 0;
+  if (!with_total) {
+    hipLaunchKernelGGL(k_total, dim3((nmax + 255) / 256, n_arms), dim3(256), 0, s, A);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_softmax, dim3(n_arms), dim3(1024), 0, s, A, with_total);
   return hipGetLastError();
 }
 

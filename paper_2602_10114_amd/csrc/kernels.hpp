@@ -114,7 +114,9 @@ hipError_t launch_sense(const SenseArgs& A, hipStream_t s);
 // waves: 64-rollout waves per workgroup (1, 2 or 4); every arm's padded
 // rollout count must be a multiple of 64 * waves.
 hipError_t launch_rollout(const RolloutArgs& A, int layout, bool debug, int waves, int grid, hipStream_t s);
-hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, hipStream_t s);  // k_total, then k_softmax
+// k_total then k_softmax, or for small problems (Nmax x Hmax <= 64 K) k_softmax
+// forming the totals itself.
+hipError_t launch_softmax(const ReduceArgs& A, int n_arms, int nmax, int hmax, hipStream_t s);
 // k_wmean (chunk partials), then with `fin` k_wmean_fin (totals and Eq. 4).
 hipError_t launch_wmean(const ReduceArgs& A, int n_arms, int hmax, int nmax, bool fin, hipStream_t s);
 // ToPlan; with `fin` it first applies the last iteration's totals and Eq. 4.
