@@ -672,23 +672,24 @@ static_assert(kItemBatch <= kWave && kItemBatch >= 3, "one lane per staged descr
 static_assert(sizeof(SurItem) == 16, "descriptors are staged as 16-byte vectors");
 
 // Two query blocks through one 256-wide layer in one chain: kQB x kFB
-// independent accumulators, the bias chunks first, then per K chunk the
-// operand reads of both blocks (kInflight2 chunks ahead) and their MFMAs.
+// independent accumulators, started from the layer's FP32 bias (`bias16`:
+// the lane's 16 output rows of accumulator block fb at bias16[32 fb], in
+// LDS), then per K chunk the operand reads of both blocks (kInflight2 chunks
+// ahead) and their MFMAs.
 constexpr int kInflight2 = 1;
-__device__ __forceinline__ void layer256x2(const bf16x8_t (&w)[kFB][16], const bf16x8_t (&wb)[kFB], bf16x8_t ones,
+__device__ __forceinline__ void layer256x2(const bf16x8_t (&w)[kFB][16], const float* bias16,
                                            const uint16_t* row0, const uint16_t* row1, f32x16_t (&acc)[2][kFB]) {
   __builtin_amdgcn_sched_barrier(0);
   bf16x8_t b0[16], b1[16];
 #pragma unroll
+  for (int fb = 0; fb < kFB; ++fb) {
+    acc[0][fb] = *reinterpret_cast<const f32x16_t*>(bias16 + fb * 32);
+    acc[1][fb] = *reinterpret_cast<const f32x16_t*>(bias16 + fb * 32);
+  }
+#pragma unroll
   for (int c = 0; c < kInflight2; ++c) {
     b0[c] = load_bf16x8(row0 + c * 16);
     b1[c] = load_bf16x8(row1 + c * 16);
-  }
-  const f32x16_t zero = {};
-#pragma unroll
-  for (int fb = 0; fb < kFB; ++fb) {
-    acc[0][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
-    acc[1][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
   }
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
@@ -702,8 +703,9 @@ __device__ __forceinline__ void layer256x2(const bf16x8_t (&w)[kFB][16], const b
       acc[1][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b1[c], acc[1][fb], 0, 0, 0);
     }
   }
-  __builtin_amdgcn_sched_group_barrier(0x100, 2 * kInflight2, 0);
-  __builtin_amdgcn_sched_group_barrier(0x008, 2 * kFB, 0);
+  // Issue order: the accumulator starts (four 16-byte reads each) and the
+  // first operand reads, then per chunk its MFMAs and the reads ahead.
+  __builtin_amdgcn_sched_group_barrier(0x100, 2 * kFB * 4 + 2 * kInflight2, 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     __builtin_amdgcn_sched_group_barrier(0x008, 2 * kFB, 0);
@@ -722,6 +724,10 @@ struct alignas(16) InferLds {
   uint16_t act2[2][kStageQ][kActLd];  // second-layer outputs
   float part[2][kStageQ][kPartLd];    // output-layer partial sums [stage][query][wave * 2 + lane half]
   alignas(16) SurItem items[2][kItemBatch];  // this block's query-block descriptors, two batches
+  // FP32 biases of layers 2 and 3 in accumulator order: [layer][wave of the
+  // group][accumulator block][lane half][register] (register r of a lane
+  // holds output row (r / 4) * 8 + half * 4 + r % 4 of the 32-row block)
+  alignas(16) float bias[2][kGroupWaves][kFB][2][16];
   float b4;
 };
 
@@ -748,40 +754,28 @@ __device__ __forceinline__ void split_bias(float b, uint16_t& hi, uint16_t& mid,
   lo = f2bf(r1 - bf2f(mid));
 }
 
-// K chunk that adds a layer's bias: A operand = the rows' three bias parts
-// on lanes 0-31 (slots 0-2), zeros elsewhere; B operand = ones_operand.
-__device__ __forceinline__ bf16x8_t bias_operand(const float* bias, int row, int half) {
-  uint16_t hi = 0, mid = 0, lo = 0;
-  if (half == 0) split_bias(bias[row], hi, mid, lo);
-  return __builtin_bit_cast(bf16x8_t, make_uint4(hi | ((uint32_t)mid << 16), lo, 0u, 0u));
-}
-__device__ __forceinline__ bf16x8_t ones_operand(int half) {
-  return __builtin_bit_cast(bf16x8_t, make_uint4(half ? 0u : 0x3F803F80u, half ? 0u : 0x3F80u, 0u, 0u));
-}
 
 // 256-wide layer for this wave's kWaveRows output features over 32 queries
 // (`row` = the input activation row of the lane's query + (lane/32)*8): the
-// bias enters as one more K chunk (`wb` against the ones operand), so the
-// accumulators start from zero and the chain's first MFMAs need no LDS data.
-__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const bf16x8_t (&wb)[kFB], bf16x8_t ones,
-                                         const uint16_t* row, f32x16_t (&acc)[kFB]) {
+// accumulators start from the layer's FP32 bias (`bias16`, as in layer256x2),
+// read from LDS with the first operands.
+__device__ __forceinline__ void layer256(const bf16x8_t (&w)[kFB][16], const float* bias16, const uint16_t* row,
+                                         f32x16_t (&acc)[kFB]) {
   __builtin_amdgcn_sched_barrier(0);
   bf16x8_t b[16];
 #pragma unroll
-  for (int c = 0; c < kInflight; ++c) b[c] = load_bf16x8(row + c * 16);
-  const f32x16_t zero = {};
+  for (int fb = 0; fb < kFB; ++fb) acc[fb] = *reinterpret_cast<const f32x16_t*>(bias16 + fb * 32);
 #pragma unroll
-  for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[fb], ones, zero, 0, 0, 0);
+  for (int c = 0; c < kInflight; ++c) b[c] = load_bf16x8(row + c * 16);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c + kInflight < 16) b[c + kInflight] = load_bf16x8(row + (c + kInflight) * 16);
 #pragma unroll
     for (int fb = 0; fb < kFB; ++fb) acc[fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[fb][c], b[c], acc[fb], 0, 0, 0);
   }
-  // Issue order: the first kInflight operand reads, the bias MFMAs, then per
-  // chunk its kFB MFMAs and the read kInflight chunks ahead.
-  __builtin_amdgcn_sched_group_barrier(0x100, kInflight, 0);
-  __builtin_amdgcn_sched_group_barrier(0x008, kFB, 0);
+  // Issue order: the accumulator starts and the first kInflight operand
+  // reads, then per chunk its kFB MFMAs and the read kInflight chunks ahead.
+  __builtin_amdgcn_sched_group_barrier(0x100, kFB * 4 + kInflight, 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     __builtin_amdgcn_sched_group_barrier(0x008, kFB, 0);
@@ -864,11 +858,15 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
       for (int c = 0; c < 16; ++c) w[fb][c] = load_bf16x8(src + fb * 32 * kHid + c * 16);
   }
-  // The bias chunk of this wave's layer.
-  bf16x8_t wb[kFB];
-#pragma unroll
-  for (int fb = 0; fb < kFB; ++fb) wb[fb] = bias_operand(A.P32 + mlp_b_off(grp == 0 ? 1 : 2), row0 + fb * 32, half);
-  const bf16x8_t ones = ones_operand(half);
+  // Biases of layers 2 and 3 in accumulator order (read after the first
+  // barrier below).
+  for (int e = tid; e < (int)(sizeof(L.bias) / sizeof(float)); e += kInferThreads) {
+    const int r = e % 16, hf = (e / 16) % 2, fb = (e / 32) % kFB, wv = (e / (32 * kFB)) % kGroupWaves;
+    const int l = e / (32 * kFB * kGroupWaves);
+    const int feat = wv * kWaveRows + fb * 32 + (r / 4) * 8 + hf * 4 + r % 4;
+    (&L.bias[0][0][0][0][0])[e] = A.P32[mlp_b_off(1 + l) + feat];
+  }
+  const float* bias16 = &L.bias[grp][wq][0][half][0];
 
   const int G = gridDim.x;
   const int n_items = *A.count;  // descriptors written for this step (uniform)
@@ -974,7 +972,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma nounroll
       for (int qb = 0; qb < kQB; ++qb) {
         f32x16_t acc[kFB];
-        layer256(w, wb, ones, &L.act1[(s - 1) & 1][qb * 32 + q][half * 8], acc);
+        layer256(w, bias16, &L.act1[(s - 1) & 1][qb * 32 + q][half * 8], acc);
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][qb * 32 + q][fcol + fb * 32]);
       }
@@ -1008,7 +1006,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
       }
       {
         f32x16_t acc3[2][kFB];
-        layer256x2(w, wb, ones, &L.act2[(s - 2) & 1][q][half * 8], &L.act2[(s - 2) & 1][32 + q][half * 8], acc3);
+        layer256x2(w, bias16, &L.act2[(s - 2) & 1][q][half * 8], &L.act2[(s - 2) & 1][32 + q][half * 8], acc3);
 #pragma unroll
         for (int qb = 0; qb < kQB; ++qb) {
           float t = 0.f;
