@@ -36,18 +36,22 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, 256 CUs at 2.4 GHz
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bfloat16 MFMA
 KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd/csrc/device.hpp",
                   "paper_2602_10114_amd/csrc/common.hpp"]
-# HBM bytes per k_rollout launch on this workload from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes, each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x2.000, write x1.000); valid only for the kernel sources
-# with this digest (see profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "570c86fbdbd43782", "bytes_per_launch": 47266176}
+# HBM bytes per k_rollout launch on this workload, by waves per workgroup,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE passes, each scaled by the same
+# counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
+# valid only for the kernel sources with this digest (see
+# profiles/k_rollout_cfg5_exact.md).
+TRAFFIC = {"sources_sha256": "29e45b0602718673",
+           "bytes_per_launch": {1: 45907057, 2: 45860368, 4: 46148895}}
 
 
-def traffic_bytes():
-    """HBM bytes per rollout launch from the recorded counters, or None when
-    the kernel sources changed since they were taken (stale counters are
-    never reported)."""
-    return TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_digest() else None
+def traffic_bytes(waves):
+    """HBM bytes per rollout launch of the instantiation with `waves` waves
+    per workgroup from the recorded counters, or None when the kernel sources
+    changed since they were taken (stale counters are never reported)."""
+    if TRAFFIC["sources_sha256"] != sources_digest():
+        return None
+    return TRAFFIC["bytes_per_launch"].get(waves)
 
 
 def sources_digest():
@@ -686,7 +690,7 @@ def main():
                        "mean": float(lat.mean())},
         "roofline": {"kernel": "k_rollout", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": traffic_bytes(),
+                     "traffic": traffic_bytes(tuning[0] // 64),
                      "kernel_ms": roll_ms, "algorithmic_flop_per_launch": flops},
     }
     if not args.no_surrogate:
