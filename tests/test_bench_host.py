@@ -43,11 +43,13 @@ def test_recorded_traffic_is_reported_only_for_its_kernel_sources(monkeypatch):
     # The HBM bytes in the bench line are measured counters, valid only for
     # the sources they were taken on: with the digest of the current sources
     # they are reported, after any edit to those sources they are not.
-    assert bench.TRAFFIC["bytes_per_launch"] > 0
+    assert set(bench.TRAFFIC["bytes_per_launch"]) == {1, 2, 4}
+    assert all(v > 0 for v in bench.TRAFFIC["bytes_per_launch"].values())
     monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", bench.sources_digest())
-    assert bench.traffic_bytes() == bench.TRAFFIC["bytes_per_launch"]
+    for w in (1, 2, 4):
+        assert bench.traffic_bytes(w) == bench.TRAFFIC["bytes_per_launch"][w]
     monkeypatch.setitem(bench.TRAFFIC, "sources_sha256", "0" * 16)
-    assert bench.traffic_bytes() is None
+    assert bench.traffic_bytes(1) is None
 
 
 def _write_counters(path, rows):
