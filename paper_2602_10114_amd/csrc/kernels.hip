@@ -1097,10 +1097,18 @@ __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin
   __shared__ float s_mu[kMaxH * 7];
   __shared__ float s_q[kMaxH][8];
   __shared__ Frame s_F[kMaxH][7];
+  __shared__ float4 s_slot[kMaxSpheres];
+  __shared__ int s_src[kMaxSpheres];
   const int a = blockIdx.x, tid = threadIdx.x;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int H = arm->H;
+  const int slots = kLayoutSlots[arm->layout];
+  // The sphere table for the plan spheres below (read after the barriers).
+  for (int e = tid; e < slots; e += kToplanThreads) {
+    s_slot[e] = reinterpret_cast<const float4*>(arm->slot)[e];
+    s_src[e] = arm->slot_src[e];
+  }
   // The arm's means (updated here after the last iteration) in LDS for the
   // integration below.
   if (fin) {
@@ -1142,17 +1150,16 @@ __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin
   // Spheres in the arm's slot order (the hand is rigid with the last link),
   // written to their user positions.
   float4* out = reinterpret_cast<float4*>(A.plan_write) + (size_t)a * P.Hmax * P.Smax;
-  const int slots = kLayoutSlots[arm->layout];
   for (int e = tid; e < H * slots; e += kToplanThreads) {
     const int h = e / slots, jslot = e % slots;
-    const int src = arm->slot_src[jslot];
+    const int src = s_src[jslot];
     if (src < 0) continue;
     int b = 0;
     while (jslot >= kLayoutStart[arm->layout][b + 1]) ++b;
-    const float* p = arm->slot[jslot];
+    const float4 p = s_slot[jslot];
     float x, y, z;
-    frame_point(s_F[h][b < 7 ? b : 6], p[0], p[1], p[2], x, y, z);
-    out[(size_t)h * P.Smax + src] = make_float4(x, y, z, p[3]);
+    frame_point(s_F[h][b < 7 ? b : 6], p.x, p.y, p.z, x, y, z);
+    out[(size_t)h * P.Smax + src] = make_float4(x, y, z, p.w);
   }
   for (int e = tid; e < H * 7; e += kToplanThreads)
     A.planq_write[((size_t)a * P.Hmax + e / 7) * 7 + e % 7] = s_q[e / 7][e % 7];

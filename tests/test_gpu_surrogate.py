@@ -713,3 +713,53 @@ def test_drop_history_screens_quiet_groups(min_drop):
     _say(f"  quiet groups {n_quiet}, through the network {n_net}, dropped blocks {n_drop}, counters {st}")
     assert n_quiet > 0 and n_net > 0 and n_drop > 0
     assert st["waves_skipped"] == n_drop
+
+
+def test_learned_graph_path_with_history_equals_direct_launches():
+    """Collision mode 1 with the drop history over eight control steps: the
+    graph-captured step and the direct launches of the debug path give
+    bitwise the same actions, means and counters.  The history's step parity
+    and the caller's U* address are read on the device, so the captured graph
+    replays them correctly from step to step."""
+    _say("case: collision mode 1 with the drop history, graph vs direct launches, config 2 shape, 8 steps")
+    sc = small_scene(2, n=192, h=12)
+    obst = sc.obstacles if sc.obstacles.shape[0] else None
+    ref = native.Controller(sc.arms, sc.params)
+    ref.debug_enable(True)
+    ref.step(sc.state, sc.goal, obst)
+    ref.sync()
+    q0 = ref.debug_get("Q", 0).cpu().numpy().astype(np.float64)
+    ref.close()
+    lim = sc.arms[0].q_lim.astype(np.float64)
+    f4 = (q0[..., 4] - 0.5 * (lim[4, 0] + lim[4, 1])) / (0.5 * (lim[4, 1] - lim[4, 0]))
+    f4 = torch.from_numpy(f4.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    params = _joint_threshold_params(4, float(np.percentile(f4, 5)))
+
+    def run(direct):
+        s = torch.cuda.Stream()
+        ctl = native.Controller(sc.arms, {**sc.params, "surrogate_probe": 3}, stream=s)
+        ctl.set_surrogate_params(params)
+        ctl.set_collision_mode(1)
+        if direct:
+            ctl.debug_enable(True)
+        us = []
+        with torch.cuda.stream(s):
+            for _ in range(8):
+                u = ctl.step(sc.state, sc.goal, obst)
+                ctl.share_plans()
+                s.synchronize()
+                us.append(u.cpu().numpy().copy())
+        st = ctl.surrogate_stats()
+        means = [ctl.get_plan(a)[2].cpu().numpy() for a in range(2)]
+        ctl.close()
+        return us, means, st
+
+    u1, m1, s1 = run(False)
+    u2, m2, s2 = run(True)
+    for a, b in zip(u1, u2):
+        np.testing.assert_array_equal(a, b)
+    for a in range(2):
+        np.testing.assert_array_equal(m1[a], m2[a])
+    _say(f"  counters {s1}")
+    assert s1 == s2
+    assert s1["waves_skipped"] > 0 and s1["network_rows"] < s1["queries"]
