@@ -218,7 +218,7 @@ def cpu_baseline(scene):
     """The FP64 oracle, as it stands, on the host cores, on bounded samples of
     one control step: (1) one thread on the first 320 rollouts of every arm;
     (2) the first 640 rollouts of every arm split over worker processes, one
-    per core this process may use, at most 16 (a one-GPU machine's CPU share),
+    per core this process may use, at most 16,
     each running the unmodified oracle on a disjoint rollout window; value =
     rollout-steps / wall time of (2).  The host's CPU count and model are
     recorded with it."""
@@ -253,8 +253,9 @@ def obstacle_track(scene, n):
     return np.stack(out)
 
 
-# Closed-loop steps of each workload (BASELINE configs): config 1 is a
-# single control step, timed here over 200 independent repetitions.
+# Closed-loop control steps of each benchmark workload, keyed by the scene
+# number of scenes.make_scene; the one-arm workload is a single control step,
+# timed here over 200 repetitions.
 CONFIG_STEPS = {1: 200, 2: 200, 3: 500, 4: 1000, 5: 1000}
 
 

@@ -55,7 +55,7 @@ def test_philox_bitwise():
 # ------------------------------------------------------------ single arm
 @pytest.fixture(scope="module")
 def cfg1_ragged():
-    _say("case: config 1, N=100 (ragged tail), H=20, one step with capture")
+    _say("case: one-arm scene, N=100 (ragged tail), H=20, one step with capture")
     sc = small_scene(1, n=100)
     ctl = native.Controller(sc.arms, sc.params)
     ctl.debug_enable(True)
@@ -150,7 +150,7 @@ def _run_multi(sc, steps, publish=True, debug_last=True, stream=None):
 
 
 def test_two_arms_plan_sharing():
-    _say("case: config 2 shape, N=128, H=12, 3 steps with plan sharing")
+    _say("case: two facing arms, N=128, H=12, 3 steps with plan sharing")
     sc = small_scene(2, n=128, h=12)
     ctl, caps, boards, u = _run_multi(sc, 3)
     for a in range(2):
@@ -167,7 +167,7 @@ def test_two_arms_plan_sharing():
 
 
 def test_uneven_batch_and_counter():
-    _say("case: config 3 shape, ragged N (64,100,128,192), H (8,12,12,16), 3 steps")
+    _say("case: four uneven arms, ragged N (64,100,128,192), H (8,12,12,16), 3 steps")
     sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
     ctl, caps, boards, u = _run_multi(sc, 3)
     for a in range(4):
@@ -184,7 +184,7 @@ def test_uneven_batch_and_counter():
 
 
 def test_unpublished_neighbours_ignored():
-    _say("case: config 2 shape without publish")
+    _say("case: two facing arms without publish")
     sc = small_scene(2, n=64, h=10)
     ctl, caps, boards, _ = _run_multi(sc, 2, publish=False)
     for a in range(2):
@@ -221,7 +221,7 @@ def test_fault_injected_plan():
 
 
 def test_update_second_step_and_shift():
-    _say("case: config 1, two steps, update stage-isolated on the shifted means")
+    _say("case: one-arm scene, two steps, update stage-isolated on the shifted means")
     sc = small_scene(1, n=128, alpha_mu=0.5)
     ctl = native.Controller(sc.arms, sc.params)
     ctl.step(sc.state, sc.goal, sc.obstacles)
@@ -243,7 +243,7 @@ def test_update_second_step_and_shift():
 
 
 def test_graph_path_bitwise_equals_capture_path():
-    _say("case: graph-captured production kernel vs capturing kernel, config 3 shape")
+    _say("case: graph-captured production kernel vs capturing kernel, four uneven arms")
     sc = small_scene(3, n=[64, 100, 128, 192], h=[8, 12, 12, 16])
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -260,7 +260,7 @@ def test_graph_path_bitwise_equals_capture_path():
 
 
 def test_deterministic_repeat():
-    _say("case: repeat run bitwise, config 2 shape")
+    _say("case: repeat run bitwise, two facing arms")
     sc = small_scene(2, n=256, h=16)
     outs = []
     for _ in range(2):
@@ -313,7 +313,7 @@ def test_tiles_do_not_change_results():
 def test_tuner_choice_is_cached_per_shape():
     """The tuner's launch shape is kept per problem shape and device: a second
     context with the same shape starts from the same choice."""
-    _say("case: tuner cache, config 3 shape")
+    _say("case: tuner cache, four uneven arms")
     sc = small_scene(3, n=[256, 200, 512, 460], h=[8, 12, 12, 16])
     shapes = []
     for _ in range(2):
@@ -376,7 +376,7 @@ def test_no_obstacles_and_errors():
 
 
 def test_padded_sphere_layout():
-    _say("case: 64-sphere layout (8 per body), config 5 arm shape, 2 arms")
+    _say("case: 64-sphere layout (8 per body), 2 arms")
     sc = scenes.make_scene(5, collision_mode=0)
     sc.arms = sc.arms[:2]
     sc.arms[1] = scenes.dataclasses.replace(sc.arms[1], base=np.array([-0.75, 0.4, 0.0, -np.pi / 2], np.float32))
@@ -449,7 +449,7 @@ def test_end_to_end_report_with_live_coordination():
     rounding of a sphere centre (1e-7 m) into cost gaps far above 1e-4, so
     end-to-end parity is not a property of an FP32 implementation here; the
     stage-isolated tests above are the gate.  Prints the measured gaps."""
-    _say("case: end to end, config 2 shape with live coordination, 3 steps (report)")
+    _say("case: end to end, two facing arms with live coordination, 3 steps (report)")
     sc = small_scene(2, n=64, h=10)
     for a, (rel, dmu, U, _) in enumerate(_end_to_end(sc, 3, None)):
         _say(f"  arm {a}: total costs max relative gap {rel:.2e}; means max gap {dmu:.2e} (max|U| {U:.2f})")

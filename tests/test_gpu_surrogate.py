@@ -43,7 +43,7 @@ def _layer_slices():
 
 @pytest.fixture(scope="module")
 def ctl2():
-    _say("case: learned distance, config 2 arms")
+    _say("case: learned distance, two facing arms")
     sc = small_scene(2, n=64, h=8)
     ctl = native.Controller(sc.arms, sc.params)
     yield sc, ctl
@@ -136,7 +136,7 @@ def test_prediction_matches_oracle_forward(ctl2):
 
 
 def test_small_training_run_learns():
-    _say("case: short training run, config 2 arms")
+    _say("case: short training run, two facing arms")
     sc = small_scene(2, n=64, h=8)
     ctl = native.Controller(sc.arms, sc.params)
     M = 1 << 18
@@ -388,7 +388,7 @@ def test_learned_mixed_drops_stage_costs_against_oracle():
     sphere pairs of the kept blocks.  The audited run keeps the same costs
     and decisions, and counts dropped queries whose exact gap is below B:
     the drops do hide live coordination terms, so the comparison bites."""
-    _say("case: collision mode 1, mixed drops, config 2 shape, 160 rollouts (ragged block) x 20 steps")
+    _say("case: collision mode 1, mixed drops, two facing arms, 160 rollouts (ragged block) x 20 steps")
     sc = small_scene(2, n=160, h=20)
     obst = sc.obstacles if sc.obstacles.shape[0] else None
     # the rollouts' joints at the second step, from an exact-mode run
@@ -488,7 +488,7 @@ def test_learned_drops_do_not_depend_on_waves_per_workgroup():
     and audited stage costs, skip decisions and counters are bitwise those of
     one wave per workgroup (a network thresholding one joint, so that waves
     of one workgroup decide differently)."""
-    _say("case: collision mode 1, config 2 shape, 256 rollouts x 20 steps, 1 / 2 / 4 waves per workgroup")
+    _say("case: collision mode 1, two facing arms, 256 rollouts x 20 steps, 1 / 2 / 4 waves per workgroup")
     sc = small_scene(2, n=256, h=20)
     obst = sc.obstacles if sc.obstacles.shape[0] else None
     ref = native.Controller(sc.arms, sc.params)
@@ -539,7 +539,7 @@ def test_screened_groups_skip_the_network_and_stay_exact():
     the oracle with the neighbour inactive exactly where the GPU dropped it
     (1e-4 relative).  With a screen wider than the scene every group is
     screened: no descriptor at all, and the costs equal exact mode bitwise."""
-    _say("case: collision mode 1 with the screen, config 2 shape, 160 rollouts x 20 steps")
+    _say("case: collision mode 1 with the screen, two facing arms, 160 rollouts x 20 steps")
     sc = small_scene(2, n=160, h=20)
     obst = sc.obstacles if sc.obstacles.shape[0] else None
     ref = native.Controller(sc.arms, sc.params)
@@ -643,7 +643,7 @@ def test_drop_history_screens_quiet_groups(min_drop):
     screened groups equal that rule applied to step 1's dropped blocks, and
     the stage costs match the oracle with the neighbour inactive exactly
     where the GPU dropped it (1e-4 relative)."""
-    _say(f"case: collision mode 1 with the drop-history screen (min_drop {min_drop}), config 2 shape, "
+    _say(f"case: collision mode 1 with the drop-history screen (min_drop {min_drop}), two facing arms, "
          "160 rollouts x 20 steps")
     sc = small_scene(2, n=160, h=20)
     obst = sc.obstacles if sc.obstacles.shape[0] else None
@@ -721,7 +721,7 @@ def test_learned_graph_path_with_history_equals_direct_launches():
     bitwise the same actions, means and counters.  The history's step parity
     and the caller's U* address are read on the device, so the captured graph
     replays them correctly from step to step."""
-    _say("case: collision mode 1 with the drop history, graph vs direct launches, config 2 shape, 8 steps")
+    _say("case: collision mode 1 with the drop history, graph vs direct launches, two facing arms, 8 steps")
     sc = small_scene(2, n=192, h=12)
     obst = sc.obstacles if sc.obstacles.shape[0] else None
     ref = native.Controller(sc.arms, sc.params)
