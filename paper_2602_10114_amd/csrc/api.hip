@@ -1551,6 +1551,7 @@ extern "C" int mpc_surrogate_adam(mpc_ctx* c, const float* grad, float lr, float
   }
   HIPCHK(c, launch_adam(c->sur_p, c->sur_m, c->sur_v, grad, kMlpParams, lr, b1, b2, eps, step, c->stream));
   HIPCHK(c, launch_params_to_bf16(c->sur_p, c->sur_p16, kMlpParams, c->stream));
+  c->hist_stale = true;  // a changed network starts without drop history
   return MPC_OK;
 }
 
