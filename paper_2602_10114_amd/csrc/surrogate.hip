@@ -877,11 +877,10 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
   if (n_my == 0) return;
   const int n_st = (n_my + kQB - 1) / kQB;  // stages holding query blocks (the last may hold a stand-in)
   const int fcol = wq * kWaveRows + half * 4;  // this lane's first feature within an accumulator block
-  // The pipeline body is straight-line code: edge stages (before the first
-  // block reaches a layer, after the last one has left it) compute on
-  // in-bounds stand-in data (zeroed activations, the last block's inputs) and
-  // only their writes are suppressed, so the compiler may interleave each
-  // wave's MFMA and VALU work freely.
+  // Within a stage each layer's chains are straight-line code (the last
+  // stage's second query block, past the end, is a stand-in: the last block's
+  // inputs, writes suppressed); the edge stages skip the layers that have no
+  // block yet or any more.  The activations start zeroed.
   for (int e = tid; e < (int)(2 * sizeof(L.act1) / sizeof(uint4)); e += kInferThreads)
     reinterpret_cast<uint4*>(&L.act1[0][0][0])[e] = make_uint4(0u, 0u, 0u, 0u);
   for (int e = tid; e < (int)(sizeof(L.part) / sizeof(float)); e += kInferThreads) (&L.part[0][0][0])[e] = 0.f;
@@ -950,6 +949,10 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
           batch_next = *reinterpret_cast<const uint4*>(A.items + blockIdx.x + (long long)e * G);
         if (k == kStagesPerBatch - 2 && e < n_my) *reinterpret_cast<uint4*>(&L.items[nb & 1][lane]) = batch_next;
       }
+      // Edge stages (before the first block reaches a layer, after the last
+      // has left it) skip that layer's chains: uniform branches around
+      // whole chains, every barrier kept.
+      if (s < n_st) {
 #pragma unroll
       for (int qb = 0; qb < kQB; ++qb) {
         const uint4 x0w = x0s[qb], r1 = r1s[qb];
@@ -969,12 +972,16 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
 #pragma unroll
         for (int fb = 0; fb < kFB; ++fb) store_block(acc1[fb], &L.act1[s & 1][qb * 32 + q][fcol + fb * 32]);
       }
+      }
+      if (s >= 1 && s <= n_st) {
 #pragma nounroll
-      for (int qb = 0; qb < kQB; ++qb) {
-        f32x16_t acc[kFB];
-        layer256(w, bias16, &L.act1[(s - 1) & 1][qb * 32 + q][half * 8], acc);
+        for (int qb = 0; qb < kQB; ++qb) {
+          f32x16_t acc[kFB];
+          layer256(w, bias16, &L.act1[(s - 1) & 1][qb * 32 + q][half * 8], acc);
 #pragma unroll
-        for (int fb = 0; fb < kFB; ++fb) store_block(acc[fb], &L.act2[(s - 1) & 1][qb * 32 + q][fcol + fb * 32]);
+          for (int fb = 0; fb < kFB; ++fb)
+            store_block(acc[fb], &L.act2[(s - 1) & 1][qb * 32 + q][fcol + fb * 32]);
+        }
       }
       __syncthreads();
     }
@@ -1004,7 +1011,7 @@ __global__ __launch_bounds__(kInferThreads, 1) void k_sur_infer(SurInferArgs A) 
         const int k = kQB * (s - 3) + half;
         if (s >= 3 && k < n_my) A.y[((long long)blockIdx.x + (long long)k * G) * 32 + q] = y;
       }
-      {
+      if (s >= 2 && s <= n_st + 1) {
         f32x16_t acc3[2][kFB];
         layer256x2(w, bias16, &L.act2[(s - 2) & 1][q][half * 8], &L.act2[(s - 2) & 1][32 + q][half * 8], acc3);
 #pragma unroll
