@@ -190,6 +190,24 @@ def test_mode1_never_skipping_equals_exact():
     assert st["predicted_far"] == 0 and st["waves_skipped"] == 0 and st["queries"] > 0
 
 
+def test_mode1_never_skipping_equals_exact_with_iterations_and_adaptation():
+    """The same with two optimisation iterations per step, covariance
+    adaptation on (the noise launch of collision mode 1 draws L_h z) and the
+    drop history on (groups without drops go quiet): over three steps the
+    stage costs, totals, weights, means and noise equal exact mode bitwise."""
+    _say("case: collision mode 1, network predicting -1 m, K = 2, adapted covariance, drop history")
+    sc = small_scene(2, n=128, h=10)
+    sc.params.update(iters=2, alpha_sigma=0.5, surrogate_probe=3)
+    (c0, _, _), (c1, st, _) = _mode1_step(sc, _const_params(-1.0), audit=False)
+    for a in range(2):
+        for f in ("eps", "stage", "cost", "w", "mu"):
+            np.testing.assert_array_equal(getattr(c1[a], f), getattr(c0[a], f), err_msg=f"{f} arm {a}")
+        assert c1[a].argmin == c0[a].argmin
+    assert st["predicted_far"] == 0 and st["waves_skipped"] == 0 and st["queries"] > 0
+    # the history screened the groups that dropped nothing: fewer network rows than queries
+    assert st["network_rows"] < st["queries"]
+
+
 def test_mode1_always_skipping_drops_coordination_and_audit_counts():
     _say("case: collision mode 1, network predicting +1 m everywhere, audited")
     sc = small_scene(2, n=128, h=10)
