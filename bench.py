@@ -163,6 +163,41 @@ def summarize_pmc(pmc_dir):
     return "\n".join(out)
 
 
+WMEAN_SIZES = (4096, 8192, 16384)
+
+
+def summarize_sizes(trace_dir):
+    """The weighted mean's launch time per problem size from a trace of
+    `bench.py --wmean-sizes`: the launches of each size are told apart by
+    their grid (one block per 1024-rollout chunk, step and arm), the median
+    of each size is taken, and the bytes it reads (the noise of every arm,
+    step and joint) give its rate and the marginal rate between sizes."""
+    import csv
+    import glob
+    from collections import defaultdict
+    tr = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    by = defaultdict(list)
+    for r in csv.DictReader(open(tr)):
+        if "k_wmean" in r["Kernel_Name"] and "fin" not in r["Kernel_Name"]:
+            blocks = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+            by[blocks].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = [f"kernel trace: {tr}", f"{'rollouts/arm':>12s} {'MB read':>8s} {'launches':>8s} {'median us':>10s} {'TB/s':>6s}"]
+    prev = None
+    for n in WMEAN_SIZES:
+        blocks = -(-n // 1024)
+        v = sorted(by.get(blocks, []))
+        if not v:
+            continue
+        t = v[len(v) // 2] / 1e3
+        mb = 8 * 40 * 7 * n * 4 / 1e6
+        line = f"{n:12d} {mb:8.1f} {len(v):8d} {t:10.2f} {mb / t:6.2f}"
+        if prev:
+            line += f"   marginal {(mb - prev[0]) / (t - prev[1]):.2f} TB/s"
+        out.append(line)
+        prev = (mb, t)
+    return "\n".join(out)
+
+
 def algorithmic_flops_per_step(scene, active_neighbours=True):
     """Algorithmic work of one rollout launch: 11 FLOP per sphere pair (3 sub,
     5 for the dot product, sqrt, minus radii, min) plus the per rollout-step
@@ -643,12 +678,19 @@ def main():
     ap.add_argument("--min-drop", type=float, default=None,
                     help="learned legs: this drop-history share instead of the sweep")
     ap.add_argument("--no-4arm", action="store_true", help="skip the 4-arm learned-distance legs")
+    ap.add_argument("--wmean-sizes", action="store_true",
+                    help="also run the 8-arm workload at 8192 and 16384 rollouts per arm (weighted-mean size sweep)")
+    ap.add_argument("--summarize-sizes", metavar="TRACE_DIR",
+                    help="print the weighted mean's launch time per size from a trace of --wmean-sizes and exit")
     args = ap.parse_args()
     if args.summarize:
         print(summarize(*args.summarize, steps=args.steps))
         return
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
+        return
+    if args.summarize_sizes:
+        print(summarize_sizes(args.summarize_sizes))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU plan all-gather "
@@ -824,6 +866,18 @@ def main():
         del red
         out["copy_calibration_bytes"] = src.numel() * 4
         out["reduction_reference_bytes"] = n_eps * 4
+    if args.wmean_sizes:
+        # The same 8-arm workload at 2x and 4x the rollouts (the weighted
+        # mean then reads 73.4 and 146.8 MB): a few closed-loop steps each,
+        # for a kernel trace of the weighted mean against its size.
+        for n in WMEAN_SIZES[1:]:
+            sc = scenes.make_scene(5, collision_mode=0)
+            for a in sc.arms:
+                a.n_rollouts = n
+            c = native.Controller(sc.arms, sc.params, stream=stream)
+            timed_loop(c, sc, stream, 5, 3, 0, dev)
+            c.close()
+        out["wmean_sizes"] = list(WMEAN_SIZES)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scenes.make_scene(5, collision_mode=0))
     ctl.close()

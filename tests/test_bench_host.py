@@ -92,3 +92,33 @@ def test_counter_summary_rates(tmp_path):
     assert vals["FP32 share of VALU insts"] == pytest.approx(0.25 / 0.3, abs=1e-4)
     # FP32 operations: 64 lanes x (2 per FMA + 1 per add)
     assert vals["FP32 VALU ops (64 lanes)"] == pytest.approx(64 * (2 * 0.2 + 0.05) * 1024 * cyc, rel=1e-5)
+
+
+def test_weighted_mean_size_summary(tmp_path):
+    # Launches of three sizes told apart by their grid (one 256-thread block
+    # per 1024-rollout chunk); medians 8, 12 and 20 us for 36.7, 73.4 and
+    # 146.8 MB of noise; other kernels and the between-iterations kernel are
+    # ignored.
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Workgroup_Size_X", "Grid_Size_X"]
+    rows = []
+    for chunks, us in ((4, (7.0, 8.0, 9.0)), (8, (12.0, 11.0, 13.0)), (16, (20.0, 19.0, 30.0))):
+        for t in us:
+            rows.append({"Kernel_Name": "mrs::k_wmean(mrs::ReduceArgs)", "Start_Timestamp": 0,
+                         "End_Timestamp": int(t * 1000), "Workgroup_Size_X": 256, "Grid_Size_X": 256 * chunks})
+    rows.append({"Kernel_Name": "mrs::k_wmean_fin(mrs::ReduceArgs)", "Start_Timestamp": 0, "End_Timestamp": 999000,
+                 "Workgroup_Size_X": 64, "Grid_Size_X": 256})
+    rows.append({"Kernel_Name": "mrs::k_total(mrs::ReduceArgs)", "Start_Timestamp": 0, "End_Timestamp": 5000,
+                 "Workgroup_Size_X": 256, "Grid_Size_X": 1024})
+    with open(tmp_path / "t_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+    out = bench.summarize_sizes(str(tmp_path)).splitlines()
+    table = [line.split() for line in out[2:]]
+    assert [int(r[0]) for r in table] == [4096, 8192, 16384]
+    assert [float(r[3]) for r in table] == [8.0, 12.0, 20.0]
+    mb = [8 * 40 * 7 * n * 4 / 1e6 for n in (4096, 8192, 16384)]
+    assert float(table[0][4]) == pytest.approx(mb[0] / 8.0, abs=0.01)
+    # marginal rate between the last two sizes: 73.4 MB in 8 us
+    assert out[-1].endswith(f"marginal {(mb[2] - mb[1]) / 8.0:.2f} TB/s")
