@@ -249,6 +249,39 @@ static int build_arm(mpc_ctx* c, const mpc_arm_desc& d, int layout, DevArm& o) {
     o.slot_src[slot] = s;
     o.link[s] = b;
   }
+  // Body bounding spheres for the kernels' pair culls: the middle of the
+  // centres' box, the largest centre offset from it plus the largest radius,
+  // with 1e-4 m for the FP32 forward kinematics (the frames stay orthonormal
+  // to about 1e-6, and offsets are at most 1.5 m).
+  for (int b = 0; b < kBodies; ++b) {
+    double lo[3] = {1e30, 1e30, 1e30}, hi[3] = {-1e30, -1e30, -1e30}, rmax = 0.0;
+    int cnt = 0;
+    for (int sl = kLayoutStart[layout][b]; sl < kLayoutStart[layout][b + 1]; ++sl) {
+      if (o.slot_src[sl] < 0) continue;
+      ++cnt;
+      for (int i = 0; i < 3; ++i) {
+        lo[i] = std::min(lo[i], (double)o.slot[sl][i]);
+        hi[i] = std::max(hi[i], (double)o.slot[sl][i]);
+      }
+      rmax = std::max(rmax, (double)o.slot[sl][3]);
+    }
+    if (cnt == 0) {
+      o.bnd[b][0] = o.bnd[b][1] = o.bnd[b][2] = 0.f;
+      o.bnd[b][3] = -1.f;
+      continue;
+    }
+    float ctr[3];
+    for (int i = 0; i < 3; ++i) ctr[i] = (float)(0.5 * (lo[i] + hi[i]));
+    double rho = 0.0;
+    for (int sl = kLayoutStart[layout][b]; sl < kLayoutStart[layout][b + 1]; ++sl) {
+      if (o.slot_src[sl] < 0) continue;
+      double d2 = 0.0;
+      for (int i = 0; i < 3; ++i) d2 += ((double)o.slot[sl][i] - ctr[i]) * ((double)o.slot[sl][i] - ctr[i]);
+      rho = std::max(rho, std::sqrt(d2));
+    }
+    for (int i = 0; i < 3; ++i) o.bnd[b][i] = ctr[i];
+    o.bnd[b][3] = std::nextafter((float)(rho + rmax + 1e-4), 1e30f);
+  }
   (void)c;
   return MPC_OK;
 }

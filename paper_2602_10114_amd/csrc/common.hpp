@@ -38,6 +38,10 @@ struct DevArm {
   int slot_src[kMaxSpheres];   // user index of each slot, -1 = parked
   int link[kMaxSpheres];       // body of each user-order sphere
   float usph[kMaxSpheres][4];  // body-frame spheres in user order
+  // Bounding sphere of each body's spheres: centre in the body frame (xyz)
+  // and radius (w) = largest centre offset from it + largest sphere radius,
+  // rounded up; w < 0 marks a body without spheres.
+  float bnd[kBodies][4];
   long long eps_off;           // float offset of this arm's [H][d][Npad] noise block
 };
 

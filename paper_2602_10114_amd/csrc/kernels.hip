@@ -30,16 +30,32 @@ namespace mrs {
 //   |c_s - p_k|^2 - (r_s + r_k + B)^2 = E_s + F_k + c_s.w_xyz + r_s w_r,
 //   E_s = |c_s|^2 - r_s^2,  w = -2 (p_k, r_k + B),  F_k = |p_k|^2 - (r_k + B)^2,
 // is negative exactly when the pair's gap rho is below B, and the own-sphere
-// terms do not depend on the set.  raw keeps (p_k, r_k) for the FP64 gap.
+// terms do not depend on the set.  The FP64 gap takes p_k = -w_xyz / 2 (exact:
+// w_xyz was formed by an exact doubling) and r_k from rr.
 constexpr int kLdsSpheres = kMaxObs + (kMaxArms - 1) * kMaxSpheres;
 constexpr int kMaxSets = kMaxArms;  // obstacles + up to 7 neighbours
 static_assert(kMaxSets * kBodies <= 64, "one near bit per (set, body) in a 64-bit mask");
 
+// Pair cull.  The staged spheres of a set are taken in groups (each obstacle
+// alone; a neighbour plan in runs of 8, one body of a table sorted by body),
+// each with a bounding sphere whose radius covers every member's centre
+// offset, radius and the set's buffer B.  An own body (bounding sphere of
+// radius R_b about a fixed point of its frame) whose distance to a group's
+// centre is at least R_b + that radius has a gap of at least B + kCullPad -
+// (FP32 rounding, below 0.005 m for coordinates within 6 m) to every member:
+// no pair of it can contribute to the hinge, so the filter skips the group
+// when that holds in every lane.  The cost is unchanged bit for bit.
+constexpr float kCullPad = 0.01f;
+constexpr int kNbGroups = kMaxSpheres / 8;
+constexpr int kMaxGroups = kMaxObs + (kMaxArms - 1) * kNbGroups;
+
 struct LdsSets {
   float4 w[kLdsSpheres];
-  float4 raw[kLdsSpheres];
+  float rr[kLdsSpheres];
   float F[kLdsSpheres];
   float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
+  float4 gq[kMaxGroups];       // group bounding spheres: centre, radius (+ B + pad)
+  int set_g0[kMaxSets], set_gsz[kMaxSets];  // first group slot, spheres per group
   int set_k0[kMaxSets], set_n[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
   // learned-distance counters of the current item (added by each wave's
@@ -50,10 +66,36 @@ struct LdsSets {
 };
 
 __device__ __forceinline__ void stage_sphere(LdsSets& L, int dst, float4 s, float buf) {
-  L.raw[dst] = s;
+  L.rr[dst] = s.w;
   const float rb = s.w + buf;
   L.w[dst] = make_float4(-2.f * s.x, -2.f * s.y, -2.f * s.z, -2.f * rb);
   L.F[dst] = fmaf_(s.x, s.x, fmaf_(s.y, s.y, fmaf_(s.z, s.z, -rb * rb)));
+}
+
+// Bounding sphere of the staged spheres src[0, cnt) of a set with buffer buf:
+// centre at the middle of the centres' box, radius the largest centre
+// distance from it plus the sphere's radius, plus buf, kCullPad and 1e-4 m
+// for the rounding of this sum.
+__device__ __forceinline__ void stage_group(LdsSets& L, int slot, const float4* __restrict__ src, int cnt,
+                                            float buf) {
+  float lx = 3.0e38f, ly = 3.0e38f, lz = 3.0e38f, hx = -3.0e38f, hy = -3.0e38f, hz = -3.0e38f;
+  for (int j = 0; j < cnt; ++j) {
+    const float4 p = src[j];
+    lx = fminf(lx, p.x);
+    ly = fminf(ly, p.y);
+    lz = fminf(lz, p.z);
+    hx = fmaxf(hx, p.x);
+    hy = fmaxf(hy, p.y);
+    hz = fmaxf(hz, p.z);
+  }
+  const float qx = 0.5f * (lx + hx), qy = 0.5f * (ly + hy), qz = 0.5f * (lz + hz);
+  float rad = 0.f;
+  for (int j = 0; j < cnt; ++j) {
+    const float4 p = src[j];
+    const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+    rad = fmaxf(rad, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) + p.w);
+  }
+  L.gq[slot] = make_float4(qx, qy, qz, rad + buf + kCullPad + 1.0e-4f);
 }
 
 // Filter value given to unused slots of a padded layout: never below the slack.
@@ -179,19 +221,54 @@ __device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSet
 // the squared-gap expansion with the body's largest own radius per set; bit
 // 8*si + b of `near` is set when body b has a pair below the slack in set si.
 // The exact pass tests the flagged bodies' pairs with their own radii.
+// Groups are first tested against the body's bounding sphere (eight at a
+// time, one ballot each), and only the groups some lane of the wave may be
+// near are filtered; the body's spheres are built at the first such group.
 template <int LAY, int B_>
 __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
                                             const LdsSets& L, int nsets, unsigned scored,
                                             unsigned long long& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
-  float ux[8], uy[8], uz[8], E[8];
-  const float rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
+  const float br = arm->bnd[B_][3];
+  if (br >= 0.f) {
+    float bx, by, bz;
+    frame_point(W, arm->bnd[B_][0], arm->bnd[B_][1], arm->bnd[B_][2], bx, by, bz);
+    float ux[8], uy[8], uz[8], E[8];
+    float rmax = 0.f;
+    bool built = false;
 #pragma nounroll
-  for (int si = 0; si < nsets; ++si) {
-    if (!((scored >> si) & 1u)) continue;  // a set this wave dropped (learned distance)
-    const float gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, L.set_k0[si], L.set_n[si], 3.0e38f);
-    near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
+    for (int si = 0; si < nsets; ++si) {
+      if (!((scored >> si) & 1u)) continue;  // a set this wave dropped (learned distance)
+      const int k0 = L.set_k0[si], K = L.set_n[si], gsz = L.set_gsz[si], g0 = L.set_g0[si];
+      const int ng = gsz == 1 ? K : (K + 7) >> 3;
+      float gb = 3.0e38f;
+#pragma nounroll
+      for (int c0 = 0; c0 < ng; c0 += 8) {
+        unsigned m = 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          // in the array for every set: obstacles use slots 0-63, a
+          // neighbour 8 slots that end at or before kMaxGroups
+          const float4 q = L.gq[g0 + c0 + u];
+          const float dx = bx - q.x, dy = by - q.y, dz = bz - q.z;
+          const float d2 = fmaf_(dx, dx, fmaf_(dy, dy, dz * dz));
+          const float R = br + q.w;
+          m |= (c0 + u < ng && wave_any(d2 < R * R)) ? 1u << u : 0u;
+        }
+        while (m) {
+          const int u = __builtin_ctz(m);
+          m &= m - 1u;
+          if (!built) {
+            rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
+            built = true;
+          }
+          const int ks = k0 + (c0 + u) * gsz;
+          gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, ks, min(gsz, k0 + K - ks), gb);
+        }
+      }
+      near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
+    }
   }
   if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, nsets, scored, near);
 }
@@ -248,8 +325,7 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
       cand |= (t + Fk < kSlack ? 1u : 0u) << j;
     }
     if (cand) {
-      const float4 r = L.raw[k];
-      exact_candidates<S0>(W, L, cand, r.x, r.y, r.z, r.w, best);
+      exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], best);
     }
   }
   }
@@ -266,14 +342,28 @@ template <int LAY, int B1, int B2>
 __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const DevArm* __restrict__ arm,
                                            const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
-                                           const float E[8], float rmb, bool refine, unsigned long long& near,
-                                           double& best) {
+                                           const float E[8], float rmb, float4 b1, bool refine,
+                                           unsigned long long& near, double& best) {
   constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
   constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
   constexpr unsigned long long bit = 1ull << (8 * B1 + B2);
   if constexpr (B2 < 7) walk(W2, arm, C, B2);
   if constexpr (B2 >= B1 + 2) {
-    if (!refine || wave_any((near & bit) != 0ull)) {
+    // Filter pass: the body pair is skipped when the bounding spheres (b1.w
+    // holds B1's radius + the buffer + kCullPad) are apart in every lane.
+    bool run;
+    if (refine) {
+      run = wave_any((near & bit) != 0ull);
+    } else {
+      const float br2 = arm->bnd[B2][3];
+      float x2, y2, z2;
+      frame_point(W2, arm->bnd[B2][0], arm->bnd[B2][1], arm->bnd[B2][2], x2, y2, z2);
+      const float dx = b1.x - x2, dy = b1.y - y2, dz = b1.z - z2;
+      const float d2 = fmaf_(dx, dx, fmaf_(dy, dy, dz * dz));
+      const float R = b1.w + br2;
+      run = b1.w >= 0.f && br2 >= 0.f && wave_any(d2 < R * R);
+    }
+    if (run) {
       float gp = 3.0e38f;
 #pragma nounroll
       for (int i = 0; i < C2; ++i) {
@@ -309,7 +399,7 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, refine, near, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, b1, refine, near, best);
 }
 
 template <int LAY, int B1>
@@ -320,15 +410,19 @@ __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__
     walk(W1, arm, C, B1);
     float ux[8], uy[8], uz[8], ur[8], E[8];
     float rmb = 0.f;
+    float4 b1 = make_float4(0.f, 0.f, 0.f, -1.f);
     if (refine) {
       body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
     } else {
       rmb = body_spheres_rmax<LAY, B1>(W1, L, buf, ux, uy, uz, E);
 #pragma unroll
       for (int j = 0; j < 8; ++j) ur[j] = 0.f;
+      const float br1 = arm->bnd[B1][3];
+      frame_point(W1, arm->bnd[B1][0], arm->bnd[B1][1], arm->bnd[B1][2], b1.x, b1.y, b1.z);
+      b1.w = br1 >= 0.f ? br1 + buf + kCullPad : -1.f;
     }
     Frame W2 = W1;
-    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, refine, near, best);
+    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, b1, refine, near, best);
     self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, near, best);
   }
 }
@@ -378,9 +472,13 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
   const Params& P = *Pp;
   const StepState& SS = *ssp;
   const int n_obs = SS.n_obs;
-  // Obstacles are the same for every item of this launch.
-  for (int o = tid; o < n_obs; o += kThreads)
-    stage_sphere(L, o, reinterpret_cast<const float4*>(obs)[o], P.buf_env);
+  // Obstacles are the same for every item of this launch; each is its own
+  // cull group (slot o).
+  for (int o = tid; o < n_obs; o += kThreads) {
+    const float4 s = reinterpret_cast<const float4*>(obs)[o];
+    stage_sphere(L, o, s, P.buf_env);
+    L.gq[o] = make_float4(s.x, s.y, s.z, s.w + P.buf_env + kCullPad + 1.0e-4f);
+  }
 
   for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) {
     const Item item = items[it];
@@ -493,6 +591,8 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
         if (tid == 0) {
           L.set_k0[0] = 0;
           L.set_n[0] = n_obs;
+          L.set_g0[0] = 0;
+          L.set_gsz[0] = 1;
           L.set_buf[0] = P.buf_env;
           L.set_wt[0] = P.w_coll;
         }
@@ -500,7 +600,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       }
       unsigned wskip = 0u;  // bit si: set si dropped for this wave
       {
-        int off = kMaxObs;
+        int off = kMaxObs, gslot = kMaxObs;
         for (int i = 0; i < nnb; ++i) {
           const Nb nb = SS.nb[a][i];
           if (h >= nb.H) continue;
@@ -518,9 +618,15 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           }
           const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
           for (int s2 = tid; s2 < nb.S; s2 += kThreads) stage_sphere(L, off + s2, src[s2], P.buf_dyn);
+          // the bounding spheres of its runs of 8, by the last threads of
+          // the workgroup (the first ones stage the spheres)
+          for (int g2 = kThreads - 1 - tid; g2 < (nb.S + 7) >> 3; g2 += kThreads)
+            stage_group(L, gslot + g2, src + 8 * g2, min(8, nb.S - 8 * g2), P.buf_dyn);
           if (tid == 0) {
             L.set_k0[nsets] = off;
             L.set_n[nsets] = nb.S;
+            L.set_g0[nsets] = gslot;
+            L.set_gsz[nsets] = 8;
             L.set_buf[nsets] = P.buf_dyn;
             L.set_wt[nsets] = P.w_dyn * nb.alpha;
           }
@@ -528,6 +634,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           if (DBG && !(SURM == 1 && wd)) pairs += (unsigned long long)arm->S * (unsigned long long)nb.S;
           ++nsets;
           off += nb.S;
+          gslot += kNbGroups;
         }
       }
       __syncthreads();
