@@ -168,5 +168,9 @@ __device__ __forceinline__ double hinge64(double rho, double B) {
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+// Value of the first active lane, in every lane.
+__device__ __forceinline__ float first_lane(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 
 }  // namespace mrs

@@ -39,12 +39,15 @@ static_assert(kMaxSets * kBodies <= 64, "one near bit per (set, body) in a 64-bi
 // Pair cull.  The staged spheres of a set are taken in groups (each obstacle
 // alone; a neighbour plan in runs of 8, one body of a table sorted by body),
 // each with a bounding sphere whose radius covers every member's centre
-// offset, radius and the set's buffer B.  An own body (bounding sphere of
-// radius R_b about a fixed point of its frame) whose distance to a group's
-// centre is at least R_b + that radius has a gap of at least B + kCullPad -
-// (FP32 rounding, below 0.005 m for coordinates within 6 m) to every member:
-// no pair of it can contribute to the hinge, so the filter skips the group
-// when that holds in every lane.  The cost is unchanged bit for bit.
+// offset, radius and the set's buffer B.  Every own body has a bounding
+// sphere about a fixed point of its frame; the wave takes lane 0's centre and
+// widens the radius by the largest distance of any lane's centre from it, so
+// one sphere covers the body in all 64 rollouts.  A group whose centre is at
+// least the two radii from that sphere has a gap of at least B + kCullPad -
+// (FP32 rounding, below 0.005 m for coordinates within 6 m) to every own
+// sphere of the body in every lane: no pair of it can contribute to the
+// hinge, so the filter skips it.  The lanes test 64 (body, group) pairs at a
+// time.  The cost is unchanged bit for bit.
 constexpr float kCullPad = 0.01f;
 constexpr int kNbGroups = kMaxSpheres / 8;
 constexpr int kMaxGroups = kMaxObs + (kMaxArms - 1) * kNbGroups;
@@ -221,56 +224,56 @@ __device__ __forceinline__ float body_spheres_rmax(const Frame& Fb, const LdsSet
 // the squared-gap expansion with the body's largest own radius per set; bit
 // 8*si + b of `near` is set when body b has a pair below the slack in set si.
 // The exact pass tests the flagged bodies' pairs with their own radii.
-// Groups are first tested against the body's bounding sphere (eight at a
-// time, one ballot each), and only the groups some lane of the wave may be
-// near are filtered; the body's spheres are built at the first such group.
+// True when the group bounding sphere q may reach the body sphere bb (both
+// radii in .w).
+__device__ __forceinline__ bool group_near(float4 bb, float4 q) {
+  const float dx = bb.x - q.x, dy = bb.y - q.y, dz = bb.z - q.z;
+  const float d2 = fmaf_(dx, dx, fmaf_(dy, dy, dz * dz));
+  const float R = bb.w + q.w;
+  return d2 < R * R;
+}
+
+// Filter pass over the groups no cull removed.  Lane l holds neighbour group
+// slot kMaxObs + l in qn (nl: staged and scored) and obstacle l in qo (ol);
+// per body the two ballots give the groups near the wave's body sphere wb[b],
+// and only their pairs are filtered (the body's spheres are built when it has
+// any).  Set 0 holds the obstacles when obs_set is 1; neighbour set si holds
+// the plan of ballot byte si - obs_set.
 template <int LAY, int B_>
 __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, int nsets, unsigned scored,
-                                            unsigned long long& near) {
+                                            const LdsSets& L, const float4* wb, float4 qn, bool nl, float4 qo,
+                                            bool ol, int obs_set, unsigned long long& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
-  const float br = arm->bnd[B_][3];
-  if (br >= 0.f) {
-    float bx, by, bz;
-    frame_point(W, arm->bnd[B_][0], arm->bnd[B_][1], arm->bnd[B_][2], bx, by, bz);
-    float ux[8], uy[8], uz[8], E[8];
-    float rmax = 0.f;
-    bool built = false;
-#pragma nounroll
-    for (int si = 0; si < nsets; ++si) {
-      if (!((scored >> si) & 1u)) continue;  // a set this wave dropped (learned distance)
-      const int k0 = L.set_k0[si], K = L.set_n[si], gsz = L.set_gsz[si], g0 = L.set_g0[si];
-      const int ng = gsz == 1 ? K : (K + 7) >> 3;
-      float gb = 3.0e38f;
-#pragma nounroll
-      for (int c0 = 0; c0 < ng; c0 += 8) {
-        unsigned m = 0u;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          // in the array for every set: obstacles use slots 0-63, a
-          // neighbour 8 slots that end at or before kMaxGroups
-          const float4 q = L.gq[g0 + c0 + u];
-          const float dx = bx - q.x, dy = by - q.y, dz = bz - q.z;
-          const float d2 = fmaf_(dx, dx, fmaf_(dy, dy, dz * dz));
-          const float R = br + q.w;
-          m |= (c0 + u < ng && wave_any(d2 < R * R)) ? 1u << u : 0u;
-        }
-        while (m) {
-          const int u = __builtin_ctz(m);
-          m &= m - 1u;
-          if (!built) {
-            rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
-            built = true;
-          }
-          const int ks = k0 + (c0 + u) * gsz;
-          gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, ks, min(gsz, k0 + K - ks), gb);
-        }
+  const float4 bb = wb[B_];
+  if (bb.w >= 0.f) {
+    const unsigned long long nbm = __ballot(nl && group_near(bb, qn));
+    const unsigned long long obm = __ballot(ol && group_near(bb, qo));
+    if ((nbm | obm) != 0ull) {
+      float ux[8], uy[8], uz[8], E[8];
+      const float rmax = body_spheres_rmax<LAY, B_>(W, L, 0.f, ux, uy, uz, E);
+      if (obm != 0ull) {
+        float gb = 3.0e38f;
+        for (unsigned long long m = obm; m != 0ull; m &= m - 1ull)
+          gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, __builtin_ctzll(m), 1, gb);
+        near |= (gb < kSlack ? 1ull : 0ull) << B_;
       }
-      near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
+      for (unsigned long long m = nbm; m != 0ull;) {
+        const int ord = __builtin_ctzll(m) >> 3;
+        unsigned grp = (unsigned)(m >> (8 * ord)) & 0xFFu;
+        m &= ~(0xFFull << (8 * ord));
+        const int si = ord + obs_set;
+        const int k0 = L.set_k0[si], K = L.set_n[si];
+        float gb = 3.0e38f;
+        for (; grp != 0u; grp &= grp - 1u) {
+          const int ks = k0 + 8 * __builtin_ctz(grp);
+          gb = filter_range_rmax<Cb>(ux, uy, uz, E, rmax, L, ks, min(8, k0 + K - ks), gb);
+        }
+        near |= (gb < kSlack ? 1ull : 0ull) << (8 * si + B_);
+      }
     }
   }
-  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, nsets, scored, near);
+  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, wb, qn, nl, qo, ol, obs_set, near);
 }
 
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
@@ -334,36 +337,26 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
 // second walking frame runs from body B1 down the chain to every B2 > B1.
-// The filter pass gives body B1's spheres its largest radius (rmb = rmax +
-// buffer, three FMAs per pair) and sets bit 8*B1+B2 of `near` for a body
-// pair with a value below the slack; the exact pass tests the flagged body
-// pairs sphere by sphere and visits only pairs some lane flagged.
+// `pairs` has bit 8*B1+B2 set for the body pairs the wave's cull kept (the
+// same body spheres as for the sets, radii widened by the buffer).  The
+// filter pass gives body B1's spheres its largest radius (rmb = rmax +
+// buffer, three FMAs per pair) and sets bit 8*B1+B2 of `near` for a kept pair
+// with a value below the slack; the exact pass tests the flagged body pairs
+// sphere by sphere and visits only pairs some lane flagged.  A walk stops
+// after the last kept pair of its body.
 template <int LAY, int B1, int B2>
 __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const DevArm* __restrict__ arm,
                                            const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
-                                           const float E[8], float rmb, float4 b1, bool refine,
+                                           const float E[8], float rmb, unsigned row, bool refine,
                                            unsigned long long& near, double& best) {
   constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
   constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
   constexpr unsigned long long bit = 1ull << (8 * B1 + B2);
+  if ((row >> B2) == 0u) return;  // no kept pair at or past B2
   if constexpr (B2 < 7) walk(W2, arm, C, B2);
   if constexpr (B2 >= B1 + 2) {
-    // Filter pass: the body pair is skipped when the bounding spheres (b1.w
-    // holds B1's radius + the buffer + kCullPad) are apart in every lane.
-    bool run;
-    if (refine) {
-      run = wave_any((near & bit) != 0ull);
-    } else {
-      const float br2 = arm->bnd[B2][3];
-      float x2, y2, z2;
-      frame_point(W2, arm->bnd[B2][0], arm->bnd[B2][1], arm->bnd[B2][2], x2, y2, z2);
-      const float dx = b1.x - x2, dy = b1.y - y2, dz = b1.z - z2;
-      const float d2 = fmaf_(dx, dx, fmaf_(dy, dy, dz * dz));
-      const float R = b1.w + br2;
-      run = b1.w >= 0.f && br2 >= 0.f && wave_any(d2 < R * R);
-    }
-    if (run) {
+    if (((row >> B2) & 1u) && (!refine || wave_any((near & bit) != 0ull))) {
       float gp = 3.0e38f;
 #pragma nounroll
       for (int i = 0; i < C2; ++i) {
@@ -399,47 +392,48 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, b1, refine, near, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, row, refine, near, best);
 }
 
 template <int LAY, int B1>
 __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, float buf, bool refine,
+                                           const LdsSets& L, float buf, unsigned long long pairs, bool refine,
                                            unsigned long long& near, double& best) {
   if constexpr (B1 + 2 < kBodies) {
     walk(W1, arm, C, B1);
-    float ux[8], uy[8], uz[8], ur[8], E[8];
-    float rmb = 0.f;
-    float4 b1 = make_float4(0.f, 0.f, 0.f, -1.f);
-    if (refine) {
-      body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
-    } else {
-      rmb = body_spheres_rmax<LAY, B1>(W1, L, buf, ux, uy, uz, E);
+    const unsigned row = (unsigned)(pairs >> (8 * B1)) & 0xFFu;
+    if (row != 0u) {
+      float ux[8], uy[8], uz[8], ur[8], E[8];
+      float rmb = 0.f;
+      if (refine) {
+        body_spheres<LAY, B1>(W1, L, buf, ux, uy, uz, ur, E);
+      } else {
+        rmb = body_spheres_rmax<LAY, B1>(W1, L, buf, ux, uy, uz, E);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) ur[j] = 0.f;
-      const float br1 = arm->bnd[B1][3];
-      frame_point(W1, arm->bnd[B1][0], arm->bnd[B1][1], arm->bnd[B1][2], b1.x, b1.y, b1.z);
-      b1.w = br1 >= 0.f ? br1 + buf + kCullPad : -1.f;
+        for (int j = 0; j < 8; ++j) ur[j] = 0.f;
+      }
+      Frame W2 = W1;
+      self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, row, refine, near, best);
     }
-    Frame W2 = W1;
-    self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, b1, refine, near, best);
-    self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, refine, near, best);
+    if ((pairs >> (8 * (B1 + 1))) != 0ull) self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, pairs, refine, near, best);
   }
 }
 
 template <int LAY>
 __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, float buf, unsigned& refines) {
+                                            const LdsSets& L, float buf, unsigned long long pairs,
+                                            unsigned& refines) {
+  if (pairs == 0ull) return 0.f;
   unsigned long long near = 0ull;
   double best = 1.0e300;
   Frame W;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, false, near, best);
+  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, false, near, best);
   const bool any_near = near != 0ull;
   if (!wave_any(any_near)) return 0.f;
   ++refines;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, true, near, best);
+  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, true, near, best);
   return any_near ? (float)hinge64(best, (double)buf) : 0.f;
 }
 
@@ -466,6 +460,8 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
   // learned distance: the waves' drop masks over the neighbour table at the
   // current step (bit i: every rollout of the wave predicted far from i)
   __shared__ unsigned s_wdrop[WPB];
+  // each wave's body spheres at the current step (pair cull)
+  __shared__ float4 s_wb[WPB][kBodies];
   static_assert(kNbrRec == 8, "neighbour record layout of the learned distance");
   constexpr int kThreads = kWave * WPB;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -619,9 +615,12 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
           for (int s2 = tid; s2 < nb.S; s2 += kThreads) stage_sphere(L, off + s2, src[s2], P.buf_dyn);
           // the bounding spheres of its runs of 8, by the last threads of
-          // the workgroup (the first ones stage the spheres)
-          for (int g2 = kThreads - 1 - tid; g2 < (nb.S + 7) >> 3; g2 += kThreads)
-            stage_group(L, gslot + g2, src + 8 * g2, min(8, nb.S - 8 * g2), P.buf_dyn);
+          // the workgroup (the first ones stage the spheres); slots past the
+          // last run get a sphere that no body reaches
+          for (int g2 = kThreads - 1 - tid; g2 < kNbGroups; g2 += kThreads) {
+            if (8 * g2 < nb.S) stage_group(L, gslot + g2, src + 8 * g2, min(8, nb.S - 8 * g2), P.buf_dyn);
+            else L.gq[gslot + g2] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.f);
+          }
           if (tid == 0) {
             L.set_k0[nsets] = off;
             L.set_n[nsets] = nb.S;
@@ -642,13 +641,52 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       // audit scores every set and zeroes the dropped ones' hinge.
       const unsigned wscored = SURM == 1 ? ~wskip : ~0u;
 
+      // Pair cull (see kCullPad).  One walk down the chain gives the
+      // body centres; lane 0 of the wave stores each body's sphere for the
+      // wave (lane 0's centre, the body radius widened by the largest
+      // distance of a lane's centre from it) in s_wb.  The same walk ends at
+      // the last link frame, where the goal pose is scored.
+      Frame W;
+      frame_base(W, arm);
+      float4* wb = s_wb[wv];
+#pragma unroll
+      for (int b = 0; b < kBodies; ++b) {
+        if (b < 7) walk(W, arm, C, b);
+        float x, y, z;
+        frame_point(W, arm->bnd[b][0], arm->bnd[b][1], arm->bnd[b][2], x, y, z);
+        const float x0 = first_lane(x), y0 = first_lane(y), z0 = first_lane(z);
+        const float dx = x - x0, dy = y - y0, dz = z - z0;
+        float spread = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
+        const float br = arm->bnd[b][3];
+        if (lane == 0) wb[b] = make_float4(x0, y0, z0, br >= 0.f ? br + spread + 1.0e-4f : -1.f);
+      }
+      // Lane l: neighbour group slot kMaxObs + l, obstacle l, and the self
+      // body pair (l / 8, l % 8).  A body pair is kept when the two body
+      // spheres (widened by the self buffer and kCullPad) may touch.
+      const int obs_set = n_obs > 0 ? 1 : 0;
+      const int nbsets = nsets - obs_set;
+      const float4 qn = L.gq[kMaxObs + min(lane, kMaxGroups - kMaxObs - 1)];
+      const bool nl = lane < 8 * nbsets && ((wscored >> (obs_set + (lane >> 3))) & 1u);
+      const float4 qo = L.gq[lane];
+      const bool ol = lane < n_obs && (wscored & 1u);
+      unsigned long long self_pairs;
+      {
+        const float4 p1 = wb[lane >> 3], p2 = wb[lane & 7];
+        const float4 pb = make_float4(p1.x, p1.y, p1.z, p1.w + P.buf_self + kCullPad);
+        self_pairs = __ballot((lane & 7) >= (lane >> 3) + 2 && p1.w >= 0.f && p2.w >= 0.f && group_near(pb, p2));
+      }
+      bool sets_kept = false;
+#pragma unroll
+      for (int b = 0; b < kBodies; ++b) {
+        const float4 bb = wb[b];
+        sets_kept = sets_kept || wave_any(bb.w >= 0.f && ((nl && group_near(bb, qn)) || (ol && group_near(bb, qo))));
+      }
+
       // Goal pose (Eq. 5, C_pose) at the end-effector point of the last link.
       float c;
       {
-        Frame W;
-        frame_base(W, arm);
-#pragma unroll
-        for (int k = 0; k < 7; ++k) walk(W, arm, C, k);
         float ex, ey, ez;
         frame_point(W, arm->tool[0], arm->tool[1], arm->tool[2], ex, ey, ez);
         const float dx = ex - g[0], dy = ey - g[1], dz = ez - g[2];
@@ -676,15 +714,14 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
         if (A.manip) c = fmaf_(P.w_manip, A.manip[((size_t)a * P.Hmax + h) * P.Nmax + n], c);
       }
       // Self collision.
-      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_refines), c);
+      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_pairs, self_refines), c);
       // Obstacles and neighbours' plans (Eqs. 6, 8, 9): one filter pass over
-      // every set, then per set the exact pass if some lane of the wave may be
-      // within B.
+      // the groups the cull kept, then per set the exact pass if some lane of
+      // the wave may be within B.
       unsigned long long near_all = 0ull;
-      if (nsets > 0) {
-        Frame W;
+      if (sets_kept) {
         frame_base(W, arm);
-        sets_filter<LAY, 0>(W, arm, C, L, nsets, wscored, near_all);
+        sets_filter<LAY, 0>(W, arm, C, L, wb, qn, nl, qo, ol, obs_set, near_all);
       }
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
