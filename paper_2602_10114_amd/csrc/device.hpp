@@ -168,6 +168,34 @@ __device__ __forceinline__ double hinge64(double rho, double B) {
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+// Lane permutations within rows of 16 (DPP): swap neighbours, swap pairs,
+// mirror each half row, mirror the row.  All lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+// min / max over each run of 8 lanes (lanes 8k..8k+7), in all 8 lanes.
+__device__ __forceinline__ float oct_min(float x) {
+  x = fminf(x, dpp_f<kDppXor1>(x));
+  x = fminf(x, dpp_f<kDppXor2>(x));
+  return fminf(x, dpp_f<kDppHalfMirror>(x));
+}
+__device__ __forceinline__ float oct_max(float x) {
+  x = fmaxf(x, dpp_f<kDppXor1>(x));
+  x = fmaxf(x, dpp_f<kDppXor2>(x));
+  return fmaxf(x, dpp_f<kDppHalfMirror>(x));
+}
+// max over the wave, in every lane: rows of 16 by DPP, then the four rows.
+__device__ __forceinline__ float wave_max(float x) {
+  x = oct_max(x);
+  x = fmaxf(x, dpp_f<kDppMirror>(x));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+}
 // Value of the first active lane, in every lane.
 __device__ __forceinline__ float first_lane(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));

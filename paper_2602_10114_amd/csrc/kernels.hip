@@ -58,7 +58,6 @@ struct LdsSets {
   float F[kLdsSpheres];
   float4 slot[kMaxSpheres];    // body-frame spheres of the item's arm (slot order)
   float4 gq[kMaxGroups];       // group bounding spheres: centre, radius (+ B + pad)
-  int set_g0[kMaxSets], set_gsz[kMaxSets];  // first group slot, spheres per group
   int set_k0[kMaxSets], set_n[kMaxSets];
   float set_buf[kMaxSets], set_wt[kMaxSets];
   // learned-distance counters of the current item (added by each wave's
@@ -73,32 +72,6 @@ __device__ __forceinline__ void stage_sphere(LdsSets& L, int dst, float4 s, floa
   const float rb = s.w + buf;
   L.w[dst] = make_float4(-2.f * s.x, -2.f * s.y, -2.f * s.z, -2.f * rb);
   L.F[dst] = fmaf_(s.x, s.x, fmaf_(s.y, s.y, fmaf_(s.z, s.z, -rb * rb)));
-}
-
-// Bounding sphere of the staged spheres src[0, cnt) of a set with buffer buf:
-// centre at the middle of the centres' box, radius the largest centre
-// distance from it plus the sphere's radius, plus buf, kCullPad and 1e-4 m
-// for the rounding of this sum.
-__device__ __forceinline__ void stage_group(LdsSets& L, int slot, const float4* __restrict__ src, int cnt,
-                                            float buf) {
-  float lx = 3.0e38f, ly = 3.0e38f, lz = 3.0e38f, hx = -3.0e38f, hy = -3.0e38f, hz = -3.0e38f;
-  for (int j = 0; j < cnt; ++j) {
-    const float4 p = src[j];
-    lx = fminf(lx, p.x);
-    ly = fminf(ly, p.y);
-    lz = fminf(lz, p.z);
-    hx = fmaxf(hx, p.x);
-    hy = fmaxf(hy, p.y);
-    hz = fmaxf(hz, p.z);
-  }
-  const float qx = 0.5f * (lx + hx), qy = 0.5f * (ly + hy), qz = 0.5f * (lz + hz);
-  float rad = 0.f;
-  for (int j = 0; j < cnt; ++j) {
-    const float4 p = src[j];
-    const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
-    rad = fmaxf(rad, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) + p.w);
-  }
-  L.gq[slot] = make_float4(qx, qy, qz, rad + buf + kCullPad + 1.0e-4f);
 }
 
 // Filter value given to unused slots of a padded layout: never below the slack.
@@ -498,18 +471,39 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       qd[j] = state[(a * 7 + j) * 3 + 1];
     }
     q[7] = qd[7] = 0.f;
-    // Integration prefix of this horizon tile.
-    for (int h = 0; h < item.h0; ++h) {
+    // Integration prefix of this horizon tile; the noise loads of eight
+    // steps go out together.
+    int hp = 0;
+    for (; hp + 8 <= item.h0; hp += 8) {
+      float z[8][7];
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) z[s2][j] = eps[(size_t)((hp + s2) * 7 + j) * Npad];
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+          const float u = z[s2][j] + mu[(hp + s2) * 7 + j];
+          qd[j] = fmaf_(P.dt, u, qd[j]);
+          q[j] = fmaf_(P.dt, qd[j], q[j]);
+        }
+    }
+    for (; hp < item.h0; ++hp) {
       float z[7];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(h * 7 + j) * Npad];
+      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(hp * 7 + j) * Npad];
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const float u = z[j] + mu[h * 7 + j];
+        const float u = z[j] + mu[hp * 7 + j];
         qd[j] = fmaf_(P.dt, u, qd[j]);
         q[j] = fmaf_(P.dt, qd[j], q[j]);
       }
     }
+    // The next step's noise is loaded one step ahead.
+    float zn[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) zn[j] = item.h0 < item.h1 ? eps[(size_t)(item.h0 * 7 + j) * Npad] : 0.f;
     const float* __restrict__ gR = goalR + a * 9;
     const float* __restrict__ g = goal + a * 7;
     const int nnb = SS.nb_count[a];
@@ -566,7 +560,10 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
 
       float z[7];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(h * 7 + j) * Npad];
+      for (int j = 0; j < 7; ++j) {
+        z[j] = zn[j];
+        if (h + 1 < item.h1) zn[j] = eps[(size_t)((h + 1) * 7 + j) * Npad];
+      }
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         const float e = z[j];
@@ -582,21 +579,77 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       // wave of the item is not staged in learned mode (SURM 1); the audit
       // (SURM 2) stages it and marks it for the waves that dropped it.
       __syncthreads();
-      int nsets = 0;
-      if (n_obs > 0) {
-        if (tid == 0) {
-          L.set_k0[0] = 0;
-          L.set_n[0] = n_obs;
-          L.set_g0[0] = 0;
-          L.set_gsz[0] = 1;
-          L.set_buf[0] = P.buf_env;
-          L.set_wt[0] = P.w_coll;
-        }
-        nsets = 1;
+      const int obs_set = n_obs > 0 ? 1 : 0;
+      if (n_obs > 0 && tid == 0) {
+        L.set_k0[0] = 0;
+        L.set_n[0] = n_obs;
+        L.set_buf[0] = P.buf_env;
+        L.set_wt[0] = P.w_coll;
       }
+      // Neighbour i of the arm's table is set obs_set + i, with its spheres
+      // at kMaxObs + 64 i and its groups at kMaxObs + 8 i; a set that is not
+      // staged at this step has no spheres.  Wave w stages the plans i = w,
+      // w + WPB, ...: each lane loads one sphere of every such plan (the
+      // loads go out together), then writes it, and each run of 8 lanes
+      // forms its group's bounding sphere by lane permutations.
+      constexpr int kPer = (kMaxArms - 1 + WPB - 1) / WPB;
+      float4 sv[kPer];
+      int sS[kPer];
+      float sA[kPer];
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int i = wv + m * WPB;
+        sS[m] = 0;
+        sA[m] = 0.f;
+        sv[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < nnb) {
+          const Nb nb = SS.nb[a][i];
+          bool st = h < nb.H;
+          if (SURM == 1 && st) {
+            bool all = true;
+#pragma unroll
+            for (int w = 0; w < WPB; ++w) all = all && ((s_wdrop[w] >> i) & 1u) != 0u;
+            st = !all;
+          }
+          if (st) {
+            sS[m] = nb.S;
+            sA[m] = nb.alpha;
+            const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
+            if (lane < nb.S) sv[m] = src[lane];
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int i = wv + m * WPB;
+        if (i < nnb) {
+          const int S = sS[m];
+          if (S > 0) {
+            const float4 p = sv[m];
+            const bool v = lane < S;
+            if (v) stage_sphere(L, kMaxObs + 64 * i + lane, p, P.buf_dyn);
+            const float qx = 0.5f * (oct_min(v ? p.x : 3.0e38f) + oct_max(v ? p.x : -3.0e38f));
+            const float qy = 0.5f * (oct_min(v ? p.y : 3.0e38f) + oct_max(v ? p.y : -3.0e38f));
+            const float qz = 0.5f * (oct_min(v ? p.z : 3.0e38f) + oct_max(v ? p.z : -3.0e38f));
+            const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+            const float rad = oct_max(v ? sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) + p.w : -3.0e38f);
+            // slots of runs past the plan's last sphere get a sphere no body reaches
+            if ((lane & 7) == 0)
+              L.gq[kMaxObs + 8 * i + (lane >> 3)] =
+                  v ? make_float4(qx, qy, qz, rad + P.buf_dyn + kCullPad + 1.0e-4f)
+                    : make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.f);
+          }
+          if (lane == 0) {
+            L.set_k0[obs_set + i] = kMaxObs + 64 * i;
+            L.set_n[obs_set + i] = S;
+            L.set_buf[obs_set + i] = P.buf_dyn;
+            L.set_wt[obs_set + i] = P.w_dyn * sA[m];
+          }
+        }
+      }
+      const int nsets = obs_set + nnb;
       unsigned wskip = 0u;  // bit si: set si dropped for this wave
-      {
-        int off = kMaxObs, gslot = kMaxObs;
+      if (SURM || DBG) {
         for (int i = 0; i < nnb; ++i) {
           const Nb nb = SS.nb[a][i];
           if (h >= nb.H) continue;
@@ -612,28 +665,8 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
             }
             if (SURM == 1 && all) continue;
           }
-          const float4* src = reinterpret_cast<const float4*>(plan_read) + ((size_t)nb.arm * P.Hmax + h) * P.Smax;
-          for (int s2 = tid; s2 < nb.S; s2 += kThreads) stage_sphere(L, off + s2, src[s2], P.buf_dyn);
-          // the bounding spheres of its runs of 8, by the last threads of
-          // the workgroup (the first ones stage the spheres); slots past the
-          // last run get a sphere that no body reaches
-          for (int g2 = kThreads - 1 - tid; g2 < kNbGroups; g2 += kThreads) {
-            if (8 * g2 < nb.S) stage_group(L, gslot + g2, src + 8 * g2, min(8, nb.S - 8 * g2), P.buf_dyn);
-            else L.gq[gslot + g2] = make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.f);
-          }
-          if (tid == 0) {
-            L.set_k0[nsets] = off;
-            L.set_n[nsets] = nb.S;
-            L.set_g0[nsets] = gslot;
-            L.set_gsz[nsets] = 8;
-            L.set_buf[nsets] = P.buf_dyn;
-            L.set_wt[nsets] = P.w_dyn * nb.alpha;
-          }
-          if (wd) wskip |= 1u << nsets;
+          if (wd) wskip |= 1u << (obs_set + i);
           if (DBG && !(SURM == 1 && wd)) pairs += (unsigned long long)arm->S * (unsigned long long)nb.S;
-          ++nsets;
-          off += nb.S;
-          gslot += kNbGroups;
         }
       }
       __syncthreads();
@@ -656,19 +689,16 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
         frame_point(W, arm->bnd[b][0], arm->bnd[b][1], arm->bnd[b][2], x, y, z);
         const float x0 = first_lane(x), y0 = first_lane(y), z0 = first_lane(z);
         const float dx = x - x0, dy = y - y0, dz = z - z0;
-        float spread = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
+        const float spread = wave_max(sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))));
         const float br = arm->bnd[b][3];
         if (lane == 0) wb[b] = make_float4(x0, y0, z0, br >= 0.f ? br + spread + 1.0e-4f : -1.f);
       }
       // Lane l: neighbour group slot kMaxObs + l, obstacle l, and the self
       // body pair (l / 8, l % 8).  A body pair is kept when the two body
       // spheres (widened by the self buffer and kCullPad) may touch.
-      const int obs_set = n_obs > 0 ? 1 : 0;
-      const int nbsets = nsets - obs_set;
       const float4 qn = L.gq[kMaxObs + min(lane, kMaxGroups - kMaxObs - 1)];
-      const bool nl = lane < 8 * nbsets && ((wscored >> (obs_set + (lane >> 3))) & 1u);
+      const int lsi = min(obs_set + (lane >> 3), kMaxSets - 1);
+      const bool nl = (lane >> 3) < nnb && L.set_n[lsi] > 0 && ((wscored >> lsi) & 1u);
       const float4 qo = L.gq[lane];
       const bool ol = lane < n_obs && (wscored & 1u);
       unsigned long long self_pairs;
@@ -727,6 +757,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       for (int si = 0; si < nsets; ++si) {
         if (!((wscored >> si) & 1u)) continue;
         const int k0 = L.set_k0[si], K = L.set_n[si];
+        if (K == 0) continue;
         const unsigned nearb = (unsigned)(near_all >> (8 * si)) & 0xFFu;
         const bool near = nearb != 0;
         ++set_passes;
