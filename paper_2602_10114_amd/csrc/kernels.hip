@@ -269,43 +269,52 @@ __device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& 
 
 // Exact pass for one set: the FP64 gap of every pair the filter can flag; the
 // minimum over them is the set distance whenever that distance is below B.
+// `fb` has bit b set for the bodies some lane flagged; only the groups the
+// cull kept for a body can hold such pairs (q, ql: the lane's group of the
+// set's kind; ord < 0: obstacles, group o = staged sphere o; else the plan
+// of ballot byte ord, groups of 8 from k0).
 template <int LAY, int B_>
 __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, int k0, int K, unsigned near, double& best) {
+                                           const LdsSets& L, int k0, int K, unsigned fb, const float4* wb,
+                                           float4 q, bool ql, int ord, double& best) {
   constexpr int Cb = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
+  if ((fb >> B_) == 0u) return;  // no flagged body at or past B_
   if constexpr (B_ < 7) walk(W, arm, C, B_);
-  // Only bodies that some lane of the wave flagged.
-  if (wave_any((near >> B_) & 1u)) {
-  float ux[8], uy[8], uz[8], ur[8], E[8];
-  body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
-  float rmax = 0.f;
+  if ((fb >> B_) & 1u) {
+    float ux[8], uy[8], uz[8], ur[8], E[8];
+    body_spheres<LAY, B_>(W, L, 0.f, ux, uy, uz, ur, E);
+    float rmax = 0.f;
 #pragma unroll
-  for (int j = 0; j < Cb; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
-  for (int k = k0; k < k0 + K; ++k) {
-    const float4 w = L.w[k];
-    const float Fk = L.F[k];
-    // Lower bound of the body's pair values for staged sphere k (each
-    // radius term r_s w_r is at least rmax w_r, w_r <= 0): k holds no
-    // candidate when the bound reaches the slack in every lane.
-    float mk = 3.0e38f;
+    for (int j = 0; j < Cb; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
+    const unsigned long long kept = __ballot(ql && group_near(wb[B_], q));
+    for (unsigned long long m = ord < 0 ? kept : (kept >> (8 * ord)) & 0xFFull; m != 0ull; m &= m - 1ull) {
+      const int g = __builtin_ctzll(m);
+      const int ka = ord < 0 ? g : k0 + 8 * g;
+      const int kb = ord < 0 ? g + 1 : min(k0 + K, ka + 8);
+      for (int k = ka; k < kb; ++k) {
+        const float4 w = L.w[k];
+        const float Fk = L.F[k];
+        // Lower bound of the body's pair values for staged sphere k (each
+        // radius term r_s w_r is at least rmax w_r, w_r <= 0): k holds no
+        // candidate when the bound reaches the slack in every lane.
+        float mk = 3.0e38f;
 #pragma unroll
-    for (int j = 0; j < Cb; ++j) mk = fminf(mk, fmaf_(uz[j], w.z, fmaf_(uy[j], w.y, fmaf_(ux[j], w.x, E[j]))));
-    if (!wave_any(mk + fmaf_(rmax, w.w, Fk) < kSlack)) continue;
-    unsigned cand = 0;
+        for (int j = 0; j < Cb; ++j) mk = fminf(mk, fmaf_(uz[j], w.z, fmaf_(uy[j], w.y, fmaf_(ux[j], w.x, E[j]))));
+        if (!wave_any(mk + fmaf_(rmax, w.w, Fk) < kSlack)) continue;
+        unsigned cand = 0;
 #pragma unroll
-    for (int j = 0; j < Cb; ++j) {
-      float t = fmaf_(ux[j], w.x, E[j]);
-      t = fmaf_(uy[j], w.y, t);
-      t = fmaf_(uz[j], w.z, t);
-      t = fmaf_(ur[j], w.w, t);
-      cand |= (t + Fk < kSlack ? 1u : 0u) << j;
-    }
-    if (cand) {
-      exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], best);
+        for (int j = 0; j < Cb; ++j) {
+          float t = fmaf_(ux[j], w.x, E[j]);
+          t = fmaf_(uy[j], w.y, t);
+          t = fmaf_(uz[j], w.z, t);
+          t = fmaf_(ur[j], w.w, t);
+          cand |= (t + Fk < kSlack ? 1u : 0u) << j;
+        }
+        if (cand) exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], best);
+      }
     }
   }
-  }
-  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, near, best);
+  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, fb, wb, q, ql, ord, best);
 }
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
@@ -766,7 +775,12 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
           double best = 1.0e300;
           Frame W;
           frame_base(W, arm);
-          set_refine<LAY, 0>(W, arm, C, L, k0, K, nearb, best);
+          unsigned fb = 0u;
+#pragma unroll
+          for (int b = 0; b < kBodies; ++b) fb |= wave_any((nearb >> b) & 1u) ? 1u << b : 0u;
+          const bool obs = si < obs_set;
+          set_refine<LAY, 0>(W, arm, C, L, k0, K, fb, wb, obs ? qo : qn, obs ? ol : nl, obs ? -1 : si - obs_set,
+                             best);
           float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
           if (SURM == 2 && ((wskip >> si) & 1u)) {
             const bool hit = live && near;
