@@ -282,6 +282,39 @@ static int build_arm(mpc_ctx* c, const mpc_arm_desc& d, int layout, DevArm& o) {
     for (int i = 0; i < 3; ++i) o.bnd[b][i] = ctr[i];
     o.bnd[b][3] = std::nextafter((float)(rho + rmax + 1e-4), 1e30f);
   }
+  // Half-body bounding spheres (the first (C+1)/2 slots of the body, then the
+  // rest): middle of the centres' box, largest centre offset plus radius.
+  for (int b = 0; b < kBodies; ++b) {
+    const int s0 = kLayoutStart[layout][b], cnt = kLayoutCount[layout][b], mid = s0 + (cnt + 1) / 2;
+    for (int half = 0; half < 2; ++half) {
+      const int a0 = half ? mid : s0, a1 = half ? s0 + cnt : mid;
+      double lo[3] = {1e30, 1e30, 1e30}, hi[3] = {-1e30, -1e30, -1e30};
+      int n = 0;
+      for (int sl = a0; sl < a1; ++sl) {
+        if (o.slot_src[sl] < 0) continue;
+        ++n;
+        for (int i = 0; i < 3; ++i) {
+          lo[i] = std::min(lo[i], (double)o.slot[sl][i]);
+          hi[i] = std::max(hi[i], (double)o.slot[sl][i]);
+        }
+      }
+      float* hb = o.hb[b][half];
+      if (n == 0) {
+        hb[0] = hb[1] = hb[2] = 0.f;
+        hb[3] = -1.f;
+        continue;
+      }
+      for (int i = 0; i < 3; ++i) hb[i] = (float)(0.5 * (lo[i] + hi[i]));
+      double rad = 0.0;
+      for (int sl = a0; sl < a1; ++sl) {
+        if (o.slot_src[sl] < 0) continue;
+        double d2 = 0.0;
+        for (int i = 0; i < 3; ++i) d2 += ((double)o.slot[sl][i] - hb[i]) * ((double)o.slot[sl][i] - hb[i]);
+        rad = std::max(rad, std::sqrt(d2) + (double)o.slot[sl][3]);
+      }
+      hb[3] = std::nextafter((float)(rad + 1e-4), 1e30f);
+    }
+  }
   (void)c;
   return MPC_OK;
 }

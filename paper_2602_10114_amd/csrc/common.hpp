@@ -42,6 +42,9 @@ struct DevArm {
   // and radius (w) = largest centre offset from it + largest sphere radius,
   // rounded up; w < 0 marks a body without spheres.
   float bnd[kBodies][4];
+  // The same for each half of a body's slots (slots [0, (C+1)/2) and the
+  // rest of the body's C slots; parked slots left out); w < 0: no spheres.
+  float hb[kBodies][2][4];
   long long eps_off;           // float offset of this arm's [H][d][Npad] noise block
 };
 

@@ -319,29 +319,40 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
 // second walking frame runs from body B1 down the chain to every B2 > B1.
-// `pairs` has bit 8*B1+B2 set for the body pairs the wave's cull kept (the
-// same body spheres as for the sets, radii widened by the buffer).  The
-// filter pass gives body B1's spheres its largest radius (rmb = rmax +
-// buffer, three FMAs per pair) and sets bit 8*B1+B2 of `near` for a kept pair
-// with a value below the slack; the exact pass tests the flagged body pairs
-// sphere by sphere and visits only pairs some lane flagged.  A walk stops
-// after the last kept pair of its body.
+// The cull keeps half pairs: K.k[h1][h2] has bit 8*B1+B2 set when half h1 of
+// body B1 and half h2 of body B2 (slots [0, (C+1)/2) and the rest) may touch
+// in some lane; only their sphere pairs are visited.  The filter pass gives
+// body B1's spheres its largest radius (rmb = rmax + buffer, three FMAs per
+// pair) and sets bit 8*B1+B2 of `near` for a body pair with a value below
+// the slack; the exact pass tests the flagged body pairs sphere by sphere and
+// visits only pairs some lane flagged.  A walk stops after the last kept pair
+// of its body.
+struct SelfKeep {
+  unsigned long long k[2][2];
+};
+
 template <int LAY, int B1, int B2>
 __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const DevArm* __restrict__ arm,
                                            const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
-                                           const float E[8], float rmb, unsigned row, bool refine,
-                                           unsigned long long& near, double& best) {
-  constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1];
-  constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2];
-  constexpr unsigned long long bit = 1ull << (8 * B1 + B2);
+                                           const float E[8], float rmb, unsigned row, const SelfKeep& K,
+                                           bool refine, unsigned long long& near, double& best) {
+  constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1], H1 = (C1 + 1) / 2;
+  constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2], H2 = (C2 + 1) / 2;
+  constexpr int sh = 8 * B1 + B2;
+  constexpr unsigned long long bit = 1ull << sh;
   if ((row >> B2) == 0u) return;  // no kept pair at or past B2
   if constexpr (B2 < 7) walk(W2, arm, C, B2);
   if constexpr (B2 >= B1 + 2) {
     if (((row >> B2) & 1u) && (!refine || wave_any((near & bit) != 0ull))) {
+      // halves of B1 kept with each half of B2
+      const unsigned m1h[2] = {(unsigned)((K.k[0][0] >> sh) & 1ull) | (unsigned)(((K.k[1][0] >> sh) & 1ull) << 1),
+                               (unsigned)((K.k[0][1] >> sh) & 1ull) | (unsigned)(((K.k[1][1] >> sh) & 1ull) << 1)};
       float gp = 3.0e38f;
 #pragma nounroll
       for (int i = 0; i < C2; ++i) {
+        const unsigned m1 = m1h[i >= H2 ? 1 : 0];
+        if (m1 == 0u) continue;
         asm volatile("" ::: "memory");
         const float4 p = L.slot[S2 + i];
         float x, y, z;
@@ -352,11 +363,11 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
         const float wx = parked ? 0.f : -2.f * x, wy = parked ? 0.f : -2.f * y;
         const float wz = parked ? 0.f : -2.f * z, wr = parked ? 0.f : -2.f * rb;
         const float Fk = parked ? kParked : fmaf_(x, x, fmaf_(y, y, fmaf_(z, z, -rb * rb)));
-        float m = 3.0e38f;
-        unsigned cand = 0;
         if (refine) {
+          unsigned cand = 0;
 #pragma unroll
           for (int j = 0; j < C1; ++j) {
+            if (!((m1 >> (j >= H1 ? 1 : 0)) & 1u)) continue;
             float t = fmaf_(ux[j], wx, E[j]);
             t = fmaf_(uy[j], wy, t);
             t = fmaf_(uz[j], wz, t);
@@ -365,8 +376,12 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
           }
           if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, best);
         } else {
+          float m = 3.0e38f;
 #pragma unroll
-          for (int j = 0; j < C1; ++j) m = fminf(m, fmaf_(uz[j], wz, fmaf_(uy[j], wy, fmaf_(ux[j], wx, E[j]))));
+          for (int j = 0; j < C1; ++j) {
+            if (!((m1 >> (j >= H1 ? 1 : 0)) & 1u)) continue;
+            m = fminf(m, fmaf_(uz[j], wz, fmaf_(uy[j], wy, fmaf_(ux[j], wx, E[j]))));
+          }
           gp = fminf(gp, m + fmaf_(rmb, wr, Fk));
         }
       }
@@ -374,13 +389,14 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, row, refine, near, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, row, K, refine, near, best);
 }
 
 template <int LAY, int B1>
 __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__ arm, const Chain& C,
-                                           const LdsSets& L, float buf, unsigned long long pairs, bool refine,
-                                           unsigned long long& near, double& best) {
+                                           const LdsSets& L, float buf, unsigned long long pairs,
+                                           const SelfKeep& K, bool refine, unsigned long long& near,
+                                           double& best) {
   if constexpr (B1 + 2 < kBodies) {
     walk(W1, arm, C, B1);
     const unsigned row = (unsigned)(pairs >> (8 * B1)) & 0xFFu;
@@ -395,27 +411,27 @@ __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__
         for (int j = 0; j < 8; ++j) ur[j] = 0.f;
       }
       Frame W2 = W1;
-      self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, row, refine, near, best);
+      self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, row, K, refine, near, best);
     }
-    if ((pairs >> (8 * (B1 + 1))) != 0ull) self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, pairs, refine, near, best);
+    if ((pairs >> (8 * (B1 + 1))) != 0ull) self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, pairs, K, refine, near, best);
   }
 }
 
 template <int LAY>
 __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, float buf, unsigned long long pairs,
-                                            unsigned& refines) {
+                                            const LdsSets& L, float buf, const SelfKeep& K, unsigned& refines) {
+  const unsigned long long pairs = K.k[0][0] | K.k[0][1] | K.k[1][0] | K.k[1][1];
   if (pairs == 0ull) return 0.f;
   unsigned long long near = 0ull;
   double best = 1.0e300;
   Frame W;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, false, near, best);
+  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, K, false, near, best);
   const bool any_near = near != 0ull;
   if (!wave_any(any_near)) return 0.f;
   ++refines;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, true, near, best);
+  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, K, true, near, best);
   return any_near ? (float)hinge64(best, (double)buf) : 0.f;
 }
 
@@ -442,8 +458,9 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
   // learned distance: the waves' drop masks over the neighbour table at the
   // current step (bit i: every rollout of the wave predicted far from i)
   __shared__ unsigned s_wdrop[WPB];
-  // each wave's body spheres at the current step (pair cull)
+  // each wave's body and half-body spheres at the current step (pair cull)
   __shared__ float4 s_wb[WPB][kBodies];
+  __shared__ float4 s_wh[WPB][kBodies][2];
   static_assert(kNbrRec == 8, "neighbour record layout of the learned distance");
   constexpr int kThreads = kWave * WPB;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -684,38 +701,56 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
       const unsigned wscored = SURM == 1 ? ~wskip : ~0u;
 
       // Pair cull (see kCullPad).  One walk down the chain gives the
-      // body centres; lane 0 of the wave stores each body's sphere for the
-      // wave (lane 0's centre, the body radius widened by the largest
-      // distance of a lane's centre from it) in s_wb.  The same walk ends at
-      // the last link frame, where the goal pose is scored.
+      // centres of each body and of its two halves; lane 0 of the wave
+      // stores their spheres for the wave (lane 0's centres, the radii
+      // widened by the largest distance of a lane's point from lane 0's) in
+      // s_wb and s_wh.  The same walk ends at the last link frame, where the
+      // goal pose is scored.
       Frame W;
       frame_base(W, arm);
       float4* wb = s_wb[wv];
+      float4(*wh)[2] = s_wh[wv];
 #pragma unroll
       for (int b = 0; b < kBodies; ++b) {
         if (b < 7) walk(W, arm, C, b);
-        float x, y, z;
-        frame_point(W, arm->bnd[b][0], arm->bnd[b][1], arm->bnd[b][2], x, y, z);
-        const float x0 = first_lane(x), y0 = first_lane(y), z0 = first_lane(z);
-        const float dx = x - x0, dy = y - y0, dz = z - z0;
-        const float spread = wave_max(sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))));
-        const float br = arm->bnd[b][3];
-        if (lane == 0) wb[b] = make_float4(x0, y0, z0, br >= 0.f ? br + spread + 1.0e-4f : -1.f);
+        // the body's centre and its two half centres, their lane-0 values
+        // and the largest distance of any lane's point from them
+        float4 c3[3];
+        float dev = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float* o = k == 0 ? arm->bnd[b] : arm->hb[b][k - 1];
+          float x, y, z;
+          frame_point(W, o[0], o[1], o[2], x, y, z);
+          c3[k] = make_float4(first_lane(x), first_lane(y), first_lane(z), o[3]);
+          const float dx = x - c3[k].x, dy = y - c3[k].y, dz = z - c3[k].z;
+          dev = fmaxf(dev, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))));
+        }
+        const float spread = wave_max(dev) + 1.0e-4f;
+        if (lane == 0) {
+          wb[b] = make_float4(c3[0].x, c3[0].y, c3[0].z, c3[0].w >= 0.f ? c3[0].w + spread : -1.f);
+          wh[b][0] = make_float4(c3[1].x, c3[1].y, c3[1].z, c3[1].w >= 0.f ? c3[1].w + spread : -1.f);
+          wh[b][1] = make_float4(c3[2].x, c3[2].y, c3[2].z, c3[2].w >= 0.f ? c3[2].w + spread : -1.f);
+        }
       }
       // Lane l: neighbour group slot kMaxObs + l, obstacle l, and the self
-      // body pair (l / 8, l % 8).  A body pair is kept when the two body
+      // body pair (l / 8, l % 8).  A half pair is kept when the two half
       // spheres (widened by the self buffer and kCullPad) may touch.
       const float4 qn = L.gq[kMaxObs + min(lane, kMaxGroups - kMaxObs - 1)];
       const int lsi = min(obs_set + (lane >> 3), kMaxSets - 1);
       const bool nl = (lane >> 3) < nnb && L.set_n[lsi] > 0 && ((wscored >> lsi) & 1u);
       const float4 qo = L.gq[lane];
       const bool ol = lane < n_obs && (wscored & 1u);
-      unsigned long long self_pairs;
-      {
-        const float4 p1 = wb[lane >> 3], p2 = wb[lane & 7];
-        const float4 pb = make_float4(p1.x, p1.y, p1.z, p1.w + P.buf_self + kCullPad);
-        self_pairs = __ballot((lane & 7) >= (lane >> 3) + 2 && p1.w >= 0.f && p2.w >= 0.f && group_near(pb, p2));
-      }
+      SelfKeep skeep;
+#pragma unroll
+      for (int h1 = 0; h1 < 2; ++h1)
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const float4 p1 = wh[lane >> 3][h1], p2 = wh[lane & 7][h2];
+          const float4 pb = make_float4(p1.x, p1.y, p1.z, p1.w + P.buf_self + kCullPad);
+          skeep.k[h1][h2] =
+              __ballot((lane & 7) >= (lane >> 3) + 2 && p1.w >= 0.f && p2.w >= 0.f && group_near(pb, p2));
+        }
       bool sets_kept = false;
 #pragma unroll
       for (int b = 0; b < kBodies; ++b) {
@@ -753,7 +788,7 @@ __global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __rest
         if (A.manip) c = fmaf_(P.w_manip, A.manip[((size_t)a * P.Hmax + h) * P.Nmax + n], c);
       }
       // Self collision.
-      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, self_pairs, self_refines), c);
+      c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, skeep, self_refines), c);
       // Obstacles and neighbours' plans (Eqs. 6, 8, 9): one filter pass over
       // the groups the cull kept, then per set the exact pass if some lane of
       // the wave may be within B.
