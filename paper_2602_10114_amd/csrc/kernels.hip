@@ -441,9 +441,12 @@ __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, cons
 // the sets staged at each rollout step (obstacles and neighbour plans), so a
 // step's staging is done once per WPB waves; every arm's padded rollout
 // count is a multiple of 64 x WPB (the host only picks such WPB), so no wave
-// of an item lies past the arm's padded rollouts.
+// of an item lies past the arm's padded rollouts.  The launch bound asks for
+// three waves per SIMD (168 VGPRs, some spilled to scratch): with the pair
+// cull the kernel waits on latency more than on the ALU, and a third wave
+// measured faster than two waves without spills.
 template <int LAY, bool DBG, int SURM, int WPB>
-__global__ __launch_bounds__(kWave * WPB, 2) void k_rollout(const DevArm* __restrict__ arms,
+__global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __restrict__ arms,
                                                          const Params* __restrict__ Pp,
                                                          const StepState* __restrict__ ssp,
                                                          const Item* __restrict__ items,
