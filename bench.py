@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
 # valid only for the kernel sources with this digest (see
 # profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "5edd71c610325b5b",
-           "bytes_per_launch": {1: 45902080, 2: 45870955, 4: 46150061}}
+TRAFFIC = {"sources_sha256": "cf81d0478e0b9753",
+           "bytes_per_launch": {1: 49189000, 2: 51005000, 4: 132113000}}
 
 
 def traffic_bytes(waves):
@@ -72,14 +72,14 @@ def summarize(trace_dir, fetch_dir, write_dir, steps):
     import glob
     from collections import defaultdict
     out = []
-    tr = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
-    rows = list(csv.DictReader(open(tr)))
     by = defaultdict(list)
-    for r in rows:
-        name = r["Kernel_Name"].split("(")[0]
-        by[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-    out.append(f"kernel trace: {tr}")
-    out.append(f"{'kernel':44s} {'calls':>6s} {'steady calls':>12s} {'steady avg us':>14s} {'min us':>9s} {'max us':>9s}")
+    if trace_dir:
+        tr = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+        for r in csv.DictReader(open(tr)):
+            name = r["Kernel_Name"].split("(")[0]
+            by[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        out.append(f"kernel trace: {tr}")
+        out.append(f"{'kernel':44s} {'calls':>6s} {'steady calls':>12s} {'steady avg us':>14s} {'min us':>9s} {'max us':>9s}")
     for name, v in sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1])):
         v.sort()
         steady = [d for _, d in v[-2 * steps:]] if "k_rollout" in name else [d for _, d in v[-steps:]]

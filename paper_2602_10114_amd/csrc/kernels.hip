@@ -206,20 +206,22 @@ __device__ __forceinline__ bool group_near(float4 bb, float4 q) {
   return d2 < R * R;
 }
 
-// Filter pass over the groups no cull removed.  Lane l holds neighbour group
-// slot kMaxObs + l in qn (nl: staged and scored) and obstacle l in qo (ol);
+// Filter pass over the groups no cull removed.  Lane l takes neighbour group
+// slot kMaxObs + l (nl: staged and scored) and obstacle l (ol);
 // per body the two ballots give the groups near the wave's body sphere wb[b],
 // and only their pairs are filtered (the body's spheres are built when it has
 // any).  Set 0 holds the obstacles when obs_set is 1; neighbour set si holds
 // the plan of ballot byte si - obs_set.
 template <int LAY, int B_>
 __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
-                                            const LdsSets& L, const float4* wb, float4 qn, bool nl, float4 qo,
-                                            bool ol, int obs_set, unsigned long long& near) {
+                                            const LdsSets& L, const float4* wb, bool nl, bool ol, int obs_set,
+                                            unsigned long long& near) {
   constexpr int Cb = kLayoutCount[LAY][B_];
   if constexpr (B_ < 7) walk(W, arm, C, B_);
   const float4 bb = wb[B_];
   if (bb.w >= 0.f) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const float4 qn = L.gq[kMaxObs + min(lane, kMaxGroups - kMaxObs - 1)], qo = L.gq[lane];
     const unsigned long long nbm = __ballot(nl && group_near(bb, qn));
     const unsigned long long obm = __ballot(ol && group_near(bb, qo));
     if ((nbm | obm) != 0ull) {
@@ -246,7 +248,7 @@ __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__
       }
     }
   }
-  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, wb, qn, nl, qo, ol, obs_set, near);
+  if constexpr (B_ + 1 < kBodies) sets_filter<LAY, B_ + 1>(W, arm, C, L, wb, nl, ol, obs_set, near);
 }
 
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
@@ -270,13 +272,13 @@ __device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& 
 // Exact pass for one set: the FP64 gap of every pair the filter can flag; the
 // minimum over them is the set distance whenever that distance is below B.
 // `fb` has bit b set for the bodies some lane flagged; only the groups the
-// cull kept for a body can hold such pairs (q, ql: the lane's group of the
-// set's kind; ord < 0: obstacles, group o = staged sphere o; else the plan
-// of ballot byte ord, groups of 8 from k0).
+// cull kept for a body can hold such pairs (qslot, ql: the lane's group slot
+// of the set's kind; ord < 0: obstacles, group o = staged sphere o; else the
+// plan of ballot byte ord, groups of 8 from k0).
 template <int LAY, int B_>
 __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
                                            const LdsSets& L, int k0, int K, unsigned fb, const float4* wb,
-                                           float4 q, bool ql, int ord, double& best) {
+                                           int qslot, bool ql, int ord, double& best) {
   constexpr int Cb = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
   if ((fb >> B_) == 0u) return;  // no flagged body at or past B_
   if constexpr (B_ < 7) walk(W, arm, C, B_);
@@ -286,7 +288,7 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
     float rmax = 0.f;
 #pragma unroll
     for (int j = 0; j < Cb; ++j) rmax = fmaxf(rmax, L.slot[S0 + j].w);
-    const unsigned long long kept = __ballot(ql && group_near(wb[B_], q));
+    const unsigned long long kept = __ballot(ql && group_near(wb[B_], L.gq[qslot]));
     for (unsigned long long m = ord < 0 ? kept : (kept >> (8 * ord)) & 0xFFull; m != 0ull; m &= m - 1ull) {
       const int g = __builtin_ctzll(m);
       const int ka = ord < 0 ? g : k0 + 8 * g;
@@ -314,7 +316,7 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
       }
     }
   }
-  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, fb, wb, q, ql, ord, best);
+  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, fb, wb, qslot, ql, ord, best);
 }
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
@@ -529,10 +531,6 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
         q[j] = fmaf_(P.dt, qd[j], q[j]);
       }
     }
-    // The next step's noise is loaded one step ahead.
-    float zn[7];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) zn[j] = item.h0 < item.h1 ? eps[(size_t)(item.h0 * 7 + j) * Npad] : 0.f;
     const float* __restrict__ gR = goalR + a * 9;
     const float* __restrict__ g = goal + a * 7;
     const int nnb = SS.nb_count[a];
@@ -589,10 +587,7 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
 
       float z[7];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        z[j] = zn[j];
-        if (h + 1 < item.h1) zn[j] = eps[(size_t)((h + 1) * 7 + j) * Npad];
-      }
+      for (int j = 0; j < 7; ++j) z[j] = eps[(size_t)(h * 7 + j) * Npad];
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         const float e = z[j];
@@ -739,10 +734,9 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
       // Lane l: neighbour group slot kMaxObs + l, obstacle l, and the self
       // body pair (l / 8, l % 8).  A half pair is kept when the two half
       // spheres (widened by the self buffer and kCullPad) may touch.
-      const float4 qn = L.gq[kMaxObs + min(lane, kMaxGroups - kMaxObs - 1)];
+      const int qn_slot = kMaxObs + min(lane, kMaxGroups - kMaxObs - 1);
       const int lsi = min(obs_set + (lane >> 3), kMaxSets - 1);
       const bool nl = (lane >> 3) < nnb && L.set_n[lsi] > 0 && ((wscored >> lsi) & 1u);
-      const float4 qo = L.gq[lane];
       const bool ol = lane < n_obs && (wscored & 1u);
       SelfKeep skeep;
 #pragma unroll
@@ -755,6 +749,7 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
               __ballot((lane & 7) >= (lane >> 3) + 2 && p1.w >= 0.f && p2.w >= 0.f && group_near(pb, p2));
         }
       bool sets_kept = false;
+      const float4 qn = L.gq[qn_slot], qo = L.gq[lane];
 #pragma unroll
       for (int b = 0; b < kBodies; ++b) {
         const float4 bb = wb[b];
@@ -798,7 +793,7 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
       unsigned long long near_all = 0ull;
       if (sets_kept) {
         frame_base(W, arm);
-        sets_filter<LAY, 0>(W, arm, C, L, wb, qn, nl, qo, ol, obs_set, near_all);
+        sets_filter<LAY, 0>(W, arm, C, L, wb, nl, ol, obs_set, near_all);
       }
 #pragma nounroll
       for (int si = 0; si < nsets; ++si) {
@@ -817,8 +812,8 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
 #pragma unroll
           for (int b = 0; b < kBodies; ++b) fb |= wave_any((nearb >> b) & 1u) ? 1u << b : 0u;
           const bool obs = si < obs_set;
-          set_refine<LAY, 0>(W, arm, C, L, k0, K, fb, wb, obs ? qo : qn, obs ? ol : nl, obs ? -1 : si - obs_set,
-                             best);
+          set_refine<LAY, 0>(W, arm, C, L, k0, K, fb, wb, obs ? lane : qn_slot, obs ? ol : nl,
+                             obs ? -1 : si - obs_set, best);
           float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
           if (SURM == 2 && ((wskip >> si) & 1u)) {
             const bool hit = live && near;
