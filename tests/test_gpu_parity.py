@@ -183,6 +183,45 @@ def test_uneven_batch_and_counter():
     ctl.close()
 
 
+def test_wide_rollout_spread_keeps_every_near_pair():
+    """The pair cull decides once per wave of 64 rollouts, with one bounding
+    sphere per body widened by the wave's spread.  With a large sampling
+    sigma the rollouts of a wave fan out (a neighbour's plan within the
+    buffer in some lanes, clear of it in others); every stage cost must still
+    equal the oracle's all-pairs one."""
+    spread = mixed = 0
+    for cfg, n, h in ((2, 128, 12), (3, [64, 128, 128, 192], [8, 12, 12, 16])):
+        _say(f"case: config {cfg} with sigma 4.0, N={n}, H={h}, 3 steps with plan sharing")
+        sc = small_scene(cfg, n=n, h=h, sigma=4.0)
+        ctl, caps, boards, _ = _run_multi(sc, 3)
+        B = sc.params["buf_dyn"]
+        for a in range(sc.n_arms):
+            ref = oracle_stage(sc, a, caps[a], sc.obstacles, boards)
+            assert rel_err(caps[a].stage, ref) < 1e-4, (cfg, a)
+            sph = caps[a].sph  # [N][H][S][4]
+            N, H = sph.shape[0], sph.shape[1]
+            # each lane's smallest gap to any neighbour plan sphere, per step
+            gap = np.full((N, H), np.inf)
+            for i in range(sc.n_arms):
+                if i == a or not boards[i][1]:
+                    continue
+                plan = boards[i][0]  # [H_i][S_i][4]
+                for hh in range(min(H, plan.shape[0])):
+                    d = np.linalg.norm(sph[:, hh, :, None, :3] - plan[None, hh, None, :, :3], axis=3)
+                    g = d - sph[:, hh, :, None, 3] - plan[None, hh, None, :, 3]
+                    gap[:, hh] = np.minimum(gap[:, hh], g.min(axis=(1, 2)))
+            for w0 in range(0, N - 63, 64):
+                c = sph[w0:w0 + 64, -1, :, :3]
+                spread = max(spread, float(np.linalg.norm(c - c[0], axis=2).max()))
+                near = gap[w0:w0 + 64] < B  # [64][H]
+                mixed += int((near.any(axis=0) & ~near.all(axis=0)).sum())
+        ctl.close()
+    # the waves did fan out, and at some steps held lanes within the buffer
+    # beside lanes clear of it
+    assert spread > 0.1
+    assert mixed > 0
+
+
 def test_unpublished_neighbours_ignored():
     _say("case: two facing arms without publish")
     sc = small_scene(2, n=64, h=10)
