@@ -885,10 +885,19 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
 // launched outside the captured graph).
 __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
   __shared__ float s_mu[kMaxArms * kMaxH * kMaxDof];
+  // the read side of the board and the arms' sizes, loaded together up front
+  __shared__ float s_bdist[kMaxArms], s_dnow[kMaxArms];
+  __shared__ int s_bvalid[kMaxArms], s_S[kMaxArms], s_H[kMaxArms];
   const int tid = threadIdx.x;
   const Params& P = *A.P;
   StepState& SS = *A.ss;
   const int nA = P.A;
+  if (tid < nA) {
+    s_bvalid[tid] = A.meta->valid[0][tid];
+    s_bdist[tid] = A.meta->dist[0][tid];
+    s_S[tid] = A.arms[tid].S;
+    s_H[tid] = A.arms[tid].H;
+  }
   for (int i = tid; i < nA * 21; i += blockDim.x) A.st_state[i] = A.state[i];
   for (int i = tid; i < nA * 7; i += blockDim.x) A.st_goal[i] = A.goal[i];
   for (int i = tid; i < A.n_obs * 4; i += blockDim.x) A.st_obs[i] = A.obstacles[i];
@@ -924,7 +933,9 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
     frame_point(F[6], arm->tool[0], arm->tool[1], arm->tool[2], ex, ey, ez);
     const float* g = A.goal + a * 7;
     const float dx = ex - g[0], dy = ey - g[1], dz = ez - g[2];
-    SS.dist_now[a] = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
+    const float dnow = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz)));
+    SS.dist_now[a] = dnow;
+    s_dnow[a] = dnow;
     // Goal rotation from the (normalised) quaternion w, x, y, z.
     float w = g[3], x = g[4], y = g[5], z = g[6];
     const float inv = 1.0f / sqrtf(fmaf_(w, w, fmaf_(x, x, fmaf_(y, y, z * z))));
@@ -940,29 +951,34 @@ __global__ __launch_bounds__(256) void k_sense(SenseArgs A) {
     SS.u_out = A.u_out;
   }
   __syncthreads();
-  // Priority factors against every published neighbour (Eq. 10) and the
-  // per-arm neighbour table.
-  if (tid < nA) {
-    const int a = tid;
-    const float da = fmaxf(SS.dist_now[a], P.dist_floor);
-    int cnt = 0;
-    for (int i = 0; i < nA; ++i) {
-      float al = 0.f;
-      if (i != a && A.meta->valid[0][i]) {
-        const float di = fmaxf(A.meta->dist[0][i], P.dist_floor);
-        al = fminf(fmaxf(powf(da / di, P.tau), P.prio_min), P.prio_max);
-        Nb nb;
-        nb.arm = i;
-        nb.S = A.arms[i].S;
-        nb.H = A.arms[i].H;
-        nb.pad = 0;
-        nb.alpha = al;
-        nb.pad1 = nb.pad2 = nb.pad3 = 0.f;
-        SS.nb[a][cnt++] = nb;
-      }
-      SS.alpha[a][i] = al;
+  // Priority factors against every published neighbour (Eq. 10), one thread
+  // of wave 0 per (arm a, neighbour i), and the per-arm neighbour table in
+  // increasing i (each entry's slot is the count of published neighbours
+  // before it, from a ballot over the arm's 8 lanes).
+  static_assert(kMaxArms * kMaxArms <= kWave, "the (arm, neighbour) threads form one wave");
+  if (tid < kMaxArms * kMaxArms) {
+    const int a = tid / kMaxArms, i = tid % kMaxArms;
+    const bool in = a < nA && i < nA;
+    const bool act = in && i != a && s_bvalid[i] != 0;
+    float al = 0.f;
+    if (act) {
+      const float da = fmaxf(s_dnow[a], P.dist_floor);
+      const float di = fmaxf(s_bdist[i], P.dist_floor);
+      al = fminf(fmaxf(powf(da / di, P.tau), P.prio_min), P.prio_max);
     }
-    SS.nb_count[a] = cnt;
+    if (in) SS.alpha[a][i] = al;
+    const unsigned row = (unsigned)(__ballot(act) >> (kMaxArms * a)) & 0xFFu;
+    if (act) {
+      Nb nb;
+      nb.arm = i;
+      nb.S = s_S[i];
+      nb.H = s_H[i];
+      nb.pad = 0;
+      nb.alpha = al;
+      nb.pad1 = nb.pad2 = nb.pad3 = 0.f;
+      SS.nb[a][__popc(row & ((1u << i) - 1u))] = nb;
+    }
+    if (in && i == 0) SS.nb_count[a] = __popc(row);
   }
 }
 
