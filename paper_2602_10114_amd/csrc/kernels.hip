@@ -1301,8 +1301,15 @@ __device__ __forceinline__ void cov_update(const ReduceArgs& A, const Params& P,
 // The chunk partials of one (arm, step) added in chunk order.
 __device__ __forceinline__ float chunk_total(const ReduceArgs& A, const Params& P, int a, int h, int nchunks, int e) {
   const float* part = A.wpart + (((size_t)a * P.Hmax + h) * kWmeanMaxChunks) * kWmeanSums + e;
-  float t = part[0];
-  for (int c2 = 1; c2 < nchunks; ++c2) t += part[(size_t)c2 * kWmeanSums];
+  // every chunk's partial is loaded before the sum (one memory round trip),
+  // then added in chunk order
+  float v[kWmeanMaxChunks];
+#pragma unroll
+  for (int c2 = 0; c2 < kWmeanMaxChunks; ++c2) v[c2] = c2 < nchunks ? part[(size_t)c2 * kWmeanSums] : 0.f;
+  float t = v[0];
+#pragma unroll
+  for (int c2 = 1; c2 < kWmeanMaxChunks; ++c2)
+    if (c2 < nchunks) t += v[c2];
   return t;
 }
 
@@ -1336,16 +1343,25 @@ __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin
   __shared__ float s_q[kMaxH][8];
   __shared__ Frame s_F[kMaxH][7];
   __shared__ float4 s_slot[kMaxSpheres];
-  __shared__ int s_src[kMaxSpheres];
+  __shared__ int s_src[kMaxSpheres], s_body[kMaxSpheres];
   const int a = blockIdx.x, tid = threadIdx.x;
   const Params& P = *A.P;
   const DevArm* arm = A.arms + a;
   const int H = arm->H;
   const int slots = kLayoutSlots[arm->layout];
+  // the sensed joint of thread j < 7, loaded while the totals come in
+  float q0 = 0.f, qd0 = 0.f;
+  if (tid < 7) {
+    q0 = A.st_state[(a * 7 + tid) * 3 + 0];
+    qd0 = A.st_state[(a * 7 + tid) * 3 + 1];
+  }
   // The sphere table for the plan spheres below (read after the barriers).
   for (int e = tid; e < slots; e += kToplanThreads) {
     s_slot[e] = reinterpret_cast<const float4*>(arm->slot)[e];
     s_src[e] = arm->slot_src[e];
+    int b = 0;
+    while (e >= kLayoutStart[arm->layout][b + 1]) ++b;
+    s_body[e] = b;
   }
   // The arm's means (updated here after the last iteration) in LDS for the
   // integration below.
@@ -1365,7 +1381,7 @@ __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin
   if (tid < 7) {
     // One thread per joint (the joints integrate independently).
     const int j = tid;
-    float q = A.st_state[(a * 7 + j) * 3 + 0], qd = A.st_state[(a * 7 + j) * 3 + 1];
+    float q = q0, qd = qd0;
     for (int h = 0; h < H; ++h) {
       if (P.plan_mode == 0) {
         qd = fmaf_(P.dt, s_mu[h * 7 + j], qd);
@@ -1392,8 +1408,7 @@ __global__ __launch_bounds__(kToplanThreads) void k_toplan(ReduceArgs A, int fin
     const int h = e / slots, jslot = e % slots;
     const int src = s_src[jslot];
     if (src < 0) continue;
-    int b = 0;
-    while (jslot >= kLayoutStart[arm->layout][b + 1]) ++b;
+    const int b = s_body[jslot];
     const float4 p = s_slot[jslot];
     float x, y, z;
     frame_point(s_F[h][b < 7 ? b : 6], p.x, p.y, p.z, x, y, z);
