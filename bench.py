@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
 # valid only for the kernel sources with this digest (see
 # profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "cf81d0478e0b9753",
-           "bytes_per_launch": {1: 49189000, 2: 51005000, 4: 132113000}}
+TRAFFIC = {"sources_sha256": "e9f60464afb40da9",
+           "bytes_per_launch": {1: 95733000, 2: 176837000, 4: 131210000}}
 
 
 def traffic_bytes(waves):
@@ -670,6 +670,9 @@ def main():
                     help="print a summary of rocprofv3 output of a bench run and exit")
     ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
                     help="print a summary of a rocprofv3 --pmc pass (per-kernel counters, MFMA busy share) and exit")
+    ap.add_argument("--tuning", metavar="R,T,G",
+                    help="exact leg: fix the rollout launch (rollouts per workgroup, horizon tile, grid) "
+                         "instead of tuning it, e.g. for counter runs at the tuner's usual pick")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference kernel for HBM byte counters) and "
                          "a plain sum over the weighted mean's bytes (read-only reference rate)")
@@ -705,6 +708,8 @@ def main():
     stream = torch.cuda.Stream()
     scene = scenes.make_scene(5, collision_mode=0)
     ctl = native.Controller(scene.arms, scene.params, stream=stream)
+    if args.tuning:
+        ctl.set_tuning(*[int(x) for x in args.tuning.split(",")])
     wall, lat, roll_ms, _ = timed_loop(ctl, scene, stream, args.steps, args.warmup, 0, dev)
     tuning = list(ctl.tuning())
     print(f"bench: exact {args.steps} steps in {wall:.3f} s, tuning {tuning}", file=sys.stderr, flush=True)
