@@ -255,15 +255,23 @@ __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__
 // sphere: `cand` has bit j set for own sphere j.  The own centre is rebuilt
 // from the body frame and the LDS table with the same operations as in the
 // filter, so it is the same FP32 value.
+// A candidate whose FP32 gap is at least 1e-4 m above min(best, B) (FP32
+// error of the gap < 2e-6 m for coordinates within 6 m) cannot bring the
+// minimum below B nor lower a minimum already below B, so its FP64 gap is
+// not formed: the hinge and the audit's tests of the minimum against B and 0
+// are those of the full FP64 scan.
 template <int S0>
 __device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& L, unsigned cand, float px,
-                                                 float py, float pz, float pr, double& best) {
+                                                 float py, float pz, float pr, float B, double& best) {
   while (cand) {
     const int j = __builtin_ctz(cand);
     cand &= cand - 1u;
     const float4 p = L.slot[S0 + j];
     float x, y, z;
     frame_point(W, p.x, p.y, p.z, x, y, z);
+    const float dx = x - px, dy = y - py, dz = z - pz;
+    const float g32 = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - p.w - pr;
+    if ((double)g32 >= fmin(best, (double)B) + 1.0e-4) continue;
     const double g = sphere_gap64(x, y, z, p.w, px, py, pz, pr);
     best = g < best ? g : best;
   }
@@ -278,7 +286,7 @@ __device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& 
 template <int LAY, int B_>
 __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ arm, const Chain& C,
                                            const LdsSets& L, int k0, int K, unsigned fb, const float4* wb,
-                                           int qslot, bool ql, int ord, double& best) {
+                                           int qslot, bool ql, int ord, float B, double& best) {
   constexpr int Cb = kLayoutCount[LAY][B_], S0 = kLayoutStart[LAY][B_];
   if ((fb >> B_) == 0u) return;  // no flagged body at or past B_
   if constexpr (B_ < 7) walk(W, arm, C, B_);
@@ -312,11 +320,11 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
           t = fmaf_(ur[j], w.w, t);
           cand |= (t + Fk < kSlack ? 1u : 0u) << j;
         }
-        if (cand) exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], best);
+        if (cand) exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], B, best);
       }
     }
   }
-  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, fb, wb, qslot, ql, ord, best);
+  if constexpr (B_ + 1 < kBodies) set_refine<LAY, B_ + 1>(W, arm, C, L, k0, K, fb, wb, qslot, ql, ord, B, best);
 }
 
 // Self collision: sphere pairs on bodies at least two apart in the chain.  A
@@ -338,7 +346,7 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
                                            const Chain& C, const LdsSets& L, float buf, const float ux[8],
                                            const float uy[8], const float uz[8], const float ur[8],
                                            const float E[8], float rmb, unsigned row, const SelfKeep& K,
-                                           bool refine, unsigned long long& near, double& best) {
+                                           float hbuf, bool refine, unsigned long long& near, double& best) {
   constexpr int C1 = kLayoutCount[LAY][B1], S1 = kLayoutStart[LAY][B1], H1 = (C1 + 1) / 2;
   constexpr int C2 = kLayoutCount[LAY][B2], S2 = kLayoutStart[LAY][B2], H2 = (C2 + 1) / 2;
   constexpr int sh = 8 * B1 + B2;
@@ -376,7 +384,7 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
             t = fmaf_(ur[j], wr, t);
             cand |= (t + Fk < kSlack ? 1u : 0u) << j;
           }
-          if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, best);
+          if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, hbuf, best);
         } else {
           float m = 3.0e38f;
 #pragma unroll
@@ -391,7 +399,7 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
     }
   }
   if constexpr (B2 + 1 < kBodies)
-    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, row, K, refine, near, best);
+    self_inner<LAY, B1, B2 + 1>(W2, W1, arm, C, L, buf, ux, uy, uz, ur, E, rmb, row, K, hbuf, refine, near, best);
 }
 
 template <int LAY, int B1>
@@ -413,7 +421,8 @@ __device__ __forceinline__ void self_outer(Frame& W1, const DevArm* __restrict__
         for (int j = 0; j < 8; ++j) ur[j] = 0.f;
       }
       Frame W2 = W1;
-      self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, row, K, refine, near, best);
+      self_inner<LAY, B1, B1 + 1>(W2, W1, arm, C, L, 0.f, ux, uy, uz, ur, E, rmb, row, K, buf, refine, near,
+                                  best);
     }
     if ((pairs >> (8 * (B1 + 1))) != 0ull) self_outer<LAY, B1 + 1>(W1, arm, C, L, buf, pairs, K, refine, near, best);
   }
@@ -431,9 +440,15 @@ __device__ __forceinline__ float self_hinge(const DevArm* __restrict__ arm, cons
   self_outer<LAY, 0>(W, arm, C, L, buf, pairs, K, false, near, best);
   const bool any_near = near != 0ull;
   if (!wave_any(any_near)) return 0.f;
+  // the exact pass walks only to the body pairs some lane flagged
+  unsigned long long flagged = 0ull;
+  for (unsigned long long m = pairs; m != 0ull; m &= m - 1ull) {
+    const int b = __builtin_ctzll(m);
+    if (wave_any(((near >> b) & 1ull) != 0ull)) flagged |= 1ull << b;
+  }
   ++refines;
   frame_base(W, arm);
-  self_outer<LAY, 0>(W, arm, C, L, buf, pairs, K, true, near, best);
+  self_outer<LAY, 0>(W, arm, C, L, buf, flagged, K, true, near, best);
   return any_near ? (float)hinge64(best, (double)buf) : 0.f;
 }
 
@@ -813,7 +828,7 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
           for (int b = 0; b < kBodies; ++b) fb |= wave_any((nearb >> b) & 1u) ? 1u << b : 0u;
           const bool obs = si < obs_set;
           set_refine<LAY, 0>(W, arm, C, L, k0, K, fb, wb, obs ? lane : qn_slot, obs ? ol : nl,
-                             obs ? -1 : si - obs_set, best);
+                             obs ? -1 : si - obs_set, L.set_buf[si], best);
           float hv = near ? (float)hinge64(best, (double)L.set_buf[si]) : 0.f;
           if (SURM == 2 && ((wskip >> si) & 1u)) {
             const bool hit = live && near;
