@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
 # valid only for the kernel sources with this digest (see
 # profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "e9f60464afb40da9",
-           "bytes_per_launch": {1: 95733000, 2: 176837000, 4: 131210000}}
+TRAFFIC = {"sources_sha256": "bdf907221a950009",
+           "bytes_per_launch": {1: 88599000, 2: 169615000, 4: 127743000}}
 
 
 def traffic_bytes(waves):
