@@ -5,8 +5,9 @@
 //                (arm, step, rollout), isotropic or from the adapted covariance.
 //   k_rollout    Rollout for every arm in one launch: dynamics, forward
 //                kinematics over the collision spheres, the stage cost of
-//                Eq. 5 with the coordination term of Eqs. 6-9, written per
-//                rollout step.
+//                Eq. 5 with the coordination term of Eqs. 6-9 (sphere pairs
+//                culled per wave by bounding spheres, the rest filtered and
+//                checked exactly), written per rollout step.
 //   k_total      Eq. 1 totals from the per-step stage costs.
 //   k_softmax    Eq. 2 weights, PickBest (Act).
 //   k_wmean      Eq. 3 weighted sums per chunk of rollouts; k_wmean_fin (or
@@ -47,7 +48,8 @@ static_assert(kMaxSets * kBodies <= 64, "one near bit per (set, body) in a 64-bi
 // (FP32 rounding, below 0.005 m for coordinates within 6 m) to every own
 // sphere of the body in every lane: no pair of it can contribute to the
 // hinge, so the filter skips it.  The lanes test 64 (body, group) pairs at a
-// time.  The cost is unchanged bit for bit.
+// time.  Self collision is culled the same way per pair of body halves.  The
+// cost is unchanged bit for bit.
 constexpr float kCullPad = 0.01f;
 constexpr int kNbGroups = kMaxSpheres / 8;
 constexpr int kMaxGroups = kMaxObs + (kMaxArms - 1) * kNbGroups;
