@@ -621,7 +621,7 @@ def min_drop_sweep(config, params, screen, dev, stream, steps=300):
     return out, min(out, key=out.get)
 
 
-def screen_sweep(config, params, stream, dev, steps, warmup, probe=SURROGATE_PROBE):
+def screen_sweep(config, params, stream, dev, steps, warmup, probe=SURROGATE_PROBE, pair_cull=1):
     """Learned step time (ms) for each screen distance of SCREEN_SWEEP (the
     mean-rollout distance below which an arm-neighbour-step group skips the
     network and is checked exactly); returns the sweep and the fastest."""
@@ -629,8 +629,8 @@ def screen_sweep(config, params, stream, dev, steps, warmup, probe=SURROGATE_PRO
     out = {}
     for tau in SCREEN_SWEEP:
         sc = scenes.make_scene(config, collision_mode=0)
-        ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": tau, "surrogate_probe": probe},
-                                stream=stream)
+        ctl = native.Controller(sc.arms, {**sc.params, "surrogate_screen": tau, "surrogate_probe": probe,
+                                          "pair_cull": pair_cull}, stream=stream)
         ctl.set_surrogate_params(params)
         w, _, _, _ = timed_loop(ctl, sc, stream, steps, warmup, 1, dev)
         ctl.close()
@@ -789,6 +789,27 @@ def main():
             "train": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()},
             "recipe": native.TRAINING_RECIPE,
         }
+        # The paper's exact check has no broad phase: the same two steps with
+        # the pair cull off (every sphere pair through the filter), on the
+        # same inputs and network, the screen distance swept again for it.
+        sweep3, tau3 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup, pair_cull=0)
+        scene3 = scenes.make_scene(5, collision_mode=0)
+        ctl3 = native.Controller(scene3.arms, {**scene3.params, "collision_mode": 0, "surrogate_screen": tau3,
+                                               "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5,
+                                               "pair_cull": 0}, stream=stream)
+        ctl3.set_surrogate_params(params)
+        w3e, _, roll3e, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
+                                       args.warmup, 0, dev)
+        w3l, _, roll3l, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
+                                       args.warmup, 1, dev)
+        ctl3.close()
+        out["surrogate"]["all_pairs"] = {
+            "exact_ms_per_step": 1e3 * w3e / args.steps, "learned_ms_per_step": 1e3 * w3l / args.steps,
+            "speedup_vs_exact": w3e / w3l, "exact_rollout_kernel_ms": roll3e,
+            "learned_rollout_kernel_ms": roll3l, "screen_m": tau3,
+            "screen_sweep_ms": {str(k): v for k, v in sweep3.items()}}
+        print(f"bench: pair cull off: exact {1e3 * w3e / args.steps:.3f} ms, learned {1e3 * w3l / args.steps:.3f} ms",
+              file=sys.stderr, flush=True)
         if args.audit_steps > 0:
             # The same 8-arm workload, audited: goals re-drawn every second so
             # the arms keep crossing, every dropped check also computed exactly.

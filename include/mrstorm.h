@@ -111,6 +111,12 @@ typedef struct {
                               ever adds exact checks. */
   float surrogate_min_drop;  /* share of a group's checks, [0, 1), see surrogate_probe; 0: a group
                               keeps running the network if it dropped any check */
+  int pair_cull;           /* 1: the rollout kernel skips sphere pairs that bounding spheres
+                              (per body, body half and group of 8 plan spheres, one per wave of
+                              64 rollouts) prove farther apart than the hinge buffer; 0: every
+                              pair goes through the filter (the all-pairs check, for comparison).
+                              Stage costs, controls and plans are bitwise the same either way;
+                              any other value is MPC_EINVAL. */
 } mpc_params;
 
 /* Create a context for n_arms arms (1..MPC_MAX_ARMS, all with the same dof).

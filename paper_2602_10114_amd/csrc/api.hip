@@ -405,6 +405,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
     return fail(nullptr, MPC_EINVAL, "surrogate_probe must be 0 or in [2, 1000]");
   if (!(p->surrogate_min_drop >= 0.f && p->surrogate_min_drop < 1.f))
     return fail(nullptr, MPC_EINVAL, "surrogate_min_drop outside [0, 1)");
+  if (p->pair_cull != 0 && p->pair_cull != 1) return fail(nullptr, MPC_EINVAL, "pair_cull must be 0 or 1");
   bool all52 = true;
   for (int i = 0; i < n_arms; ++i) {
     int counts[kBodies];
@@ -450,6 +451,7 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   Params& P = c->P;
   P.dt = p->dt; P.sigma = p->sigma; P.lambda = p->lambda; P.gamma = p->gamma; P.alpha_mu = p->alpha_mu;
   P.w_pose = p->w_pose; P.w_rot = p->w_rot; P.w_stop = p->w_stop; P.w_joint = p->w_joint;
+  P.pair_cull = p->pair_cull;
   P.w_coll = p->w_coll; P.w_dyn = p->w_dyn; P.buf_env = p->buf_env; P.buf_self = p->buf_self;
   P.buf_dyn = p->buf_dyn; P.tau = p->tau; P.prio_min = p->prio_min; P.prio_max = p->prio_max;
   P.dist_floor = p->dist_floor; P.joint_margin = p->joint_margin;
@@ -583,7 +585,7 @@ static std::vector<long long> tune_key(const mpc_ctx* c) {
   int dev = -1;
   (void)hipGetDevice(&dev);
   std::vector<long long> k = {dev, c->layout, c->collision_mode, c->sur_audit ? 1 : 0, c->P.cov,
-                              c->manip ? 1 : 0, c->P.max_obs, c->A};
+                              c->manip ? 1 : 0, c->P.max_obs, c->A, c->P.pair_cull};
   for (const DevArm& arm : c->harms) {
     k.push_back(arm.N);
     k.push_back(arm.H);

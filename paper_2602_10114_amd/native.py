@@ -77,7 +77,7 @@ class MpcParams(C.Structure):
                 ("surrogate_margin", C.c_float), ("alpha_sigma", C.c_float), ("sigma_floor", C.c_float),
                 ("plan_mode", C.c_int), ("w_manip", C.c_float), ("manip_thresh", C.c_float),
                 ("surrogate_screen", C.c_float), ("surrogate_probe", C.c_int),
-                ("surrogate_min_drop", C.c_float)]
+                ("surrogate_min_drop", C.c_float), ("pair_cull", C.c_int)]
 
 
 _lib = None
@@ -150,6 +150,8 @@ def params_struct(p: dict) -> MpcParams:
             s.surrogate_probe = int(p.get("surrogate_probe", 0))
         elif name == "surrogate_min_drop":
             s.surrogate_min_drop = float(p.get("surrogate_min_drop", 0.0))
+        elif name == "pair_cull":
+            s.pair_cull = int(p.get("pair_cull", 1))
         elif name == "seed":
             s.seed = int(p["seed"])
         else:

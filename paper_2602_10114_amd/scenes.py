@@ -102,7 +102,7 @@ def default_params(**over) -> dict:
              collision_mode=0, surrogate_margin=0.05,
              alpha_sigma=0.0, sigma_floor=1e-3, plan_mode=0,
              w_manip=0.0, manip_thresh=0.1, surrogate_screen=0.0, surrogate_probe=0,
-             surrogate_min_drop=0.0)
+             surrogate_min_drop=0.0, pair_cull=1)
     p.update(over)
     return p
 

@@ -38,10 +38,10 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(mpc_arm_desc), offsetof(mpc_arm_desc, sphere_link),
          offsetof(mpc_arm_desc, base), offsetof(mpc_arm_desc, tool), sizeof(mpc_params));
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(mpc_params, iters), offsetof(mpc_params, seed),
          offsetof(mpc_params, collision_mode), offsetof(mpc_params, surrogate_margin),
          offsetof(mpc_params, surrogate_screen), offsetof(mpc_params, surrogate_probe),
-         offsetof(mpc_params, surrogate_min_drop));
+         offsetof(mpc_params, surrogate_min_drop), offsetof(mpc_params, pair_cull));
   printf("%zu %zu %zu %zu\\n", sizeof(mpc_train_params), offsetof(mpc_train_params, seed),
          offsetof(mpc_train_params, lr_final), offsetof(mpc_train_params, target_floor));
   printf("%zu %zu %zu\\n", sizeof(mpc_train_report), offsetof(mpc_train_report, steps),
@@ -57,6 +57,7 @@ int main(void) {
     expect = [C.sizeof(A), A.sphere_link.offset, A.base.offset, A.tool.offset, C.sizeof(P),
               P.iters.offset, P.seed.offset, P.collision_mode.offset, P.surrogate_margin.offset,
               P.surrogate_screen.offset, P.surrogate_probe.offset, P.surrogate_min_drop.offset,
+              P.pair_cull.offset,
               C.sizeof(T), T.seed.offset, T.lr_final.offset, T.target_floor.offset,
               C.sizeof(R), R.steps.offset, R.val_max_over_near.offset]
     assert [int(x) for x in out] == expect
@@ -112,6 +113,10 @@ def test_descriptor_and_parameter_errors_need_no_device():
     for bad in (-0.1, 1.0, float("nan")):
         rc, msg = _init_rc(sc.arms, {**sc.params, "surrogate_min_drop": bad})
         assert rc == native.MPC_EINVAL and "surrogate_min_drop" in msg
+    # the pair cull is on (1) or off (0)
+    for bad in (-1, 2):
+        rc, msg = _init_rc(sc.arms, {**sc.params, "pair_cull": bad})
+        assert rc == native.MPC_EINVAL and "pair_cull" in msg
     # only 7-DoF chains are built
     six = scenes.dataclasses.replace(sc.arms[0], dh=sc.arms[0].dh[:6], q_lim=sc.arms[0].q_lim[:6],
                                      qd_max=sc.arms[0].qd_max[:6])

@@ -222,6 +222,44 @@ def test_wide_rollout_spread_keeps_every_near_pair():
     assert mixed > 0
 
 
+def _closed_loop(sc, steps, setup=None):
+    """Controls of `steps` closed-loop steps (Publish, step, plant) and the
+    final plans, as host arrays; `setup(ctl)` runs after init."""
+    import torch
+    ctl = native.Controller(sc.arms, sc.params)
+    if setup is not None:
+        setup(ctl)
+    state = torch.as_tensor(sc.state.astype(np.float32), device="cuda").contiguous()
+    us = []
+    for _ in range(steps):
+        ctl.share_plans()
+        u = ctl.step(state, sc.goal, _obs(sc))
+        ctl.sim_execute(state, u)
+        us.append(u.cpu().numpy().copy())
+    ctl.sync()
+    plans = [ctl.get_plan(a)[0].cpu().numpy().copy() for a in range(sc.n_arms)]
+    stats = ctl.surrogate_stats() if setup is not None else None
+    ctl.close()
+    return np.stack(us), plans, stats
+
+
+def test_pair_cull_changes_no_bit():
+    """The bounding-sphere cull of sphere pairs (pair_cull 1) against every
+    pair through the filter (pair_cull 0): closed-loop controls and plans
+    bitwise equal, on scenes where the coordination, obstacle and self terms
+    are live (two facing arms 1 cm apart, also with sigma 4 so the waves fan
+    out; four uneven arms with obstacles; eight arms of 64 spheres)."""
+    cases = ((2, 128, 12, {}), (2, 128, 12, {"sigma": 4.0}), (3, [64, 100, 128, 192], [8, 12, 12, 16], {}),
+             (5, 128, 10, {}))
+    for cfg, n, h, over in cases:
+        _say(f"case: config {cfg} {over} N={n} H={h}, 6 closed-loop steps with pair_cull 1 and 0")
+        (u1, p1, _), (u0, p0, _) = [_closed_loop(small_scene(cfg, n=n, h=h, pair_cull=cull, collision_mode=0,
+                                                             **over), 6) for cull in (1, 0)]
+        assert np.array_equal(u1.view(np.uint32), u0.view(np.uint32)), cfg
+        for a, b in zip(p1, p0):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), cfg
+
+
 def test_unpublished_neighbours_ignored():
     _say("case: two facing arms without publish")
     sc = small_scene(2, n=64, h=10)

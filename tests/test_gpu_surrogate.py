@@ -473,6 +473,48 @@ def test_learned_mixed_drops_stage_costs_against_oracle():
     assert st2["misses"] > 0
 
 
+def test_pair_cull_changes_no_bit_in_learned_and_audited_modes():
+    """Collision mode 1 with a seeded random network (some blocks dropped,
+    some kept), plain and audited: the pair cull on and off give bitwise
+    equal controls and plans over a closed loop, and equal query, drop and
+    audit counters."""
+    import torch
+    rng = np.random.default_rng(11)
+    params = np.zeros(native.MLP_PARAMS, np.float32)
+    o = 0
+    for l in range(len(native.MLP_WIDTHS) - 1):
+        nw = native.MLP_WIDTHS[l + 1] * native.MLP_WIDTHS[l]
+        params[o:o + nw] = rng.uniform(-1, 1, nw) * math.sqrt(6 / native.MLP_WIDTHS[l])
+        params[o + nw:o + nw + native.MLP_WIDTHS[l + 1]] = rng.normal(size=native.MLP_WIDTHS[l + 1]) * 0.3
+        o += nw + native.MLP_WIDTHS[l + 1]
+    for audit in (False, True):
+        _say(f"case: collision mode 1 (audit {audit}), four arms, 128 rollouts x 10 steps, pair_cull 1 and 0")
+        runs = []
+        for cull in (1, 0):
+            sc = small_scene(4, n=128, h=10, pair_cull=cull)
+            ctl = native.Controller(sc.arms, {**sc.params, "collision_mode": 0})
+            ctl.set_surrogate_params(params)
+            ctl.set_collision_mode(1)
+            ctl.surrogate_audit(audit)
+            state = torch.as_tensor(sc.state.astype(np.float32), device="cuda").contiguous()
+            us = []
+            for _ in range(5):
+                ctl.share_plans()
+                u = ctl.step(state, sc.goal, sc.obstacles)
+                ctl.sim_execute(state, u)
+                us.append(u.cpu().numpy().copy())
+            ctl.sync()
+            plans = [ctl.get_plan(a)[0].cpu().numpy().copy() for a in range(sc.n_arms)]
+            runs.append((np.stack(us), plans, ctl.surrogate_stats()))
+            ctl.close()
+        (u1, p1, s1), (u0, p0, s0) = runs
+        assert np.array_equal(u1.view(np.uint32), u0.view(np.uint32))
+        for a, b in zip(p1, p0):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        assert s1 == s0
+        assert 0 < s1["predicted_far"] < s1["queries"]
+
+
 def test_adam_matches_oracle_over_three_steps():
     """The training loop's Adam kernel (bias-corrected, FP32) against the
     oracle's FP64 Adam on the same FP32 parameters and gradients, over three
