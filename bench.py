@@ -638,6 +638,31 @@ def screen_sweep(config, params, stream, dev, steps, warmup, probe=SURROGATE_PRO
     return out, min(out, key=out.get)
 
 
+def all_pairs_leg(out, params, md5, stream, dev, args):
+    """The 8-arm exact and learned steps with the pair cull off (every sphere
+    pair through the filter, as in the paper's exact check), the screen
+    distance swept for that setting; adds out["surrogate"]["all_pairs"]."""
+    from paper_2602_10114_amd import native
+    sweep3, tau3 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup, pair_cull=0)
+    scene3 = scenes.make_scene(5, collision_mode=0)
+    ctl3 = native.Controller(scene3.arms, {**scene3.params, "collision_mode": 0, "surrogate_screen": tau3,
+                                           "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5,
+                                           "pair_cull": 0}, stream=stream)
+    ctl3.set_surrogate_params(params)
+    w3e, _, roll3e, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
+                                   args.warmup, 0, dev)
+    w3l, _, roll3l, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
+                                   args.warmup, 1, dev)
+    ctl3.close()
+    out["surrogate"]["all_pairs"] = {
+        "exact_ms_per_step": 1e3 * w3e / args.steps, "learned_ms_per_step": 1e3 * w3l / args.steps,
+        "speedup_vs_exact": w3e / w3l, "exact_rollout_kernel_ms": roll3e,
+        "learned_rollout_kernel_ms": roll3l, "screen_m": tau3,
+        "screen_sweep_ms": {str(k): v for k, v in sweep3.items()}}
+    print(f"bench: pair cull off: exact {1e3 * w3e / args.steps:.3f} ms, learned {1e3 * w3l / args.steps:.3f} ms",
+          file=sys.stderr, flush=True)
+
+
 def train_surrogate(scene):
     from paper_2602_10114_amd import native
     ctl = native.Controller(scene.arms, {**scene.params, "collision_mode": 0})
@@ -670,6 +695,8 @@ def main():
                     help="print a summary of rocprofv3 output of a bench run and exit")
     ap.add_argument("--summarize-pmc", metavar="PMC_DIR",
                     help="print a summary of a rocprofv3 --pmc pass (per-kernel counters, MFMA busy share) and exit")
+    ap.add_argument("--no-all-pairs", action="store_true",
+                    help="skip the legs with the pair cull off (the all-pairs check)")
     ap.add_argument("--tuning", metavar="R,T,G",
                     help="exact leg: fix the rollout launch (rollouts per workgroup, horizon tile, grid) "
                          "instead of tuning it, e.g. for counter runs at the tuner's usual pick")
@@ -792,24 +819,8 @@ def main():
         # The paper's exact check has no broad phase: the same two steps with
         # the pair cull off (every sphere pair through the filter), on the
         # same inputs and network, the screen distance swept again for it.
-        sweep3, tau3 = screen_sweep(5, params, stream, dev, max(5, args.steps // 2), args.warmup, pair_cull=0)
-        scene3 = scenes.make_scene(5, collision_mode=0)
-        ctl3 = native.Controller(scene3.arms, {**scene3.params, "collision_mode": 0, "surrogate_screen": tau3,
-                                               "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5,
-                                               "pair_cull": 0}, stream=stream)
-        ctl3.set_surrogate_params(params)
-        w3e, _, roll3e, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
-                                       args.warmup, 0, dev)
-        w3l, _, roll3l, _ = timed_loop(ctl3, scenes.make_scene(5, collision_mode=0), stream, args.steps,
-                                       args.warmup, 1, dev)
-        ctl3.close()
-        out["surrogate"]["all_pairs"] = {
-            "exact_ms_per_step": 1e3 * w3e / args.steps, "learned_ms_per_step": 1e3 * w3l / args.steps,
-            "speedup_vs_exact": w3e / w3l, "exact_rollout_kernel_ms": roll3e,
-            "learned_rollout_kernel_ms": roll3l, "screen_m": tau3,
-            "screen_sweep_ms": {str(k): v for k, v in sweep3.items()}}
-        print(f"bench: pair cull off: exact {1e3 * w3e / args.steps:.3f} ms, learned {1e3 * w3l / args.steps:.3f} ms",
-              file=sys.stderr, flush=True)
+        if not args.no_all_pairs:
+            all_pairs_leg(out, params, md5, stream, dev, args)
         if args.audit_steps > 0:
             # The same 8-arm workload, audited: goals re-drawn every second so
             # the arms keep crossing, every dropped check also computed exactly.

@@ -125,6 +125,7 @@ struct mpc_ctx {
   int n_items = 0;
   int h_tile = 0, grid = 0, waves = 1;  // launch shape: horizon tile, workgroups, 64-rollout waves per workgroup
   int force_tile = 0, force_grid = 0, force_waves = 0;
+  int pair_cull = 1;                   // 0: every body bound is unbounded (no pair is culled)
   unsigned long long* tune_counts = nullptr;  // learned-distance counters of tuner replays [A][kSurCounters]
   bool tuned = false;
   int n_published = 0;                 // arms whose plan has been published at least once
@@ -443,15 +444,25 @@ extern "C" int mpc_init(const mpc_arm_desc* arms, int n_arms, const mpc_params* 
   c->layout = all52 ? 0 : 1;
   c->harms.resize(n_arms);
   long long eps_off = 0;
+  c->pair_cull = p->pair_cull;
   for (int i = 0; i < n_arms; ++i) {
     build_arm(c, arms[i], c->layout, c->harms[i]);
+    if (!c->pair_cull) {
+      // Every body and half-body bound reaches every group (1e18 m; squares
+      // stay finite in FP32), so the kernels' cull keeps every sphere pair:
+      // the all-pairs check.
+      for (int b = 0; b < kBodies; ++b) {
+        if (c->harms[i].bnd[b][3] >= 0.f) c->harms[i].bnd[b][3] = 1.0e18f;
+        for (int half = 0; half < 2; ++half)
+          if (c->harms[i].hb[b][half][3] >= 0.f) c->harms[i].hb[b][half][3] = 1.0e18f;
+      }
+    }
     c->harms[i].eps_off = eps_off;
     eps_off += (long long)arms[i].horizon * 7 * c->harms[i].Npad;
   }
   Params& P = c->P;
   P.dt = p->dt; P.sigma = p->sigma; P.lambda = p->lambda; P.gamma = p->gamma; P.alpha_mu = p->alpha_mu;
   P.w_pose = p->w_pose; P.w_rot = p->w_rot; P.w_stop = p->w_stop; P.w_joint = p->w_joint;
-  P.pair_cull = p->pair_cull;
   P.w_coll = p->w_coll; P.w_dyn = p->w_dyn; P.buf_env = p->buf_env; P.buf_self = p->buf_self;
   P.buf_dyn = p->buf_dyn; P.tau = p->tau; P.prio_min = p->prio_min; P.prio_max = p->prio_max;
   P.dist_floor = p->dist_floor; P.joint_margin = p->joint_margin;
@@ -585,7 +596,7 @@ static std::vector<long long> tune_key(const mpc_ctx* c) {
   int dev = -1;
   (void)hipGetDevice(&dev);
   std::vector<long long> k = {dev, c->layout, c->collision_mode, c->sur_audit ? 1 : 0, c->P.cov,
-                              c->manip ? 1 : 0, c->P.max_obs, c->A, c->P.pair_cull};
+                              c->manip ? 1 : 0, c->P.max_obs, c->A, c->pair_cull};
   for (const DevArm& arm : c->harms) {
     k.push_back(arm.N);
     k.push_back(arm.H);

@@ -68,7 +68,6 @@ struct Params {
   uint32_t seed_lo, seed_hi;
   int iters, A, dof, Hmax, Smax, Nmax, max_obs;
   int plan_mode, cov;          // cov: covariance adaptation on (alpha_sigma > 0)
-  int pair_cull, pad_pc;       // bounding-sphere cull of sphere pairs on (1) or off (0)
   float gpow[kMaxH];           // gamma^h rounded to FP32
 };
 

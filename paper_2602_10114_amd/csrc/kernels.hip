@@ -741,8 +741,7 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
           const float dx = x - c3[k].x, dy = y - c3[k].y, dz = z - c3[k].z;
           dev = fmaxf(dev, sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))));
         }
-        // with the cull off every sphere reaches every group (all pairs)
-        const float spread = P.pair_cull ? wave_max(dev) + 1.0e-4f : 1.0e18f;
+        const float spread = wave_max(dev) + 1.0e-4f;
         if (lane == 0) {
           wb[b] = make_float4(c3[0].x, c3[0].y, c3[0].z, c3[0].w >= 0.f ? c3[0].w + spread : -1.f);
           wh[b][0] = make_float4(c3[1].x, c3[1].y, c3[1].z, c3[1].w >= 0.f ? c3[1].w + spread : -1.f);
