@@ -483,6 +483,8 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
   // each wave's body and half-body spheres at the current step (pair cull)
   __shared__ float4 s_wb[WPB][kBodies];
   __shared__ float4 s_wh[WPB][kBodies][2];
+  // each lane's joints while the self and set checks run (one column per lane)
+  __shared__ float s_qq[14][kWave * WPB];
   static_assert(kNbrRec == 8, "neighbour record layout of the learned distance");
   constexpr int kThreads = kWave * WPB;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -802,6 +804,13 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
         c = fmaf_(P.w_joint, joint, c);
         if (A.manip) c = fmaf_(P.w_manip, A.manip[((size_t)a * P.Hmax + h) * P.Nmax + n], c);
       }
+      // The joints wait in LDS while the self and set checks run (fewer
+      // registers live through them).
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        s_qq[j][tid] = q[j];
+        s_qq[7 + j][tid] = qd[j];
+      }
       // Self collision.
       c = fmaf_(P.w_coll, self_hinge<LAY>(arm, C, L, P.buf_self, skeep, self_refines), c);
       // Obstacles and neighbours' plans (Eqs. 6, 8, 9): one filter pass over
@@ -853,6 +862,12 @@ __global__ __launch_bounds__(kWave * WPB, 3) void k_rollout(const DevArm* __rest
       // The stage cost goes out per step; Eq. 1's discounted sum is formed in
       // k_total over h in a fixed order, so it does not depend on the tiling.
       if (live) A.partial[((size_t)a * kMaxH + h) * P.Nmax + n] = c;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        asm volatile("" ::: "memory");
+        q[j] = s_qq[j][tid];
+        qd[j] = s_qq[7 + j][tid];
+      }
 
       if (DBG && live) {
         const size_t row = ((size_t)a * P.Nmax + n) * P.Hmax + h;
