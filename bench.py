@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
 # valid only for the kernel sources with this digest (see
 # profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "3795adc9d279ae14",
-           "bytes_per_launch": {1: 47807000, 2: 97052000, 4: 76092000}}
+TRAFFIC = {"sources_sha256": "eb4067fd07970610",
+           "bytes_per_launch": {1: 48012000, 2: 128296000, 4: 93154000}}
 
 
 def traffic_bytes(waves):

@@ -254,26 +254,41 @@ __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__
 }
 
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
-// sphere: `cand` has bit j set for own sphere j.  The own centre is rebuilt
-// from the body frame and the LDS table with the same operations as in the
-// filter, so it is the same FP32 value.
-// A candidate whose FP32 gap is at least 1e-4 m above min(best, B) (FP32
-// error of the gap < 2e-6 m for coordinates within 6 m) cannot bring the
-// minimum below B nor lower a minimum already below B, so its FP64 gap is
-// not formed: the hinge and the audit's tests of the minimum against B and 0
-// are those of the full FP64 scan.
-template <int S0>
-__device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& L, unsigned cand, float px,
-                                                 float py, float pz, float pr, float B, double& best) {
-  while (cand) {
-    const int j = __builtin_ctz(cand);
-    cand &= cand - 1u;
+// sphere: `cand` has bit j set for own sphere j, whose centre the caller
+// holds in (ux, uy, uz)[j] (built from the body frame and the LDS table).
+// First the FP32 gaps of every candidate, then the FP64 gap of each
+// candidate whose FP32 gap is below min(best, B, smallest FP32 gap) + 1e-4 m,
+// its centre rebuilt with the same operations (the same FP32 value).  With
+// the FP32 error of a gap below 2e-6 m (coordinates within 6 m), a skipped
+// candidate's FP64 gap exceeds min(best, B) or the FP64 gap of the candidate
+// with the smallest FP32 gap, which is never skipped while it can matter: the
+// hinge and the audit's tests of the minimum against B and 0 are those of the
+// full FP64 scan.
+template <int S0, int Cb>
+__device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& L, unsigned cand, const float ux[8],
+                                                 const float uy[8], const float uz[8], float px, float py, float pz,
+                                                 float pr, float B, double& best) {
+  float g32[Cb];
+  float m32 = 3.0e38f;
+#pragma unroll
+  for (int j = 0; j < Cb; ++j) {
+    g32[j] = 3.0e38f;
+    if ((cand >> j) & 1u) {
+      const float dx = ux[j] - px, dy = uy[j] - py, dz = uz[j] - pz;
+      g32[j] = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - L.slot[S0 + j].w - pr;
+      m32 = fminf(m32, g32[j]);
+    }
+  }
+  const double thr = fmin(fmin(best, (double)B), (double)m32) + 1.0e-4;
+  unsigned need = 0u;
+#pragma unroll
+  for (int j = 0; j < Cb; ++j) need |= ((cand >> j) & 1u) && (double)g32[j] < thr ? 1u << j : 0u;
+  while (need) {
+    const int j = __builtin_ctz(need);
+    need &= need - 1u;
     const float4 p = L.slot[S0 + j];
     float x, y, z;
     frame_point(W, p.x, p.y, p.z, x, y, z);
-    const float dx = x - px, dy = y - py, dz = z - pz;
-    const float g32 = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - p.w - pr;
-    if ((double)g32 >= fmin(best, (double)B) + 1.0e-4) continue;
     const double g = sphere_gap64(x, y, z, p.w, px, py, pz, pr);
     best = g < best ? g : best;
   }
@@ -322,7 +337,8 @@ __device__ __forceinline__ void set_refine(Frame& W, const DevArm* __restrict__ 
           t = fmaf_(ur[j], w.w, t);
           cand |= (t + Fk < kSlack ? 1u : 0u) << j;
         }
-        if (cand) exact_candidates<S0>(W, L, cand, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], B, best);
+        if (cand)
+          exact_candidates<S0, Cb>(W, L, cand, ux, uy, uz, -0.5f * w.x, -0.5f * w.y, -0.5f * w.z, L.rr[k], B, best);
       }
     }
   }
@@ -386,7 +402,7 @@ __device__ __forceinline__ void self_inner(Frame& W2, const Frame& W1, const Dev
             t = fmaf_(ur[j], wr, t);
             cand |= (t + Fk < kSlack ? 1u : 0u) << j;
           }
-          if (cand) exact_candidates<S1>(W1, L, cand, x, y, z, r, hbuf, best);
+          if (cand) exact_candidates<S1, C1>(W1, L, cand, ux, uy, uz, x, y, z, r, hbuf, best);
         } else {
           float m = 3.0e38f;
 #pragma unroll
