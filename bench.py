@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["paper_2602_10114_amd/csrc/kernels.hip", "paper_2602_10114_amd
 # counter's reading for a 256 MiB device copy (fetch x2.000, write x1.000);
 # valid only for the kernel sources with this digest (see
 # profiles/k_rollout_cfg5_exact.md).
-TRAFFIC = {"sources_sha256": "eb4067fd07970610",
-           "bytes_per_launch": {1: 48012000, 2: 128296000, 4: 93154000}}
+TRAFFIC = {"sources_sha256": "9ff49b4953348398",
+           "bytes_per_launch": {1: 48041000, 2: 105265000, 4: 76774000}}
 
 
 def traffic_bytes(waves):

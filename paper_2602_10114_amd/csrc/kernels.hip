@@ -256,33 +256,30 @@ __device__ __forceinline__ void sets_filter(Frame& W, const DevArm* __restrict__
 // Exact FP64 gaps of the candidate pairs of one own body against one staged
 // sphere: `cand` has bit j set for own sphere j, whose centre the caller
 // holds in (ux, uy, uz)[j] (built from the body frame and the LDS table).
-// First the FP32 gaps of every candidate, then the FP64 gap of each
-// candidate whose FP32 gap is below min(best, B, smallest FP32 gap) + 1e-4 m,
-// its centre rebuilt with the same operations (the same FP32 value).  With
-// the FP32 error of a gap below 2e-6 m (coordinates within 6 m), a skipped
-// candidate's FP64 gap exceeds min(best, B) or the FP64 gap of the candidate
-// with the smallest FP32 gap, which is never skipped while it can matter: the
-// hinge and the audit's tests of the minimum against B and 0 are those of the
-// full FP64 scan.
+// One pass forms the candidates' FP32 gaps (no dependent loads) and marks
+// each whose gap is below min(best, B, smallest FP32 gap so far) + 1e-4 m;
+// then the marked candidates' FP64 gaps, their centres rebuilt with the same
+// operations (the same FP32 values).  With the FP32 error of a gap below
+// 2e-6 m (coordinates within 6 m), an unmarked candidate's FP64 gap exceeds
+// min(best, B) or the FP64 gap of a marked candidate with a smaller FP32
+// gap: the hinge and the audit's tests of the minimum against B and 0 are
+// those of the full FP64 scan.
 template <int S0, int Cb>
 __device__ __forceinline__ void exact_candidates(const Frame& W, const LdsSets& L, unsigned cand, const float ux[8],
                                                  const float uy[8], const float uz[8], float px, float py, float pz,
                                                  float pr, float B, double& best) {
-  float g32[Cb];
+  const double lim = fmin(best, (double)B);
   float m32 = 3.0e38f;
-#pragma unroll
-  for (int j = 0; j < Cb; ++j) {
-    g32[j] = 3.0e38f;
-    if ((cand >> j) & 1u) {
-      const float dx = ux[j] - px, dy = uy[j] - py, dz = uz[j] - pz;
-      g32[j] = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - L.slot[S0 + j].w - pr;
-      m32 = fminf(m32, g32[j]);
-    }
-  }
-  const double thr = fmin(fmin(best, (double)B), (double)m32) + 1.0e-4;
   unsigned need = 0u;
 #pragma unroll
-  for (int j = 0; j < Cb; ++j) need |= ((cand >> j) & 1u) && (double)g32[j] < thr ? 1u << j : 0u;
+  for (int j = 0; j < Cb; ++j) {
+    if ((cand >> j) & 1u) {
+      const float dx = ux[j] - px, dy = uy[j] - py, dz = uz[j] - pz;
+      const float g32 = sqrtf(fmaf_(dx, dx, fmaf_(dy, dy, dz * dz))) - L.slot[S0 + j].w - pr;
+      m32 = fminf(m32, g32);
+      need |= (double)g32 < fmin(lim, (double)m32) + 1.0e-4 ? 1u << j : 0u;
+    }
+  }
   while (need) {
     const int j = __builtin_ctz(need);
     need &= need - 1u;
