@@ -248,3 +248,45 @@ def test_full_size_learned_step_sampled_against_oracle(config):
     assert np.mean(d > 1e-5) < 0.1
     assert d.max() < 2e-3
     c.close()
+
+
+def _contact_loop(cull, steps):
+    """Closed loop of the 8-arm workload (goals fixed, obstacles moving) with
+    the pair cull on or off; the last step runs with the capture on, whose
+    per-arm counts of filter passes, set exact passes and self exact passes
+    come back with the controls and the final plans."""
+    sc = scenes.make_scene(5, collision_mode=0, pair_cull=cull)
+    ctl = native.Controller(sc.arms, sc.params)
+    state = torch.as_tensor(sc.state.astype(np.float32), device="cuda").contiguous()
+    us = []
+    for t in range(steps):
+        if t == steps - 1:
+            ctl.debug_enable(True)
+        ctl.share_plans()
+        u = ctl.step(state, sc.goal, _obs(sc))
+        ctl.sim_execute(state, u)
+        us.append(u.cpu().numpy().copy())
+        scenes.move_obstacles(sc, sc.params["dt"])
+    ctl.sync()
+    passes = np.stack([ctl.debug_get("PASSES", a).cpu().numpy() for a in range(sc.n_arms)])
+    plans = [ctl.get_plan(a)[0].cpu().numpy().copy() for a in range(sc.n_arms)]
+    ctl.close()
+    return np.stack(us), plans, passes
+
+
+def test_full_size_closed_loop_in_contact_cull_changes_no_bit():
+    """Eq. 6 and the self term late in a closed loop, where bodies of one arm
+    and of neighbouring arms come within the buffers and the exact passes
+    (FP32 screen, FP64 gaps) run in many waves: 320 steps of the 8-arm
+    workload with the pair cull and with every pair through the filter give
+    bitwise-equal controls and plans, and the last step's capture shows
+    set and self exact passes at work."""
+    steps = 320
+    _say(f"case: 8 arms x 4096 x 40, {steps} closed-loop steps, pair_cull 1 then 0")
+    u1, p1, n1 = _contact_loop(1, steps)
+    u0, p0, n0 = _contact_loop(0, steps)
+    _say(f"  last step: set exact passes {int(n1[:, 1].sum())}, self exact passes {int(n1[:, 2].sum())}")
+    assert n1[:, 1].sum() > 0 and n1[:, 2].sum() > 0
+    assert np.array_equal(u1.view(np.uint32), u0.view(np.uint32))
+    for a, b in zip(p1, p0):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
