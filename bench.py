@@ -360,10 +360,16 @@ def latency_leg(config, steps, dev, stream, params=None, warmup=10, screen=0.0, 
     return out
 
 
-def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
+def timed_loop(ctl, scene, stream, steps, warmup, mode, dev, replay=None):
     """Closed-loop control steps (Publish + mpc_step + plant) on inputs resident
     in HBM; returns wall seconds of the timed steps, per-step latencies (ms)
-    from HIP events, and the rollout-kernel event time per launch."""
+    from HIP events, and the rollout-kernel event time per launch.  The
+    rollout launches are timed with HIP events around each launch, which
+    turns the step's graph off, so in a leg of their own: with `replay` (a
+    function of the chosen tuning that returns a fresh controller) the same
+    warm-up and timed steps again from the same start, so the events time the
+    launches of the timed steps themselves; without it the next `steps`
+    steps of the loop."""
     import torch
     A = scene.n_arms
     obs = torch.as_tensor(obstacle_track(scene, warmup + 2 * steps), device=dev)
@@ -374,15 +380,15 @@ def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
         ctl.set_collision_mode(mode)
         k = 0
 
-        def one_step():
+        def one_step(c):
             nonlocal k
-            ctl.share_plans()
-            ctl.step(state, goal, obs[k], u_out=u)
-            ctl.sim_execute(state, u)
+            c.share_plans()
+            c.step(state, goal, obs[k], u_out=u)
+            c.sim_execute(state, u)
             k += 1
 
         for _ in range(warmup):
-            one_step()
+            one_step(ctl)
         stream.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         ctl.surrogate_stats(reset=True)
@@ -390,21 +396,31 @@ def timed_loop(ctl, scene, stream, steps, warmup, mode, dev):
         t0 = time.perf_counter()
         for i in range(steps):
             ev[i][0].record(stream)
-            one_step()
+            one_step(ctl)
             ev[i][1].record(stream)
         stream.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         stats = ctl.surrogate_stats()
         lat = np.array([a.elapsed_time(b) for a, b in ev])
-        # Same steps again with the rollout launches bracketed by HIP events.
-        ctl.profile_enable(True)
+        pc = ctl
+        if replay is not None:
+            pc = replay(ctl.tuning())
+            pc.set_collision_mode(mode)
+            state.copy_(torch.as_tensor(scene.state, device=dev))
+            u.zero_()
+            k = 0
+            for _ in range(warmup):
+                one_step(pc)
+        pc.profile_enable(True)
         for i in range(steps):
-            one_step()
-        ms_roll, n_roll = ctl.profile_read()
-        ms_inf, n_inf = ctl.profile_read_surrogate()
-        ctl.profile_enable(False)
+            one_step(pc)
+        ms_roll, n_roll = pc.profile_read()
+        ms_inf, n_inf = pc.profile_read_surrogate()
+        pc.profile_enable(False)
         stream.synchronize()
+        if pc is not ctl:
+            pc.close()
     stats["infer_ms"] = ms_inf / n_inf if n_inf else None
     return wall, lat, ms_roll / max(n_roll, 1), stats
 
@@ -737,7 +753,13 @@ def main():
     ctl = native.Controller(scene.arms, scene.params, stream=stream)
     if args.tuning:
         ctl.set_tuning(*[int(x) for x in args.tuning.split(",")])
-    wall, lat, roll_ms, _ = timed_loop(ctl, scene, stream, args.steps, args.warmup, 0, dev)
+
+    def fresh(tuning):
+        c = native.Controller(scene.arms, scene.params, stream=stream)
+        c.set_tuning(*tuning)
+        return c
+
+    wall, lat, roll_ms, _ = timed_loop(ctl, scene, stream, args.steps, args.warmup, 0, dev, replay=fresh)
     tuning = list(ctl.tuning())
     print(f"bench: exact {args.steps} steps in {wall:.3f} s, tuning {tuning}", file=sys.stderr, flush=True)
     scene = scenes.make_scene(5, collision_mode=0)
