@@ -809,11 +809,19 @@ def main():
         else:
             drops5, md5 = {}, args.min_drop
         scene = scenes.make_scene(5, collision_mode=0)
-        ctl2 = native.Controller(scene.arms, {**scene.params, "collision_mode": 0, "surrogate_screen": tau5,
-                                              "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5},
-                                 stream=stream)
-        ctl2.set_surrogate_params(params)
-        w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev)
+        learned_params = {**scene.params, "collision_mode": 0, "surrogate_screen": tau5,
+                          "surrogate_probe": SURROGATE_PROBE, "surrogate_min_drop": md5}
+
+        def fresh_learned(tuning=None):
+            c = native.Controller(scene.arms, learned_params, stream=stream)
+            c.set_surrogate_params(params)
+            if tuning is not None:
+                c.set_tuning(*tuning)
+            return c
+
+        ctl2 = fresh_learned()
+        w2, lat2, roll2, st = timed_loop(ctl2, scene, stream, args.steps, args.warmup, 1, dev,
+                                         replay=fresh_learned)
         ctl2.close()
         q = max(st["queries"], 1)
         # Inference roofline: every query row the network runs (the screened
